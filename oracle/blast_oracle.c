@@ -1,0 +1,712 @@
+/*
+ * blast_oracle.c -- plain, slow, FP64 CPU oracle for the beyond-Limber angular
+ * power spectra of Chiarenza, Bonici, Percival & White, "Blast.jl" (arXiv:2410.03632).
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load this library.  It shares no code, header, table or
+ * helper with the HIP library; the two meet only through the seeded inputs.
+ *
+ * What it computes (the "discrete target" of the method):
+ *
+ *   C^t_ij(l) = N_t(l) sum_a sum_b Wchi_a WR_b chi_a
+ *                 [K_i(chi_a) K_j(R_b chi_a) + K_j(chi_a) K_i(R_b chi_a)]
+ *                 * int_{kmin}^{kmax} dk f_t(k) Phat(k; chi_a, R_b chi_a)
+ *                                        j_l(k chi_a) j_l(k R_b chi_a)
+ *
+ *   - the chi-R form with symmetrisation: Eq. final_cls and Appendix A;
+ *   - f_gg = k^2, f_gs = 1, f_ss = 1/k^2: the definition after Eq. t_tilde;
+ *   - N_gg = 2/pi, N_gs = (2/pi) sqrt((l+2)!/(l-2)!), N_ss = (2/pi)(l+2)!/(l-2)!:
+ *     Eqs. gg, gs, ss (the prefactor is applied after the quadrature; the paper
+ *     drops it from Eq. final_cls);
+ *   - Phat: the polynomial of degree < N that interpolates P at the N first-kind
+ *     Chebyshev points (Eq. chebpoints, Eq. a2) in the variable
+ *     x = 2 (ln k - ln kmin)/(ln kmax - ln kmin) - 1.
+ *
+ * By linearity, sum_n c_n Ttilde_n = int f Phat j j (Eqs. pmd, t_tilde), so the
+ * oracle evaluates the k-integral of the interpolant directly, by brute force,
+ * instead of through a basis and a contraction:
+ *   - Phat(k) by the barycentric formula for first-kind Chebyshev points
+ *     (Berrut & Trefethen, SIAM Review 46 (2004) 501), not by coefficients;
+ *   - j_l by three-term recurrence (upward for x > lmax, otherwise Miller's
+ *     downward recurrence normalised by j_0 or j_1; Abramowitz & Stegun 10.1);
+ *   - the k-integral by composite 16-point Gauss-Legendre on panels that resolve
+ *     both the Chebyshev structure in ln k and the Bessel oscillation (frequency
+ *     chi1 + chi2), refined by doubling until the C_l aggregate stops changing.
+ *
+ * Precision: IEEE double throughout, no fast-math.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_GG 1
+#define OR_GS 2
+#define OR_SS 4
+
+#define OR_P_NODAL 0 /* Phat from nodal values (barycentric)              */
+#define OR_P_GAUSS 1 /* exact P = amp * k^m * exp(-(p k)^2)               */
+#define OR_P_CHEB 2  /* exact P = sum_{n<d} a_n T_n(x(k))  (Clenshaw)     */
+
+static const double OR_PI = 3.14159265358979323846264338327950288;
+
+/* ------------------------------------------------------------------------- */
+/* Gauss-Legendre, 16 points on [-1, 1] (Newton iteration on P_16)           */
+/* ------------------------------------------------------------------------- */
+static double GLX[16], GLW[16];
+
+static void gl_legendre(int n, double x, double *pn, double *dpn)
+{
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= n; k++) {
+        double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+    }
+    *pn = p1;
+    *dpn = n * (x * p1 - p0) / (x * x - 1.0);
+}
+
+__attribute__((constructor)) static void gl_init(void)
+{
+    const int n = 16;
+    for (int i = 0; i < n; i++) {
+        double x = cos(OR_PI * (i + 0.75) / (n + 0.5));
+        double pn, dpn;
+        for (int it = 0; it < 100; it++) {
+            gl_legendre(n, x, &pn, &dpn);
+            double dx = pn / dpn;
+            x -= dx;
+            if (fabs(dx) < 1e-17)
+                break;
+        }
+        gl_legendre(n, x, &pn, &dpn);
+        GLX[i] = x;
+        GLW[i] = 2.0 / ((1.0 - x * x) * dpn * dpn);
+    }
+}
+
+void or_gl16(double *x, double *w)
+{
+    for (int i = 0; i < 16; i++) {
+        x[i] = GLX[i];
+        w[i] = GLW[i];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Grids (defined from the paper's text; see the readings listed with them)  */
+/* ------------------------------------------------------------------------- */
+
+/* chi nodes: n evenly spaced points on [lo, hi] (Sec. "The implementation"),
+ * composite Simpson weights.  For an odd n: Simpson 1/3 on all intervals.  For
+ * an even n (the paper's 96 points): Simpson 1/3 on the first n-4 intervals and
+ * Simpson 3/8 on the last three. */
+int or_grid_chi(int n, double lo, double hi, double *chi, double *w)
+{
+    if (n < 4 || !(hi > lo))
+        return 1;
+    double h = (hi - lo) / (n - 1);
+    for (int i = 0; i < n; i++) {
+        chi[i] = lo + h * i;
+        w[i] = 0.0;
+    }
+    int n13 = (n % 2 == 1) ? n - 1 : n - 4; /* intervals handled by 1/3 */
+    for (int i = 0; i + 2 <= n13; i += 2) {
+        w[i] += h / 3.0;
+        w[i + 1] += 4.0 * h / 3.0;
+        w[i + 2] += h / 3.0;
+    }
+    if (n % 2 == 0) {
+        int s = n - 4;
+        w[s] += 3.0 * h / 8.0;
+        w[s + 1] += 9.0 * h / 8.0;
+        w[s + 2] += 9.0 * h / 8.0;
+        w[s + 3] += 3.0 * h / 8.0;
+    }
+    return 0;
+}
+
+/* R nodes: the n first-kind Chebyshev points of Eq. chebpoints mapped to
+ * [Rmin, 1], ascending, with Fejer's first rule (the Clenshaw-Curtis-type rule
+ * for first-kind points):  w_j = (2/n)[1 - 2 sum_{m=1}^{n/2} cos(2 m th_j)/(4m^2-1)]
+ * on [-1, 1], scaled by (1 - Rmin)/2. */
+int or_grid_R(int n, double Rmin, double *R, double *w)
+{
+    if (n < 1 || !(Rmin >= 0.0) || !(Rmin < 1.0))
+        return 1;
+    for (int i = 0; i < n; i++) {
+        int j = n - 1 - i; /* standard index: t_j descends, we store ascending */
+        double th = (2.0 * j + 1.0) * OR_PI / (2.0 * n);
+        double x = cos(th);
+        double s = 0.0;
+        for (int m = 1; m <= n / 2; m++)
+            s += cos(2.0 * m * th) / (4.0 * m * m - 1.0);
+        double wx = (2.0 / n) * (1.0 - 2.0 * s);
+        R[i] = Rmin + 0.5 * (1.0 - Rmin) * (x + 1.0);
+        w[i] = 0.5 * (1.0 - Rmin) * wx;
+    }
+    return 0;
+}
+
+/* k nodes: the n first-kind Chebyshev points (Eq. chebpoints) in
+ * x = 2 (ln k - ln kmin)/(ln kmax - ln kmin) - 1, stored by ascending k:
+ * x_i = -cos((2i+1) pi / 2n). */
+int or_grid_k(int n, double kmin, double kmax, double *k, double *x)
+{
+    if (n < 1 || !(kmin > 0.0) || !(kmax > kmin))
+        return 1;
+    double lo = log(kmin), L = log(kmax / kmin);
+    for (int i = 0; i < n; i++) {
+        double xi = -cos((2.0 * i + 1.0) * OR_PI / (2.0 * n));
+        if (x)
+            x[i] = xi;
+        k[i] = exp(lo + 0.5 * (xi + 1.0) * L);
+    }
+    return 0;
+}
+
+/* N_t(l) of Eqs. gg, gs, ss. */
+double or_prefactor(int type, int ell)
+{
+    double l = (double)ell;
+    double pi4 = (l + 2.0) * (l + 1.0) * l * (l - 1.0); /* (l+2)!/(l-2)! */
+    if (type == OR_GG)
+        return 2.0 / OR_PI;
+    if (type == OR_GS)
+        return 2.0 / OR_PI * sqrt(pi4);
+    if (type == OR_SS)
+        return 2.0 / OR_PI * pi4;
+    return 0.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Spherical Bessel functions j_0..j_lmax(x), x >= 0                          */
+/* ------------------------------------------------------------------------- */
+void or_sph_jn(int lmax, double x, double *j)
+{
+    if (lmax < 0)
+        return;
+    if (x == 0.0) {
+        j[0] = 1.0;
+        for (int l = 1; l <= lmax; l++)
+            j[l] = 0.0;
+        return;
+    }
+    double s = sin(x), c = cos(x);
+    if (x > (double)lmax && x >= 1.0) {
+        /* every requested order lies below the turning point: upward is stable */
+        j[0] = s / x;
+        if (lmax >= 1)
+            j[1] = (s / x - c) / x;
+        for (int l = 1; l < lmax; l++)
+            j[l + 1] = (2.0 * l + 1.0) / x * j[l] - j[l - 1];
+        return;
+    }
+    /* Miller: downward from well above max(lmax, x), with rescaling against
+     * overflow, then normalised by the closed form of j_0 or j_1. */
+    int L = lmax + 20 + (int)sqrt(40.0 * (lmax > 1 ? lmax : 1));
+    double inv_x = 1.0 / x;
+    double y_up = 0.0; /* y_{l+1} */
+    double y = 1.0;    /* y_l    */
+    int hi = L < lmax ? L : lmax;
+    for (int l = L; l >= 1; l--) {
+        if (l <= lmax)
+            j[l] = y;
+        double y_dn = (2.0 * l + 1.0) * inv_x * y - y_up;
+        y_up = y;
+        y = y_dn;
+        if (fabs(y) > 1e250) {
+            y *= 1e-250;
+            y_up *= 1e-250;
+            for (int m = l; m <= hi; m++)
+                j[m] *= 1e-250;
+            while (hi >= l && j[hi] == 0.0)
+                hi--;
+        }
+    }
+    /* y = y_0, y_up = y_1 */
+    double j0 = s / x;
+    double j1;
+    if (x < 0.5) {
+        double x2 = x * x; /* series: x/3 - x^3/30 + x^5/840 - x^7/45360 + x^9/3991680 */
+        j1 = x * (1.0 / 3.0 + x2 * (-1.0 / 30.0 + x2 * (1.0 / 840.0 + x2 * (-1.0 / 45360.0 + x2 / 3991680.0))));
+    } else {
+        j1 = (s / x - c) / x;
+    }
+    double scale = (fabs(j0) >= fabs(j1)) ? j0 / y : j1 / y_up;
+    j[0] = y * scale;
+    for (int l = 1; l <= lmax; l++)
+        j[l] = (l <= hi) ? j[l] * scale : 0.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Chebyshev interpolant (barycentric, first-kind points)                     */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int n;
+    double *xn;  /* ascending nodes x_i = -cos((2i+1)pi/2n) */
+    double *lam; /* barycentric weights (-1)^i sin((2i+1)pi/2n) */
+} cheb_t;
+
+static int cheb_make(cheb_t *cb, int n)
+{
+    cb->n = n;
+    cb->xn = (double *)malloc(sizeof(double) * n);
+    cb->lam = (double *)malloc(sizeof(double) * n);
+    if (!cb->xn || !cb->lam)
+        return 1;
+    for (int i = 0; i < n; i++) {
+        double th = (2.0 * i + 1.0) * OR_PI / (2.0 * n);
+        cb->xn[i] = -cos(th);
+        cb->lam[i] = ((i & 1) ? -1.0 : 1.0) * sin(th);
+    }
+    return 0;
+}
+
+static void cheb_free(cheb_t *cb)
+{
+    free(cb->xn);
+    free(cb->lam);
+}
+
+static double cheb_bary(const cheb_t *cb, const double *f, double x)
+{
+    double num = 0.0, den = 0.0;
+    for (int i = 0; i < cb->n; i++) {
+        double d = x - cb->xn[i];
+        if (d == 0.0)
+            return f[i];
+        double t = cb->lam[i] / d;
+        num += t * f[i];
+        den += t;
+    }
+    return num / den;
+}
+
+double or_cheb_interp(int n, const double *f, double x)
+{
+    cheb_t cb;
+    if (cheb_make(&cb, n))
+        return NAN;
+    double v = cheb_bary(&cb, f, x);
+    cheb_free(&cb);
+    return v;
+}
+
+/* sum_{n<d} a_n T_n(x) by Clenshaw's recurrence */
+static double cheb_clenshaw(int d, const double *a, double x)
+{
+    double b1 = 0.0, b2 = 0.0;
+    for (int n = d - 1; n >= 1; n--) {
+        double b0 = 2.0 * x * b1 - b2 + a[n];
+        b2 = b1;
+        b1 = b0;
+    }
+    return x * b1 - b2 + (d > 0 ? a[0] : 0.0);
+}
+
+/* ------------------------------------------------------------------------- */
+/* The k-integral w_t,l(chi1, chi2) = int dk f_t(k) P(k) j_l(k chi1) j_l(k chi2) */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int nl;
+    const int *ell; /* strictly increasing, >= 0 */
+    int types;      /* OR_GG | OR_GS | OR_SS */
+    double kmin, kmax;
+    int nc; /* Chebyshev node count of the interpolant (nodal mode) */
+} or_spec;
+
+typedef struct {
+    int mode;
+    const double *data; /* nodal: nc values per point; cheb: d coefficients per point */
+    long stride;        /* values between consecutive points (0 = shared) */
+    int d;              /* cheb mode: number of coefficients */
+    double p, m, amp;   /* gauss mode */
+} or_pspec;
+
+static inline void neumaier(double *sum, double *comp, double v)
+{
+    double t = *sum + v;
+    if (fabs(*sum) >= fabs(v))
+        *comp += (*sum - t) + v;
+    else
+        *comp += (v - t) + *sum;
+    *sum = t;
+}
+
+static void kint_point(const or_spec *sp, const cheb_t *cb, const or_pspec *ps, long pt, double chi1,
+                       double chi2, int M, double Phi, double *w /* [3][nl] */, double *jb1, double *jb2,
+                       double *pacc, double *comp)
+{
+    const int nl = sp->nl;
+    const int lmax = sp->ell[nl - 1];
+    const double lnkmin = log(sp->kmin), L = log(sp->kmax / sp->kmin);
+    const double omega = chi1 + chi2;
+    const double *pd = ps->data ? ps->data + (ps->stride ? pt * ps->stride : 0) : NULL;
+    for (int q = 0; q < 3 * nl; q++) {
+        w[q] = 0.0;
+        comp[q] = 0.0;
+    }
+    for (int i = 0; i < M; i++) {
+        double xa = -cos(OR_PI * i / M), xb = -cos(OR_PI * (i + 1) / M);
+        double ka = (i == 0) ? sp->kmin : exp(lnkmin + 0.5 * (xa + 1.0) * L);
+        double kb = (i == M - 1) ? sp->kmax : exp(lnkmin + 0.5 * (xb + 1.0) * L);
+        int ns = (int)ceil(omega * (kb - ka) / Phi);
+        if (ns < 1)
+            ns = 1;
+        double h = (kb - ka) / ns;
+        for (int u = 0; u < ns; u++) {
+            double mid = ka + (u + 0.5) * h, half = 0.5 * h;
+            for (int q = 0; q < 3 * nl; q++)
+                pacc[q] = 0.0;
+            for (int g = 0; g < 16; g++) {
+                double k = mid + half * GLX[g];
+                double wq = half * GLW[g];
+                double x = 2.0 * (log(k) - lnkmin) / L - 1.0;
+                double P;
+                if (ps->mode == OR_P_NODAL)
+                    P = cheb_bary(cb, pd, x);
+                else if (ps->mode == OR_P_CHEB)
+                    P = cheb_clenshaw(ps->d, pd, x);
+                else
+                    P = ps->amp * pow(k, ps->m) * exp(-(ps->p * k) * (ps->p * k));
+                or_sph_jn(lmax, k * chi1, jb1);
+                or_sph_jn(lmax, k * chi2, jb2);
+                double base = wq * P;
+                if (sp->types & OR_GG) {
+                    double cf = base * k * k;
+                    double *a = pacc;
+                    for (int il = 0; il < nl; il++)
+                        a[il] += cf * jb1[sp->ell[il]] * jb2[sp->ell[il]];
+                }
+                if (sp->types & OR_GS) {
+                    double cf = base;
+                    double *a = pacc + nl;
+                    for (int il = 0; il < nl; il++)
+                        a[il] += cf * jb1[sp->ell[il]] * jb2[sp->ell[il]];
+                }
+                if (sp->types & OR_SS) {
+                    double cf = base / (k * k);
+                    double *a = pacc + 2 * nl;
+                    for (int il = 0; il < nl; il++)
+                        a[il] += cf * jb1[sp->ell[il]] * jb2[sp->ell[il]];
+                }
+            }
+            for (int q = 0; q < 3 * nl; q++)
+                neumaier(&w[q], &comp[q], pacc[q]);
+        }
+    }
+    for (int q = 0; q < 3 * nl; q++)
+        w[q] += comp[q];
+}
+
+static int spec_ok(const or_spec *sp)
+{
+    if (sp->nl < 1 || !sp->ell || sp->ell[0] < 0)
+        return 0;
+    for (int i = 1; i < sp->nl; i++)
+        if (sp->ell[i] <= sp->ell[i - 1])
+            return 0;
+    if (!(sp->kmin > 0.0) || !(sp->kmax > sp->kmin))
+        return 0;
+    return 1;
+}
+
+/* w[t][il][m] for npts points (chi1_m, chi2_m).  P per point per `ps`.
+ * M coarse panels uniform in theta (x = -cos theta), each split into
+ * ceil((chi1+chi2) dk / Phi) equal sub-panels in k. */
+int or_w_points(int nl, const int *ell, int types, double kmin, double kmax, int nc, long npts,
+                const double *chi1, const double *chi2, int pmode, const double *pdata, long pstride,
+                int pd, double pp, double pm, double pamp, int M, double Phi, double *w, int nthreads)
+{
+    or_spec sp = {nl, ell, types, kmin, kmax, nc};
+    or_pspec ps = {pmode, pdata, pstride, pd, pp, pm, pamp};
+    if (!spec_ok(&sp) || npts < 0 || M < 1 || !(Phi > 0.0))
+        return 1;
+    if (pmode == OR_P_NODAL && (nc < 1 || !pdata))
+        return 1;
+    if (pmode == OR_P_CHEB && (pd < 1 || !pdata))
+        return 1;
+    cheb_t cb = {0, NULL, NULL};
+    if (pmode == OR_P_NODAL && cheb_make(&cb, nc))
+        return 2;
+    int lmax = ell[nl - 1];
+    int err = 0;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        double *jb1 = (double *)malloc(sizeof(double) * (lmax + 1));
+        double *jb2 = (double *)malloc(sizeof(double) * (lmax + 1));
+        double *acc = (double *)malloc(sizeof(double) * 3 * nl);
+        double *pacc = (double *)malloc(sizeof(double) * 3 * nl);
+        double *comp = (double *)malloc(sizeof(double) * 3 * nl);
+        if (!jb1 || !jb2 || !acc || !pacc || !comp) {
+#pragma omp atomic write
+            err = 2;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (long m = 0; m < npts; m++) {
+                kint_point(&sp, &cb, &ps, m, chi1[m], chi2[m], M, Phi, acc, jb1, jb2, pacc, comp);
+                for (int t = 0; t < 3; t++)
+                    for (int il = 0; il < nl; il++)
+                        w[((long)t * nl + il) * npts + m] = acc[t * nl + il];
+            }
+        }
+        free(jb1);
+        free(jb2);
+        free(acc);
+        free(pacc);
+        free(comp);
+    }
+    if (pmode == OR_P_NODAL)
+        cheb_free(&cb);
+    return err;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Outer sums                                                                 */
+/* ------------------------------------------------------------------------- */
+static int npairs_of(int ng, int ns, int types)
+{
+    int n = 0;
+    if (types & OR_GG)
+        n += ng * (ng + 1) / 2;
+    if (types & OR_GS)
+        n += ng * ns;
+    if (types & OR_SS)
+        n += ns * (ns + 1) / 2;
+    return n;
+}
+
+int or_npairs(int ng, int ns, int types) { return npairs_of(ng, ns, types); }
+
+/* pair p -> (type, i, j) with global bin indices (clustering bins first) */
+static void pair_of(int p, int ng, int ns, int types, int *t, int *bi, int *bj)
+{
+    if (types & OR_GG) {
+        for (int i = 0; i < ng; i++)
+            for (int j = i; j < ng; j++)
+                if (p-- == 0) {
+                    *t = OR_GG;
+                    *bi = i;
+                    *bj = j;
+                    return;
+                }
+    }
+    if (types & OR_GS) {
+        for (int i = 0; i < ng; i++)
+            for (int j = 0; j < ns; j++)
+                if (p-- == 0) {
+                    *t = OR_GS;
+                    *bi = i;
+                    *bj = ng + j;
+                    return;
+                }
+    }
+    for (int i = 0; i < ns; i++)
+        for (int j = i; j < ns; j++)
+            if (p-- == 0) {
+                *t = OR_SS;
+                *bi = ng + i;
+                *bj = ng + j;
+                return;
+            }
+}
+
+void or_pair(int p, int ng, int ns, int types, int *t, int *bi, int *bj) { pair_of(p, ng, ns, types, t, bi, bj); }
+
+static int tidx(int t) { return t == OR_GG ? 0 : (t == OR_GS ? 1 : 2); }
+
+/* R-form sum (Eq. final_cls) over the (chi_a, R_b) grid. */
+int or_sum_rform(int na, int nb, const double *chi, const double *wchi, const double *wR, int ng, int ns,
+                 const double *Kchi, const double *Kchi2, int nl, const int *ell, int types, const double *w,
+                 double *C)
+{
+    int np = npairs_of(ng, ns, types);
+    long npts = (long)na * nb;
+    for (int p = 0; p < np; p++) {
+        int t, bi, bj;
+        pair_of(p, ng, ns, types, &t, &bi, &bj);
+        const double *wt = w + (long)tidx(t) * nl * npts;
+        for (int il = 0; il < nl; il++) {
+            double s = 0.0, cp = 0.0;
+            for (int a = 0; a < na; a++) {
+                double sa = 0.0, ca = 0.0;
+                for (int b = 0; b < nb; b++) {
+                    long m = (long)a * nb + b;
+                    double kk = Kchi[(long)bi * na + a] * Kchi2[(long)bj * npts + m] +
+                                Kchi[(long)bj * na + a] * Kchi2[(long)bi * npts + m];
+                    neumaier(&sa, &ca, wR[b] * kk * wt[(long)il * npts + m]);
+                }
+                neumaier(&s, &cp, wchi[a] * chi[a] * (sa + ca));
+            }
+            C[(long)p * nl + il] = or_prefactor(t, ell[il]) * (s + cp);
+        }
+    }
+    return 0;
+}
+
+/* Full-square (chi1-chi2) sum over arbitrary points with weights W_m:
+ *   C_ij = N_t sum_m W_m K_i(chi1_m) K_j(chi2_m) w_t(chi1_m, chi2_m)   (Eq. cls-general) */
+int or_sum_points(long npts, const double *W, int ng, int ns, const double *K1, const double *K2, int nl,
+                  const int *ell, int types, const double *w, double *C)
+{
+    int np = npairs_of(ng, ns, types);
+    for (int p = 0; p < np; p++) {
+        int t, bi, bj;
+        pair_of(p, ng, ns, types, &t, &bi, &bj);
+        const double *wt = w + (long)tidx(t) * nl * npts;
+        for (int il = 0; il < nl; il++) {
+            double s = 0.0, cp = 0.0;
+            for (long m = 0; m < npts; m++)
+                neumaier(&s, &cp, W[m] * K1[(long)bi * npts + m] * K2[(long)bj * npts + m] * wt[(long)il * npts + m]);
+            C[(long)p * nl + il] = or_prefactor(t, ell[il]) * (s + cp);
+        }
+    }
+    return 0;
+}
+
+/* First-order Limber (Sec. "The Limber approximation"), written for the
+ * calligraphic kernels: int dk f_t P j_l(k chi1) j_l(k chi2) ->
+ * [f_t P / k^2]_{k=(l+1/2)/chi1} (pi / 2 chi1^2) delta(chi1 - chi2), so
+ *   C = N_t (pi/2) sum_a wchi_a K_i K_j f_t(k) P(k) / (k^2 chi_a^2),  k = (l+1/2)/chi_a.
+ * P is chi-independent here: nodal values pnodal[nc] (Phat, zero outside [kmin,kmax]). */
+int or_limber(int na, const double *chi, const double *wchi, int ng, int ns, const double *K, int nl,
+              const int *ell, int types, double kmin, double kmax, int nc, const double *pnodal, double *C)
+{
+    cheb_t cb;
+    if (cheb_make(&cb, nc))
+        return 2;
+    int np = npairs_of(ng, ns, types);
+    double lnkmin = log(kmin), L = log(kmax / kmin);
+    for (int p = 0; p < np; p++) {
+        int t, bi, bj;
+        pair_of(p, ng, ns, types, &t, &bi, &bj);
+        for (int il = 0; il < nl; il++) {
+            double s = 0.0, cp = 0.0;
+            for (int a = 0; a < na; a++) {
+                double k = (ell[il] + 0.5) / chi[a];
+                if (k < kmin || k > kmax)
+                    continue;
+                double P = cheb_bary(&cb, pnodal, 2.0 * (log(k) - lnkmin) / L - 1.0);
+                double f = (t == OR_GG) ? k * k : ((t == OR_GS) ? 1.0 : 1.0 / (k * k));
+                neumaier(&s, &cp, wchi[a] * K[(long)bi * na + a] * K[(long)bj * na + a] * f * P / (k * k * chi[a] * chi[a]));
+            }
+            C[(long)p * nl + il] = or_prefactor(t, ell[il]) * 0.5 * OR_PI * (s + cp);
+        }
+    }
+    cheb_free(&cb);
+    return 0;
+}
+
+/* Relative change between two C arrays with the denominator
+ * max(|C|, 1e-3 sqrt(|C_ii C_jj|)) (auto spectra of the same multipole). */
+static double rel_change(int ng, int ns, int types, int nl, const double *Cn, const double *Co)
+{
+    int np = npairs_of(ng, ns, types);
+    double worst = 0.0;
+    for (int p = 0; p < np; p++) {
+        int t, bi, bj;
+        pair_of(p, ng, ns, types, &t, &bi, &bj);
+        int pi_ = -1, pj_ = -1;
+        for (int q = 0; q < np; q++) {
+            int tq, qi, qj;
+            pair_of(q, ng, ns, types, &tq, &qi, &qj);
+            if (qi == qj && qi == bi)
+                pi_ = q;
+            if (qi == qj && qi == bj)
+                pj_ = q;
+        }
+        for (int il = 0; il < nl; il++) {
+            double c = Cn[(long)p * nl + il];
+            double den = fabs(c);
+            if (pi_ >= 0 && pj_ >= 0) {
+                double f = 1e-3 * sqrt(fabs(Cn[(long)pi_ * nl + il] * Cn[(long)pj_ * nl + il]));
+                if (f > den)
+                    den = f;
+            }
+            double d = fabs(c - Co[(long)p * nl + il]);
+            if (den > 0.0 && d / den > worst)
+                worst = d / den;
+        }
+    }
+    return worst;
+}
+
+/* The full discrete target on the (chi, R) grid, with the k-panels refined by
+ * doubling (M -> 2M, Phi -> Phi/2) until the relative change of C is below tol
+ * (or maxlev levels).  P nodal values per (a,b): P[(a*nb+b)*nc + j], ascending k.
+ * w_out (nullable) receives the last level's w[t][il][a*nb+b]. */
+int or_cl_grid(int nl, const int *ell, int types, double kmin, double kmax, int nc, int na, int nb,
+               const double *chi, const double *wchi, const double *R, const double *wR, const double *P, int ng,
+               int ns, const double *Kchi, const double *Kchi2, int M0, double Phi0, double tol, int maxlev,
+               double *C, double *w_out, double *err, int *levels, int nthreads)
+{
+    long npts = (long)na * nb;
+    int np = npairs_of(ng, ns, types);
+    double *c1 = (double *)malloc(sizeof(double) * npts);
+    double *c2 = (double *)malloc(sizeof(double) * npts);
+    double *w = (double *)malloc(sizeof(double) * 3 * nl * npts);
+    double *Cold = (double *)malloc(sizeof(double) * (np > 0 ? np : 1) * nl);
+    if (!c1 || !c2 || !w || !Cold) {
+        free(c1);
+        free(c2);
+        free(w);
+        free(Cold);
+        return 2;
+    }
+    for (int a = 0; a < na; a++)
+        for (int b = 0; b < nb; b++) {
+            c1[(long)a * nb + b] = chi[a];
+            c2[(long)a * nb + b] = R[b] * chi[a];
+        }
+    int M = M0;
+    double Phi = Phi0;
+    int rc = 0, lev;
+    double change = INFINITY;
+    for (lev = 0; lev < maxlev; lev++) {
+        memset(w, 0, sizeof(double) * 3 * nl * npts);
+        rc = or_w_points(nl, ell, types, kmin, kmax, nc, npts, c1, c2, OR_P_NODAL, P, nc, 0, 0, 0, 0, M, Phi, w,
+                         nthreads);
+        if (rc)
+            break;
+        or_sum_rform(na, nb, chi, wchi, wR, ng, ns, Kchi, Kchi2, nl, ell, types, w, C);
+        if (lev > 0) {
+            change = rel_change(ng, ns, types, nl, C, Cold);
+            if (change < tol) {
+                lev++;
+                break;
+            }
+        }
+        memcpy(Cold, C, sizeof(double) * np * nl);
+        M *= 2;
+        Phi *= 0.5;
+    }
+    if (w_out && !rc)
+        memcpy(w_out, w, sizeof(double) * 3 * nl * npts);
+    if (err)
+        *err = change;
+    if (levels)
+        *levels = lev;
+    free(c1);
+    free(c2);
+    free(w);
+    free(Cold);
+    return rc;
+}
+
+int or_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
