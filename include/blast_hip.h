@@ -1,0 +1,171 @@
+/*
+ * blast_hip.h -- C ABI of the MI355X (gfx950) beyond-Limber C_ell library.
+ *
+ * The library evaluates, for every tomographic bin pair (i, j) and multipole l,
+ *
+ *   C^{AB}_ij(l) = N_AB(l) int dchi int_0^1 dR chi
+ *                  [K_i^A(chi) K_j^B(R chi) + K_j^B(chi) K_i^A(R chi)] w^{AB}_l(chi, R chi)
+ *
+ * (Eq. final_cls of Chiarenza et al., arXiv:2410.03632, with the prefactors
+ * N_gg = 2/pi, N_gs = (2/pi) sqrt((l+2)!/(l-2)!), N_ss = (2/pi) (l+2)!/(l-2)! of
+ * Eqs. gg, gs, ss), where the projected matter density is the contraction
+ *
+ *   w^{AB}_l(chi1, chi2) = sum_n c_n(chi1, chi2) Ttilde^{AB}_{n;l}(chi1, chi2)      (Eq. pmd)
+ *   Ttilde^{AB}_{n;l}    = int_{kmin}^{kmax} dk f^{AB}(k) T_n(x(k)) j_l(k chi1) j_l(k chi2)
+ *                                                                                     (Eq. t_tilde)
+ *
+ * with f_gg = k^2, f_gs = 1, f_ss = 1/k^2, T_n the Chebyshev polynomials in
+ * x(k) = 2 ln(k/kmin)/ln(kmax/kmin) - 1, and c_n the coefficients of the
+ * polynomial that interpolates P at the first-kind Chebyshev points
+ * (Eqs. chebpoints, a2, dft).  The outer integrals are quadrature sums over the
+ * caller's chi nodes and R nodes (Sec. "The implementation").
+ *
+ * Conventions
+ *  - Every entry point returns a blast_status and never throws or aborts.  On
+ *    failure blast_last_error() returns a thread-local message.
+ *  - "host" pointers are read during the call only.  "device" pointers are HIP
+ *    device memory owned by the caller; the library never frees them.  Work is
+ *    enqueued on the caller's stream (hipStream_t passed as void*, NULL = the
+ *    null stream) and the call returns before it completes.
+ *  - Multipoles are integers.  Types: bit 1 = gg (clustering x clustering),
+ *    bit 2 = gs (clustering x shear), bit 4 = ss (shear x shear).
+ *  - Bins: n_g clustering bins first, then n_s shear bins.  Pair order of every
+ *    output: gg (i <= j, row-major), then gs (i over clustering, j over shear),
+ *    then ss (i <= j).
+ *  - Kernels are the calligraphic K of Eq. final_cls: K = W for clustering and
+ *    K = W / chi^2 for lensing.
+ */
+#ifndef BLAST_HIP_H
+#define BLAST_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BLAST_OK = 0,
+    BLAST_E_INVALID = 1,     /* bad argument, shape or grid                      */
+    BLAST_E_OOM = 2,         /* device or host allocation failed / over budget   */
+    BLAST_E_HIP = 3,         /* a HIP runtime call failed                        */
+    BLAST_E_UNSUPPORTED = 4, /* valid request this build does not implement      */
+    BLAST_E_BUSY = 5,        /* server queue full                                */
+    BLAST_E_CANCELLED = 6    /* request cancelled                                */
+} blast_status;
+
+/* Arithmetic of the contraction (Eq. pmd).  FP64: FP64 basis, FP64 MFMA.
+ * FP32: FP32 basis and coefficients, FP32 MFMA.  BF16: BF16 basis and
+ * coefficients (per-row power-of-two scales), FP32 accumulate.  BF16X3: basis and
+ * coefficients split into BF16 hi + lo parts, hi*hi + hi*lo + lo*hi, FP32
+ * accumulate.  The basis precompute is always FP64; the quadrature always
+ * accumulates in FP64. */
+typedef enum { BLAST_FP64 = 0, BLAST_FP32 = 1, BLAST_BF16 = 2, BLAST_BF16X3 = 3 } blast_precision;
+
+enum { BLAST_GG = 1, BLAST_GS = 2, BLAST_SS = 4 };
+
+const char *blast_last_error(void);
+const char *blast_version(void);
+
+/* ------------------------------------------------------------------------- */
+/* Grids (host only, no GPU).  Helpers that build the paper's default rules.  */
+/* ------------------------------------------------------------------------- */
+
+/* n evenly spaced chi nodes on [lo, hi] with composite Simpson weights
+ * (Sec. "The implementation": Simpson rule on evenly spaced chi).  For an even n
+ * the last three intervals use Simpson's 3/8 rule.  n >= 4.  Outputs: host [n]. */
+blast_status blast_grid_chi_simpson(int32_t n, double lo, double hi, double *chi, double *w);
+
+/* n first-kind Chebyshev points (Eq. chebpoints) mapped to [R_min, 1], ascending,
+ * with Fejer's first-rule weights (the Clenshaw-Curtis-type rule for those
+ * points; Sec. "The implementation").  0 <= R_min < 1.  Outputs: host [n]. */
+blast_status blast_grid_R_fejer(int32_t n, double R_min, double *R, double *w);
+
+/* The n first-kind Chebyshev points in ln k on [k_min, k_max] (Eqs. chebpoints,
+ * cheb_pk), ascending in k: the k at which the caller samples P.  Output: host [n]. */
+blast_status blast_grid_k_cheb(int32_t n, double k_min, double k_max, double *k);
+
+/* ------------------------------------------------------------------------- */
+/* Plan: grids + the resident, cosmology-independent basis (Eq. t_tilde)      */
+/* ------------------------------------------------------------------------- */
+
+typedef struct blast_plan blast_plan;
+
+typedef struct {
+    int32_t n_ell;
+    const int32_t *ell;   /* host [n_ell], strictly increasing, >= 2, <= 4096        */
+    int32_t n_chi;
+    const double *chi;    /* host [n_chi] chi nodes (> 0)                            */
+    const double *w_chi;  /* host [n_chi] outer chi weights                          */
+    int32_t n_R;
+    const double *R;      /* host [n_R] R = chi2/chi1 nodes in (0, 1]                */
+    const double *w_R;    /* host [n_R] R weights                                    */
+    double k_min, k_max;  /* Chebyshev range, 0 < k_min < k_max                      */
+    int32_t n_cheb;       /* Chebyshev nodes = coefficients, 2..128                  */
+    uint32_t types;       /* subset of BLAST_GG | BLAST_GS | BLAST_SS                */
+    uint32_t precisions;  /* bitmask of (1 << blast_precision) kept resident; FP64
+                             is always built                                        */
+    int32_t kq_panels;    /* k-quadrature: coarse panels uniform in arccos(x);
+                             0 = n_cheb                                              */
+    double kq_phase;      /* k-quadrature: max Bessel phase (chi1+chi2) dk per
+                             16-point Gauss-Legendre sub-panel; 0 = 8                */
+} blast_plan_desc;
+
+/* Builds the grids and computes the basis on `device` in FP64 (synchronously),
+ * then derives the other requested precisions.  The plan owns all of its device
+ * memory.  Errors: INVALID (grids, ell list, sizes), OOM, HIP. */
+blast_status blast_plan_create(const blast_plan_desc *desc, int32_t device, blast_plan **out);
+blast_status blast_plan_destroy(blast_plan *plan);
+
+/* Sizes: number of basis rows (types x ell), padded Chebyshev length, bytes of
+ * resident basis per precision (host [4]), k-quadrature node count, basis build
+ * time in milliseconds.  Any output pointer may be NULL. */
+blast_status blast_plan_info(const blast_plan *plan, int32_t *rows, int32_t *n_cheb_pad, size_t *basis_bytes,
+                             int64_t *kq_nodes, double *build_ms);
+
+/* Where to sample P: the k nodes (host [n_cheb], ascending). */
+blast_status blast_plan_k_nodes(const blast_plan *plan, double *k);
+
+/* Copies the FP64 basis rows of one (chi_a, R_b) point to host:
+ * out[t_slot * n_ell + l][n] for n < n_cheb (t_slot over the plan's types in the
+ * order gg, gs, ss).  For tests and inspection. */
+blast_status blast_plan_basis_point(const blast_plan *plan, int32_t a, int32_t b, double *out);
+
+/* ------------------------------------------------------------------------- */
+/* Forward: P grid + kernels -> C_ell for every bin pair                      */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t batch;        /* number of independent cosmologies, >= 1              */
+    int32_t precision;    /* blast_precision; must be resident in the plan        */
+    int32_t p_dtype;      /* 0: P is FP64, 1: P is FP32                            */
+    const void *P;        /* device [batch][n_chi][n_R][n_cheb]: P(k_j, chi_a, R_b chi_a),
+                             k ascending (blast_plan_k_nodes)                        */
+    int32_t n_g, n_s;     /* clustering / shear bins, n_g + n_s <= 32              */
+    const double *K_chi;  /* device [batch][n_g+n_s][n_chi]: K at chi_a             */
+    const double *K_chi2; /* device [batch][n_g+n_s][n_chi][n_R]: K at R_b chi_a    */
+    uint32_t types;       /* subset of the plan's types                            */
+    int32_t n_ell_out;    /* 0 = every plan multipole, else a subset:               */
+    const int32_t *ell_idx; /* host [n_ell_out] increasing indices into the plan's ell */
+    double *C;            /* device [batch][n_pairs][n_ell_out (or n_ell)]          */
+    void *w_save;         /* device, nullable: [batch][n_chi*n_R][rows_pad] w of Eq. pmd
+                             (FP64 for FP64, else FP32), rows as in blast_plan_basis_point */
+    void *workspace;      /* device, nullable: caller scratch (blast_cl_workspace_bytes);
+                             NULL = plan-owned scratch (then calls on one plan must not
+                             overlap in time)                                        */
+    size_t workspace_bytes;
+} blast_cl_args;
+
+blast_status blast_cl_workspace_bytes(const blast_plan *plan, int32_t batch, int32_t precision, int32_t n_bins,
+                                      size_t *bytes);
+
+/* Enqueues projection (Eq. dft) -> contraction (Eq. pmd) -> quadrature
+ * (Eq. final_cls) on `stream`.  Errors: INVALID (shapes, types, precision not
+ * resident), OOM (plan scratch), HIP. */
+blast_status blast_cl_forward(blast_plan *plan, const blast_cl_args *args, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BLAST_HIP_H */

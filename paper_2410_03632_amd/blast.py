@@ -1,0 +1,269 @@
+"""Python binding of ``libblast_hip.so`` (ctypes; argument marshalling only).
+
+Every step of the C_ell evaluation runs in the HIP library; this module only
+converts torch device tensors and numpy host arrays into the pointers and sizes
+of the C ABI declared in ``include/blast_hip.h``.  If the library is missing the
+import of any entry point raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libblast_hip.so")
+
+OK, E_INVALID, E_OOM, E_HIP, E_UNSUPPORTED, E_BUSY, E_CANCELLED = range(7)
+FP64, FP32, BF16, BF16X3 = range(4)
+GG, GS, SS = 1, 2, 4
+PRECISION = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "bf16x3": BF16X3}
+TYPE_BITS = {"gg": GG, "gs": GS, "ss": SS}
+
+
+class BlastError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("blast status %d: %s" % (status, msg))
+        self.status = status
+
+
+class PlanDesc(C.Structure):
+    _fields_ = [
+        ("n_ell", C.c_int32), ("ell", C.POINTER(C.c_int32)),
+        ("n_chi", C.c_int32), ("chi", C.POINTER(C.c_double)), ("w_chi", C.POINTER(C.c_double)),
+        ("n_R", C.c_int32), ("R", C.POINTER(C.c_double)), ("w_R", C.POINTER(C.c_double)),
+        ("k_min", C.c_double), ("k_max", C.c_double),
+        ("n_cheb", C.c_int32), ("types", C.c_uint32), ("precisions", C.c_uint32),
+        ("kq_panels", C.c_int32), ("kq_phase", C.c_double),
+    ]
+
+
+class ClArgs(C.Structure):
+    _fields_ = [
+        ("batch", C.c_int32), ("precision", C.c_int32), ("p_dtype", C.c_int32),
+        ("P", C.c_void_p), ("n_g", C.c_int32), ("n_s", C.c_int32),
+        ("K_chi", C.c_void_p), ("K_chi2", C.c_void_p), ("types", C.c_uint32),
+        ("n_ell_out", C.c_int32), ("ell_idx", C.POINTER(C.c_int32)),
+        ("C", C.c_void_p), ("w_save", C.c_void_p),
+        ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+    ]
+
+
+EXPORTS = [
+    "blast_last_error", "blast_version", "blast_grid_chi_simpson", "blast_grid_R_fejer", "blast_grid_k_cheb",
+    "blast_plan_create", "blast_plan_destroy", "blast_plan_info", "blast_plan_k_nodes", "blast_plan_basis_point",
+    "blast_cl_workspace_bytes", "blast_cl_forward",
+]
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libblast_hip.so is not built; run `python -m paper_2410_03632_amd.build_lib`")
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        L.blast_last_error.restype = C.c_char_p
+        L.blast_version.restype = C.c_char_p
+        L.blast_grid_chi_simpson.argtypes = [C.c_int32, C.c_double, C.c_double, dp, dp]
+        L.blast_grid_R_fejer.argtypes = [C.c_int32, C.c_double, dp, dp]
+        L.blast_grid_k_cheb.argtypes = [C.c_int32, C.c_double, C.c_double, dp]
+        L.blast_plan_create.argtypes = [C.POINTER(PlanDesc), C.c_int32, C.POINTER(C.c_void_p)]
+        L.blast_plan_destroy.argtypes = [C.c_void_p]
+        L.blast_plan_info.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_size_t), C.POINTER(C.c_int64), dp]
+        L.blast_plan_k_nodes.argtypes = [C.c_void_p, dp]
+        L.blast_plan_basis_point.argtypes = [C.c_void_p, C.c_int32, C.c_int32, dp]
+        L.blast_cl_workspace_bytes.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                               C.POINTER(C.c_size_t)]
+        L.blast_cl_forward.argtypes = [C.c_void_p, C.POINTER(ClArgs), C.c_void_p]
+        for name in EXPORTS:
+            if name not in ("blast_last_error", "blast_version"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != OK:
+        raise BlastError(st, lib().blast_last_error().decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def version() -> str:
+    return lib().blast_version().decode()
+
+
+# ------------------------------------------------------------------------------- grids
+
+def grid_chi_simpson(n, lo, hi):
+    chi, w = np.empty(n), np.empty(n)
+    _check(lib().blast_grid_chi_simpson(n, lo, hi, _dptr(chi), _dptr(w)))
+    return chi, w
+
+
+def grid_R_fejer(n, R_min):
+    R, w = np.empty(n), np.empty(n)
+    _check(lib().blast_grid_R_fejer(n, R_min, _dptr(R), _dptr(w)))
+    return R, w
+
+
+def grid_k_cheb(n, k_min, k_max):
+    k = np.empty(n)
+    _check(lib().blast_grid_k_cheb(n, k_min, k_max, _dptr(k)))
+    return k
+
+
+def types_mask(types) -> int:
+    if isinstance(types, int):
+        return types
+    m = 0
+    for t in types:
+        m |= TYPE_BITS[t]
+    return m
+
+
+def n_pairs(n_g, n_s, types=7) -> int:
+    t = types_mask(types)
+    return ((n_g * (n_g + 1) // 2) if t & GG else 0) + ((n_g * n_s) if t & GS else 0) + \
+        ((n_s * (n_s + 1) // 2) if t & SS else 0)
+
+
+# ------------------------------------------------------------------------------- plan
+
+class Plan:
+    """Grids plus the resident basis of Eq. t_tilde on one GPU."""
+
+    def __init__(self, ell, chi, w_chi, R, w_R, k_min, k_max, n_cheb, *, types=7,
+                 precisions=("fp64",), kq_panels=0, kq_phase=0.0, device=0):
+        self.ell = np.ascontiguousarray(ell, dtype=np.int32)
+        self.chi = np.ascontiguousarray(chi, dtype=np.float64)
+        self.w_chi = np.ascontiguousarray(w_chi, dtype=np.float64)
+        self.R = np.ascontiguousarray(R, dtype=np.float64)
+        self.w_R = np.ascontiguousarray(w_R, dtype=np.float64)
+        self.k_min, self.k_max, self.n_cheb = float(k_min), float(k_max), int(n_cheb)
+        self.types = types_mask(types)
+        self.device = int(device)
+        pmask = 0
+        for p in precisions:
+            pmask |= 1 << (PRECISION[p] if isinstance(p, str) else int(p))
+        d = PlanDesc(len(self.ell), self.ell.ctypes.data_as(C.POINTER(C.c_int32)),
+                     len(self.chi), _dptr(self.chi), _dptr(self.w_chi),
+                     len(self.R), _dptr(self.R), _dptr(self.w_R),
+                     self.k_min, self.k_max, self.n_cheb, self.types, pmask, int(kq_panels), float(kq_phase))
+        h = C.c_void_p()
+        _check(lib().blast_plan_create(C.byref(d), self.device, C.byref(h)))
+        self._h = h
+        rows, ncp = C.c_int32(), C.c_int32()
+        bb = (C.c_size_t * 4)()
+        kq = C.c_int64()
+        ms = C.c_double()
+        _check(lib().blast_plan_info(h, C.byref(rows), C.byref(ncp), bb, C.byref(kq), C.byref(ms)))
+        self.rows, self.nc_pad = rows.value, ncp.value
+        self.rows_pad = (self.rows + 15) // 16 * 16
+        self.basis_bytes = list(bb)
+        self.kq_nodes, self.build_ms = kq.value, ms.value
+        self.k_nodes = np.empty(self.n_cheb)
+        _check(lib().blast_plan_k_nodes(h, _dptr(self.k_nodes)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n_ell(self):
+        return len(self.ell)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().blast_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def basis_point(self, a, b):
+        out = np.empty((self.rows, self.n_cheb))
+        _check(lib().blast_plan_basis_point(self._h, a, b, _dptr(out)))
+        return out
+
+    def eval_points(self):
+        """(chi_a, R_b chi_a): where to evaluate the kernels and P."""
+        return self.chi, self.chi[:, None] * self.R[None, :]
+
+    def workspace_bytes(self, batch, precision, n_bins):
+        n = C.c_size_t()
+        _check(lib().blast_cl_workspace_bytes(self._h, batch, PRECISION.get(precision, precision), n_bins,
+                                              C.byref(n)))
+        return n.value
+
+    def forward(self, P, K_chi, K_chi2, n_g, n_s, *, precision="fp64", types=None, ell_idx=None,
+                out=None, w_save=None, workspace=None, stream=None):
+        """C[batch][pair][ell] for device tensors P [B, n_chi, n_R, n_cheb] (float64/float32),
+        K_chi [B, bins, n_chi] and K_chi2 [B, bins, n_chi, n_R] (float64)."""
+        import torch
+        prec = PRECISION.get(precision, precision)
+        if P.dim() == 3:
+            P = P.unsqueeze(0)
+        if K_chi.dim() == 2:
+            K_chi = K_chi.unsqueeze(0)
+        if K_chi2.dim() == 3:
+            K_chi2 = K_chi2.unsqueeze(0)
+        B = P.shape[0]
+        for t, nm in ((P, "P"), (K_chi, "K_chi"), (K_chi2, "K_chi2")):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("%s must be a contiguous device tensor" % nm)
+        if P.dtype not in (torch.float64, torch.float32):
+            raise ValueError("P must be float64 or float32")
+        if K_chi.dtype != torch.float64 or K_chi2.dtype != torch.float64:
+            raise ValueError("kernels must be float64")
+        nb = n_g + n_s
+        if tuple(P.shape) != (B, len(self.chi), len(self.R), self.n_cheb):
+            raise ValueError("P shape %s, expected %s" % (tuple(P.shape), (B, len(self.chi), len(self.R), self.n_cheb)))
+        if tuple(K_chi.shape) != (B, nb, len(self.chi)) or tuple(K_chi2.shape) != (B, nb, len(self.chi), len(self.R)):
+            raise ValueError("kernel shapes do not match (batch, bins, chi[, R])")
+        tmask = self.types if types is None else types_mask(types)
+        npair = n_pairs(n_g, n_s, tmask)
+        if ell_idx is None:
+            n_out, idx_arr = 0, None
+            n_l = self.n_ell
+        else:
+            idx_arr = np.ascontiguousarray(ell_idx, dtype=np.int32)
+            n_out = n_l = len(idx_arr)
+        if out is None:
+            out = torch.empty((B, npair, n_l), dtype=torch.float64, device=P.device)
+        elif tuple(out.shape) != (B, npair, n_l) or out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of shape %s" % ((B, npair, n_l),))
+        if w_save is not None:
+            wdt = torch.float64 if prec == FP64 else torch.float32
+            if w_save.dtype != wdt or w_save.numel() != B * len(self.chi) * len(self.R) * self.rows_pad:
+                raise ValueError("w_save must hold batch*n_chi*n_R*rows_pad values of %s" % wdt)
+        ws_ptr, ws_bytes = (None, 0)
+        if workspace is not None:
+            ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+        args = ClArgs(B, prec, 0 if P.dtype == torch.float64 else 1, P.data_ptr(), n_g, n_s,
+                      K_chi.data_ptr(), K_chi2.data_ptr(), tmask, n_out,
+                      idx_arr.ctypes.data_as(C.POINTER(C.c_int32)) if idx_arr is not None else None,
+                      out.data_ptr(), w_save.data_ptr() if w_save is not None else None, ws_ptr, ws_bytes)
+        if stream is None:
+            stream = torch.cuda.current_stream(P.device).cuda_stream
+        _check(lib().blast_cl_forward(self._h, C.byref(args), C.c_void_p(stream)))
+        return out
+
+
+def plan_for_config(cfg, precisions=("fp64",), device=0, **kw):
+    """Plan with the default grids of a workloads.Config (Simpson chi, Fejer R, Chebyshev k)."""
+    chi, wchi = grid_chi_simpson(cfg.n_chi, cfg.chi_min, cfg.chi_max)
+    R, wR = grid_R_fejer(cfg.n_R, cfg.R_min)
+    return Plan(cfg.ells(), chi, wchi, R, wR, cfg.k_min, cfg.k_max, cfg.n_cheb, precisions=precisions,
+                device=device, **kw)

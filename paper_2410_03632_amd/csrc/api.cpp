@@ -1,0 +1,333 @@
+// C ABI entry points: errors, grids, plan lifetime, forward dispatch.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace {
+thread_local char g_err[1024] = "";
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+const double kPi = 3.141592653589793238462643383279502884;
+}  // namespace
+
+namespace blast {
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+void clear_error() { g_err[0] = 0; }
+}  // namespace blast
+
+extern "C" const char *blast_last_error(void) { return g_err; }
+extern "C" const char *blast_version(void) { return "blast-hip 0.1 (gfx950)"; }
+
+// --------------------------------------------------------------------------------------------
+// grids
+// --------------------------------------------------------------------------------------------
+
+extern "C" blast_status blast_grid_chi_simpson(int32_t n, double lo, double hi, double *chi, double *w) {
+    if (n < 4 || !(hi > lo) || !chi || !w) {
+        blast::set_error("blast_grid_chi_simpson: need n >= 4 and hi > lo");
+        return BLAST_E_INVALID;
+    }
+    const double h = (hi - lo) / (n - 1);
+    for (int i = 0; i < n; ++i) {
+        chi[i] = lo + i * h;
+        w[i] = 0.0;
+    }
+    // panels of two intervals (1/3 rule) while more than three intervals remain odd
+    int intervals = n - 1;
+    int start = 0;
+    if (intervals % 2 == 1) {
+        // three-interval 3/8 panel at the end
+        const int s = n - 4;
+        const double c = 3.0 * h / 8.0;
+        w[s] += c;
+        w[s + 1] += 3.0 * c;
+        w[s + 2] += 3.0 * c;
+        w[s + 3] += c;
+        intervals -= 3;
+    }
+    for (int p = 0; p < intervals / 2; ++p) {
+        const int s = start + 2 * p;
+        w[s] += h / 3.0;
+        w[s + 1] += 4.0 * h / 3.0;
+        w[s + 2] += h / 3.0;
+    }
+    return BLAST_OK;
+}
+
+extern "C" blast_status blast_grid_R_fejer(int32_t n, double R_min, double *R, double *w) {
+    if (n < 1 || !(R_min >= 0.0 && R_min < 1.0) || !R || !w) {
+        blast::set_error("blast_grid_R_fejer: need n >= 1 and 0 <= R_min < 1");
+        return BLAST_E_INVALID;
+    }
+    const double half = 0.5 * (1.0 - R_min);
+    for (int i = 0; i < n; ++i) {
+        // ascending order: node i is the first-kind point with angle pi - (2i+1)pi/2n
+        const double th = kPi - (2.0 * i + 1.0) * kPi / (2.0 * n);
+        double acc = 1.0;
+        for (int m = 1; 2 * m <= n; ++m) acc -= 2.0 * std::cos(2.0 * m * th) / (4.0 * m * m - 1.0);
+        R[i] = R_min + half * (1.0 + std::cos(th));
+        w[i] = half * 2.0 / n * acc;
+    }
+    return BLAST_OK;
+}
+
+extern "C" blast_status blast_grid_k_cheb(int32_t n, double k_min, double k_max, double *k) {
+    if (n < 1 || !(k_min > 0.0) || !(k_max > k_min) || !k) {
+        blast::set_error("blast_grid_k_cheb: need n >= 1 and 0 < k_min < k_max");
+        return BLAST_E_INVALID;
+    }
+    const double l0 = std::log(k_min), span = std::log(k_max) - std::log(k_min);
+    for (int i = 0; i < n; ++i) {
+        const double x = std::cos(kPi - (2.0 * i + 1.0) * kPi / (2.0 * n));
+        k[i] = std::exp(l0 + 0.5 * (x + 1.0) * span);
+    }
+    return BLAST_OK;
+}
+
+// --------------------------------------------------------------------------------------------
+// plan
+// --------------------------------------------------------------------------------------------
+
+static double prefactor(int type_bit, int l) {
+    const double L = l;
+    const double r = (L + 2.0) * (L + 1.0) * L * (L - 1.0);  // (l+2)!/(l-2)!
+    if (type_bit == BLAST_GG) return 2.0 / kPi;
+    if (type_bit == BLAST_GS) return 2.0 / kPi * std::sqrt(r);
+    return 2.0 / kPi * r;
+}
+
+static void free_plan(blast_plan *p) {
+    if (!p) return;
+    auto f = [](void *q) {
+        if (q) (void)hipFree(q);
+    };
+    f(p->basis.f64);
+    f(p->basis.f32);
+    f(p->basis.hi);
+    f(p->basis.lo);
+    f(p->basis.scale);
+    f(p->d_dct64);
+    f(p->d_dct32);
+    f(p->d_chi);
+    f(p->d_wchi);
+    f(p->d_wR);
+    f(p->d_pref);
+    f(p->d_ell);
+    f(p->scratch);
+    delete p;
+}
+
+static blast_status validate_desc(const blast_plan_desc *d) {
+    if (!d) return blast::set_error("blast_plan_create: desc is NULL"), BLAST_E_INVALID;
+    if (d->n_ell < 1 || d->n_ell > blast::kMaxEll || !d->ell)
+        return blast::set_error("n_ell must be in [1, %d]", blast::kMaxEll), BLAST_E_INVALID;
+    for (int i = 0; i < d->n_ell; ++i) {
+        if (d->ell[i] < 2 || d->ell[i] > 4096)
+            return blast::set_error("ell[%d] = %d outside [2, 4096]", i, d->ell[i]), BLAST_E_INVALID;
+        if (i && d->ell[i] <= d->ell[i - 1])
+            return blast::set_error("ell must be strictly increasing (index %d)", i), BLAST_E_INVALID;
+    }
+    if (d->n_chi < 1 || !d->chi || !d->w_chi) return blast::set_error("bad chi grid"), BLAST_E_INVALID;
+    for (int i = 0; i < d->n_chi; ++i)
+        if (!(d->chi[i] > 0.0) || !std::isfinite(d->chi[i]) || !std::isfinite(d->w_chi[i]))
+            return blast::set_error("chi[%d] must be positive and finite", i), BLAST_E_INVALID;
+    if (d->n_R < 1 || !d->R || !d->w_R) return blast::set_error("bad R grid"), BLAST_E_INVALID;
+    for (int i = 0; i < d->n_R; ++i)
+        if (!(d->R[i] > 0.0 && d->R[i] <= 1.0) || !std::isfinite(d->w_R[i]))
+            return blast::set_error("R[%d] must lie in (0, 1]", i), BLAST_E_INVALID;
+    if (!(d->k_min > 0.0) || !(d->k_max > d->k_min) || !std::isfinite(d->k_max))
+        return blast::set_error("need 0 < k_min < k_max"), BLAST_E_INVALID;
+    if (d->n_cheb < 2 || d->n_cheb > blast::kMaxCheb)
+        return blast::set_error("n_cheb must be in [2, %d]", blast::kMaxCheb), BLAST_E_INVALID;
+    if (d->types == 0 || (d->types & ~7u)) return blast::set_error("types must be a non-empty subset of 7"), BLAST_E_INVALID;
+    if (d->precisions & ~15u) return blast::set_error("unknown precision bits"), BLAST_E_INVALID;
+    if (d->kq_panels < 0 || d->kq_panels > 4096) return blast::set_error("kq_panels out of range"), BLAST_E_INVALID;
+    if (d->kq_phase < 0 || !std::isfinite(d->kq_phase)) return blast::set_error("kq_phase must be >= 0"), BLAST_E_INVALID;
+    return BLAST_OK;
+}
+
+extern "C" blast_status blast_plan_create(const blast_plan_desc *d, int32_t device, blast_plan **out) {
+    blast::clear_error();
+    if (!out) return blast::set_error("out is NULL"), BLAST_E_INVALID;
+    *out = nullptr;
+    blast_status st = validate_desc(d);
+    if (st != BLAST_OK) return st;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return blast::set_error("device %d not available (%d devices)", device, ndev), BLAST_E_INVALID;
+
+    blast_plan *p = new (std::nothrow) blast_plan();
+    if (!p) return blast::set_error("host allocation failed"), BLAST_E_OOM;
+    p->device = device;
+    p->n_ell = d->n_ell;
+    p->ell.assign(d->ell, d->ell + d->n_ell);
+    p->lmax = p->ell.back();
+    p->types = d->types;
+    const int bits[3] = {BLAST_GG, BLAST_GS, BLAST_SS};
+    for (int t = 0; t < 3; ++t)
+        if (d->types & bits[t]) {
+            p->slot[t] = p->nt;
+            p->tslot_type[p->nt] = bits[t];
+            p->nt++;
+        }
+    p->rows = p->nt * p->n_ell;
+    p->rows_pad = blast::round_up(p->rows, 16);
+    p->n_chi = d->n_chi;
+    p->n_R = d->n_R;
+    p->NP = d->n_chi * d->n_R;
+    p->chi.assign(d->chi, d->chi + d->n_chi);
+    p->w_chi.assign(d->w_chi, d->w_chi + d->n_chi);
+    p->R.assign(d->R, d->R + d->n_R);
+    p->w_R.assign(d->w_R, d->w_R + d->n_R);
+    p->kmin = d->k_min;
+    p->kmax = d->k_max;
+    p->n_cheb = d->n_cheb;
+    p->nc_pad = blast::round_up(d->n_cheb, 32);
+    p->knodes.resize(d->n_cheb);
+    blast_grid_k_cheb(d->n_cheb, d->k_min, d->k_max, p->knodes.data());
+    p->kq_panels = d->kq_panels ? d->kq_panels : d->n_cheb;
+    p->kq_phase = d->kq_phase > 0 ? d->kq_phase : 8.0;
+    p->precisions = d->precisions | 1u;
+
+    DeviceGuard guard(device);
+    hipStream_t s = nullptr;
+    auto fail = [&](blast_status e) {
+        if (s) (void)hipStreamDestroy(s);
+        free_plan(p);
+        return e;
+    };
+    if (hipStreamCreate(&s) != hipSuccess) return blast::set_error("hipStreamCreate failed"), fail(BLAST_E_HIP);
+
+    // small device tables
+    {
+        const int N = p->n_cheb, ncp = p->nc_pad;
+        std::vector<double> dct((size_t)N * ncp, 0.0);
+        std::vector<float> dct32((size_t)N * ncp, 0.0f);
+        // c_n = sum_j D[n][j] P_j with j the ascending-k node index (node angle pi - (2j+1)pi/2N):
+        // D[n][j] = (2 - delta_n0)/N cos(n (pi - (2j+1)pi/2N))
+        for (int j = 0; j < N; ++j)
+            for (int n = 0; n < N; ++n) {
+                double v = (n == 0 ? 1.0 : 2.0) / N * std::cos(n * (kPi - (2.0 * j + 1.0) * kPi / (2.0 * N)));
+                dct[(size_t)j * ncp + n] = v;
+                dct32[(size_t)j * ncp + n] = (float)v;
+            }
+        std::vector<double> pref(p->rows);
+        for (int sl = 0; sl < p->nt; ++sl)
+            for (int l = 0; l < p->n_ell; ++l) pref[sl * p->n_ell + l] = prefactor(p->tslot_type[sl], p->ell[l]);
+        auto up = [&](void **dst, const void *src, size_t bytes) -> hipError_t {
+            hipError_t e = hipMalloc(dst, bytes);
+            if (e != hipSuccess) return e;
+            return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+        };
+        hipError_t e = hipSuccess;
+        if (e == hipSuccess) e = up((void **)&p->d_dct64, dct.data(), dct.size() * sizeof(double));
+        if (e == hipSuccess) e = up((void **)&p->d_dct32, dct32.data(), dct32.size() * sizeof(float));
+        if (e == hipSuccess) e = up((void **)&p->d_chi, p->chi.data(), p->n_chi * sizeof(double));
+        if (e == hipSuccess) e = up((void **)&p->d_wchi, p->w_chi.data(), p->n_chi * sizeof(double));
+        if (e == hipSuccess) e = up((void **)&p->d_wR, p->w_R.data(), p->n_R * sizeof(double));
+        if (e == hipSuccess) e = up((void **)&p->d_pref, pref.data(), pref.size() * sizeof(double));
+        if (e == hipSuccess) e = up((void **)&p->d_ell, p->ell.data(), p->n_ell * sizeof(int));
+        if (e != hipSuccess) {
+            blast::set_error("device tables: %s", hipGetErrorString(e));
+            return fail(e == hipErrorOutOfMemory ? BLAST_E_OOM : BLAST_E_HIP);
+        }
+    }
+
+    auto t0 = std::chrono::steady_clock::now();
+    st = blast::build_basis(p, s);
+    if (st == BLAST_OK) st = blast::derive_precisions(p, s);
+    if (st == BLAST_OK && hipStreamSynchronize(s) != hipSuccess) {
+        blast::set_error("basis build failed on the device");
+        st = BLAST_E_HIP;
+    }
+    if (st != BLAST_OK) return fail(st);
+    p->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    (void)hipStreamDestroy(s);
+    *out = p;
+    return BLAST_OK;
+}
+
+extern "C" blast_status blast_plan_destroy(blast_plan *plan) {
+    if (!plan) return BLAST_OK;
+    DeviceGuard guard(plan->device);
+    (void)hipDeviceSynchronize();
+    free_plan(plan);
+    return BLAST_OK;
+}
+
+extern "C" blast_status blast_plan_info(const blast_plan *p, int32_t *rows, int32_t *n_cheb_pad, size_t *basis_bytes,
+                                        int64_t *kq_nodes, double *build_ms) {
+    if (!p) return blast::set_error("plan is NULL"), BLAST_E_INVALID;
+    if (rows) *rows = p->rows;
+    if (n_cheb_pad) *n_cheb_pad = p->nc_pad;
+    if (basis_bytes) {
+        const size_t n = (size_t)p->NP * p->rows_pad * p->nc_pad;
+        basis_bytes[0] = p->basis.f64 ? n * 8 : 0;
+        basis_bytes[1] = p->basis.f32 ? n * 4 : 0;
+        basis_bytes[2] = p->basis.hi ? n * 2 + (size_t)p->NP * p->rows_pad * 4 : 0;
+        basis_bytes[3] = p->basis.lo ? n * 4 + (size_t)p->NP * p->rows_pad * 4 : 0;
+    }
+    if (kq_nodes) *kq_nodes = p->kq_nodes;
+    if (build_ms) *build_ms = p->build_ms;
+    return BLAST_OK;
+}
+
+extern "C" blast_status blast_plan_k_nodes(const blast_plan *p, double *k) {
+    if (!p || !k) return blast::set_error("NULL argument"), BLAST_E_INVALID;
+    std::memcpy(k, p->knodes.data(), sizeof(double) * p->n_cheb);
+    return BLAST_OK;
+}
+
+extern "C" blast_status blast_plan_basis_point(const blast_plan *p, int32_t a, int32_t b, double *out) {
+    if (!p || !out) return blast::set_error("NULL argument"), BLAST_E_INVALID;
+    if (a < 0 || a >= p->n_chi || b < 0 || b >= p->n_R) return blast::set_error("(a, b) out of range"), BLAST_E_INVALID;
+    DeviceGuard guard(p->device);
+    std::vector<double> tmp((size_t)p->rows_pad * p->nc_pad);
+    const size_t off = ((size_t)a * p->n_R + b) * p->rows_pad * p->nc_pad;
+    BLAST_HIP_TRY(hipMemcpy(tmp.data(), p->basis.f64 + off, tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int r = 0; r < p->rows; ++r)
+        for (int n = 0; n < p->n_cheb; ++n) out[(size_t)r * p->n_cheb + n] = tmp[(size_t)r * p->nc_pad + n];
+    return BLAST_OK;
+}
+
+// --------------------------------------------------------------------------------------------
+// forward
+// --------------------------------------------------------------------------------------------
+
+extern "C" blast_status blast_cl_workspace_bytes(const blast_plan *p, int32_t batch, int32_t precision, int32_t n_bins,
+                                                 size_t *bytes) {
+    if (!p || !bytes || batch < 1 || precision < 0 || precision > 3 || n_bins < 1 || n_bins > blast::kMaxBins)
+        return blast::set_error("blast_cl_workspace_bytes: bad argument"), BLAST_E_INVALID;
+    *bytes = blast::workspace_bytes(p, batch, precision, n_bins);
+    return BLAST_OK;
+}
+
+extern "C" blast_status blast_cl_forward(blast_plan *p, const blast_cl_args *a, void *stream) {
+    blast::clear_error();
+    if (!p || !a) return blast::set_error("NULL argument"), BLAST_E_INVALID;
+    DeviceGuard guard(p->device);
+    return blast::forward(p, a, (hipStream_t)stream);
+}

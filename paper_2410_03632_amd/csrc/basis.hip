@@ -1,0 +1,456 @@
+// Cosmology-independent basis (Eq. t_tilde), computed once per plan on the GPU in FP64:
+//
+//   Ttilde[a][b][t][l][n] = sum_q v_q f_t(k_q) T_n(x(k_q)) j_l(k_q chi_a) j_l(k_q R_b chi_a)
+//
+// The k-integral over [k_min, k_max] is a composite 16-point Gauss-Legendre rule.  For each
+// chi_a the coarse panels are uniform in theta = arccos(x) (they resolve T_n near both ends
+// of the ln-k range) and each is split into equal k sub-panels so that the Bessel phase
+// (chi_a + R_b chi_a) dk across one sub-panel stays below `kq_phase` (8 by default, where
+// 16-point Gauss-Legendre is accurate far below 1e-12 for a pure oscillation).  The nodes
+// depend on a only, so j_l(k chi_a) is shared by every R_b.
+//
+// Per launch, up to G items (distinct a, one chunk of <= Qc nodes each) go through
+//   tq_kernel      : T_n(x_q) (three-term recurrence), v_q f_t(k_q), k_q
+//   bessel_kernel  : j_l(k_q chi) for chi in {chi_a, R_b chi_a} and the plan's multipoles
+//   gemm_kernel    : Ttilde += sum_q [v f_t j j]_q,l * T_n(x_q)   (FP64 MFMA 16x16x4)
+// and the chunk sums accumulate in the resident FP64 basis.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace blast {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kG = 4;        // items per launch
+constexpr int kQc = 4096;    // nodes per item
+constexpr int kMaxTypes = 3;
+
+__constant__ double c_glx[16];
+__constant__ double c_glw[16];
+
+struct Items {
+    int a[kG];
+    int p0[kG];   // first sub-panel of the item
+    int nq[kG];   // nodes in the item (<= kQc)
+    int n;        // number of items
+};
+
+// ---------------------------------------------------------------------------------------------
+// j_l(x) for increasing multipoles ell[0..nl) (all >= 2), x > 0.
+//  x >= lmax : upward three-term recurrence from j_0, j_1 (stable below the turning point).
+//  x <  lmax : upward to m = floor(x), then Miller's downward recurrence from a start L where
+//              the Debye exponent nu (alpha - tanh alpha), cosh alpha = nu/x, reaches 100
+//              (j_L / j_m ~ e^-100, so the start error is invisible and nothing overflows),
+//              normalised to the upward value j_m(x) > 0 (x < m+1 lies before j_m's first zero).
+// Orders above L are set to zero (they are below e^-70 of the turning-point amplitude).
+// ---------------------------------------------------------------------------------------------
+__device__ void bessel_list(double x, const int *__restrict__ ell, int nl, double *__restrict__ out) {
+    const int lmax = ell[nl - 1];
+    double sx, cx;
+    sincos(x, &sx, &cx);
+    const double inv = 1.0 / x;
+    const double j0 = sx * inv;
+    if (x >= (double)lmax) {
+        double jm = j0, jc = (j0 - cx) * inv;  // j_0, j_1
+        int il = 0, next = ell[0];
+        for (int l = 1; il < nl; ++l) {
+            const double jn = (2.0 * l + 1.0) * inv * jc - jm;
+            jm = jc;
+            jc = jn;
+            if (l + 1 == next) {
+                out[il] = jc;
+                ++il;
+                next = il < nl ? ell[il] : -1;
+            }
+        }
+        return;
+    }
+    const int m = (int)x;
+    int il = 0;
+    double jmv;
+    if (m == 0) {
+        jmv = j0;
+    } else {
+        double a0 = j0, a1 = (j0 - cx) * inv;  // x >= 1 here
+        int next = ell[0];
+        for (int l = 1; l < m; ++l) {
+            const double an = (2.0 * l + 1.0) * inv * a1 - a0;
+            a0 = a1;
+            a1 = an;
+            if (l + 1 == next) {
+                out[il] = a1;
+                ++il;
+                next = il < nl ? ell[il] : 1 << 30;
+            }
+        }
+        jmv = a1;
+    }
+    // start of the downward recurrence: Newton from above on E(nu) = 100 (E convex, dE/dnu = alpha)
+    double nu = x + 10.0 + 25.0 * cbrt(x + 8.0);
+    for (int it = 0; it < 12; ++it) {
+        const double al = acosh(nu / x);
+        const double a2 = al * al;
+        const double E = al < 0.1 ? nu * al * a2 * (1.0 / 3.0 - a2 * (2.0 / 15.0 - a2 * (17.0 / 315.0)))
+                                  : nu * (al - tanh(al));
+        const double d = (E - 100.0) / al;
+        nu -= d;
+        if (nu < x + 1e-3) nu = x + 1e-3;
+        if (fabs(d) < 0.25) break;
+    }
+    int L = (int)ceil(nu) + 2;
+    if (L < m + 2) L = m + 2;
+    int ih = nl - 1;
+    while (ih >= il && ell[ih] > L) {
+        out[ih] = 0.0;
+        --ih;
+    }
+    double yp = 0.0, y = 1.0;  // y_{l+1}, y_l
+    int nxt = ih >= il ? ell[ih] : -1;
+    for (int l = L; l > m; --l) {
+        if (l == nxt) {
+            out[ih] = y;
+            --ih;
+            nxt = ih >= il ? ell[ih] : -1;
+        }
+        const double yn = (2.0 * l + 1.0) * inv * y - yp;
+        yp = y;
+        y = yn;
+    }
+    const double scale = jmv / y;  // y = y_m
+    for (int q = il; q < nl && ell[q] <= L; ++q) out[q] *= scale;
+}
+
+// node tables of one launch: Tq[g][q][n], Fq[g][q][3], Kq[g][q]
+__global__ __launch_bounds__(256) void tq_kernel(Items it, const double2 *__restrict__ panels, double lnkmin,
+                                                 double span, int n_cheb, int ncp, int nt, int t0, int t1, int t2,
+                                                 double *__restrict__ Tq, double *__restrict__ Fq,
+                                                 double *__restrict__ Kq) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y;
+    if (q >= kQc || g >= it.n) return;
+    double *T = Tq + ((size_t)g * kQc + q) * ncp;
+    double *F = Fq + ((size_t)g * kQc + q) * kMaxTypes;
+    if (q >= it.nq[g]) {
+        for (int n = 0; n < ncp; ++n) T[n] = 0.0;
+        F[0] = F[1] = F[2] = 0.0;
+        Kq[(size_t)g * kQc + q] = 0.0;
+        return;
+    }
+    const double2 pk = panels[it.p0[g] + q / 16];
+    const int node = q % 16;
+    const double mid = 0.5 * (pk.x + pk.y), half = 0.5 * (pk.y - pk.x);
+    const double k = mid + half * c_glx[node];
+    const double v = half * c_glw[node];
+    const double x = 2.0 * (log(k) - lnkmin) / span - 1.0;
+    double tm = 1.0, tc = x;
+    T[0] = 1.0;
+    if (n_cheb > 1) T[1] = x;
+    for (int n = 2; n < n_cheb; ++n) {
+        const double tn = 2.0 * x * tc - tm;
+        tm = tc;
+        tc = tn;
+        T[n] = tn;
+    }
+    for (int n = n_cheb; n < ncp; ++n) T[n] = 0.0;
+    const int tb[3] = {t0, t1, t2};
+    for (int s = 0; s < kMaxTypes; ++s) {
+        double f = 0.0;
+        if (s < nt) f = tb[s] == BLAST_GG ? k * k : (tb[s] == BLAST_GS ? 1.0 : 1.0 / (k * k));
+        F[s] = v * f;
+    }
+    Kq[(size_t)g * kQc + q] = k;
+}
+
+// J[g][s][q][ilp]: s = 0 -> chi_a, s = 1 + b -> R_b chi_a
+__global__ __launch_bounds__(256) void bessel_kernel(Items it, const double *__restrict__ Kq,
+                                                     const double *__restrict__ chi, const double *__restrict__ R,
+                                                     int S, const int *__restrict__ ell, int nl, int ilp,
+                                                     double *__restrict__ J) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y, g = blockIdx.z;
+    if (q >= kQc || g >= it.n) return;
+    double *out = J + (((size_t)g * S + s) * kQc + q) * ilp;
+    const double k = Kq[(size_t)g * kQc + q];
+    if (q >= it.nq[g] || k <= 0.0) {
+        for (int il = 0; il < ilp; ++il) out[il] = 0.0;
+        return;
+    }
+    const double c = chi[it.a[g]] * (s == 0 ? 1.0 : R[s - 1]);
+    bessel_list(k * c, ell, nl, out);
+    for (int il = nl; il < ilp; ++il) out[il] = 0.0;
+}
+
+// Ttilde[a][b][slot*n_ell + l][n] += sum_q (v f_slot j_l(k chi_a) j_l(k R_b chi_a))_q T_n(x_q)
+// grid (ilp/32, n_R, items), 4 waves; wave w owns n-tiles w and w+4 for both 16-row l-tiles and
+// every type slot: 12 FP64 16x16 accumulators.  v_mfma_f64_16x16x4f64 lane layout: A[i][k] and
+// B[k][j] in lane i (or j) + 16k; D[i][j] in register r of lane j + 16*(i%4), r = i/4.
+__global__ __launch_bounds__(256) void gemm_kernel(Items it, const double *__restrict__ J,
+                                                   const double *__restrict__ Tq, const double *__restrict__ Fq,
+                                                   int S, int ilp, int ncp, int n_ell, int nt, int nR, int rows_pad,
+                                                   double *__restrict__ basis) {
+    const int g = blockIdx.z, b = blockIdx.y, il0 = blockIdx.x * 32;
+    if (g >= it.n) return;
+    const int a = it.a[g], nq = it.nq[g];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int ntiles = ncp >> 4;
+    d4 acc[kMaxTypes][2][2];
+#pragma unroll
+    for (int t = 0; t < kMaxTypes; ++t)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[t][m][j] = d4{0.0, 0.0, 0.0, 0.0};
+    const double *J0 = J + ((size_t)g * S) * kQc * ilp;
+    const double *Jb = J + ((size_t)g * S + 1 + b) * kQc * ilp;
+    const double *T = Tq + (size_t)g * kQc * ncp;
+    const double *F = Fq + (size_t)g * kQc * kMaxTypes;
+    const bool has0 = w < ntiles, has1 = w + 4 < ntiles;
+    const int nsteps = (nq + 3) >> 2;
+    for (int st = 0; st < nsteps; ++st) {
+        const int q = 4 * st + lk;
+        double p0 = 0.0, p1 = 0.0, f[kMaxTypes] = {0.0, 0.0, 0.0}, tv0 = 0.0, tv1 = 0.0;
+        if (q < nq) {
+            const double *j0 = J0 + (size_t)q * ilp + il0;
+            const double *jb = Jb + (size_t)q * ilp + il0;
+            p0 = j0[lr] * jb[lr];
+            p1 = j0[16 + lr] * jb[16 + lr];
+#pragma unroll
+            for (int t = 0; t < kMaxTypes; ++t) f[t] = F[(size_t)q * kMaxTypes + t];
+            if (has0) tv0 = T[(size_t)q * ncp + 16 * w + lr];
+            if (has1) tv1 = T[(size_t)q * ncp + 16 * (w + 4) + lr];
+        }
+#pragma unroll
+        for (int t = 0; t < kMaxTypes; ++t) {
+            if (t < nt) {
+                const double a0 = p0 * f[t], a1 = p1 * f[t];
+                acc[t][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, tv0, acc[t][0][0], 0, 0, 0);
+                acc[t][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, tv0, acc[t][1][0], 0, 0, 0);
+                if (ntiles > 4) {
+                    acc[t][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, tv1, acc[t][0][1], 0, 0, 0);
+                    acc[t][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, tv1, acc[t][1][1], 0, 0, 0);
+                }
+            }
+        }
+    }
+    const size_t base = ((size_t)a * nR + b) * rows_pad;
+#pragma unroll
+    for (int t = 0; t < kMaxTypes; ++t) {
+        if (t >= nt) continue;
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const bool ok = j == 0 ? has0 : has1;
+                if (!ok) continue;
+                const int n = 16 * (w + 4 * j) + lr;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int il = il0 + 16 * m + lk + 4 * r;  // FP64 16x16 output: row lane/16 + 4r
+                    if (il < n_ell) basis[(base + (size_t)t * n_ell + il) * ncp + n] += acc[t][m][j][r];
+                }
+            }
+    }
+}
+
+__global__ void to_f32_kernel(const double *__restrict__ src, float *__restrict__ dst, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (float)src[i];
+}
+
+__device__ inline uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// one wave per basis row: power-of-two scale, BF16 hi and (optionally) lo parts
+__global__ __launch_bounds__(256) void to_bf16_kernel(const double *__restrict__ src, size_t nrows, int ncp,
+                                                      uint16_t *__restrict__ hi, uint16_t *__restrict__ lo,
+                                                      float *__restrict__ scale) {
+    const size_t row = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= nrows) return;
+    const double *r = src + row * ncp;
+    double mx = 0.0;
+    for (int n = lane; n < ncp; n += 64) mx = fmax(mx, fabs(r[n]));
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    const double sc = mx > 0.0 ? ldexp(1.0, ilogb(mx) + 1) : 1.0;  // |value / sc| < 1
+    if (lane == 0) scale[row] = (float)sc;
+    for (int n = lane; n < ncp; n += 64) {
+        const double v = r[n] / sc;
+        const uint16_t h = f32_to_bf16_rne((float)v);
+        hi[row * ncp + n] = h;
+        if (lo) lo[row * ncp + n] = f32_to_bf16_rne((float)(v - (double)bf16_to_f32(h)));
+    }
+}
+
+void gauss_legendre16(double *x, double *w) {
+    const int n = 16;
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 60; ++it) {
+            double p1 = 1.0, p2 = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                const double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+            }
+            dp = n * (z * p1 - p2) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+}  // namespace
+
+blast_status build_basis(blast_plan *p, hipStream_t s) {
+    const int M = p->kq_panels;
+    const double phase = p->kq_phase;
+    const double lnkmin = std::log(p->kmin), span = std::log(p->kmax) - std::log(p->kmin);
+    const double Rmax = *std::max_element(p->R.begin(), p->R.end());
+    // sub-panels per chi node
+    std::vector<double2> panels;
+    std::vector<int> pstart(p->n_chi + 1, 0);
+    for (int a = 0; a < p->n_chi; ++a) {
+        pstart[a] = (int)panels.size();
+        const double omega = p->chi[a] * (1.0 + Rmax);
+        for (int i = 0; i < M; ++i) {
+            const double xa = -std::cos(M_PI * i / M), xb = -std::cos(M_PI * (i + 1) / M);
+            const double ka = i == 0 ? p->kmin : std::exp(lnkmin + 0.5 * (xa + 1.0) * span);
+            const double kb = i == M - 1 ? p->kmax : std::exp(lnkmin + 0.5 * (xb + 1.0) * span);
+            const int ns = std::max(1, (int)std::ceil(omega * (kb - ka) / phase));
+            const double h = (kb - ka) / ns;
+            for (int u = 0; u < ns; ++u)
+                panels.push_back(make_double2(ka + u * h, u == ns - 1 ? kb : ka + (u + 1) * h));
+        }
+    }
+    pstart[p->n_chi] = (int)panels.size();
+    p->kq_nodes = (int64_t)panels.size() * 16;
+
+    double glx[16], glw[16];
+    gauss_legendre16(glx, glw);
+    BLAST_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_glx), glx, sizeof(glx)));
+    BLAST_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_glw), glw, sizeof(glw)));
+
+    const int S = p->n_R + 1;
+    const int ilp = round_up(p->n_ell, 32);
+    const int ncp = p->nc_pad;
+    const size_t nb = (size_t)p->NP * p->rows_pad * ncp;
+    hipError_t e = hipMalloc(&p->basis.f64, nb * sizeof(double));
+    if (e != hipSuccess) {
+        p->basis.f64 = nullptr;
+        set_error("basis allocation of %zu bytes failed: %s", nb * sizeof(double), hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? BLAST_E_OOM : BLAST_E_HIP;
+    }
+    BLAST_HIP_TRY(hipMemsetAsync(p->basis.f64, 0, nb * sizeof(double), s));
+
+    double2 *d_panels = nullptr;
+    double *d_Tq = nullptr, *d_Fq = nullptr, *d_Kq = nullptr, *d_J = nullptr, *d_R = nullptr;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(s);
+        if (d_panels) (void)hipFree(d_panels);
+        if (d_Tq) (void)hipFree(d_Tq);
+        if (d_Fq) (void)hipFree(d_Fq);
+        if (d_Kq) (void)hipFree(d_Kq);
+        if (d_J) (void)hipFree(d_J);
+        if (d_R) (void)hipFree(d_R);
+    };
+    auto alloc = [&](void **q, size_t bytes) {
+        hipError_t r = hipMalloc(q, bytes);
+        if (r != hipSuccess) *q = nullptr;
+        return r;
+    };
+    e = alloc((void **)&d_panels, panels.size() * sizeof(double2));
+    if (e == hipSuccess) e = alloc((void **)&d_Tq, (size_t)kG * kQc * ncp * sizeof(double));
+    if (e == hipSuccess) e = alloc((void **)&d_Fq, (size_t)kG * kQc * kMaxTypes * sizeof(double));
+    if (e == hipSuccess) e = alloc((void **)&d_Kq, (size_t)kG * kQc * sizeof(double));
+    if (e == hipSuccess) e = alloc((void **)&d_J, (size_t)kG * S * kQc * ilp * sizeof(double));
+    if (e == hipSuccess) e = alloc((void **)&d_R, p->n_R * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(d_panels, panels.data(), panels.size() * sizeof(double2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_R, p->R.data(), p->n_R * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        set_error("basis workspace: %s", hipGetErrorString(e));
+        cleanup();
+        return e == hipErrorOutOfMemory ? BLAST_E_OOM : BLAST_E_HIP;
+    }
+
+    // items: groups of kG consecutive chi nodes, chunk c of each
+    const int t0 = p->tslot_type[0], t1 = p->tslot_type[1], t2 = p->tslot_type[2];
+    for (int ag = 0; ag < p->n_chi; ag += kG) {
+        int maxch = 0;
+        for (int a = ag; a < std::min(ag + kG, p->n_chi); ++a)
+            maxch = std::max(maxch, ((pstart[a + 1] - pstart[a]) * 16 + kQc - 1) / kQc);
+        for (int c = 0; c < maxch; ++c) {
+            Items it{};
+            it.n = 0;
+            for (int a = ag; a < std::min(ag + kG, p->n_chi); ++a) {
+                const int nq_a = (pstart[a + 1] - pstart[a]) * 16;
+                if (c * kQc >= nq_a) continue;
+                it.a[it.n] = a;
+                it.p0[it.n] = pstart[a] + c * (kQc / 16);
+                it.nq[it.n] = std::min(kQc, nq_a - c * kQc);
+                it.n++;
+            }
+            if (!it.n) continue;
+            hipLaunchKernelGGL(tq_kernel, dim3(kQc / 256, it.n), dim3(256), 0, s, it, d_panels, lnkmin, span,
+                               p->n_cheb, ncp, p->nt, t0, t1, t2, d_Tq, d_Fq, d_Kq);
+            hipLaunchKernelGGL(bessel_kernel, dim3(kQc / 256, S, it.n), dim3(256), 0, s, it, d_Kq, p->d_chi, d_R, S,
+                               p->d_ell, p->n_ell, ilp, d_J);
+            hipLaunchKernelGGL(gemm_kernel, dim3(ilp / 32, p->n_R, it.n), dim3(256), 0, s, it, d_J, d_Tq, d_Fq, S, ilp,
+                               ncp, p->n_ell, p->nt, p->n_R, p->rows_pad, p->basis.f64);
+            e = hipGetLastError();
+            if (e != hipSuccess) {
+                set_error("basis kernels: %s", hipGetErrorString(e));
+                cleanup();
+                return BLAST_E_HIP;
+            }
+        }
+    }
+    cleanup();
+    return BLAST_OK;
+}
+
+blast_status derive_precisions(blast_plan *p, hipStream_t s) {
+    const size_t n = (size_t)p->NP * p->rows_pad * p->nc_pad;
+    const size_t nrows = (size_t)p->NP * p->rows_pad;
+    auto fail = [&](hipError_t e, const char *what) {
+        set_error("%s: %s", what, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? BLAST_E_OOM : BLAST_E_HIP;
+    };
+    if (p->precisions & (1u << BLAST_FP32)) {
+        hipError_t e = hipMalloc(&p->basis.f32, n * sizeof(float));
+        if (e != hipSuccess) return p->basis.f32 = nullptr, fail(e, "FP32 basis");
+        hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->basis.f64,
+                           p->basis.f32, n);
+    }
+    const bool want_hi = p->precisions & ((1u << BLAST_BF16) | (1u << BLAST_BF16X3));
+    const bool want_lo = p->precisions & (1u << BLAST_BF16X3);
+    if (want_hi) {
+        hipError_t e = hipMalloc(&p->basis.hi, n * sizeof(uint16_t));
+        if (e != hipSuccess) return p->basis.hi = nullptr, fail(e, "BF16 basis");
+        e = hipMalloc(&p->basis.scale, nrows * sizeof(float));
+        if (e != hipSuccess) return p->basis.scale = nullptr, fail(e, "basis scales");
+        if (want_lo) {
+            e = hipMalloc(&p->basis.lo, n * sizeof(uint16_t));
+            if (e != hipSuccess) return p->basis.lo = nullptr, fail(e, "BF16 lo basis");
+        }
+        hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((nrows + 3) / 4)), dim3(256), 0, s, p->basis.f64, nrows,
+                           p->nc_pad, p->basis.hi, p->basis.lo, p->basis.scale);
+    }
+    BLAST_HIP_TRY(hipGetLastError());
+    return BLAST_OK;
+}
+
+}  // namespace blast

@@ -1,0 +1,91 @@
+// Internal declarations of the beyond-Limber C_ell library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "blast_hip.h"
+
+namespace blast {
+
+void set_error(const char *fmt, ...);
+void clear_error();
+
+constexpr int kMaxBins = 32;     // n_g + n_s per call
+constexpr int kMaxEll = 512;     // multipoles per plan
+constexpr int kMaxCheb = 128;    // Chebyshev nodes per plan
+constexpr int kBatchTile = 64;   // cosmologies per contraction work-group pass
+
+inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Power-of-two scale and the BF16 bit pattern helpers shared by host conversions.
+struct BasisBuffers {
+    double *f64 = nullptr;     // [NP][rows_pad][nc_pad]
+    float *f32 = nullptr;      // [NP][rows_pad][nc_pad]
+    uint16_t *hi = nullptr;    // BF16 bits of (value / scale), same layout
+    uint16_t *lo = nullptr;    // BF16 bits of the remainder
+    float *scale = nullptr;    // [NP][rows_pad] power-of-two row scales
+};
+
+}  // namespace blast
+
+struct blast_plan {
+    int device = 0;
+    // multipoles and types
+    int n_ell = 0;
+    std::vector<int> ell;
+    int lmax = 0;
+    uint32_t types = 0;
+    int nt = 0;              // number of resident types
+    int slot[3] = {-1, -1, -1};  // slot of gg, gs, ss rows (or -1)
+    int tslot_type[3] = {0, 0, 0}; // type bit of each slot
+    int rows = 0, rows_pad = 0;
+    // grids
+    int n_chi = 0, n_R = 0, NP = 0;
+    std::vector<double> chi, w_chi, R, w_R;
+    double kmin = 0, kmax = 0;
+    int n_cheb = 0, nc_pad = 0;
+    std::vector<double> knodes;
+    // quadrature of the basis
+    int kq_panels = 0;
+    double kq_phase = 0;
+    int64_t kq_nodes = 0;
+    double build_ms = 0;
+    uint32_t precisions = 0;
+    // device data
+    blast::BasisBuffers basis;
+    double *d_dct64 = nullptr;  // projection matrix, transposed: [n_cheb j][nc_pad n]
+    float *d_dct32 = nullptr;
+    double *d_chi = nullptr, *d_wchi = nullptr, *d_wR = nullptr;
+    double *d_pref = nullptr;   // [rows] N_t(l)
+    int *d_ell = nullptr;
+    // plan-owned scratch for calls without a caller workspace
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    std::mutex mu;
+};
+
+namespace blast {
+
+// basis.hip
+blast_status build_basis(blast_plan *p, hipStream_t s);
+blast_status derive_precisions(blast_plan *p, hipStream_t s);
+
+// eval.hip
+blast_status forward(blast_plan *p, const blast_cl_args *a, hipStream_t s);
+size_t workspace_bytes(const blast_plan *p, int batch, int prec, int n_bins);
+
+}  // namespace blast
+
+#define BLAST_HIP_TRY(expr)                                                                          \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) {                                                                      \
+            blast::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return BLAST_E_HIP;                                                                      \
+        }                                                                                            \
+    } while (0)
