@@ -1,0 +1,247 @@
+"""Throughput of the beyond-Limber 3x2pt C_ell path on one MI355X.
+
+One step = the whole per-cosmology path (Chebyshev projection -> contraction with
+the resident basis -> chi/R quadrature for every bin pair) over one batch of
+synthetic cosmologies whose inputs are already resident in HBM.  The basis
+precompute is done once before timing (as in the paper, where it is excluded from
+the timings) and reported separately.
+
+    python bench.py [--steps K] [--warmup W] [--batch B] [--precision fp32|bf16x3|fp64]
+
+Prints ONE JSON line (see the keys at the bottom).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "3x2pt C_ell sets/sec at ≤1e-3 rel err vs FP64 oracle; p50/p99 latency"
+PEAK = {"hbm": 8.0e12, "fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16": "bf16"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stage_work(plan, cfg, prec, batch):
+    """Algorithmic flops and HBM bytes of each stage for one launch over `batch` sets."""
+    NP = cfg.n_chi * cfg.n_R
+    N = cfg.n_cheb
+    rows = plan.rows
+    nb = cfg.n_g + cfg.n_s
+    eb = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4}[prec]       # basis bytes per element (hi+lo)
+    ec = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4}[prec]       # coefficient bytes
+    ew = 8 if prec == "fp64" else 4                                    # w bytes
+    ep = 8 if prec == "fp64" else 4                                    # P bytes
+    rows_bins = plan.n_ell * (cfg.n_g + nb + cfg.n_s)                 # (row, bin) products in the R-sum
+    return {
+        "projection": dict(flops=2.0 * NP * N * N * batch, bytes=float(NP * N * (ep + ec) * batch)),
+        "contraction": dict(flops=2.0 * rows * N * NP * batch,
+                            bytes=float(NP * rows * N * eb + NP * N * ec * batch + NP * rows * ew * batch)),
+        "quad_R": dict(flops=2.0 * rows_bins * NP * batch,
+                       bytes=float((NP * rows * ew + nb * NP * 8 + cfg.n_chi * rows * nb * 8) * batch)),
+        "quad_chi": dict(flops=4.0 * cfg.n_chi * plan.n_ell * 120 * batch,
+                         bytes=float(cfg.n_chi * rows * nb * 8 * batch)),
+    }
+
+
+def roofline(work, ms_per_launch, prec):
+    flops, nbytes = work["flops"], work["bytes"]
+    t = ms_per_launch * 1e-3
+    peak_f = PEAK["fp64" if prec == "fp64" else ("bf16" if prec.startswith("bf16") else "fp32")]
+    ridge = peak_f / PEAK["hbm"]
+    if flops / nbytes >= ridge:
+        a = flops / t / 1e12
+        return {"bound": "mfma", "achieved": a, "peak": peak_f / 1e12, "unit": "TFLOP/s", "frac": a * 1e12 / peak_f,
+                "traffic": None, "algorithmic_flops": flops, "algorithmic_bytes": nbytes}
+    a = nbytes / t / 1e9
+    return {"bound": "hbm", "achieved": a, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s", "frac": a * 1e9 / PEAK["hbm"],
+            "traffic": None, "algorithmic_flops": flops, "algorithmic_bytes": nbytes}
+
+
+def cpu_baseline(cfg, plan, inp, n_sample=48, seed=11):
+    """The FP64 oracle on a stratified sample of (chi_a, R_b) points of the same workload,
+    with the same two k-panel levels its doubling test runs, scaled to one full set."""
+    import oracle as O
+    rng = np.random.default_rng(seed)
+    a_idx = (np.arange(n_sample) * cfg.n_chi) // n_sample
+    b_idx = rng.integers(0, cfg.n_R, n_sample)
+    c1 = plan.chi[a_idx]
+    c2 = plan.chi[a_idx] * plan.R[b_idx]
+    P = inp.P[a_idx, b_idx]
+    M0 = max(64, 2 * cfg.n_cheb)
+    t0 = time.time()
+    for M, Phi in ((M0, 10.0), (2 * M0, 5.0)):
+        O.w_points(cfg.ells(), ("gg", "gs", "ss"), cfg.k_min, cfg.k_max, c1, c2, nc=cfg.n_cheb, P=P, M=M, Phi=Phi)
+    t = time.time() - t0
+    s_per_set = t * (cfg.n_chi * cfg.n_R) / n_sample
+    return {"value": 1.0 / s_per_set, "unit": "sets/s", "cores": O.max_threads(), "kind": "oracle",
+            "sample": "%d of %d (chi_a, R_b) points (stratified in chi), k-integrals at the oracle's first two "
+                      "refinement levels, %.1f s wall, scaled by points" % (n_sample, cfg.n_chi * cfg.n_R, t),
+            "s_per_set": s_per_set, "cpu": platform.processor() or platform.machine()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64", "bf16"])
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP64-path and batch-1 timings")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (asked for %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2410_03632_amd import blast as B
+    from paper_2410_03632_amd import workloads as W
+    from tests._util import g16_err
+
+    cfg = W.CONFIGS[args.config]
+    prec = args.precision
+    log("building plan for config", args.config, cfg.name)
+    t0 = time.time()
+    precs = ("fp64", "fp32", "bf16x3") if prec != "bf16" else ("fp64", "bf16")
+    plan = B.plan_for_config(cfg, precisions=precs)
+    build_s = time.time() - t0
+    log("plan built in %.1f s (%d k-nodes, basis %s bytes)" % (build_s, plan.kq_nodes, plan.basis_bytes))
+
+    # inputs: batch of seeded cosmologies, resident on the device
+    Bn = args.batch
+    chi, chi2 = plan.eval_points()
+    Kchi, Kchi2 = W.kernels(W.bins_of(cfg), chi, chi2)
+    inps = [W.make_inputs(cfg, W.seed_for(args.config, i), plan.k_nodes, plan.chi, plan.R) for i in range(min(Bn, 4))]
+    rng_cos = [W.draw_cosmo(np.random.default_rng(W.seed_for(args.config, i))) for i in range(Bn)]
+    dev = torch.device("cuda:0")
+    pdt = torch.float64 if prec == "fp64" else torch.float32
+    P = torch.empty((Bn, cfg.n_chi, cfg.n_R, cfg.n_cheb), dtype=pdt, device=dev)
+    for i, cos in enumerate(rng_cos):
+        P[i] = torch.as_tensor(W.p_grid(plan.k_nodes, chi, chi2, cos), dtype=pdt)
+    K1 = torch.as_tensor(Kchi, device=dev).unsqueeze(0).expand(Bn, -1, -1).contiguous()
+    K2 = torch.as_tensor(Kchi2, device=dev).unsqueeze(0).expand(Bn, -1, -1, -1).contiguous()
+    out = torch.empty((Bn, B.n_pairs(cfg.n_g, cfg.n_s), plan.n_ell), dtype=torch.float64, device=dev)
+    ws = torch.empty(plan.workspace_bytes(Bn, prec, cfg.n_g + cfg.n_s), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        plan.forward(P, K1, K2, cfg.n_g, cfg.n_s, precision=prec, out=out, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.profile(False)
+    stage_ms, ncalls = plan.profile_read()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = Bn / (ms_per_step * 1e-3)
+    per_launch = {k: v / max(ncalls, 1) for k, v in stage_ms.items()}
+    log("ms/step %.3f  sets/s %.1f  stages(ms/launch) %s" % (ms_per_step, value, per_launch))
+    work = stage_work(plan, cfg, prec, Bn)
+    dom = max(per_launch, key=per_launch.get)
+    roof = roofline(work[dom], per_launch[dom], prec)
+    roof["kernel"] = {"projection": "project_kernel", "contraction": "contract_kernel", "quad_R": "quad_y_kernel",
+                      "quad_chi": "quad_c_kernel"}[dom]
+    roof["stage_ms_per_launch"] = per_launch
+    roof["stage_roofline"] = {k: roofline(work[k], per_launch[k], prec) for k in per_launch}
+    for v in roof["stage_roofline"].values():
+        v.pop("algorithmic_flops", None)
+        v.pop("algorithmic_bytes", None)
+
+    # accuracy of the timed path: cosmology 0 against the oracle's golden values
+    res = out[0].cpu().numpy()
+    err = {}
+    gpath = os.path.join(ROOT, "tests", "golden", "c%d_oracle.json" % args.config)
+    if os.path.exists(gpath):
+        g = json.load(open(gpath))
+        if g["seed"] == W.seed_for(args.config, 0):
+            e = g16_err(res, np.array(g["C"]), cfg.n_g, cfg.n_s)
+            err["max_rel_err_vs_oracle"] = float(e.max())
+    extras = {}
+    if not args.no_extras:
+        # FP64 path on a smaller batch, and single-cosmology latency of the timed path
+        P64 = torch.as_tensor(inps[0].P[None], device=dev)
+        r64 = plan.forward(P64, K1[:1].contiguous(), K2[:1].contiguous(), cfg.n_g, cfg.n_s, precision="fp64")
+        torch.cuda.synchronize()
+        if "max_rel_err_vs_oracle" not in err:
+            e = g16_err(res, r64[0].cpu().numpy(), cfg.n_g, cfg.n_s)
+            err["max_rel_err_vs_fp64_path"] = float(e.max())
+        nb64 = min(Bn, 16)
+        P64b = P[:nb64].double().contiguous()
+        for _ in range(2):
+            plan.forward(P64b, K1[:nb64].contiguous(), K2[:nb64].contiguous(), cfg.n_g, cfg.n_s, precision="fp64")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            plan.forward(P64b, K1[:nb64].contiguous(), K2[:nb64].contiguous(), cfg.n_g, cfg.n_s, precision="fp64")
+        torch.cuda.synchronize()
+        ms64 = (time.perf_counter() - t0) * 1e3 / 5
+        extras["fp64_path"] = {"batch": nb64, "ms_per_step": ms64, "sets_per_s": nb64 / (ms64 * 1e-3)}
+        extras["mixed_vs_fp64_speedup"] = value / extras["fp64_path"]["sets_per_s"]
+        P1, K11, K21 = P[:1].contiguous(), K1[:1].contiguous(), K2[:1].contiguous()
+        lat = []
+        for i in range(12):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            plan.forward(P1, K11, K21, cfg.n_g, cfg.n_s, precision=prec)
+            torch.cuda.synchronize()
+            if i >= 2:
+                lat.append((time.perf_counter() - ta) * 1e3)
+        extras["batch1_latency_ms"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        cpu = cpu_baseline(cfg, plan, inps[0])
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "sets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[prec],
+        "data": "synthetic",
+        "config": {"workload": "full 3x2pt: %d clustering + %d shear bins (%d pairs), %d ell in [%d, %d], "
+                               "chi %d on [%g, %g] Mpc, R %d on [%g, 1], %d Chebyshev nodes in ln k on [%g, %g]"
+                               % (cfg.n_g, cfg.n_s, B.n_pairs(cfg.n_g, cfg.n_s), cfg.n_ell, cfg.ell_min,
+                                  cfg.ell_max, cfg.n_chi, cfg.chi_min, cfg.chi_max, cfg.n_R, cfg.R_min,
+                                  cfg.n_cheb, cfg.k_min, cfg.k_max),
+                   "batch": Bn, "precision": prec, "basis_build_s": build_s, "kq_nodes": plan.kq_nodes},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    line.update(err)
+    line.update(extras)
+    print(json.dumps(line), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -165,6 +165,19 @@ blast_status blast_cl_workspace_bytes(const blast_plan *plan, int32_t batch, int
  * resident), OOM (plan scratch), HIP. */
 blast_status blast_cl_forward(blast_plan *plan, const blast_cl_args *args, void *stream);
 
+/* ------------------------------------------------------------------------- */
+/* Stage timing                                                               */
+/* ------------------------------------------------------------------------- */
+
+/* While enabled, blast_cl_forward records HIP events on the call's stream around
+ * its four stages: 0 projection, 1 contraction, 2 R-quadrature, 3 chi-quadrature
+ * and pair assembly.  The events cost a few microseconds per call. */
+blast_status blast_plan_profile(blast_plan *plan, int32_t enable);
+
+/* Waits for the recorded events, writes the summed milliseconds of each stage
+ * (host [4]) and the number of recorded calls, and clears the record. */
+blast_status blast_plan_profile_read(blast_plan *plan, double *stage_ms, int64_t *calls);
+
 #ifdef __cplusplus
 }
 #endif

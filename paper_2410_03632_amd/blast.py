@@ -53,8 +53,9 @@ class ClArgs(C.Structure):
 EXPORTS = [
     "blast_last_error", "blast_version", "blast_grid_chi_simpson", "blast_grid_R_fejer", "blast_grid_k_cheb",
     "blast_plan_create", "blast_plan_destroy", "blast_plan_info", "blast_plan_k_nodes", "blast_plan_basis_point",
-    "blast_cl_workspace_bytes", "blast_cl_forward",
+    "blast_cl_workspace_bytes", "blast_cl_forward", "blast_plan_profile", "blast_plan_profile_read",
 ]
+STAGES = ("projection", "contraction", "quad_R", "quad_chi")
 
 _lib = None
 
@@ -81,6 +82,8 @@ def lib():
         L.blast_cl_workspace_bytes.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                                C.POINTER(C.c_size_t)]
         L.blast_cl_forward.argtypes = [C.c_void_p, C.POINTER(ClArgs), C.c_void_p]
+        L.blast_plan_profile.argtypes = [C.c_void_p, C.c_int32]
+        L.blast_plan_profile_read.argtypes = [C.c_void_p, dp, C.POINTER(C.c_int64)]
         for name in EXPORTS:
             if name not in ("blast_last_error", "blast_version"):
                 getattr(L, name).restype = C.c_int
@@ -196,6 +199,17 @@ class Plan:
         out = np.empty((self.rows, self.n_cheb))
         _check(lib().blast_plan_basis_point(self._h, a, b, _dptr(out)))
         return out
+
+    def profile(self, enable=True):
+        """Record HIP events around the four stages of every forward call."""
+        _check(lib().blast_plan_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(dict stage -> summed ms, number of calls) since the last read."""
+        ms = (C.c_double * 4)()
+        n = C.c_int64()
+        _check(lib().blast_plan_profile_read(self._h, ms, C.byref(n)))
+        return dict(zip(STAGES, list(ms))), n.value
 
     def eval_points(self):
         """(chi_a, R_b chi_a): where to evaluate the kernels and P."""

@@ -131,12 +131,15 @@ static void free_plan(blast_plan *p) {
     f(p->basis.scale);
     f(p->d_dct64);
     f(p->d_dct32);
+    f(p->d_dctn64);
+    f(p->d_dctn32);
     f(p->d_chi);
     f(p->d_wchi);
     f(p->d_wR);
     f(p->d_pref);
     f(p->d_ell);
     f(p->scratch);
+    for (hipEvent_t e : p->prof_events) (void)hipEventDestroy(e);
     delete p;
 }
 
@@ -224,8 +227,8 @@ extern "C" blast_status blast_plan_create(const blast_plan_desc *d, int32_t devi
     // small device tables
     {
         const int N = p->n_cheb, ncp = p->nc_pad;
-        std::vector<double> dct((size_t)N * ncp, 0.0);
-        std::vector<float> dct32((size_t)N * ncp, 0.0f);
+        std::vector<double> dct((size_t)N * ncp, 0.0), dctn((size_t)ncp * N, 0.0);
+        std::vector<float> dct32((size_t)N * ncp, 0.0f), dctn32((size_t)ncp * N, 0.0f);
         // c_n = sum_j D[n][j] P_j with j the ascending-k node index (node angle pi - (2j+1)pi/2N):
         // D[n][j] = (2 - delta_n0)/N cos(n (pi - (2j+1)pi/2N))
         for (int j = 0; j < N; ++j)
@@ -233,6 +236,8 @@ extern "C" blast_status blast_plan_create(const blast_plan_desc *d, int32_t devi
                 double v = (n == 0 ? 1.0 : 2.0) / N * std::cos(n * (kPi - (2.0 * j + 1.0) * kPi / (2.0 * N)));
                 dct[(size_t)j * ncp + n] = v;
                 dct32[(size_t)j * ncp + n] = (float)v;
+                dctn[(size_t)n * N + j] = v;
+                dctn32[(size_t)n * N + j] = (float)v;
             }
         std::vector<double> pref(p->rows);
         for (int sl = 0; sl < p->nt; ++sl)
@@ -245,6 +250,8 @@ extern "C" blast_status blast_plan_create(const blast_plan_desc *d, int32_t devi
         hipError_t e = hipSuccess;
         if (e == hipSuccess) e = up((void **)&p->d_dct64, dct.data(), dct.size() * sizeof(double));
         if (e == hipSuccess) e = up((void **)&p->d_dct32, dct32.data(), dct32.size() * sizeof(float));
+        if (e == hipSuccess) e = up((void **)&p->d_dctn64, dctn.data(), dctn.size() * sizeof(double));
+        if (e == hipSuccess) e = up((void **)&p->d_dctn32, dctn32.data(), dctn32.size() * sizeof(float));
         if (e == hipSuccess) e = up((void **)&p->d_chi, p->chi.data(), p->n_chi * sizeof(double));
         if (e == hipSuccess) e = up((void **)&p->d_wchi, p->w_chi.data(), p->n_chi * sizeof(double));
         if (e == hipSuccess) e = up((void **)&p->d_wR, p->w_R.data(), p->n_R * sizeof(double));
@@ -330,4 +337,45 @@ extern "C" blast_status blast_cl_forward(blast_plan *p, const blast_cl_args *a, 
     if (!p || !a) return blast::set_error("NULL argument"), BLAST_E_INVALID;
     DeviceGuard guard(p->device);
     return blast::forward(p, a, (hipStream_t)stream);
+}
+
+// --------------------------------------------------------------------------------------------
+// stage timing
+// --------------------------------------------------------------------------------------------
+
+extern "C" blast_status blast_plan_profile(blast_plan *p, int32_t enable) {
+    if (!p) return blast::set_error("plan is NULL"), BLAST_E_INVALID;
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->profile = enable != 0;
+    return BLAST_OK;
+}
+
+extern "C" blast_status blast_plan_profile_read(blast_plan *p, double *stage_ms, int64_t *calls) {
+    if (!p || !stage_ms) return blast::set_error("NULL argument"), BLAST_E_INVALID;
+    DeviceGuard guard(p->device);
+    std::lock_guard<std::mutex> lk(p->mu);
+    for (int i = 0; i < 4; ++i) stage_ms[i] = 0.0;
+    const size_t n = p->prof_events.size() / 5;
+    blast_status st = BLAST_OK;
+    for (size_t c = 0; c < n && st == BLAST_OK; ++c) {
+        hipEvent_t *e = &p->prof_events[5 * c];
+        if (hipEventSynchronize(e[4]) != hipSuccess) {
+            blast::set_error("hipEventSynchronize failed");
+            st = BLAST_E_HIP;
+            break;
+        }
+        for (int i = 0; i < 4; ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e[i], e[i + 1]) != hipSuccess) {
+                blast::set_error("hipEventElapsedTime failed");
+                st = BLAST_E_HIP;
+                break;
+            }
+            stage_ms[i] += ms;
+        }
+    }
+    for (hipEvent_t e : p->prof_events) (void)hipEventDestroy(e);
+    p->prof_events.clear();
+    if (calls) *calls = (int64_t)n;
+    return st;
 }

@@ -60,9 +60,14 @@ struct blast_plan {
     blast::BasisBuffers basis;
     double *d_dct64 = nullptr;  // projection matrix, transposed: [n_cheb j][nc_pad n]
     float *d_dct32 = nullptr;
+    double *d_dctn64 = nullptr; // projection matrix [nc_pad n][n_cheb j] (MFMA path)
+    float *d_dctn32 = nullptr;
     double *d_chi = nullptr, *d_wchi = nullptr, *d_wR = nullptr;
     double *d_pref = nullptr;   // [rows] N_t(l)
     int *d_ell = nullptr;
+    // stage timing: 5 events per recorded forward call
+    bool profile = false;
+    std::vector<hipEvent_t> prof_events;
     // plan-owned scratch for calls without a caller workspace
     void *scratch = nullptr;
     size_t scratch_bytes = 0;

@@ -49,6 +49,7 @@ TINY = [
     dict(),                                                            # 6 ell, 12 chi, 10 R, 24 nodes
     dict(n_ell=17, ell_max=90, n_chi=9, n_R=7, n_cheb=40, k_max=1.2),  # ragged everything
     dict(n_ell=3, ell_max=12, n_chi=5, n_R=3, n_cheb=2, k_max=0.3, n_g=1, n_s=3),
+    dict(n_ell=9, ell_max=60, n_chi=7, n_R=6, n_cheb=32, k_max=0.8, n_g=3, n_s=1),  # MFMA projection
 ]
 
 
