@@ -140,8 +140,10 @@ typedef struct {
     int32_t batch;        /* number of independent cosmologies, >= 1              */
     int32_t precision;    /* blast_precision; must be resident in the plan        */
     int32_t p_dtype;      /* 0: P is FP64, 1: P is FP32                            */
-    const void *P;        /* device [batch][n_chi][n_R][n_cheb]: P(k_j, chi_a, R_b chi_a),
-                             k ascending (blast_plan_k_nodes)                        */
+    int32_t p_kind;       /* 0: P holds nodal values P(k_j, chi_a, R_b chi_a), k ascending
+                             (blast_plan_k_nodes); 1: P holds the Chebyshev coefficients
+                             c_n(chi_a, R_b chi_a) of Eq. cheb_pk (the projection is skipped) */
+    const void *P;        /* device [batch][n_chi][n_R][n_cheb]                      */
     int32_t n_g, n_s;     /* clustering / shear bins, n_g + n_s <= 32              */
     const double *K_chi;  /* device [batch][n_g+n_s][n_chi]: K at chi_a             */
     const double *K_chi2; /* device [batch][n_g+n_s][n_chi][n_R]: K at R_b chi_a    */
@@ -157,6 +159,7 @@ typedef struct {
     size_t workspace_bytes;
 } blast_cl_args;
 
+/* Device scratch for one forward or backward call with these sizes. */
 blast_status blast_cl_workspace_bytes(const blast_plan *plan, int32_t batch, int32_t precision, int32_t n_bins,
                                       size_t *bytes);
 
@@ -164,6 +167,18 @@ blast_status blast_cl_workspace_bytes(const blast_plan *plan, int32_t batch, int
  * (Eq. final_cls) on `stream`.  Errors: INVALID (shapes, types, precision not
  * resident), OOM (plan scratch), HIP. */
 blast_status blast_cl_forward(blast_plan *plan, const blast_cl_args *args, void *stream);
+
+/* Adjoint of blast_cl_forward (reverse mode; not in the paper, whose conclusion lists
+ * differentiability as future work).  With the same `args` (precision FP64 or FP32)
+ * and dC = dL/dC (device, FP64, shaped like args->C) it enqueues on `stream`:
+ *   dP      device, nullable, P's dtype and shape: dL/dP (nodal values or coefficients
+ *           per args->p_kind) -- the transposed contraction streams the basis again;
+ *   dK_chi  device, nullable, FP64 [batch][bins][n_chi]: dL/dK_chi;
+ *   dK_chi2 device, nullable, FP64 [batch][bins][n_chi][n_R]: dL/dK_chi2.
+ * args->C is not read.  args->w_save, if given, must hold w of a forward call with the
+ * same inputs (saves recomputing it).  Errors: INVALID, UNSUPPORTED (BF16 paths), OOM, HIP. */
+blast_status blast_cl_backward(blast_plan *plan, const blast_cl_args *args, const double *dC, void *dP,
+                               double *dK_chi, double *dK_chi2, void *stream);
 
 /* ------------------------------------------------------------------------- */
 /* Stage timing                                                               */

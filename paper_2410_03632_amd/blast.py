@@ -41,7 +41,7 @@ class PlanDesc(C.Structure):
 
 class ClArgs(C.Structure):
     _fields_ = [
-        ("batch", C.c_int32), ("precision", C.c_int32), ("p_dtype", C.c_int32),
+        ("batch", C.c_int32), ("precision", C.c_int32), ("p_dtype", C.c_int32), ("p_kind", C.c_int32),
         ("P", C.c_void_p), ("n_g", C.c_int32), ("n_s", C.c_int32),
         ("K_chi", C.c_void_p), ("K_chi2", C.c_void_p), ("types", C.c_uint32),
         ("n_ell_out", C.c_int32), ("ell_idx", C.POINTER(C.c_int32)),
@@ -53,7 +53,8 @@ class ClArgs(C.Structure):
 EXPORTS = [
     "blast_last_error", "blast_version", "blast_grid_chi_simpson", "blast_grid_R_fejer", "blast_grid_k_cheb",
     "blast_plan_create", "blast_plan_destroy", "blast_plan_info", "blast_plan_k_nodes", "blast_plan_basis_point",
-    "blast_cl_workspace_bytes", "blast_cl_forward", "blast_plan_profile", "blast_plan_profile_read",
+    "blast_cl_workspace_bytes", "blast_cl_forward", "blast_cl_backward", "blast_plan_profile",
+    "blast_plan_profile_read",
 ]
 STAGES = ("projection", "contraction", "quad_R", "quad_chi")
 
@@ -82,6 +83,8 @@ def lib():
         L.blast_cl_workspace_bytes.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                                C.POINTER(C.c_size_t)]
         L.blast_cl_forward.argtypes = [C.c_void_p, C.POINTER(ClArgs), C.c_void_p]
+        L.blast_cl_backward.argtypes = [C.c_void_p, C.POINTER(ClArgs), C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p]
         L.blast_plan_profile.argtypes = [C.c_void_p, C.c_int32]
         L.blast_plan_profile_read.argtypes = [C.c_void_p, dp, C.POINTER(C.c_int64)]
         for name in EXPORTS:
@@ -221,10 +224,7 @@ class Plan:
                                               C.byref(n)))
         return n.value
 
-    def forward(self, P, K_chi, K_chi2, n_g, n_s, *, precision="fp64", types=None, ell_idx=None,
-                out=None, w_save=None, workspace=None, stream=None):
-        """C[batch][pair][ell] for device tensors P [B, n_chi, n_R, n_cheb] (float64/float32),
-        K_chi [B, bins, n_chi] and K_chi2 [B, bins, n_chi, n_R] (float64)."""
+    def _prepare(self, P, K_chi, K_chi2, n_g, n_s, precision, types, ell_idx, coef):
         import torch
         prec = PRECISION.get(precision, precision)
         if P.dim() == 3:
@@ -249,30 +249,114 @@ class Plan:
         tmask = self.types if types is None else types_mask(types)
         npair = n_pairs(n_g, n_s, tmask)
         if ell_idx is None:
-            n_out, idx_arr = 0, None
-            n_l = self.n_ell
+            n_out, idx_arr, n_l = 0, None, self.n_ell
         else:
             idx_arr = np.ascontiguousarray(ell_idx, dtype=np.int32)
             n_out = n_l = len(idx_arr)
-        if out is None:
-            out = torch.empty((B, npair, n_l), dtype=torch.float64, device=P.device)
-        elif tuple(out.shape) != (B, npair, n_l) or out.dtype != torch.float64 or not out.is_contiguous():
-            raise ValueError("out must be a contiguous float64 tensor of shape %s" % ((B, npair, n_l),))
-        if w_save is not None:
-            wdt = torch.float64 if prec == FP64 else torch.float32
-            if w_save.dtype != wdt or w_save.numel() != B * len(self.chi) * len(self.R) * self.rows_pad:
-                raise ValueError("w_save must hold batch*n_chi*n_R*rows_pad values of %s" % wdt)
-        ws_ptr, ws_bytes = (None, 0)
-        if workspace is not None:
-            ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
-        args = ClArgs(B, prec, 0 if P.dtype == torch.float64 else 1, P.data_ptr(), n_g, n_s,
+        args = ClArgs(B, prec, 0 if P.dtype == torch.float64 else 1, 1 if coef else 0, P.data_ptr(), n_g, n_s,
                       K_chi.data_ptr(), K_chi2.data_ptr(), tmask, n_out,
                       idx_arr.ctypes.data_as(C.POINTER(C.c_int32)) if idx_arr is not None else None,
-                      out.data_ptr(), w_save.data_ptr() if w_save is not None else None, ws_ptr, ws_bytes)
+                      None, None, None, 0)
+        return args, (P, K_chi, K_chi2, idx_arr), (B, npair, n_l), prec
+
+    def _w_ws(self, args, B, prec, w_save, workspace):
+        import torch
+        if w_save is not None:
+            wdt = torch.float64 if prec == FP64 else torch.float32
+            if w_save.dtype != wdt or w_save.numel() != B * len(self.chi) * len(self.R) * self.rows_pad \
+                    or not w_save.is_contiguous():
+                raise ValueError("w_save must hold batch*n_chi*n_R*rows_pad contiguous values of %s" % wdt)
+            args.w_save = w_save.data_ptr()
+        if workspace is not None:
+            args.workspace = workspace.data_ptr()
+            args.workspace_bytes = workspace.numel() * workspace.element_size()
+
+    def forward(self, P, K_chi, K_chi2, n_g, n_s, *, precision="fp64", types=None, ell_idx=None,
+                out=None, w_save=None, workspace=None, stream=None, coef=False):
+        """C[batch][pair][ell] for device tensors P [B, n_chi, n_R, n_cheb] (float64/float32; nodal
+        values, or Chebyshev coefficients with coef=True), K_chi [B, bins, n_chi] and
+        K_chi2 [B, bins, n_chi, n_R] (float64)."""
+        import torch
+        args, keep, shape, prec = self._prepare(P, K_chi, K_chi2, n_g, n_s, precision, types, ell_idx, coef)
+        P = keep[0]
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64, device=P.device)
+        elif tuple(out.shape) != shape or out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of shape %s" % (shape,))
+        args.C = out.data_ptr()
+        self._w_ws(args, shape[0], prec, w_save, workspace)
         if stream is None:
             stream = torch.cuda.current_stream(P.device).cuda_stream
         _check(lib().blast_cl_forward(self._h, C.byref(args), C.c_void_p(stream)))
         return out
+
+    def backward(self, P, K_chi, K_chi2, n_g, n_s, dC, *, precision="fp64", types=None, ell_idx=None,
+                 w_save=None, workspace=None, stream=None, coef=False, want=("P", "K_chi", "K_chi2")):
+        """Gradients (dP, dK_chi, dK_chi2) of a scalar loss given dC = dL/dC (device float64,
+        shaped like the forward output); entries not in `want` are None."""
+        import torch
+        args, keep, shape, prec = self._prepare(P, K_chi, K_chi2, n_g, n_s, precision, types, ell_idx, coef)
+        P, K_chi, K_chi2 = keep[:3]
+        if tuple(dC.shape) != shape or dC.dtype != torch.float64 or not dC.is_contiguous() or not dC.is_cuda:
+            raise ValueError("dC must be a contiguous float64 device tensor of shape %s" % (shape,))
+        self._w_ws(args, shape[0], prec, w_save, workspace)
+        dP = torch.empty_like(P) if "P" in want else None
+        dK = torch.empty_like(K_chi) if "K_chi" in want else None
+        dK2 = torch.empty_like(K_chi2) if "K_chi2" in want else None
+        if stream is None:
+            stream = torch.cuda.current_stream(P.device).cuda_stream
+        ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+        _check(lib().blast_cl_backward(self._h, C.byref(args), C.c_void_p(dC.data_ptr()), ptr(dP), ptr(dK),
+                                       ptr(dK2), C.c_void_p(stream)))
+        return dP, dK, dK2
+
+
+def _make_cl_function():
+    import torch
+
+    class ClFunction(torch.autograd.Function):
+        """C = ClFunction.apply(plan, P, K_chi, K_chi2, n_g, n_s, precision, coef), differentiable in
+        P (nodal values or Chebyshev coefficients) and the two kernel tables through the
+        library's hand-written adjoint."""
+
+        @staticmethod
+        def forward(ctx, plan, P, K_chi, K_chi2, n_g, n_s, precision="fp64", coef=False):
+            P, K_chi, K_chi2 = P.contiguous(), K_chi.contiguous(), K_chi2.contiguous()
+            wdt = torch.float64 if PRECISION.get(precision, precision) == FP64 else torch.float32
+            B = P.shape[0] if P.dim() == 4 else 1
+            w = torch.empty(B * len(plan.chi) * len(plan.R) * plan.rows_pad, dtype=wdt, device=P.device)
+            C = plan.forward(P, K_chi, K_chi2, n_g, n_s, precision=precision, w_save=w, coef=coef)
+            ctx.plan, ctx.args = plan, (n_g, n_s, precision, coef)
+            ctx.save_for_backward(P, K_chi, K_chi2, w)
+            return C if P.dim() == 4 else C[0]
+
+        @staticmethod
+        def backward(ctx, gC):
+            P, K_chi, K_chi2, w = ctx.saved_tensors
+            n_g, n_s, precision, coef = ctx.args
+            squeeze = P.dim() == 3
+            g = gC.unsqueeze(0) if squeeze else gC
+            want = tuple(nm for nm, need in zip(("P", "K_chi", "K_chi2"), ctx.needs_input_grad[1:4]) if need)
+            dP, dK, dK2 = ctx.plan.backward(P, K_chi, K_chi2, n_g, n_s, g.contiguous().double(), precision=precision,
+                                            w_save=w, coef=coef, want=want)
+            if squeeze:
+                dP = dP[0] if dP is not None else None
+                dK = dK[0] if dK is not None else None
+                dK2 = dK2[0] if dK2 is not None else None
+            return None, dP, dK, dK2, None, None, None, None
+
+    return ClFunction
+
+
+_CLF = None
+
+
+def cl_function():
+    """The torch.autograd.Function wrapping forward and adjoint."""
+    global _CLF
+    if _CLF is None:
+        _CLF = _make_cl_function()
+    return _CLF
 
 
 def plan_for_config(cfg, precisions=("fp64",), device=0, **kw):

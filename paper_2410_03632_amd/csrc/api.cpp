@@ -339,6 +339,14 @@ extern "C" blast_status blast_cl_forward(blast_plan *p, const blast_cl_args *a, 
     return blast::forward(p, a, (hipStream_t)stream);
 }
 
+extern "C" blast_status blast_cl_backward(blast_plan *p, const blast_cl_args *a, const double *dC, void *dP,
+                                          double *dK_chi, double *dK_chi2, void *stream) {
+    blast::clear_error();
+    if (!p || !a) return blast::set_error("NULL argument"), BLAST_E_INVALID;
+    DeviceGuard guard(p->device);
+    return blast::backward(p, a, dC, dP, dK_chi, dK_chi2, (hipStream_t)stream);
+}
+
 // --------------------------------------------------------------------------------------------
 // stage timing
 // --------------------------------------------------------------------------------------------

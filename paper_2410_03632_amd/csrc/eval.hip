@@ -286,21 +286,24 @@ __global__ __launch_bounds__(256) void contract_kernel(const typename Cfg<PREC>:
 #pragma unroll
         for (int i = 0; i < kRowTilesPerWave; ++i) rt[i] = pass * 4 * kRowTilesPerWave + w + 4 * i;
 
-        for (int s = 0; s < nsteps; ++s) {
-            const int kof = s * KSTEP + lk * VEC;
+        // basis tiles of step s+1 are in flight while step s runs on the MFMA units
+        auto loadA = [&](int st, U4(&dst)[kRowTilesPerWave], U4(&dstl)[kRowTilesPerWave]) {
+            const int kof = st * KSTEP + lk * VEC;
+#pragma unroll
+            for (int i = 0; i < kRowTilesPerWave; ++i) {
+                const int r = rt[i] < RT ? rt[i] : RT - 1;
+                const size_t off = (size_t)(16 * r + lr) * ncp + kof;
+                dst[i] = *(const U4 *)(brow + off);
+                if (X3) dstl[i] = *(const U4 *)(blo + off);
+            }
+        };
+        auto compute = [&](int st, const U4(&av)[kRowTilesPerWave], const U4(&avl)[kRowTilesPerWave]) {
+            const int kof = st * KSTEP + lk * VEC;
             U4 bv[BTN], bvl[BTN];
 #pragma unroll
             for (int j = 0; j < BTN; ++j) {
                 bv[j] = *(const U4 *)(cs + (size_t)(16 * j + lr) * cst + kof);
                 if (X3) bvl[j] = *(const U4 *)(cls + (size_t)(16 * j + lr) * cst + kof);
-            }
-            U4 av[kRowTilesPerWave], avl[kRowTilesPerWave];
-#pragma unroll
-            for (int i = 0; i < kRowTilesPerWave; ++i) {
-                if (rt[i] >= RT) continue;
-                const size_t off = (size_t)(16 * rt[i] + lr) * ncp + kof;
-                av[i] = *(const U4 *)(brow + off);
-                if (X3) avl[i] = *(const U4 *)(blo + off);
             }
             // consecutive MFMAs target different accumulators
             if constexpr (PREC == BLAST_FP64) {
@@ -359,6 +362,25 @@ __global__ __launch_bounds__(256) void contract_kernel(const typename Cfg<PREC>:
                     }
                 }
             }
+        };
+        U4 a0[kRowTilesPerWave], a0l[kRowTilesPerWave];
+        if constexpr (X3) {
+            // hi and lo tiles together already fill the registers: no second buffer
+            for (int st = 0; st < nsteps; ++st) {
+                loadA(st, a0, a0l);
+                compute(st, a0, a0l);
+            }
+        } else {
+            U4 a1[kRowTilesPerWave], a1l[kRowTilesPerWave];
+            loadA(0, a0, a0l);
+            for (int st = 0; st < nsteps; st += 2) {
+                if (st + 1 < nsteps) loadA(st + 1, a1, a1l);
+                compute(st, a0, a0l);
+                if (st + 1 < nsteps) {
+                    if (st + 2 < nsteps) loadA(st + 2, a0, a0l);
+                    compute(st + 1, a1, a1l);
+                }
+            }
         }
         // epilogue: lane holds rows 16*rt + 4*lk + r for cosmology 16*j + lr
 #pragma unroll
@@ -396,87 +418,78 @@ __global__ __launch_bounds__(256) void contract_kernel(const typename Cfg<PREC>:
 // ---------------------------------------------------------------------------------------------
 // quadrature
 // ---------------------------------------------------------------------------------------------
-// R-quadrature on MFMA: per (chi_a, cosmology) the product Y[row][bin] = sum_b w[b][row] Khat[b][bin]
-// with Khat[b][bin] = wR_b K_bin(R_b chi_a).  M = rows (wave w owns row tiles w, w+4, ...),
-// N = bins (one or two 16-wide tiles), K = b, staged through LDS 16 b at a time with 16-byte
-// loads.  Y layout [beta][row][a][NBP] (contiguous per row for the chi-quadrature).
-template <bool F64, int NBT>
-__global__ __launch_bounds__(256) void quad_y_mfma_kernel(const typename std::conditional<F64, double, float>::type
-                                                              *__restrict__ w,
-                                                          const double *__restrict__ Kchi2,
-                                                          const double *__restrict__ wR, int NP, int nR, int n_chi,
-                                                          int rows_pad, int nbins,
-                                                          typename std::conditional<F64, double, float>::type
-                                                              *__restrict__ Y) {
-    using T = typename std::conditional<F64, double, float>::type;
-    using Acc = typename std::conditional<F64, d4, f4>::type;
-    constexpr int NBP = 16 * NBT;
-    constexpr int RTW = 5;
-    constexpr int BCH = 16;  // b per LDS chunk
+// R-quadrature: Y[beta][row][a][bin] = sum_b wR_b K_bin(R_b chi_a) w[beta][a][b][row].
+// One thread owns V consecutive rows (one 16-byte load of w per b) of one chi_a and all NB
+// (padded) bins; consecutive threads own consecutive row groups, so every load instruction of
+// a wave reads a contiguous 1 KB.  The weighted kernels of the work-group's chi_a values sit in
+// LDS.  Y layout [beta][row][a][NB] (contiguous per row for the chi-quadrature).
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void quad_y_kernel(const T *__restrict__ w, const double *__restrict__ Kchi2,
+                                                     const double *__restrict__ wR, int NP, int nR, int n_chi,
+                                                     int rows_pad, int nbins, T *__restrict__ Y) {
+    constexpr int V = 16 / sizeof(T);
     extern __shared__ __align__(16) unsigned char smem_q[];
-    const int a = blockIdx.x, beta = blockIdx.y;
-    const int nRc = (nR + BCH - 1) / BCH * BCH;
-    T *Kh = (T *)smem_q;                       // [nRc][NBP]
-    T *Ws = Kh + (size_t)nRc * NBP;            // [BCH][rows_pad]
-    for (int i = threadIdx.x; i < nRc * NBP; i += blockDim.x) {
-        const int b = i / NBP, bin = i % NBP;
+    T *Kh = (T *)smem_q;  // [a - a_lo][b][NB]
+    const int RQ = rows_pad / V;
+    const int beta = blockIdx.y;
+    const long g0 = (long)blockIdx.x * blockDim.x;
+    const int a_lo = (int)(g0 / RQ);
+    const int a_hi = min(n_chi - 1, (int)((g0 + blockDim.x - 1) / RQ));
+    const int na = a_hi - a_lo + 1;
+    for (int i = threadIdx.x; i < na * nR * NB; i += blockDim.x) {
+        const int al = i / (nR * NB), b = (i / NB) % nR, bin = i % NB;
         double v = 0.0;
-        if (b < nR && bin < nbins) v = wR[b] * Kchi2[(((size_t)beta * nbins + bin) * n_chi + a) * nR + b];
+        if (bin < nbins) v = wR[b] * Kchi2[(((size_t)beta * nbins + bin) * n_chi + a_lo + al) * nR + b];
         Kh[i] = (T)v;
     }
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int RT = rows_pad >> 4;
-    const T *wa = w + ((size_t)beta * NP + (size_t)a * nR) * rows_pad;
-    constexpr int V = 16 / sizeof(T);
-    for (int pass = 0; pass * 4 * RTW < RT; ++pass) {
-        Acc acc[RTW][NBT];
+    __syncthreads();
+    const long g = g0 + threadIdx.x;
+    const int a = (int)(g / RQ), rq = (int)(g % RQ);
+    if (a >= n_chi) return;
+    const T *kh = Kh + (size_t)(a - a_lo) * nR * NB;
+    const T *wp = w + ((size_t)beta * NP + (size_t)a * nR) * rows_pad + (size_t)rq * V;
+    T acc[V][NB];
 #pragma unroll
-        for (int i = 0; i < RTW; ++i)
+    for (int r = 0; r < V; ++r)
 #pragma unroll
-            for (int j = 0; j < NBT; ++j) acc[i][j] = Acc{0, 0, 0, 0};
-        for (int b0 = 0; b0 < nRc; b0 += BCH) {
-            __syncthreads();
-            const int nvec = BCH * rows_pad / V;
-            for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
-                const int bb = (i * V) / rows_pad, rr = (i * V) % rows_pad;
-                U4 v = {0u, 0u, 0u, 0u};
-                if (b0 + bb < nR) v = *(const U4 *)(wa + (size_t)(b0 + bb) * rows_pad + rr);
-                *(U4 *)(Ws + (size_t)bb * rows_pad + rr) = v;
-            }
-            __syncthreads();
+        for (int q = 0; q < NB; ++q) acc[r][q] = (T)0;
+    constexpr int UB = 4;
+    int b = 0;
+    for (; b + UB <= nR; b += UB) {
+        U4 v[UB];
 #pragma unroll
-            for (int s = 0; s < BCH / 4; ++s) {
-                const int b = 4 * s + lk;
-                T bv[NBT];
+        for (int u = 0; u < UB; ++u) v[u] = *(const U4 *)(wp + (size_t)(b + u) * rows_pad);
 #pragma unroll
-                for (int j = 0; j < NBT; ++j) bv[j] = Kh[(size_t)(b0 + b) * NBP + 16 * j + lr];
+        for (int u = 0; u < UB; ++u) {
+            const T *wv = (const T *)&v[u];
 #pragma unroll
-                for (int i = 0; i < RTW; ++i) {
-                    const int rt = pass * 4 * RTW + wv + 4 * i;
-                    if (rt >= RT) continue;
-                    const T av = Ws[(size_t)b * rows_pad + 16 * rt + lr];
+            for (int q = 0; q < NB; ++q) {
+                const T k = kh[(b + u) * NB + q];
 #pragma unroll
-                    for (int j = 0; j < NBT; ++j) {
-                        if constexpr (F64)
-                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[j], acc[i][j], 0, 0, 0);
-                        else
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[j], acc[i][j], 0, 0, 0);
-                    }
-                }
+                for (int r = 0; r < V; ++r) acc[r][q] += wv[r] * k;
             }
         }
+    }
+    for (; b < nR; ++b) {
+        const U4 v = *(const U4 *)(wp + (size_t)b * rows_pad);
+        const T *wv = (const T *)&v;
 #pragma unroll
-        for (int i = 0; i < RTW; ++i) {
-            const int rt = pass * 4 * RTW + wv + 4 * i;
-            if (rt >= RT) continue;
+        for (int q = 0; q < NB; ++q) {
+            const T k = kh[b * NB + q];
 #pragma unroll
-            for (int j = 0; j < NBT; ++j)
+            for (int r = 0; r < V; ++r) acc[r][q] += wv[r] * k;
+        }
+    }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * rt + (F64 ? lk + 4 * r : 4 * lk + r);
-                    Y[(((size_t)beta * rows_pad + row) * n_chi + a) * NBP + 16 * j + lr] = acc[i][j][r];
-                }
+    for (int r = 0; r < V; ++r) {
+        T *y = Y + (((size_t)beta * rows_pad + (size_t)rq * V + r) * n_chi + a) * NB;
+#pragma unroll
+        for (int q = 0; q < NB; q += 16 / sizeof(T)) {
+            U4 o;
+            T *op = (T *)&o;
+#pragma unroll
+            for (int e = 0; e < (int)(16 / sizeof(T)); ++e) op[e] = acc[r][q + e];
+            *(U4 *)(y + q) = o;
         }
     }
 }
@@ -490,36 +503,40 @@ struct EllSel {
     int16_t idx[kMaxEll];
 };
 
-// chi-quadrature and pair assembly, one work-group per (type slot x output multipole, cosmology):
-//   C[beta][p][io] = N_t(l) sum_a wchi_a chi_a [K_i(chi_a) Y[a][row][j] + K_j(chi_a) Y[a][row][i]]
-// The row's Y[a][bin] and the weighted kernels are staged in LDS; each wave reduces pairs over a.
-template <typename YT>
-__global__ __launch_bounds__(256) void quad_c_row_kernel(const YT *__restrict__ Y, int nbp,
-                                                         const double *__restrict__ Kchi,
-                                                         const double *__restrict__ wchi,
-                                                         const double *__restrict__ chi,
-                                                         const double *__restrict__ pref, int n_chi, int rows_pad,
-                                                         int n_ell, Slots slot_type, int ng, int ns, uint32_t types,
-                                                         int npairs, EllSel sel, double *__restrict__ C) {
-    extern __shared__ double smem_c[];
+// chi-quadrature and pair assembly.  For one cosmology and one basis row (type t, multipole l):
+//   Z[i][j] = sum_a Ktil_i(chi_a) Y[row][a][j],  Ktil_i(chi_a) = wchi_a chi_a K_i(chi_a)
+//   C[p = (i, j)][l] = N_t(l) (Z[i][j] + Z[j][i])                                  (Eq. final_cls)
+// Z is a [bins x n_chi] x [n_chi x bins] product on FP64 MFMA (Ktil from LDS, Y straight from
+// global, 16 consecutive bins per lane group).  Work-group = (type slot x 16 output multipoles,
+// cosmology); wave w handles rows w, w+4, ...
+constexpr int kChiRows = 16;
+
+template <typename YT, int NBT>
+__global__ __launch_bounds__(256) void quad_c_mfma_kernel(const YT *__restrict__ Y, const double *__restrict__ Kchi,
+                                                          const double *__restrict__ wchi,
+                                                          const double *__restrict__ chi,
+                                                          const double *__restrict__ pref, int n_chi, int rows_pad,
+                                                          int n_ell, Slots slot_type, int ng, int ns, uint32_t types,
+                                                          int npairs, EllSel sel, double *__restrict__ C) {
+    constexpr int NBP = 16 * NBT;
+    extern __shared__ __align__(16) double smem_c[];
     const int nbins = ng + ns;
-    double *Ys = smem_c;                         // [nbins][n_chi]
-    double *Ks = smem_c + (size_t)nbins * n_chi; // [nbins][n_chi], weighted
-    const int slot = blockIdx.x / sel.n_out, io = blockIdx.x % sel.n_out;
+    const int nc4 = (n_chi + 3) & ~3;
+    double *Kt = smem_c;                           // [NBP][nc4]
+    double *Zs = smem_c + (size_t)NBP * nc4;       // [4 waves][NBP][NBP]
+    const int nblk = (sel.n_out + kChiRows - 1) / kChiRows;
+    const int slot = blockIdx.x / nblk, io0 = (blockIdx.x % nblk) * kChiRows;
     const int beta = blockIdx.y;
     const int t = slot_type.s[slot];
     if (!(t & types)) return;
-    const int row = slot * n_ell + sel.idx[io];
-    for (int i = threadIdx.x; i < nbins * n_chi; i += blockDim.x) {
-        const int a = i / nbins, bin = i % nbins;
-        Ys[bin * n_chi + a] = (double)Y[(((size_t)beta * rows_pad + row) * n_chi + a) * nbp + bin];
-        const int bin2 = i / n_chi, a2 = i % n_chi;
-        Ks[bin2 * n_chi + a2] = wchi[a2] * chi[a2] * Kchi[((size_t)beta * nbins + bin2) * n_chi + a2];
+    for (int i = threadIdx.x; i < NBP * nc4; i += blockDim.x) {
+        const int bin = i / nc4, a = i % nc4;
+        Kt[i] = (bin < nbins && a < n_chi) ? wchi[a] * chi[a] * Kchi[((size_t)beta * nbins + bin) * n_chi + a] : 0.0;
     }
     __syncthreads();
-    // pairs of this type and their position in the output
-    int off = 0, ntp, ni, nj;
+    int off, ntp;
     if (t == BLAST_GG) {
+        off = 0;
         ntp = ng * (ng + 1) / 2;
     } else if (t == BLAST_GS) {
         off = (types & BLAST_GG) ? ng * (ng + 1) / 2 : 0;
@@ -528,61 +545,383 @@ __global__ __launch_bounds__(256) void quad_c_row_kernel(const YT *__restrict__ 
         off = ((types & BLAST_GG) ? ng * (ng + 1) / 2 : 0) + ((types & BLAST_GS) ? ng * ns : 0);
         ntp = ns * (ns + 1) / 2;
     }
-    (void)ni;
-    (void)nj;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const double pf = pref[row];
-    for (int q = wv; q < ntp; q += 4) {
-        int i, j;
-        if (t == BLAST_GS) {
-            i = q / ns;
-            j = ng + q % ns;
-        } else {
-            const int n = t == BLAST_GG ? ng : ns, base = t == BLAST_GG ? 0 : ng;
-            int r = 0, p = q;
-            while (p >= n - r) {
-                p -= n - r;
-                ++r;
+    const int lr = lane & 15, lk = lane >> 4;
+    double *Z = Zs + (size_t)wv * NBP * NBP;
+    for (int io = io0 + wv; io < min(io0 + kChiRows, sel.n_out); io += 4) {
+        const int row = slot * n_ell + sel.idx[io];
+        const YT *yr = Y + ((size_t)beta * rows_pad + row) * n_chi * NBP;
+        d4 acc[NBT][NBT];
+#pragma unroll
+        for (int i = 0; i < NBT; ++i)
+#pragma unroll
+            for (int j = 0; j < NBT; ++j) acc[i][j] = d4{0, 0, 0, 0};
+        // full blocks of KB K-steps: all loads first (clamped addresses, masked values), then MFMAs
+        constexpr int KB = 16;
+        const int nsteps = nc4 / 4;
+        auto kstep = [&](int st, const double(&b)[NBT]) {
+            const int a = 4 * st + lk;
+            double av[NBT];
+#pragma unroll
+            for (int i = 0; i < NBT; ++i) av[i] = Kt[(size_t)(16 * i + lr) * nc4 + a];
+#pragma unroll
+            for (int i = 0; i < NBT; ++i)
+#pragma unroll
+                for (int j = 0; j < NBT; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], b[j], acc[i][j], 0, 0, 0);
+        };
+        auto loadB = [&](int st, double(&b)[NBT]) {
+            const int a = 4 * st + lk;
+            const int ac = a < n_chi ? a : n_chi - 1;
+#pragma unroll
+            for (int i = 0; i < NBT; ++i) {
+                const double v = (double)yr[(size_t)ac * NBP + 16 * i + lr];
+                b[i] = a < n_chi ? v : 0.0;
             }
-            i = base + r;
-            j = base + r + p;
+        };
+        int s0 = 0;
+        for (; s0 + KB <= nsteps; s0 += KB) {
+            double bv[KB][NBT];
+#pragma unroll
+            for (int u = 0; u < KB; ++u) loadB(s0 + u, bv[u]);
+#pragma unroll
+            for (int u = 0; u < KB; ++u) kstep(s0 + u, bv[u]);
         }
-        double acc = 0.0;
-        for (int a = lane; a < n_chi; a += 64)
-            acc += Ks[i * n_chi + a] * Ys[j * n_chi + a] + Ks[j * n_chi + a] * Ys[i * n_chi + a];
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) C[((size_t)beta * npairs + off + q) * sel.n_out + io] = pf * acc;
+        for (; s0 < nsteps; ++s0) {
+            double bv[NBT];
+            loadB(s0, bv);
+            kstep(s0, bv);
+        }
+        // D layout of f64 16x16: Z[i = 16*ti + lk + 4r][j = 16*tj + lr]
+#pragma unroll
+        for (int i = 0; i < NBT; ++i)
+#pragma unroll
+            for (int j = 0; j < NBT; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Z[(16 * i + lk + 4 * r) * NBP + 16 * j + lr] = acc[i][j][r];
+        // Z is private to this wave: a fence orders its LDS writes before the reads of other lanes
+        __threadfence_block();
+        const double pf = pref[row];
+        for (int q = lane; q < ntp; q += 64) {
+            int i, j;
+            if (t == BLAST_GS) {
+                i = q / ns;
+                j = ng + q % ns;
+            } else {
+                const int n = t == BLAST_GG ? ng : ns, base = t == BLAST_GG ? 0 : ng;
+                int r = 0, pp = q;
+                while (pp >= n - r) {
+                    pp -= n - r;
+                    ++r;
+                }
+                i = base + r;
+                j = base + r + pp;
+            }
+            C[((size_t)beta * npairs + off + q) * sel.n_out + io] = pf * (Z[i * NBP + j] + Z[j * NBP + i]);
+        }
+        __threadfence_block();
     }
 }
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
-struct Layout {
-    size_t c, clo, w, y, total;
+// ---------------------------------------------------------------------------------------------
+// coefficient input (P given as the c_n of Eq. cheb_pk instead of nodal values)
+// ---------------------------------------------------------------------------------------------
+template <typename PT, int OUT>
+__global__ __launch_bounds__(256) void coef_in_kernel(const PT *__restrict__ cin, int N, int ncp, long nrows,
+                                                      void *__restrict__ c_out, uint16_t *__restrict__ c_lo) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows * ncp) return;
+    const long row = i / ncp;
+    const int n = (int)(i % ncp);
+    const double v = n < N ? (double)cin[row * N + n] : 0.0;
+    if (OUT == 0) {
+        ((double *)c_out)[i] = v;
+    } else if (OUT == 1) {
+        ((float *)c_out)[i] = (float)v;
+    } else {
+        const float f = (float)v;
+        const uint16_t h = bf16_rne(f);
+        ((uint16_t *)c_out)[i] = h;
+        if (c_lo) c_lo[i] = bf16_rne(f - bf16_val(h));
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// adjoint kernels (FP64 or FP32 arithmetic T; small reductions in FP64)
+// ---------------------------------------------------------------------------------------------
+struct EllInv {
+    int16_t io[kMaxEll];  // output position of each plan multipole, -1 if not requested
 };
 
-Layout layout_of(const blast_plan *p, int batch, int prec, int nbins, bool need_w) {
+// dY[beta][row][a][m] = sum_l S[m][l] Ktil_l(chi_a), with S the symmetric matrix of pair
+// cotangents of this row: S[i][j] = S[j][i] = N_t(l) dC[p=(i,j)] (2 N_t dC on the diagonal).
+// S is also stored for the kernel gradient.  Rows that are not part of the output get zeros.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void adj_dy_kernel(const double *__restrict__ dC, const double *__restrict__ Kchi,
+                                                     const double *__restrict__ wchi, const double *__restrict__ chi,
+                                                     const double *__restrict__ pref, int n_chi, int rows_pad,
+                                                     int n_ell, Slots slot_type, int ng, int ns, uint32_t types,
+                                                     int npairs, int n_out, EllInv inv, T *__restrict__ dY,
+                                                     double *__restrict__ Sg) {
+    __shared__ double S[NB][NB];
+    const int row = blockIdx.x, beta = blockIdx.y;
+    const int slot = row / n_ell, il = row % n_ell;
+    const int t = slot_type.s[slot];
+    const int io = inv.io[il];
+    const bool active = (t & types) && io >= 0;
+    const int nbins = ng + ns;
+    for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) S[i / NB][i % NB] = 0.0;
+    __syncthreads();
+    if (active) {
+        int off, ntp;
+        if (t == BLAST_GG) {
+            off = 0;
+            ntp = ng * (ng + 1) / 2;
+        } else if (t == BLAST_GS) {
+            off = (types & BLAST_GG) ? ng * (ng + 1) / 2 : 0;
+            ntp = ng * ns;
+        } else {
+            off = ((types & BLAST_GG) ? ng * (ng + 1) / 2 : 0) + ((types & BLAST_GS) ? ng * ns : 0);
+            ntp = ns * (ns + 1) / 2;
+        }
+        const double pf = pref[row];
+        for (int q = threadIdx.x; q < ntp; q += blockDim.x) {
+            int i, j;
+            if (t == BLAST_GS) {
+                i = q / ns;
+                j = ng + q % ns;
+            } else {
+                const int n = t == BLAST_GG ? ng : ns, base = t == BLAST_GG ? 0 : ng;
+                int r = 0, pp = q;
+                while (pp >= n - r) {
+                    pp -= n - r;
+                    ++r;
+                }
+                i = base + r;
+                j = base + r + pp;
+            }
+            const double g = pf * dC[((size_t)beta * npairs + off + q) * n_out + io];
+            if (i == j) {
+                S[i][i] = 2.0 * g;
+            } else {
+                S[i][j] = g;
+                S[j][i] = g;
+            }
+        }
+    }
+    __syncthreads();
+    double *sg = Sg + ((size_t)beta * rows_pad + row) * NB * NB;
+    for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) sg[i] = S[i / NB][i % NB];
+    T *dy = dY + ((size_t)beta * rows_pad + row) * n_chi * NB;
+    const double *Kb = Kchi + (size_t)beta * nbins * n_chi;
+    for (int i = threadIdx.x; i < n_chi * NB; i += blockDim.x) {
+        const int a = i / NB, m = i % NB;
+        double v = 0.0;
+        if (active && m < nbins) {
+            const double wa = wchi[a] * chi[a];
+            for (int l = 0; l < nbins; ++l) v += S[m][l] * wa * Kb[(size_t)l * n_chi + a];
+        }
+        dy[i] = (T)v;
+    }
+}
+
+// dK_chi[beta][l][a] = wchi_a chi_a sum_{row, m} S[row][m][l] Y[row][a][m]
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void adj_kchi_kernel(const T *__restrict__ Y, const double *__restrict__ Sg,
+                                                       const double *__restrict__ wchi,
+                                                       const double *__restrict__ chi, int n_chi, int rows,
+                                                       int rows_pad, int nbins, double *__restrict__ dK) {
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int beta = blockIdx.y;
+    if (gid >= (long)nbins * n_chi) return;
+    const int l = (int)(gid / n_chi), a = (int)(gid % n_chi);
+    double acc = 0.0;
+    for (int row = 0; row < rows; ++row) {
+        const double *sg = Sg + ((size_t)beta * rows_pad + row) * NB * NB;
+        const T *y = Y + (((size_t)beta * rows_pad + row) * n_chi + a) * NB;
+        for (int m = 0; m < nbins; ++m) acc += sg[m * NB + l] * (double)y[m];
+    }
+    dK[((size_t)beta * nbins + l) * n_chi + a] = wchi[a] * chi[a] * acc;
+}
+
+// per (chi_a, cosmology):  dw[b][row] = wR_b sum_m K2_m(a, b) dY[row][a][m]
+//                          dK2[m][a][b] = wR_b sum_row dY[row][a][m] w[b][row]
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void adj_w_kernel(const T *__restrict__ dY, const T *__restrict__ w,
+                                                    const double *__restrict__ Kchi2, const double *__restrict__ wR,
+                                                    int NP, int nR, int n_chi, int rows, int rows_pad, int nbins,
+                                                    T *__restrict__ dw, double *__restrict__ dK2) {
+    extern __shared__ __align__(16) unsigned char smem_a[];
+    double *Kh = (double *)smem_a;                   // [nR][NB]
+    double *dYa = Kh + (size_t)nR * NB;              // [rows_pad][NB]
+    const int a = blockIdx.x, beta = blockIdx.y;
+    for (int i = threadIdx.x; i < nR * NB; i += blockDim.x) {
+        const int b = i / NB, m = i % NB;
+        Kh[i] = m < nbins ? wR[b] * Kchi2[(((size_t)beta * nbins + m) * n_chi + a) * nR + b] : 0.0;
+    }
+    for (int i = threadIdx.x; i < rows_pad * NB; i += blockDim.x) {
+        const int row = i / NB, m = i % NB;
+        dYa[i] = row < rows ? (double)dY[(((size_t)beta * rows_pad + row) * n_chi + a) * NB + m] : 0.0;
+    }
+    __syncthreads();
+    const size_t base = ((size_t)beta * NP + (size_t)a * nR) * rows_pad;
+    for (int i = threadIdx.x; i < nR * rows_pad; i += blockDim.x) {
+        const int b = i / rows_pad, row = i % rows_pad;
+        double v = 0.0;
+#pragma unroll
+        for (int m = 0; m < NB; ++m) v += Kh[b * NB + m] * dYa[row * NB + m];
+        dw[base + i] = (T)v;
+    }
+    if (dK2) {
+        for (int i = threadIdx.x; i < nR * NB; i += blockDim.x) {
+            const int b = i / NB, m = i % NB;
+            if (m >= nbins) continue;
+            const T *wr = w + base + (size_t)b * rows_pad;
+            double v = 0.0;
+            for (int row = 0; row < rows; ++row) v += dYa[row * NB + m] * (double)wr[row];
+            dK2[(((size_t)beta * nbins + m) * n_chi + a) * nR + b] = wR[b] * v;
+        }
+    }
+}
+
+// transpose contraction: dc[beta][ab][n] = sum_row Ttilde[ab][row][n] dw[beta][ab][row]
+// M = n (wave w owns n tiles w, w+4), N = cosmologies (BT), K = rows, on MFMA.
+template <bool F64>
+__global__ __launch_bounds__(256) void contract_t_kernel(const typename std::conditional<F64, double, float>::type
+                                                             *__restrict__ basis,
+                                                         const typename std::conditional<F64, double, float>::type
+                                                             *__restrict__ dw,
+                                                         int batch, int NP, int rows_pad, int ncp,
+                                                         typename std::conditional<F64, double, float>::type
+                                                             *__restrict__ dc) {
+    using T = typename std::conditional<F64, double, float>::type;
+    using Acc = typename std::conditional<F64, d4, f4>::type;
+    constexpr int BT = F64 ? 32 : 64, BTN = BT / 16;
+    extern __shared__ __align__(16) unsigned char smem_t[];
+    const int dst = rows_pad + 1;
+    T *ws = (T *)smem_t;  // [BT][rows_pad + 1]
+    const int ab = blockIdx.x, beta0 = blockIdx.y * BT;
+    const int nb = min(BT, batch - beta0);
+    for (int i = threadIdx.x; i < BT * rows_pad; i += blockDim.x) {
+        const int bb = i / rows_pad, row = i % rows_pad;
+        ws[bb * dst + row] = bb < nb ? dw[((size_t)(beta0 + bb) * NP + ab) * rows_pad + row] : (T)0;
+    }
+    __syncthreads();
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int NT = ncp >> 4;
+    const T *bp = basis + (size_t)ab * rows_pad * ncp;
+    Acc acc[2][BTN];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < BTN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+    for (int st = 0; st < rows_pad / 4; ++st) {
+        const int row = 4 * st + lk;
+        T av[2], bv[BTN];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int nt = wv + 4 * i;
+            av[i] = nt < NT ? bp[(size_t)row * ncp + 16 * nt + lr] : (T)0;
+        }
+#pragma unroll
+        for (int j = 0; j < BTN; ++j) bv[j] = ws[(16 * j + lr) * dst + row];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < BTN; ++j) {
+                if constexpr (F64)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+                else
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int nt = wv + 4 * i;
+        if (nt >= NT) continue;
+#pragma unroll
+        for (int j = 0; j < BTN; ++j) {
+            const int bb = 16 * j + lr;
+            if (bb >= nb) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * nt + (F64 ? lk + 4 * r : 4 * lk + r);
+                dc[((size_t)(beta0 + bb) * NP + ab) * ncp + n] = acc[i][j][r];
+            }
+        }
+    }
+}
+
+// dP[row][j] = sum_{n < N} D[n][j] dc[row][n] (nodal input) or dP[row][n] = dc[row][n]
+// (coefficient input), written in P's dtype.
+template <typename T, typename PT>
+__global__ __launch_bounds__(256) void adj_project_kernel(const T *__restrict__ dc, const double *__restrict__ Dn,
+                                                          int N, int ncp, long nrows, int coef, PT *__restrict__ dP) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows * N) return;
+    const long row = i / N;
+    const int j = (int)(i % N);
+    const T *c = dc + row * ncp;
+    double v;
+    if (coef) {
+        v = (double)c[j];
+    } else {
+        v = 0.0;
+        for (int n = 0; n < N; ++n) v += Dn[(size_t)n * N + j] * (double)c[n];
+    }
+    dP[i] = (PT)v;
+}
+
+// ---------------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------------
+struct Ctx {
+    int prec, ng, ns, nbins, npairs, nbp;
+    EllSel sel;
+    EllInv inv;
+};
+
+struct Layout {
+    size_t c, clo, w, y, dy, sg, dw, dc, total;
+};
+
+Layout layout_of(const blast_plan *p, int batch, int prec, int nbins, bool need_w, bool adjoint) {
     Layout L{};
     const size_t nc = (size_t)batch * p->NP * p->nc_pad;
     const size_t ce = prec == BLAST_FP64 ? 8 : (prec == BLAST_FP32 ? 4 : 2);
+    const size_t te = prec == BLAST_FP64 ? 8 : 4;
+    const int nbp = nbins <= 16 ? 16 : 32;
+    const size_t ny = (size_t)batch * p->n_chi * p->rows_pad * nbp;
     size_t off = 0;
     L.c = off;
     off += align256(nc * ce);
     L.clo = off;
     if (prec == BLAST_BF16X3) off += align256(nc * 2);
     L.w = off;
-    if (need_w) off += align256((size_t)batch * p->NP * p->rows_pad * (prec == BLAST_FP64 ? 8 : 4));
+    if (need_w) off += align256((size_t)batch * p->NP * p->rows_pad * te);
     L.y = off;
-    const int nbp = nbins <= 16 ? 16 : 32;
-    off += align256((size_t)batch * p->n_chi * p->rows_pad * nbp * (prec == BLAST_FP64 ? 8 : 4));
+    off += align256(ny * te);
+    if (adjoint) {
+        L.dy = off;
+        off += align256(ny * te);
+        L.sg = off;
+        off += align256((size_t)batch * p->rows_pad * nbp * nbp * 8);
+        L.dw = off;
+        off += align256((size_t)batch * p->NP * p->rows_pad * te);
+        L.dc = off;
+        off += align256(nc * te);
+    }
     L.total = off;
     return L;
 }
 
-}  // namespace
-
-size_t workspace_bytes(const blast_plan *p, int batch, int prec, int n_bins) {
-    return layout_of(p, batch, prec, n_bins, true).total;
+size_t workspace_bytes_impl(const blast_plan *p, int batch, int prec, int n_bins) {
+    const size_t f = layout_of(p, batch, prec, n_bins, true, false).total;
+    const size_t b = prec <= BLAST_FP32 ? layout_of(p, batch, prec, n_bins, true, true).total : 0;
+    return f > b ? f : b;
 }
 
 static int npairs_of(int ng, int ns, uint32_t types) {
@@ -603,8 +942,13 @@ hipError_t allow_large_lds() {
         const void *fns[] = {
             (const void *)project_mfma_kernel<float, false, 1>, (const void *)project_mfma_kernel<float, false, 2>,
             (const void *)project_mfma_kernel<double, false, 1>, (const void *)project_mfma_kernel<double, false, 2>,
-            (const void *)quad_y_mfma_kernel<true, 1>, (const void *)quad_y_mfma_kernel<true, 2>,
-            (const void *)quad_y_mfma_kernel<false, 1>, (const void *)quad_y_mfma_kernel<false, 2>,
+            (const void *)quad_y_kernel<double, 16>, (const void *)quad_y_kernel<double, 32>,
+            (const void *)quad_y_kernel<float, 16>, (const void *)quad_y_kernel<float, 32>,
+            (const void *)quad_c_mfma_kernel<double, 1>, (const void *)quad_c_mfma_kernel<double, 2>,
+            (const void *)quad_c_mfma_kernel<float, 1>, (const void *)quad_c_mfma_kernel<float, 2>,
+            (const void *)adj_w_kernel<double, 16>, (const void *)adj_w_kernel<double, 32>,
+            (const void *)adj_w_kernel<float, 16>, (const void *)adj_w_kernel<float, 32>,
+            (const void *)contract_t_kernel<true>, (const void *)contract_t_kernel<false>,
         };
         for (const void *f : fns) {
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
@@ -614,163 +958,217 @@ hipError_t allow_large_lds() {
     return err;
 }
 
-template <typename Mark>
-blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, Mark &mark) {
+blast_status check_args(const blast_plan *p, const blast_cl_args *a, Ctx &x) {
     if (a->batch < 1) return set_error("batch must be >= 1"), BLAST_E_INVALID;
     if (a->precision < 0 || a->precision > 3) return set_error("unknown precision %d", a->precision), BLAST_E_INVALID;
-    const int prec = a->precision;
+    x.prec = a->precision;
+    const int prec = x.prec;
     const bool resident = (prec == BLAST_FP64 && p->basis.f64) || (prec == BLAST_FP32 && p->basis.f32) ||
                           (prec == BLAST_BF16 && p->basis.hi) || (prec == BLAST_BF16X3 && p->basis.lo);
     if (!resident) return set_error("precision %d is not resident in this plan", prec), BLAST_E_INVALID;
     if (a->p_dtype != 0 && a->p_dtype != 1) return set_error("p_dtype must be 0 (FP64) or 1 (FP32)"), BLAST_E_INVALID;
-    if (!a->P || !a->K_chi || !a->K_chi2 || !a->C) return set_error("P, K_chi, K_chi2 and C are required"), BLAST_E_INVALID;
-    const int ng = a->n_g, ns = a->n_s, nbins = ng + ns;
-    if (ng < 0 || ns < 0 || nbins < 1 || nbins > kMaxBins)
+    if (a->p_kind != 0 && a->p_kind != 1) return set_error("p_kind must be 0 (nodal) or 1 (coefficients)"), BLAST_E_INVALID;
+    if (!a->P || !a->K_chi || !a->K_chi2) return set_error("P, K_chi and K_chi2 are required"), BLAST_E_INVALID;
+    x.ng = a->n_g;
+    x.ns = a->n_s;
+    x.nbins = x.ng + x.ns;
+    if (x.ng < 0 || x.ns < 0 || x.nbins < 1 || x.nbins > kMaxBins)
         return set_error("need n_g, n_s >= 0 and 1 <= n_g + n_s <= %d", kMaxBins), BLAST_E_INVALID;
+    x.nbp = x.nbins <= 16 ? 16 : 32;
     if (a->types == 0 || (a->types & ~p->types))
         return set_error("types 0x%x not a non-empty subset of the plan's 0x%x", a->types, p->types), BLAST_E_INVALID;
-    const int npairs = npairs_of(ng, ns, a->types);
-    if (npairs < 1) return set_error("no bin pairs for these types and bins"), BLAST_E_INVALID;
-    EllSel sel{};
+    x.npairs = npairs_of(x.ng, x.ns, a->types);
+    if (x.npairs < 1) return set_error("no bin pairs for these types and bins"), BLAST_E_INVALID;
+    x.sel = EllSel{};
+    for (int i = 0; i < kMaxEll; ++i) x.inv.io[i] = -1;
     if (a->n_ell_out == 0) {
-        sel.n_out = p->n_ell;
-        for (int i = 0; i < p->n_ell; ++i) sel.idx[i] = (int16_t)i;
+        x.sel.n_out = p->n_ell;
+        for (int i = 0; i < p->n_ell; ++i) x.sel.idx[i] = (int16_t)i;
     } else {
         if (a->n_ell_out < 0 || a->n_ell_out > p->n_ell || !a->ell_idx)
             return set_error("bad n_ell_out / ell_idx"), BLAST_E_INVALID;
-        sel.n_out = a->n_ell_out;
+        x.sel.n_out = a->n_ell_out;
         for (int i = 0; i < a->n_ell_out; ++i) {
             const int v = a->ell_idx[i];
             if (v < 0 || v >= p->n_ell || (i && v <= a->ell_idx[i - 1]))
                 return set_error("ell_idx must be increasing indices into the plan's ell"), BLAST_E_INVALID;
-            sel.idx[i] = (int16_t)v;
+            x.sel.idx[i] = (int16_t)v;
         }
     }
-    if ((size_t)nbins * p->n_chi * 2 * sizeof(double) > 64 * 1024)
-        return set_error("(n_g + n_s) * n_chi must be <= 4096"), BLAST_E_UNSUPPORTED;
+    for (int i = 0; i < x.sel.n_out; ++i) x.inv.io[x.sel.idx[i]] = (int16_t)i;
+    if (((size_t)x.nbp * (p->n_chi + 4) + 4 * 32 * 32) * sizeof(double) > 160 * 1024)
+        return set_error("n_chi too large for the chi-quadrature tile"), BLAST_E_UNSUPPORTED;
+    if ((size_t)(256 / (p->rows_pad / 4) + 2) * p->n_R * x.nbp * 8 > 160 * 1024)
+        return set_error("n_R too large for the R-quadrature tile"), BLAST_E_UNSUPPORTED;
+    return BLAST_OK;
+}
 
-    BLAST_HIP_TRY(allow_large_lds());
-    const bool need_w = a->w_save == nullptr;
-    Layout L = layout_of(p, a->batch, prec, nbins, need_w);
-    unsigned char *ws = (unsigned char *)a->workspace;
-    if (ws) {
-        if (a->workspace_bytes < L.total)
-            return set_error("workspace of %zu bytes is smaller than the %zu needed", a->workspace_bytes, L.total),
-                   BLAST_E_INVALID;
-    } else {
-        std::lock_guard<std::mutex> lk(p->mu);
-        if (p->scratch_bytes < L.total) {
-            (void)hipDeviceSynchronize();
-            if (p->scratch) (void)hipFree(p->scratch);
-            p->scratch = nullptr;
-            p->scratch_bytes = 0;
-            hipError_t e = hipMalloc(&p->scratch, L.total);
-            if (e != hipSuccess) {
-                p->scratch = nullptr;
-                return set_error("plan scratch of %zu bytes: %s", L.total, hipGetErrorString(e)), BLAST_E_OOM;
-            }
-            p->scratch_bytes = L.total;
+unsigned char *get_workspace(blast_plan *p, const blast_cl_args *a, size_t need, blast_status &st) {
+    st = BLAST_OK;
+    if (a->workspace) {
+        if (a->workspace_bytes < need) {
+            set_error("workspace of %zu bytes is smaller than the %zu needed", a->workspace_bytes, need);
+            st = BLAST_E_INVALID;
+            return nullptr;
         }
-        ws = (unsigned char *)p->scratch;
+        return (unsigned char *)a->workspace;
     }
-    void *c = ws + L.c;
-    uint16_t *clo = prec == BLAST_BF16X3 ? (uint16_t *)(ws + L.clo) : nullptr;
-    void *w = need_w ? (void *)(ws + L.w) : a->w_save;
-    void *Y = ws + L.y;
-    const int nbp = nbins <= 16 ? 16 : 32;
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->scratch_bytes < need) {
+        (void)hipDeviceSynchronize();
+        if (p->scratch) (void)hipFree(p->scratch);
+        p->scratch = nullptr;
+        p->scratch_bytes = 0;
+        hipError_t e = hipMalloc(&p->scratch, need);
+        if (e != hipSuccess) {
+            p->scratch = nullptr;
+            set_error("plan scratch of %zu bytes: %s", need, hipGetErrorString(e));
+            st = BLAST_E_OOM;
+            return nullptr;
+        }
+        p->scratch_bytes = need;
+    }
+    return (unsigned char *)p->scratch;
+}
+
+// stage 1: P (nodal values or coefficients) -> c in the contraction's layout
+void stage_project(blast_plan *p, const blast_cl_args *a, const Ctx &x, void *c, uint16_t *clo, hipStream_t s) {
+    const int prec = x.prec;
     const long nrows = (long)a->batch * p->NP;
     const int N = p->n_cheb, ncp = p->nc_pad;
-
-    // 1. projection
-    mark(0);
-    {
-        const bool f64 = prec == BLAST_FP64;
-        const bool p64 = a->p_dtype == 0;
-        const int out = f64 ? 0 : (prec == BLAST_FP32 ? 1 : 2);
-        if (N % (f64 ? 8 : 16) == 0) {
-            dim3 grid((unsigned)((nrows + 255) / 256));
-            const size_t shp = f64 ? 0 : (size_t)ncp * (N + 4) * sizeof(float);
+    const bool f64 = prec == BLAST_FP64;
+    const bool p64 = a->p_dtype == 0;
+    const int out = f64 ? 0 : (prec == BLAST_FP32 ? 1 : 2);
+    if (a->p_kind == 1) {
+        dim3 grid((unsigned)((nrows * ncp + 255) / 256));
+#define BLAST_CI(PT, O) \
+    hipLaunchKernelGGL((coef_in_kernel<PT, O>), grid, dim3(256), 0, s, (const PT *)a->P, N, ncp, nrows, c, clo)
+        if (p64 && out == 0) BLAST_CI(double, 0);
+        if (p64 && out == 1) BLAST_CI(double, 1);
+        if (p64 && out == 2) BLAST_CI(double, 2);
+        if (!p64 && out == 0) BLAST_CI(float, 0);
+        if (!p64 && out == 1) BLAST_CI(float, 1);
+        if (!p64 && out == 2) BLAST_CI(float, 2);
+#undef BLAST_CI
+        return;
+    }
+    if (N % (f64 ? 8 : 16) == 0) {
+        dim3 grid((unsigned)((nrows + 255) / 256));
+        const size_t shp = f64 ? 0 : (size_t)ncp * (N + 4) * sizeof(float);
 #define BLAST_PROJ(PT, F, O, D)                                                                                  \
     hipLaunchKernelGGL((project_mfma_kernel<PT, F, O>), grid, dim3(256), shp, s, (const PT *)a->P, D, N, ncp, nrows, \
                        c, clo)
-            if (f64 && p64) BLAST_PROJ(double, true, 0, p->d_dctn64);
-            if (f64 && !p64) BLAST_PROJ(float, true, 0, p->d_dctn64);
-            if (!f64 && p64 && out == 1) BLAST_PROJ(double, false, 1, p->d_dctn32);
-            if (!f64 && p64 && out == 2) BLAST_PROJ(double, false, 2, p->d_dctn32);
-            if (!f64 && !p64 && out == 1) BLAST_PROJ(float, false, 1, p->d_dctn32);
-            if (!f64 && !p64 && out == 2) BLAST_PROJ(float, false, 2, p->d_dctn32);
+        if (f64 && p64) BLAST_PROJ(double, true, 0, p->d_dctn64);
+        if (f64 && !p64) BLAST_PROJ(float, true, 0, p->d_dctn64);
+        if (!f64 && p64 && out == 1) BLAST_PROJ(double, false, 1, p->d_dctn32);
+        if (!f64 && p64 && out == 2) BLAST_PROJ(double, false, 2, p->d_dctn32);
+        if (!f64 && !p64 && out == 1) BLAST_PROJ(float, false, 1, p->d_dctn32);
+        if (!f64 && !p64 && out == 2) BLAST_PROJ(float, false, 2, p->d_dctn32);
 #undef BLAST_PROJ
-        } else {
-            dim3 grid((unsigned)((nrows + kProjRows - 1) / kProjRows));
+    } else {
+        dim3 grid((unsigned)((nrows + kProjRows - 1) / kProjRows));
 #define BLAST_PROJ(PT, AT, O, D) \
     hipLaunchKernelGGL((project_kernel<PT, AT, O>), grid, dim3(256), 0, s, (const PT *)a->P, D, N, ncp, nrows, c, clo)
-            if (f64 && p64) BLAST_PROJ(double, double, 0, p->d_dct64);
-            if (f64 && !p64) BLAST_PROJ(float, double, 0, p->d_dct64);
-            if (!f64 && p64 && out == 1) BLAST_PROJ(double, float, 1, p->d_dct32);
-            if (!f64 && p64 && out == 2) BLAST_PROJ(double, float, 2, p->d_dct32);
-            if (!f64 && !p64 && out == 1) BLAST_PROJ(float, float, 1, p->d_dct32);
-            if (!f64 && !p64 && out == 2) BLAST_PROJ(float, float, 2, p->d_dct32);
+        if (f64 && p64) BLAST_PROJ(double, double, 0, p->d_dct64);
+        if (f64 && !p64) BLAST_PROJ(float, double, 0, p->d_dct64);
+        if (!f64 && p64 && out == 1) BLAST_PROJ(double, float, 1, p->d_dct32);
+        if (!f64 && p64 && out == 2) BLAST_PROJ(double, float, 2, p->d_dct32);
+        if (!f64 && !p64 && out == 1) BLAST_PROJ(float, float, 1, p->d_dct32);
+        if (!f64 && !p64 && out == 2) BLAST_PROJ(float, float, 2, p->d_dct32);
 #undef BLAST_PROJ
-        }
     }
-    // 2. contraction
+}
+
+// stage 2: w = Ttilde c
+void stage_contract(blast_plan *p, const blast_cl_args *a, const Ctx &x, const void *c, const uint16_t *clo, void *w,
+                    hipStream_t s) {
+    const int ncp = p->nc_pad;
+    auto launch = [&](auto tag) {
+        constexpr int PR = decltype(tag)::value;
+        using E = typename Cfg<PR>::E;
+        const int BT = Cfg<PR>::BT;
+        const size_t cst = ncp + 16 / sizeof(E);
+        const size_t sh = (size_t)BT * cst * sizeof(E) + (PR == BLAST_BF16X3 ? (size_t)BT * cst * 2 : 0);
+        dim3 grid(p->NP, (a->batch + BT - 1) / BT);
+        const E *bas = PR == BLAST_FP64 ? (const E *)p->basis.f64
+                                        : (PR == BLAST_FP32 ? (const E *)p->basis.f32 : (const E *)p->basis.hi);
+        hipLaunchKernelGGL((contract_kernel<PR>), grid, dim3(256), sh, s, bas, p->basis.lo, p->basis.scale,
+                           (const E *)c, clo, a->batch, p->NP, p->rows_pad, ncp, w);
+    };
+    if (x.prec == BLAST_FP64) launch(std::integral_constant<int, BLAST_FP64>());
+    if (x.prec == BLAST_FP32) launch(std::integral_constant<int, BLAST_FP32>());
+    if (x.prec == BLAST_BF16) launch(std::integral_constant<int, BLAST_BF16>());
+    if (x.prec == BLAST_BF16X3) launch(std::integral_constant<int, BLAST_BF16X3>());
+}
+
+// stage 3: Y = R-quadrature of w
+void stage_quad_y(blast_plan *p, const blast_cl_args *a, const Ctx &x, const void *w, void *Y, hipStream_t s) {
+    const bool f64 = x.prec == BLAST_FP64;
+    const int rq = p->rows_pad / (f64 ? 2 : 4);
+    const long total = (long)p->n_chi * rq;
+    dim3 gq((unsigned)((total + 255) / 256), a->batch);
+    const int na_max = 256 / rq + 2;
+#define BLAST_QY(T, NB)                                                                                      \
+    hipLaunchKernelGGL((quad_y_kernel<T, NB>), gq, dim3(256), (size_t)na_max * p->n_R * NB * sizeof(T), s, \
+                       (const T *)w, a->K_chi2, p->d_wR, p->NP, p->n_R, p->n_chi, p->rows_pad, x.nbins, (T *)Y)
+    if (f64 && x.nbp == 16) BLAST_QY(double, 16);
+    if (f64 && x.nbp == 32) BLAST_QY(double, 32);
+    if (!f64 && x.nbp == 16) BLAST_QY(float, 16);
+    if (!f64 && x.nbp == 32) BLAST_QY(float, 32);
+#undef BLAST_QY
+}
+
+// stage 4: C = chi-quadrature and pair assembly
+void stage_quad_c(blast_plan *p, const blast_cl_args *a, const Ctx &x, const void *Y, hipStream_t s) {
+    Slots st{{p->tslot_type[0], p->tslot_type[1], p->tslot_type[2]}};
+    const int nblk = (x.sel.n_out + kChiRows - 1) / kChiRows;
+    dim3 g2((unsigned)(p->nt * nblk), a->batch);
+    const int nc4 = (p->n_chi + 3) & ~3;
+    const size_t sh2 = ((size_t)x.nbp * nc4 + 4 * (size_t)x.nbp * x.nbp) * sizeof(double);
+#define BLAST_QC(YT, NB)                                                                                          \
+    hipLaunchKernelGGL((quad_c_mfma_kernel<YT, NB>), g2, dim3(256), sh2, s, (const YT *)Y, a->K_chi, p->d_wchi, \
+                       p->d_chi, p->d_pref, p->n_chi, p->rows_pad, p->n_ell, st, x.ng, x.ns, a->types, x.npairs,  \
+                       x.sel, a->C)
+    const bool f64 = x.prec == BLAST_FP64;
+    if (f64 && x.nbp == 16) BLAST_QC(double, 1);
+    if (f64 && x.nbp == 32) BLAST_QC(double, 2);
+    if (!f64 && x.nbp == 16) BLAST_QC(float, 1);
+    if (!f64 && x.nbp == 32) BLAST_QC(float, 2);
+#undef BLAST_QC
+}
+
+template <typename Mark>
+blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, Mark &mark) {
+    Ctx x;
+    blast_status st = check_args(p, a, x);
+    if (st != BLAST_OK) return st;
+    if (!a->C) return set_error("C is required"), BLAST_E_INVALID;
+    BLAST_HIP_TRY(allow_large_lds());
+    const bool need_w = a->w_save == nullptr;
+    const Layout L = layout_of(p, a->batch, x.prec, x.nbins, need_w, false);
+    unsigned char *ws = get_workspace(p, a, L.total, st);
+    if (!ws) return st;
+    void *c = ws + L.c;
+    uint16_t *clo = x.prec == BLAST_BF16X3 ? (uint16_t *)(ws + L.clo) : nullptr;
+    void *w = need_w ? (void *)(ws + L.w) : a->w_save;
+    void *Y = ws + L.y;
+    mark(0);
+    stage_project(p, a, x, c, clo, s);
     mark(1);
-    {
-        auto launch = [&](auto tag) {
-            constexpr int PR = decltype(tag)::value;
-            using E = typename Cfg<PR>::E;
-            const int BT = Cfg<PR>::BT;
-            const size_t cst = ncp + 16 / sizeof(E);
-            const size_t sh = (size_t)BT * cst * sizeof(E) + (PR == BLAST_BF16X3 ? (size_t)BT * cst * 2 : 0);
-            dim3 grid(p->NP, (a->batch + BT - 1) / BT);
-            const E *bas = PR == BLAST_FP64 ? (const E *)p->basis.f64
-                                            : (PR == BLAST_FP32 ? (const E *)p->basis.f32 : (const E *)p->basis.hi);
-            hipLaunchKernelGGL((contract_kernel<PR>), grid, dim3(256), sh, s, bas, p->basis.lo, p->basis.scale,
-                               (const E *)c, clo, a->batch, p->NP, p->rows_pad, ncp, w);
-        };
-        if (prec == BLAST_FP64) launch(std::integral_constant<int, BLAST_FP64>());
-        if (prec == BLAST_FP32) launch(std::integral_constant<int, BLAST_FP32>());
-        if (prec == BLAST_BF16) launch(std::integral_constant<int, BLAST_BF16>());
-        if (prec == BLAST_BF16X3) launch(std::integral_constant<int, BLAST_BF16X3>());
-    }
-    // 3. quadrature
+    stage_contract(p, a, x, c, clo, w, s);
     mark(2);
-    {
-        dim3 grid(p->n_chi, a->batch);
-        const int nRc = (p->n_R + 15) / 16 * 16;
-        if (prec == BLAST_FP64) {
-            const size_t sh = ((size_t)nRc * nbp + 16 * (size_t)p->rows_pad) * sizeof(double);
-            if (nbp == 16)
-                hipLaunchKernelGGL((quad_y_mfma_kernel<true, 1>), grid, dim3(256), sh, s, (const double *)w, a->K_chi2,
-                                   p->d_wR, p->NP, p->n_R, p->n_chi, p->rows_pad, nbins, (double *)Y);
-            else
-                hipLaunchKernelGGL((quad_y_mfma_kernel<true, 2>), grid, dim3(256), sh, s, (const double *)w, a->K_chi2,
-                                   p->d_wR, p->NP, p->n_R, p->n_chi, p->rows_pad, nbins, (double *)Y);
-        } else {
-            const size_t sh = ((size_t)nRc * nbp + 16 * (size_t)p->rows_pad) * sizeof(float);
-            if (nbp == 16)
-                hipLaunchKernelGGL((quad_y_mfma_kernel<false, 1>), grid, dim3(256), sh, s, (const float *)w, a->K_chi2,
-                                   p->d_wR, p->NP, p->n_R, p->n_chi, p->rows_pad, nbins, (float *)Y);
-            else
-                hipLaunchKernelGGL((quad_y_mfma_kernel<false, 2>), grid, dim3(256), sh, s, (const float *)w, a->K_chi2,
-                                   p->d_wR, p->NP, p->n_R, p->n_chi, p->rows_pad, nbins, (float *)Y);
-        }
-        mark(3);
-        Slots st{{p->tslot_type[0], p->tslot_type[1], p->tslot_type[2]}};
-        dim3 g2((unsigned)(p->nt * sel.n_out), a->batch);
-        const size_t sh2 = (size_t)nbins * p->n_chi * 2 * sizeof(double);
-        if (prec == BLAST_FP64)
-            hipLaunchKernelGGL((quad_c_row_kernel<double>), g2, dim3(256), sh2, s, (const double *)Y, nbp, a->K_chi,
-                               p->d_wchi, p->d_chi, p->d_pref, p->n_chi, p->rows_pad, p->n_ell, st, ng, ns, a->types,
-                               npairs, sel, a->C);
-        else
-            hipLaunchKernelGGL((quad_c_row_kernel<float>), g2, dim3(256), sh2, s, (const float *)Y, nbp, a->K_chi,
-                               p->d_wchi, p->d_chi, p->d_pref, p->n_chi, p->rows_pad, p->n_ell, st, ng, ns, a->types,
-                               npairs, sel, a->C);
-        mark(4);
-    }
+    stage_quad_y(p, a, x, w, Y, s);
+    mark(3);
+    stage_quad_c(p, a, x, Y, s);
+    mark(4);
     BLAST_HIP_TRY(hipGetLastError());
     return BLAST_OK;
+}
+
+}  // namespace
+
+size_t workspace_bytes(const blast_plan *p, int batch, int prec, int n_bins) {
+    return workspace_bytes_impl(p, batch, prec, n_bins);
 }
 
 blast_status forward(blast_plan *p, const blast_cl_args *a, hipStream_t s) {
@@ -800,6 +1198,76 @@ blast_status forward(blast_plan *p, const blast_cl_args *a, hipStream_t s) {
         }
     }
     return st;
+}
+
+blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, void *dP, double *dK_chi,
+                      double *dK_chi2, hipStream_t s) {
+    Ctx x;
+    blast_status st = check_args(p, a, x);
+    if (st != BLAST_OK) return st;
+    if (x.prec != BLAST_FP64 && x.prec != BLAST_FP32)
+        return set_error("the adjoint runs in FP64 or FP32"), BLAST_E_UNSUPPORTED;
+    if (!dC) return set_error("dC is required"), BLAST_E_INVALID;
+    BLAST_HIP_TRY(allow_large_lds());
+    const bool f64 = x.prec == BLAST_FP64;
+    const bool need_w = a->w_save == nullptr;
+    const Layout L = layout_of(p, a->batch, x.prec, x.nbins, need_w, true);
+    unsigned char *ws = get_workspace(p, a, L.total, st);
+    if (!ws) return st;
+    void *c = ws + L.c;
+    void *w = need_w ? (void *)(ws + L.w) : a->w_save;
+    void *Y = ws + L.y, *dY = ws + L.dy, *dw = ws + L.dw, *dc = ws + L.dc;
+    double *Sg = (double *)(ws + L.sg);
+    if (need_w) {
+        stage_project(p, a, x, c, nullptr, s);
+        stage_contract(p, a, x, c, nullptr, w, s);
+    }
+    if (dK_chi) stage_quad_y(p, a, x, w, Y, s);
+    Slots sl{{p->tslot_type[0], p->tslot_type[1], p->tslot_type[2]}};
+    dim3 g1((unsigned)(p->nt * p->n_ell), a->batch);
+#define BLAST_ADJ(T, NB)                                                                                          \
+    do {                                                                                                          \
+        hipLaunchKernelGGL((adj_dy_kernel<T, NB>), g1, dim3(256), 0, s, dC, a->K_chi, p->d_wchi, p->d_chi,        \
+                           p->d_pref, p->n_chi, p->rows_pad, p->n_ell, sl, x.ng, x.ns, a->types, x.npairs,        \
+                           x.sel.n_out, x.inv, (T *)dY, Sg);                                                      \
+        if (dK_chi) {                                                                                             \
+            dim3 gk((unsigned)(((long)x.nbins * p->n_chi + 255) / 256), a->batch);                                \
+            hipLaunchKernelGGL((adj_kchi_kernel<T, NB>), gk, dim3(256), 0, s, (const T *)Y, Sg, p->d_wchi,        \
+                               p->d_chi, p->n_chi, p->rows, p->rows_pad, x.nbins, dK_chi);                        \
+        }                                                                                                         \
+        dim3 gw(p->n_chi, a->batch);                                                                              \
+        const size_t shw = ((size_t)p->n_R * NB + (size_t)p->rows_pad * NB) * sizeof(double);                     \
+        hipLaunchKernelGGL((adj_w_kernel<T, NB>), gw, dim3(256), shw, s, (const T *)dY, (const T *)w, a->K_chi2, \
+                           p->d_wR, p->NP, p->n_R, p->n_chi, p->rows, p->rows_pad, x.nbins, (T *)dw, dK_chi2);   \
+    } while (0)
+    if (f64 && x.nbp == 16) BLAST_ADJ(double, 16);
+    if (f64 && x.nbp == 32) BLAST_ADJ(double, 32);
+    if (!f64 && x.nbp == 16) BLAST_ADJ(float, 16);
+    if (!f64 && x.nbp == 32) BLAST_ADJ(float, 32);
+#undef BLAST_ADJ
+    if (dP) {
+        const int BT = f64 ? 32 : 64;
+        dim3 gt(p->NP, (a->batch + BT - 1) / BT);
+        const size_t sht = (size_t)BT * (p->rows_pad + 1) * (f64 ? 8 : 4);
+        if (f64)
+            hipLaunchKernelGGL((contract_t_kernel<true>), gt, dim3(256), sht, s, p->basis.f64, (const double *)dw,
+                               a->batch, p->NP, p->rows_pad, p->nc_pad, (double *)dc);
+        else
+            hipLaunchKernelGGL((contract_t_kernel<false>), gt, dim3(256), sht, s, p->basis.f32, (const float *)dw,
+                               a->batch, p->NP, p->rows_pad, p->nc_pad, (float *)dc);
+        const long nrows = (long)a->batch * p->NP;
+        dim3 gp((unsigned)((nrows * p->n_cheb + 255) / 256));
+#define BLAST_AP(T, PT)                                                                                        \
+    hipLaunchKernelGGL((adj_project_kernel<T, PT>), gp, dim3(256), 0, s, (const T *)dc, p->d_dctn64, p->n_cheb, \
+                       p->nc_pad, nrows, a->p_kind, (PT *)dP)
+        if (f64 && a->p_dtype == 0) BLAST_AP(double, double);
+        if (f64 && a->p_dtype == 1) BLAST_AP(double, float);
+        if (!f64 && a->p_dtype == 0) BLAST_AP(float, double);
+        if (!f64 && a->p_dtype == 1) BLAST_AP(float, float);
+#undef BLAST_AP
+    }
+    BLAST_HIP_TRY(hipGetLastError());
+    return BLAST_OK;
 }
 
 }  // namespace blast

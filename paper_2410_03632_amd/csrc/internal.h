@@ -82,6 +82,8 @@ blast_status derive_precisions(blast_plan *p, hipStream_t s);
 
 // eval.hip
 blast_status forward(blast_plan *p, const blast_cl_args *a, hipStream_t s);
+blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, void *dP, double *dK_chi,
+                      double *dK_chi2, hipStream_t s);
 size_t workspace_bytes(const blast_plan *p, int batch, int prec, int n_bins);
 
 }  // namespace blast

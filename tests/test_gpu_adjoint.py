@@ -1,0 +1,134 @@
+"""GPU checks of the hand-written adjoint (blast_cl_backward) and its autograd wrapper.
+
+C is linear in P (nodal values or Chebyshev coefficients), in K_chi and in K_chi2
+separately, so for L = <G, C> central finite differences on the FP64 path are exact
+up to rounding; the bar there is 1e-9 relative.  The gradient with respect to the
+Chebyshev coefficients is also compared with the oracle: for one (chi_a, R_b) point
+and one n, dL/dc_n = <G, dC> where dC comes from the oracle's k-integral of T_n at
+that point and its own chi-R sum.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2410_03632_amd import blast as B
+from paper_2410_03632_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ALL = ("gg", "gs", "ss")
+
+
+def _dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).cuda()
+
+
+@pytest.fixture(scope="module", params=[0, 1])
+def setup(request):
+    kw = [dict(), dict(n_ell=11, ell_max=70, n_chi=9, n_R=7, n_cheb=32, k_max=0.9, n_g=3, n_s=2)][request.param]
+    cfg = W.tiny_config(**kw)
+    plan = B.plan_for_config(cfg, precisions=("fp64", "fp32"))
+    inps = [W.make_inputs(cfg, W.seed_for(5, request.param * 10 + i), plan.k_nodes, plan.chi, plan.R)
+            for i in range(3)]
+    P = _dev(np.stack([x.P for x in inps]))
+    K1 = _dev(np.stack([x.Kchi for x in inps]))
+    K2 = _dev(np.stack([x.Kchi2 for x in inps]))
+    yield cfg, plan, P, K1, K2
+    plan.close()
+
+
+def _loss(plan, cfg, P, K1, K2, G, precision="fp64", coef=False):
+    C = plan.forward(P, K1, K2, cfg.n_g, cfg.n_s, precision=precision, coef=coef)
+    return float((C * G).sum())
+
+
+def test_adjoint_matches_exact_finite_differences(setup):
+    cfg, plan, P, K1, K2 = setup
+    gen = torch.Generator(device="cpu").manual_seed(1)
+    shape = (P.shape[0], B.n_pairs(cfg.n_g, cfg.n_s), plan.n_ell)
+    G = torch.randn(shape, generator=gen, dtype=torch.float64).cuda()
+    dP, dK, dK2 = plan.backward(P, K1, K2, cfg.n_g, cfg.n_s, G)
+    for X, dX, name in ((P, dP, "P"), (K1, dK, "K_chi"), (K2, dK2, "K_chi2")):
+        for trial in range(3):
+            v = torch.randn(X.shape, generator=gen, dtype=torch.float64).cuda() * X.abs().mean()
+            h = 1e-3
+            args = {"P": P, "K_chi": K1, "K_chi2": K2}
+            args[name] = (X + h * v).contiguous()
+            Lp = _loss(plan, cfg, args["P"], args["K_chi"], args["K_chi2"], G)
+            args[name] = (X - h * v).contiguous()
+            Lm = _loss(plan, cfg, args["P"], args["K_chi"], args["K_chi2"], G)
+            fd = (Lp - Lm) / (2 * h)
+            an = float((dX * v).sum())
+            assert abs(fd - an) <= 1e-9 * max(abs(fd), abs(an)) + 1e-300, (name, fd, an)
+
+
+def test_fp32_adjoint_close_to_fp64(setup):
+    cfg, plan, P, K1, K2 = setup
+    gen = torch.Generator(device="cpu").manual_seed(2)
+    shape = (P.shape[0], B.n_pairs(cfg.n_g, cfg.n_s), plan.n_ell)
+    G = torch.randn(shape, generator=gen, dtype=torch.float64).cuda()
+    r64 = plan.backward(P, K1, K2, cfg.n_g, cfg.n_s, G, precision="fp64")
+    r32 = plan.backward(P.float(), K1, K2, cfg.n_g, cfg.n_s, G, precision="fp32")
+    for a, b in zip(r64, r32):
+        a, b = a.double(), b.double()
+        assert float((a - b).norm() / a.norm()) < 1e-4
+
+
+def test_coefficient_input_mode(setup):
+    """Forward with the Chebyshev coefficients of P gives the same C as with its nodal
+    values; the coefficient gradient maps to the nodal one by the transposed projection."""
+    cfg, plan, P, K1, K2 = setup
+    N = plan.n_cheb
+    _, x = O.grid_k(N, cfg.k_min, cfg.k_max)
+    T = np.cos(np.outer(np.arange(N), np.arccos(x)))          # T[n][j] = T_n(x_j)
+    c = np.linalg.solve(T.T, P.cpu().numpy().reshape(-1, N).T).T.reshape(P.shape)  # sum_n c_n T_n(x_j) = P_j
+    cd = _dev(c)
+    C1 = plan.forward(P, K1, K2, cfg.n_g, cfg.n_s)
+    C2 = plan.forward(cd, K1, K2, cfg.n_g, cfg.n_s, coef=True)
+    assert float((C1 - C2).abs().max() / C1.abs().max()) < 1e-12
+    G = torch.randn(C1.shape, dtype=torch.float64, device="cuda")
+    dPn = plan.backward(P, K1, K2, cfg.n_g, cfg.n_s, G, want=("P",))[0]
+    dc = plan.backward(cd, K1, K2, cfg.n_g, cfg.n_s, G, coef=True, want=("P",))[0]
+    # P = c T  =>  dL/dc = dL/dP T^T
+    dc_from_nodal = dPn.cpu().numpy().reshape(-1, N) @ T.T
+    assert np.allclose(dc.cpu().numpy().reshape(-1, N), dc_from_nodal, rtol=1e-9,
+                       atol=1e-12 * np.abs(dc_from_nodal).max())
+
+
+def test_coefficient_gradient_matches_oracle(setup):
+    cfg, plan, P, K1, K2 = setup
+    rng = np.random.default_rng(4)
+    G = torch.as_tensor(rng.normal(size=(1, B.n_pairs(cfg.n_g, cfg.n_s), plan.n_ell))).cuda()
+    N = plan.n_cheb
+    _, x = O.grid_k(N, cfg.k_min, cfg.k_max)
+    dc = plan.backward(P[:1].contiguous(), K1[:1].contiguous(), K2[:1].contiguous(), cfg.n_g, cfg.n_s, G,
+                       want=("P",), coef=True)[0]  # gradient w.r.t. coefficients (values of P unused)
+    dc = dc.cpu().numpy()[0]
+    chi, wchi = O.grid_chi(cfg.n_chi, cfg.chi_min, cfg.chi_max)
+    R, wR = O.grid_R(cfg.n_R, cfg.R_min)
+    Kc, Kc2 = K1[0].cpu().numpy(), K2[0].cpu().numpy()
+    Gn = G[0].cpu().numpy()
+    for trial in range(4):
+        a, b, n = int(rng.integers(cfg.n_chi)), int(rng.integers(cfg.n_R)), int(rng.integers(N))
+        Tn = np.cos(n * np.arccos(x))                           # nodal values of T_n
+        w1 = O.w_points(plan.ell, ALL, cfg.k_min, cfg.k_max, [chi[a]], [R[b] * chi[a]], nc=N, P=Tn, shared=True)
+        w = np.zeros((3, plan.n_ell, cfg.n_chi * cfg.n_R))
+        w[:, :, a * cfg.n_R + b] = w1[:, :, 0]
+        dC = O.sum_rform(chi, wchi, wR, cfg.n_g, cfg.n_s, Kc, Kc2, plan.ell, ALL, w)
+        ref = float((Gn * dC).sum())
+        assert abs(dc[a, b, n] - ref) <= 1e-9 * abs(ref) + 1e-12 * np.abs(dc).max(), (a, b, n, dc[a, b, n], ref)
+
+
+def test_autograd_function(setup):
+    cfg, plan, P, K1, K2 = setup
+    f = B.cl_function()
+    Pr = P.clone().requires_grad_(True)
+    K1r = K1.clone().requires_grad_(True)
+    K2r = K2.clone().requires_grad_(True)
+    C = f.apply(plan, Pr, K1r, K2r, cfg.n_g, cfg.n_s, "fp64", False)
+    G = torch.randn(C.shape, dtype=torch.float64, device="cuda")
+    (C * G).sum().backward()
+    ref = plan.backward(P, K1, K2, cfg.n_g, cfg.n_s, G)
+    for g, r in zip((Pr.grad, K1r.grad, K2r.grad), ref):
+        assert torch.equal(g, r)
