@@ -91,6 +91,81 @@ def cpu_baseline(cfg, plan, inp, n_sample=48, seed=11):
             "s_per_set": s_per_set, "cpu": platform.processor() or platform.machine()}
 
 
+def serving_run(seconds, rate_hz=200.0, batch=16, precision="fp32", pool=32):
+    """The serving configuration: a Poisson stream of single-cosmology requests (3-15
+    clustering and 1-5 shear bins, 20-200 of the 200 master multipoles each) through the
+    continuous-batching server.  Host-side generation of a 12.6 MB P grid per request cannot
+    keep up with 200 requests/s, so the requests' cosmologies cycle through a pool of
+    `pool` seed-drawn ones."""
+    import threading
+
+    import torch
+    from paper_2410_03632_amd import blast as B
+    from paper_2410_03632_amd import workloads as W
+
+    cfg = W.SERVING
+    t0 = time.time()
+    plan = B.plan_for_config(cfg, precisions=(precision,))
+    build_s = time.time() - t0
+    chi, chi2 = plan.eval_points()
+    Kchi, Kchi2 = W.kernels(W.bins_of(cfg), chi, chi2)
+    n = max(1, int(seconds * rate_hz))
+    reqs = W.serving_requests(n, rate_hz)
+    pdt = torch.float32 if precision != "fp64" else torch.float64
+    Ps = []
+    for i in range(min(pool, n)):
+        t = torch.empty((cfg.n_chi, cfg.n_R, cfg.n_cheb), dtype=pdt, pin_memory=True)
+        t.copy_(torch.as_tensor(W.p_grid(plan.k_nodes, chi, chi2, reqs[i].cosmo)))
+        Ps.append(t)
+    kcache = {}
+
+    def kern(ng, ns):
+        if (ng, ns) not in kcache:
+            K1, K2 = W.request_kernels(Kchi, Kchi2, ng, ns, max_g=15)
+            kcache[(ng, ns)] = (torch.as_tensor(K1).pin_memory(), torch.as_tensor(K2).pin_memory())
+        return kcache[(ng, ns)]
+
+    for r in reqs:
+        kern(r.n_g, r.n_s)
+    srv = B.Server(plan, precision=precision, p_dtype="fp64" if precision == "fp64" else "fp32", batch=batch,
+                   n_sets=2, max_g=15, max_s=5, max_wait_ms=2.0)
+    tickets = []
+    waiter_done = []
+
+    def waiter():
+        k = 0
+        while k < n:
+            if k < len(tickets):
+                srv.wait(tickets[k])
+                k += 1
+            else:
+                time.sleep(0.0002)
+        waiter_done.append(True)
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t_start = time.perf_counter()
+    t_next = t_start
+    for i, r in enumerate(reqs):
+        t_next += r.gap_s
+        dt = t_next - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        K1, K2 = kern(r.n_g, r.n_s)
+        tickets.append(srv.submit(Ps[i % len(Ps)], K1, K2, r.n_g, r.n_s, r.ell_idx))
+    th.join()
+    st = srv.stats()
+    srv.close()
+    plan.close()
+    return {"rate_hz": rate_hz, "requests": n, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+            "throughput_req_s": st["completed"] / (st["span_ms"] * 1e-3) if st["span_ms"] else None,
+            "mean_fill": st["mean_fill"], "launches": st["launches"], "batch_slots": batch,
+            "precision": precision, "plan_build_s": build_s,
+            "workload": "200 master ell on [2,1000], chi 256, R 96, 128 Chebyshev nodes; per request 3-15 "
+                        "clustering + 1-5 shear bins and 20-200 ell, Poisson arrivals; cosmologies cycle "
+                        "through %d seed-drawn ones" % len(Ps)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +176,9 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64-path and batch-1 timings")
+    ap.add_argument("--serving-seconds", type=float, default=5.0, help="seconds of Poisson arrivals (0: skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (asked for %d)" % args.gpus,
@@ -108,6 +186,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n}))
+        return
     from paper_2410_03632_amd import blast as B
     from paper_2410_03632_amd import workloads as W
     from tests._util import g16_err
@@ -210,6 +297,13 @@ def main():
                 lat.append((time.perf_counter() - ta) * 1e3)
         extras["batch1_latency_ms"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}
 
+    serving = None
+    if args.serving_seconds > 0:
+        log("serving run: %.1f s of arrivals at 200 requests/s" % args.serving_seconds)
+        plan.close()
+        serving = serving_run(args.serving_seconds)
+        log("serving: %s" % serving)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
@@ -239,6 +333,10 @@ def main():
     }
     line.update(err)
     line.update(extras)
+    if serving:
+        line["p50_ms"] = serving["p50_ms"]
+        line["p99_ms"] = serving["p99_ms"]
+        line["serving"] = serving
     print(json.dumps(line), flush=True)
     plan.close()
 

@@ -181,6 +181,68 @@ blast_status blast_cl_backward(blast_plan *plan, const blast_cl_args *args, cons
                                double *dK_chi, double *dK_chi2, void *stream);
 
 /* ------------------------------------------------------------------------- */
+/* Serving: continuous batching of single-cosmology requests                  */
+/* ------------------------------------------------------------------------- */
+/* The paper evaluates one data vector at a time and notes that running more
+ * chains in parallel is the way to use a whole machine (Sec. "Discussion").  The
+ * server turns independent requests (one cosmology each, with their own bins and
+ * multipoles) into batched forward calls:
+ *  - it allocates `n_sets` slot-sets of `batch` slots each (device inputs, outputs and
+ *    workspace) within `hbm_budget`; each set has its own stream, so a batch that is
+ *    formed while others run overlaps with them on the device;
+ *  - a scheduler thread admits queued requests into free slots as soon as a set is
+ *    free, launches a set when it is full, when its oldest request has waited
+ *    `max_wait_ms`, or when no other set is running, and completes requests as their
+ *    set's event fires;
+ *  - every set replays one hipGraph captured at creation (fixed shapes: bins padded to
+ *    max_g + max_s, every plan multipole), so a launch is one graph launch;
+ *  - each request's result depends only on its own inputs (per-cosmology arithmetic
+ *    never mixes batch entries), so it is the same alone and in any mix.          */
+
+typedef struct blast_server blast_server;
+
+typedef struct {
+    int32_t precision;    /* blast_precision resident in the plan                        */
+    int32_t p_dtype;      /* dtype of request P: 0 FP64, 1 FP32                           */
+    int32_t batch;        /* slots per set (cosmologies per launch), >= 1                */
+    int32_t n_sets;       /* sets (concurrent batches); 0 = as many as hbm_budget allows, max 4 */
+    int32_t max_g, max_s; /* largest clustering / shear bin counts a request may carry    */
+    size_t hbm_budget;    /* device bytes the server may allocate; 0 = 8 GiB              */
+    int32_t max_queue;    /* queued requests before submit returns BUSY; 0 = 4096         */
+    double max_wait_ms;   /* launch a partly filled set after this wait                    */
+    int32_t use_graphs;   /* 1: replay captured hipGraphs, 0: plain forward calls          */
+} blast_server_desc;
+
+typedef struct {
+    const void *P;          /* host [n_chi][n_R][n_cheb] nodal P (p_dtype); read until completion */
+    int32_t n_g, n_s;       /* bins of this request (<= max_g, max_s)                       */
+    const double *K_chi;    /* host [n_g+n_s][n_chi]; read until completion                 */
+    const double *K_chi2;   /* host [n_g+n_s][n_chi][n_R]; read until completion            */
+    int32_t n_ell;          /* multipoles wanted (indices into the plan's ell, increasing)  */
+    const int32_t *ell_idx; /* host [n_ell], copied at submit                               */
+    double *C_out;          /* host [n_pairs(n_g, n_s)][n_ell]; written before completion   */
+} blast_request;
+
+typedef struct {
+    int64_t submitted, completed, rejected, launches, queued, in_flight;
+    double mean_fill;       /* mean requests per launch                                     */
+    double p50_ms, p99_ms;  /* submit -> completion latency of completed requests           */
+    double span_ms;         /* first submit -> last completion                              */
+} blast_server_stats;
+
+/* Errors: INVALID, OOM (budget below one set), HIP. */
+blast_status blast_server_create(blast_plan *plan, const blast_server_desc *desc, blast_server **out);
+/* Queues a request.  BUSY when the queue is full, INVALID for a malformed request. */
+blast_status blast_server_submit(blast_server *srv, const blast_request *req, uint64_t *ticket);
+/* Waits up to timeout_ms (< 0: forever) for a ticket.  Returns BUSY on timeout; on
+ * completion writes the request's status and latency (either may be NULL). */
+blast_status blast_server_wait(blast_server *srv, uint64_t ticket, int32_t timeout_ms, blast_status *req_status,
+                               double *latency_ms);
+blast_status blast_server_stats_get(blast_server *srv, blast_server_stats *stats);
+/* Drains pending work, stops the scheduler and frees the server. */
+blast_status blast_server_destroy(blast_server *srv);
+
+/* ------------------------------------------------------------------------- */
 /* Stage timing                                                               */
 /* ------------------------------------------------------------------------- */
 

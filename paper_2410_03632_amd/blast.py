@@ -50,11 +50,31 @@ class ClArgs(C.Structure):
     ]
 
 
+class ServerDesc(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("p_dtype", C.c_int32), ("batch", C.c_int32), ("n_sets", C.c_int32),
+                ("max_g", C.c_int32), ("max_s", C.c_int32), ("hbm_budget", C.c_size_t), ("max_queue", C.c_int32),
+                ("max_wait_ms", C.c_double), ("use_graphs", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("P", C.c_void_p), ("n_g", C.c_int32), ("n_s", C.c_int32), ("K_chi", C.c_void_p),
+                ("K_chi2", C.c_void_p), ("n_ell", C.c_int32), ("ell_idx", C.POINTER(C.c_int32)),
+                ("C_out", C.c_void_p)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
+                ("launches", C.c_int64), ("queued", C.c_int64), ("in_flight", C.c_int64),
+                ("mean_fill", C.c_double), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("span_ms", C.c_double)]
+
+
 EXPORTS = [
     "blast_last_error", "blast_version", "blast_grid_chi_simpson", "blast_grid_R_fejer", "blast_grid_k_cheb",
     "blast_plan_create", "blast_plan_destroy", "blast_plan_info", "blast_plan_k_nodes", "blast_plan_basis_point",
     "blast_cl_workspace_bytes", "blast_cl_forward", "blast_cl_backward", "blast_plan_profile",
-    "blast_plan_profile_read",
+    "blast_plan_profile_read", "blast_server_create", "blast_server_submit", "blast_server_wait",
+    "blast_server_stats_get", "blast_server_destroy",
 ]
 STAGES = ("projection", "contraction", "quad_R", "quad_chi")
 
@@ -85,6 +105,12 @@ def lib():
         L.blast_cl_forward.argtypes = [C.c_void_p, C.POINTER(ClArgs), C.c_void_p]
         L.blast_cl_backward.argtypes = [C.c_void_p, C.POINTER(ClArgs), C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p]
+        L.blast_server_create.argtypes = [C.c_void_p, C.POINTER(ServerDesc), C.POINTER(C.c_void_p)]
+        L.blast_server_submit.argtypes = [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]
+        L.blast_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(C.c_int),
+                                        C.POINTER(C.c_double)]
+        L.blast_server_stats_get.argtypes = [C.c_void_p, C.POINTER(ServerStats)]
+        L.blast_server_destroy.argtypes = [C.c_void_p]
         L.blast_plan_profile.argtypes = [C.c_void_p, C.c_int32]
         L.blast_plan_profile_read.argtypes = [C.c_void_p, dp, C.POINTER(C.c_int64)]
         for name in EXPORTS:
@@ -357,6 +383,77 @@ def cl_function():
     if _CLF is None:
         _CLF = _make_cl_function()
     return _CLF
+
+
+class Server:
+    """Continuous-batching server over one plan (blast_server_*).  Request inputs are host
+    arrays (numpy, or pinned torch CPU tensors for asynchronous copies) that must stay alive
+    until the request completes; the wrapper keeps references until `wait` returns."""
+
+    def __init__(self, plan, *, precision="fp32", p_dtype="fp32", batch=16, n_sets=0, max_g=15, max_s=5,
+                 hbm_budget=0, max_queue=0, max_wait_ms=2.0, use_graphs=True):
+        self.plan = plan
+        self.p_dtype = p_dtype
+        self.max_g, self.max_s = max_g, max_s
+        d = ServerDesc(PRECISION.get(precision, precision), 0 if p_dtype == "fp64" else 1, batch, n_sets, max_g,
+                       max_s, int(hbm_budget), max_queue, float(max_wait_ms), 1 if use_graphs else 0)
+        h = C.c_void_p()
+        _check(lib().blast_server_create(plan.handle, C.byref(d), C.byref(h)))
+        self._h = h
+        self._live = {}
+
+    @staticmethod
+    def _ptr(x):
+        if hasattr(x, "data_ptr"):
+            return x.data_ptr()
+        return x.ctypes.data
+
+    def submit(self, P, K_chi, K_chi2, n_g, n_s, ell_idx, out=None):
+        plan = self.plan
+        want = np.float64 if self.p_dtype == "fp64" else np.float32
+        if hasattr(P, "data_ptr"):
+            import torch
+            ok = P.dtype == (torch.float64 if want is np.float64 else torch.float32) and P.is_contiguous() \
+                and not P.is_cuda
+        else:
+            ok = P.dtype == want and P.flags.c_contiguous
+        if not ok or tuple(P.shape) != (len(plan.chi), len(plan.R), plan.n_cheb):
+            raise ValueError("P must be a contiguous host array [n_chi, n_R, n_cheb] of the server's dtype")
+        K_chi = np.ascontiguousarray(K_chi, dtype=np.float64) if not hasattr(K_chi, "data_ptr") else K_chi
+        K_chi2 = np.ascontiguousarray(K_chi2, dtype=np.float64) if not hasattr(K_chi2, "data_ptr") else K_chi2
+        idx = np.ascontiguousarray(ell_idx, dtype=np.int32)
+        if out is None:
+            out = np.empty((n_pairs(n_g, n_s, plan.types), len(idx)))
+        r = Request(self._ptr(P), n_g, n_s, self._ptr(K_chi), self._ptr(K_chi2), len(idx),
+                    idx.ctypes.data_as(C.POINTER(C.c_int32)), out.ctypes.data)
+        t = C.c_uint64()
+        _check(lib().blast_server_submit(self._h, C.byref(r), C.byref(t)))
+        self._live[t.value] = (P, K_chi, K_chi2, idx, out)
+        return t.value
+
+    def wait(self, ticket, timeout_ms=-1):
+        st, lat = C.c_int(), C.c_double()
+        _check(lib().blast_server_wait(self._h, ticket, timeout_ms, C.byref(st), C.byref(lat)))
+        keep = self._live.pop(ticket)
+        if st.value != OK:
+            raise BlastError(st.value, "request %d failed" % ticket)
+        return keep[4], lat.value
+
+    def stats(self):
+        s = ServerStats()
+        _check(lib().blast_server_stats_get(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().blast_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def plan_for_config(cfg, precisions=("fp64",), device=0, **kw):

@@ -280,3 +280,45 @@ def pair_list(n_g: int, n_s: int, types=("gg", "gs", "ss")):
     if "ss" in types:
         out += [("ss", n_g + i, n_g + j) for i in range(n_s) for j in range(i, n_s)]
     return out
+
+
+# ----------------------------------------------------------------------------
+# serving workload: Poisson stream of requests with uneven bins and multipoles
+# ----------------------------------------------------------------------------
+
+SERVING = Config("serving", 200, 2, 1000, 256, 20.0, 4500.0, 96, 0.3, 128, 1e-4, 10.0,
+                 tuple(500.0 + 280.0 * i for i in range(15)), 150.0,
+                 tuple(1200.0 + 600.0 * i for i in range(5)), 400.0)
+
+
+@dataclasses.dataclass
+class ServingRequest:
+    cosmo: Cosmo
+    n_g: int
+    n_s: int
+    ell_idx: np.ndarray   # increasing indices into the 200-multipole master list
+    gap_s: float          # time since the previous arrival
+
+
+def serving_requests(n: int, rate_hz: float = 200.0, index0: int = 0):
+    """n requests of the serving configuration: each draws (in this order) a cosmology
+    (A, tilt, D-scale), its bins (3-15 clustering, 1-5 shear), a sorted subset of 20-200 of
+    the master multipoles and an exponential arrival gap of mean 1/rate."""
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng(seed_for(4, index0 + i))
+        cos = draw_cosmo(rng, vary=True)
+        ng = int(rng.integers(3, 16))
+        ns = int(rng.integers(1, 6))
+        nl = int(rng.integers(20, 201))
+        idx = np.sort(rng.choice(SERVING.n_ell, size=nl, replace=False)).astype(np.int32)
+        gap = float(rng.exponential(1.0 / rate_hz))
+        out.append(ServingRequest(cos, ng, ns, idx, gap))
+    return out
+
+
+def request_kernels(Kchi, Kchi2, n_g, n_s, max_g=15):
+    """Kernel tables of a request that uses the first n_g clustering and n_s shear bins of
+    the serving layout (tables for all 15 + 5 bins given)."""
+    sel = list(range(n_g)) + [max_g + j for j in range(n_s)]
+    return np.ascontiguousarray(Kchi[sel]), np.ascontiguousarray(Kchi2[sel])
