@@ -127,6 +127,30 @@ blast_status blast_plan_info(const blast_plan *plan, int32_t *rows, int32_t *n_c
 /* Where to sample P: the k nodes (host [n_cheb], ascending). */
 blast_status blast_plan_k_nodes(const blast_plan *plan, double *k);
 
+/* The grids a plan was made with (useful after blast_plan_load).  Sizes and scalars are
+ * written to the non-NULL pointers; the arrays (host, caller-owned, sized n_ell, n_chi,
+ * n_chi, n_R, n_R) are filled when non-NULL. */
+blast_status blast_plan_grids(const blast_plan *plan, int32_t *n_ell, int32_t *n_chi, int32_t *n_R,
+                              int32_t *n_cheb, uint32_t *types, double *k_min, double *k_max, int32_t *ell,
+                              double *chi, double *w_chi, double *R, double *w_R);
+
+/* Where to evaluate the kernels and P: chi_a (host [n_chi]) and R_b chi_a (host
+ * [n_chi][n_R]).  Either pointer may be NULL. */
+blast_status blast_plan_eval_points(const blast_plan *plan, double *chi, double *chi2);
+
+/* Checkpoint of the cosmology-independent basis, which the method computes a single time
+ * and reuses for every cosmology (Eq. t_tilde; Sec. "The implementation"): writes the grids and
+ * the FP64 basis, followed by a 64-bit checksum of everything before it, to `path`.  The
+ * file holds n_chi*n_R*rows_pad*n_cheb_pad doubles (several GB for a 256x96-point
+ * 3x2pt grid).  Errors: INVALID (I/O), HIP. */
+blast_status blast_plan_save(const blast_plan *plan, const char *path);
+
+/* Rebuilds a plan from a file written by blast_plan_save on `device` without recomputing
+ * the basis; `precisions` is a mask like the plan descriptor's, 0 meaning the saved set.
+ * The reduced-precision copies are derived again on the device.  Errors: INVALID (not a
+ * plan file, other version, truncated, checksum mismatch), OOM, HIP. */
+blast_status blast_plan_load(const char *path, int32_t device, uint32_t precisions, blast_plan **out);
+
 /* Copies the FP64 basis rows of one (chi_a, R_b) point to host:
  * out[t_slot * n_ell + l][n] for n < n_cheb (t_slot over the plan's types in the
  * order gg, gs, ss).  For tests and inspection. */

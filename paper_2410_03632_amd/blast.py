@@ -73,7 +73,9 @@ EXPORTS = [
     "blast_last_error", "blast_version", "blast_grid_chi_simpson", "blast_grid_R_fejer", "blast_grid_k_cheb",
     "blast_plan_create", "blast_plan_destroy", "blast_plan_info", "blast_plan_k_nodes", "blast_plan_basis_point",
     "blast_cl_workspace_bytes", "blast_cl_forward", "blast_cl_backward", "blast_plan_profile",
-    "blast_plan_profile_read", "blast_server_create", "blast_server_submit", "blast_server_wait",
+    "blast_plan_profile_read", "blast_plan_save", "blast_plan_load", "blast_plan_eval_points",
+    "blast_plan_grids",
+    "blast_server_create", "blast_server_submit", "blast_server_wait",
     "blast_server_stats_get", "blast_server_destroy",
 ]
 STAGES = ("projection", "contraction", "quad_R", "quad_chi")
@@ -112,6 +114,12 @@ def lib():
         L.blast_server_stats_get.argtypes = [C.c_void_p, C.POINTER(ServerStats)]
         L.blast_server_destroy.argtypes = [C.c_void_p]
         L.blast_plan_profile.argtypes = [C.c_void_p, C.c_int32]
+        L.blast_plan_save.argtypes = [C.c_void_p, C.c_char_p]
+        L.blast_plan_load.argtypes = [C.c_char_p, C.c_int32, C.c_uint32, C.POINTER(C.c_void_p)]
+        L.blast_plan_eval_points.argtypes = [C.c_void_p, dp, dp]
+        i32p = C.POINTER(C.c_int32)
+        L.blast_plan_grids.argtypes = [C.c_void_p, i32p, i32p, i32p, i32p, C.POINTER(C.c_uint32), dp, dp,
+                                       i32p, dp, dp, dp, dp]
         L.blast_plan_profile_read.argtypes = [C.c_void_p, dp, C.POINTER(C.c_int64)]
         for name in EXPORTS:
             if name not in ("blast_last_error", "blast_version"):
@@ -170,40 +178,73 @@ def n_pairs(n_g, n_s, types=7) -> int:
 
 # ------------------------------------------------------------------------------- plan
 
+def _pmask(precisions):
+    m = 0
+    for p in precisions or ():
+        m |= 1 << (PRECISION[p] if isinstance(p, str) else int(p))
+    return m
+
+
 class Plan:
     """Grids plus the resident basis of Eq. t_tilde on one GPU."""
 
     def __init__(self, ell, chi, w_chi, R, w_R, k_min, k_max, n_cheb, *, types=7,
                  precisions=("fp64",), kq_panels=0, kq_phase=0.0, device=0):
-        self.ell = np.ascontiguousarray(ell, dtype=np.int32)
-        self.chi = np.ascontiguousarray(chi, dtype=np.float64)
-        self.w_chi = np.ascontiguousarray(w_chi, dtype=np.float64)
-        self.R = np.ascontiguousarray(R, dtype=np.float64)
-        self.w_R = np.ascontiguousarray(w_R, dtype=np.float64)
-        self.k_min, self.k_max, self.n_cheb = float(k_min), float(k_max), int(n_cheb)
-        self.types = types_mask(types)
         self.device = int(device)
-        pmask = 0
-        for p in precisions:
-            pmask |= 1 << (PRECISION[p] if isinstance(p, str) else int(p))
-        d = PlanDesc(len(self.ell), self.ell.ctypes.data_as(C.POINTER(C.c_int32)),
-                     len(self.chi), _dptr(self.chi), _dptr(self.w_chi),
-                     len(self.R), _dptr(self.R), _dptr(self.w_R),
-                     self.k_min, self.k_max, self.n_cheb, self.types, pmask, int(kq_panels), float(kq_phase))
+        ell = np.ascontiguousarray(ell, dtype=np.int32)
+        chi = np.ascontiguousarray(chi, dtype=np.float64)
+        w_chi = np.ascontiguousarray(w_chi, dtype=np.float64)
+        R = np.ascontiguousarray(R, dtype=np.float64)
+        w_R = np.ascontiguousarray(w_R, dtype=np.float64)
+        d = PlanDesc(len(ell), ell.ctypes.data_as(C.POINTER(C.c_int32)),
+                     len(chi), _dptr(chi), _dptr(w_chi), len(R), _dptr(R), _dptr(w_R),
+                     float(k_min), float(k_max), int(n_cheb), types_mask(types), _pmask(precisions),
+                     int(kq_panels), float(kq_phase))
         h = C.c_void_p()
         _check(lib().blast_plan_create(C.byref(d), self.device, C.byref(h)))
+        self._attach(h)
+
+    @classmethod
+    def load(cls, path, device=0, precisions=()):
+        """Rebuild a plan from a checkpoint written by save() (blast_plan_load); an empty
+        `precisions` keeps the saved set."""
+        h = C.c_void_p()
+        _check(lib().blast_plan_load(os.fsencode(path), int(device), _pmask(precisions), C.byref(h)))
+        self = cls.__new__(cls)
+        self.device = int(device)
+        self._attach(h)
+        return self
+
+    def save(self, path):
+        """Checkpoint the grids and the FP64 basis (blast_plan_save)."""
+        _check(lib().blast_plan_save(self._h, os.fsencode(path)))
+
+    def _attach(self, h):
         self._h = h
+        L = lib()
+        ne, nc, nr, nch = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        ty = C.c_uint32()
+        kmin, kmax = C.c_double(), C.c_double()
+        _check(L.blast_plan_grids(h, C.byref(ne), C.byref(nc), C.byref(nr), C.byref(nch), C.byref(ty),
+                                  C.byref(kmin), C.byref(kmax), None, None, None, None, None))
+        self.ell = np.empty(ne.value, np.int32)
+        self.chi, self.w_chi = np.empty(nc.value), np.empty(nc.value)
+        self.R, self.w_R = np.empty(nr.value), np.empty(nr.value)
+        _check(L.blast_plan_grids(h, None, None, None, None, None, None, None,
+                                  self.ell.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(self.chi),
+                                  _dptr(self.w_chi), _dptr(self.R), _dptr(self.w_R)))
+        self.k_min, self.k_max, self.n_cheb, self.types = kmin.value, kmax.value, nch.value, ty.value
         rows, ncp = C.c_int32(), C.c_int32()
         bb = (C.c_size_t * 4)()
         kq = C.c_int64()
         ms = C.c_double()
-        _check(lib().blast_plan_info(h, C.byref(rows), C.byref(ncp), bb, C.byref(kq), C.byref(ms)))
+        _check(L.blast_plan_info(h, C.byref(rows), C.byref(ncp), bb, C.byref(kq), C.byref(ms)))
         self.rows, self.nc_pad = rows.value, ncp.value
         self.rows_pad = (self.rows + 15) // 16 * 16
         self.basis_bytes = list(bb)
         self.kq_nodes, self.build_ms = kq.value, ms.value
         self.k_nodes = np.empty(self.n_cheb)
-        _check(lib().blast_plan_k_nodes(h, _dptr(self.k_nodes)))
+        _check(L.blast_plan_k_nodes(h, _dptr(self.k_nodes)))
 
     @property
     def handle(self):
@@ -241,8 +282,10 @@ class Plan:
         return dict(zip(STAGES, list(ms))), n.value
 
     def eval_points(self):
-        """(chi_a, R_b chi_a): where to evaluate the kernels and P."""
-        return self.chi, self.chi[:, None] * self.R[None, :]
+        """(chi_a, R_b chi_a): where to evaluate the kernels and P (blast_plan_eval_points)."""
+        chi, chi2 = np.empty(len(self.chi)), np.empty((len(self.chi), len(self.R)))
+        _check(lib().blast_plan_eval_points(self._h, _dptr(chi), _dptr(chi2)))
+        return chi, chi2
 
     def workspace_bytes(self, batch, precision, n_bins):
         n = C.c_size_t()

@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <algorithm>
+#include <cstdio>
 
 #include "internal.h"
 
@@ -172,8 +174,11 @@ static blast_status validate_desc(const blast_plan_desc *d) {
     return BLAST_OK;
 }
 
-extern "C" blast_status blast_plan_create(const blast_plan_desc *d, int32_t device, blast_plan **out) {
-    blast::clear_error();
+// the basis comes either from the device precompute or from a saved file (reader != nullptr)
+typedef blast_status (*BasisReader)(blast_plan *p, void *ctx);
+
+static blast_status plan_create_impl(const blast_plan_desc *d, int32_t device, BasisReader reader, void *rctx,
+                                     blast_plan **out) {
     if (!out) return blast::set_error("out is NULL"), BLAST_E_INVALID;
     *out = nullptr;
     blast_status st = validate_desc(d);
@@ -264,7 +269,7 @@ extern "C" blast_status blast_plan_create(const blast_plan_desc *d, int32_t devi
     }
 
     auto t0 = std::chrono::steady_clock::now();
-    st = blast::build_basis(p, s);
+    st = reader ? reader(p, rctx) : blast::build_basis(p, s);
     if (st == BLAST_OK) st = blast::derive_precisions(p, s);
     if (st == BLAST_OK && hipStreamSynchronize(s) != hipSuccess) {
         blast::set_error("basis build failed on the device");
@@ -274,6 +279,209 @@ extern "C" blast_status blast_plan_create(const blast_plan_desc *d, int32_t devi
     p->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     (void)hipStreamDestroy(s);
     *out = p;
+    return BLAST_OK;
+}
+
+extern "C" blast_status blast_plan_create(const blast_plan_desc *d, int32_t device, blast_plan **out) {
+    blast::clear_error();
+    return plan_create_impl(d, device, nullptr, nullptr, out);
+}
+
+// --------------------------------------------------------------------------------------------
+// persistence of the basis
+// --------------------------------------------------------------------------------------------
+
+namespace {
+const char kMagic[8] = {'B', 'L', 'A', 'S', 'T', 'P', 'L', '1'};
+const uint32_t kFileVersion = 1;
+
+// 64-bit word-wise FNV-1a style hash (tail bytes folded one by one)
+struct Hash64 {
+    uint64_t h = 1469598103934665603ull;
+    void add(const void *data, size_t n) {
+        const unsigned char *c = (const unsigned char *)data;
+        size_t i = 0;
+        for (; i + 8 <= n; i += 8) {
+            uint64_t w;
+            std::memcpy(&w, c + i, 8);
+            h = (h ^ w) * 1099511628211ull;
+        }
+        for (; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    }
+};
+
+struct Writer {
+    FILE *f;
+    Hash64 hs;
+    bool ok = true;
+    void put(const void *d, size_t n) {
+        if (ok && n && fwrite(d, 1, n, f) != n) ok = false;
+        hs.add(d, n);
+    }
+};
+
+struct Reader {
+    FILE *f;
+    Hash64 hs;
+    bool ok = true;
+    void get(void *d, size_t n) {
+        if (ok && n && fread(d, 1, n, f) != n) ok = false;
+        if (ok) hs.add(d, n);
+    }
+};
+
+blast_status read_basis_from_file(blast_plan *p, void *ctx) {
+    Reader &r = *(Reader *)ctx;
+    const size_t n = (size_t)p->NP * p->rows_pad * p->nc_pad;
+    hipError_t e = hipMalloc(&p->basis.f64, n * sizeof(double));
+    if (e != hipSuccess) {
+        p->basis.f64 = nullptr;
+        blast::set_error("basis allocation: %s", hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? BLAST_E_OOM : BLAST_E_HIP;
+    }
+    const size_t chunk = (size_t)8 << 20;  // doubles per read
+    std::vector<double> buf(std::min(n, chunk));
+    for (size_t off = 0; off < n; off += chunk) {
+        const size_t m = std::min(chunk, n - off);
+        r.get(buf.data(), m * sizeof(double));
+        if (!r.ok) return blast::set_error("plan file truncated"), BLAST_E_INVALID;
+        BLAST_HIP_TRY(hipMemcpy(p->basis.f64 + off, buf.data(), m * sizeof(double), hipMemcpyHostToDevice));
+    }
+    uint64_t stored = 0;
+    const uint64_t computed = r.hs.h;
+    if (fread(&stored, 1, 8, r.f) != 8 || stored != computed)
+        return blast::set_error("plan file checksum mismatch"), BLAST_E_INVALID;
+    return BLAST_OK;
+}
+}  // namespace
+
+extern "C" blast_status blast_plan_save(const blast_plan *p, const char *path) {
+    blast::clear_error();
+    if (!p || !path) return blast::set_error("NULL argument"), BLAST_E_INVALID;
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return blast::set_error("cannot open %s for writing", path), BLAST_E_INVALID;
+    DeviceGuard guard(p->device);
+    Writer w{f};
+    w.put(kMagic, 8);
+    const int32_t hdr[8] = {(int32_t)kFileVersion, p->n_ell, p->n_chi, p->n_R, p->n_cheb, (int32_t)p->types,
+                            (int32_t)p->precisions, p->kq_panels};
+    w.put(hdr, sizeof(hdr));
+    const double hd[3] = {p->kmin, p->kmax, p->kq_phase};
+    w.put(hd, sizeof(hd));
+    w.put(p->ell.data(), sizeof(int) * p->n_ell);
+    w.put(p->chi.data(), sizeof(double) * p->n_chi);
+    w.put(p->w_chi.data(), sizeof(double) * p->n_chi);
+    w.put(p->R.data(), sizeof(double) * p->n_R);
+    w.put(p->w_R.data(), sizeof(double) * p->n_R);
+    const size_t n = (size_t)p->NP * p->rows_pad * p->nc_pad;
+    const size_t chunk = (size_t)8 << 20;
+    std::vector<double> buf(std::min(n, chunk));
+    blast_status st = BLAST_OK;
+    for (size_t off = 0; off < n && st == BLAST_OK; off += chunk) {
+        const size_t m = std::min(chunk, n - off);
+        if (hipMemcpy(buf.data(), p->basis.f64 + off, m * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+            blast::set_error("basis download failed");
+            st = BLAST_E_HIP;
+            break;
+        }
+        w.put(buf.data(), m * sizeof(double));
+    }
+    const uint64_t h = w.hs.h;
+    if (st == BLAST_OK && fwrite(&h, 1, 8, f) != 8) w.ok = false;
+    if (std::fclose(f) != 0) w.ok = false;
+    if (st == BLAST_OK && !w.ok) {
+        blast::set_error("write to %s failed", path);
+        st = BLAST_E_INVALID;
+    }
+    return st;
+}
+
+extern "C" blast_status blast_plan_load(const char *path, int32_t device, uint32_t precisions, blast_plan **out) {
+    blast::clear_error();
+    if (!path || !out) return blast::set_error("NULL argument"), BLAST_E_INVALID;
+    *out = nullptr;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return blast::set_error("cannot open %s", path), BLAST_E_INVALID;
+    Reader r{f};
+    char magic[8];
+    r.get(magic, 8);
+    int32_t hdr[8] = {0};
+    double hd[3] = {0};
+    r.get(hdr, sizeof(hdr));
+    r.get(hd, sizeof(hd));
+    blast_status st = BLAST_OK;
+    if (!r.ok || std::memcmp(magic, kMagic, 8) != 0) {
+        st = BLAST_E_INVALID;
+        blast::set_error("%s is not a plan file", path);
+    } else if (hdr[0] != (int32_t)kFileVersion) {
+        st = BLAST_E_INVALID;
+        blast::set_error("plan file version %d, expected %u", hdr[0], kFileVersion);
+    } else if (hdr[1] < 1 || hdr[1] > blast::kMaxEll || hdr[2] < 1 || hdr[2] > (1 << 20) || hdr[3] < 1 ||
+               hdr[3] > (1 << 20)) {
+        st = BLAST_E_INVALID;
+        blast::set_error("corrupt plan header");
+    }
+    if (st != BLAST_OK) {
+        std::fclose(f);
+        return st;
+    }
+    std::vector<int32_t> ell(hdr[1]);
+    std::vector<double> chi(hdr[2]), wchi(hdr[2]), R(hdr[3]), wR(hdr[3]);
+    r.get(ell.data(), sizeof(int32_t) * ell.size());
+    r.get(chi.data(), sizeof(double) * chi.size());
+    r.get(wchi.data(), sizeof(double) * wchi.size());
+    r.get(R.data(), sizeof(double) * R.size());
+    r.get(wR.data(), sizeof(double) * wR.size());
+    if (!r.ok) {
+        std::fclose(f);
+        return blast::set_error("plan file truncated"), BLAST_E_INVALID;
+    }
+    blast_plan_desc d{};
+    d.n_ell = hdr[1];
+    d.ell = ell.data();
+    d.n_chi = hdr[2];
+    d.chi = chi.data();
+    d.w_chi = wchi.data();
+    d.n_R = hdr[3];
+    d.R = R.data();
+    d.w_R = wR.data();
+    d.k_min = hd[0];
+    d.k_max = hd[1];
+    d.n_cheb = hdr[4];
+    d.types = (uint32_t)hdr[5];
+    d.precisions = precisions ? precisions : (uint32_t)hdr[6];
+    d.kq_panels = hdr[7];
+    d.kq_phase = hd[2];
+    st = plan_create_impl(&d, device, read_basis_from_file, &r, out);
+    std::fclose(f);
+    return st;
+}
+
+extern "C" blast_status blast_plan_grids(const blast_plan *p, int32_t *n_ell, int32_t *n_chi, int32_t *n_R,
+                                         int32_t *n_cheb, uint32_t *types, double *k_min, double *k_max,
+                                         int32_t *ell, double *chi, double *w_chi, double *R, double *w_R) {
+    if (!p) return blast::set_error("plan is NULL"), BLAST_E_INVALID;
+    if (n_ell) *n_ell = p->n_ell;
+    if (n_chi) *n_chi = p->n_chi;
+    if (n_R) *n_R = p->n_R;
+    if (n_cheb) *n_cheb = p->n_cheb;
+    if (types) *types = p->types;
+    if (k_min) *k_min = p->kmin;
+    if (k_max) *k_max = p->kmax;
+    if (ell) std::memcpy(ell, p->ell.data(), sizeof(int32_t) * p->n_ell);
+    if (chi) std::memcpy(chi, p->chi.data(), sizeof(double) * p->n_chi);
+    if (w_chi) std::memcpy(w_chi, p->w_chi.data(), sizeof(double) * p->n_chi);
+    if (R) std::memcpy(R, p->R.data(), sizeof(double) * p->n_R);
+    if (w_R) std::memcpy(w_R, p->w_R.data(), sizeof(double) * p->n_R);
+    return BLAST_OK;
+}
+
+extern "C" blast_status blast_plan_eval_points(const blast_plan *p, double *chi, double *chi2) {
+    if (!p) return blast::set_error("plan is NULL"), BLAST_E_INVALID;
+    if (chi) std::memcpy(chi, p->chi.data(), sizeof(double) * p->n_chi);
+    if (chi2)
+        for (int a = 0; a < p->n_chi; ++a)
+            for (int b = 0; b < p->n_R; ++b) chi2[(size_t)a * p->n_R + b] = p->R[b] * p->chi[a];
     return BLAST_OK;
 }
 

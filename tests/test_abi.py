@@ -87,3 +87,19 @@ def test_plan_create_rejects_bad_descriptor(bad):
     assert st == B.E_INVALID
     assert not h.value
     assert len(B.lib().blast_last_error()) > 0
+
+
+@pytest.mark.parametrize("content", [b"", b"not a plan file at all", b"BLASTPL1" + b"\x07\x00\x00\x00" * 8])
+def test_plan_load_rejects_foreign_files(tmp_path, content):
+    """A file that is not a plan checkpoint is refused before any device work."""
+    path = tmp_path / "x.blastplan"
+    path.write_bytes(content)
+    with pytest.raises(B.BlastError) as e:
+        B.Plan.load(str(path))
+    assert e.value.status == B.E_INVALID
+
+
+def test_plan_load_missing_file(tmp_path):
+    with pytest.raises(B.BlastError) as e:
+        B.Plan.load(str(tmp_path / "absent.blastplan"))
+    assert e.value.status == B.E_INVALID
