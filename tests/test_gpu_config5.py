@@ -1,0 +1,227 @@
+"""Differentiation workload: the gradient of
+
+    chi2 = sum_{pairs, ell} (C - C_tgt)^2 / sigma^2
+
+with respect to the Chebyshev coefficients c of P (Eq. cheb_pk) and the centres and
+widths of the Gaussian n(chi) of every bin, through the hand-written adjoint
+(blast_cl_backward behind the autograd function) and the differentiable kernel builder.
+
+sigma^2 is the Gaussian (Knox) variance of the target spectra for a survey fraction
+f_sky = 0.4 (the error model of the paper's model-error appendix), held fixed;
+C_tgt comes from a second seeded cosmology and shifted bins.
+
+* At the full 3x2pt shapes (10 + 5 bins, 96 ell, 256 x 96 points, 128 nodes) the FP32
+  gradient is checked against central finite differences of the FP64 path with a
+  relative step of 1e-5: 20 random coefficients, 3 random coefficient directions and
+  every centre and width.
+* At small shapes the FP64 gradient is checked against the oracle's: its C from its own
+  k-integrals and chi-R sums, differentiated by central differences in the bin
+  parameters (C is bilinear in the kernels, so only the kernel builder's curvature
+  enters, at O(h^2)), and its coefficient derivative from the k-integral of T_n.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2410_03632_amd import blast as B
+from paper_2410_03632_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ALL = ("gg", "gs", "ss")
+FSKY = 0.4
+STEP = 1e-5
+
+
+def knox_sigma2(Ct, ell, n_g, n_s):
+    """Gaussian variance of C_ij(ell): (C_ii C_jj + C_ij^2) / ((2 ell + 1) f_sky)."""
+    pairs = W.pair_list(n_g, n_s)
+    auto = {i: p for p, (t, i, j) in enumerate(pairs) if i == j}
+    s2 = np.empty_like(Ct)
+    for p, (t, i, j) in enumerate(pairs):
+        s2[p] = (Ct[auto[i]] * Ct[auto[j]] + Ct[p] ** 2) / ((2 * np.asarray(ell) + 1.0) * FSKY)
+    return s2
+
+
+def cheb_coefficients(P, N, k_min, k_max):
+    """c with sum_n c_n T_n(x_j) = P_j at the nodes, by a dense solve (not the DCT)."""
+    _, x = O.grid_k(N, k_min, k_max)
+    T = np.cos(np.outer(np.arange(N), np.arccos(x)))
+    return np.linalg.solve(T.T, P.reshape(-1, N).T).T.reshape(P.shape)
+
+
+def _setup(cfg, plan, device):
+    chi, chi2 = plan.eval_points()
+    bins = W.bins_of(cfg)
+    kinds = [b[0] for b in bins]
+    theta0 = np.array([b[1] for b in bins] + [b[2] for b in bins])
+    rng = np.random.default_rng(W.seed_for(5, 2))
+    theta_t = theta0 * (1.0 + 0.02 * rng.standard_normal(theta0.size))
+    nb = len(bins)
+
+    def K(theta):
+        th = torch.as_tensor(theta, dtype=torch.float64, device=device)
+        return W.kernels_torch(kinds, th[:nb], th[nb:], chi, chi2)
+
+    cos = W.draw_cosmo(np.random.default_rng(W.seed_for(5, 0)), vary=True)
+    cos_t = W.draw_cosmo(np.random.default_rng(W.seed_for(5, 1)), vary=True)
+    P = W.p_grid(plan.k_nodes, chi, chi2, cos)
+    Pt = W.p_grid(plan.k_nodes, chi, chi2, cos_t)
+    c = cheb_coefficients(P, plan.n_cheb, cfg.k_min, cfg.k_max)
+    return kinds, theta0, theta_t, K, P, Pt, c
+
+
+def _chi2(C, Ct, s2):
+    return ((C - Ct) ** 2 / s2).sum(dim=(-1, -2))
+
+
+@pytest.fixture(scope="module")
+def full():
+    cfg = W.CONFIGS[2]
+    print("building the full 3x2pt plan", flush=True)
+    plan = B.plan_for_config(cfg, precisions=("fp64", "fp32"))
+    kinds, theta0, theta_t, K, P, Pt, c = _setup(cfg, plan, "cuda")
+    K1t, K2t = K(theta_t)
+    Ct = plan.forward(torch.as_tensor(Pt[None]).cuda(), K1t[None], K2t[None], cfg.n_g, cfg.n_s)[0]
+    s2 = torch.as_tensor(knox_sigma2(Ct.cpu().numpy(), plan.ell, cfg.n_g, cfg.n_s)).cuda()
+    yield cfg, plan, K, theta0, torch.as_tensor(c).cuda(), Ct, s2
+    plan.close()
+
+
+def _fd_coefficients(plan, cfg, K1, K2, c, Ct, s2, dirs):
+    """Central differences of chi2 along each direction (FP64 path, one batched call)."""
+    X = torch.stack([c + d for d in dirs] + [c - d for d in dirs]).contiguous()
+    n = len(dirs)
+    C = plan.forward(X, K1.expand(2 * n, -1, -1).contiguous(), K2.expand(2 * n, -1, -1, -1).contiguous(),
+                     cfg.n_g, cfg.n_s, coef=True)
+    L = _chi2(C, Ct, s2)
+    return (L[:n] - L[n:]) / 2.0
+
+
+def test_full_shapes_fp32_gradient_vs_finite_differences(full):
+    cfg, plan, K, theta0, c, Ct, s2 = full
+    nb = cfg.n_g + cfg.n_s
+    f = B.cl_function()
+    th = torch.as_tensor(theta0, device="cuda").requires_grad_(True)
+    c32 = c.float().requires_grad_(True)
+    K1, K2 = W.kernels_torch(["g"] * cfg.n_g + ["s"] * cfg.n_s, th[:nb], th[nb:], *plan.eval_points())
+    C = f.apply(plan, c32[None], K1[None], K2[None], cfg.n_g, cfg.n_s, "fp32", True)[0]
+    L32 = _chi2(C, Ct, s2)
+    L32.backward()
+    g_c, g_th = c32.grad.double(), th.grad.clone()
+    print("chi2 (fp32 path)", float(L32.detach()), flush=True)
+
+    # FP64 values and finite differences
+    K1d, K2d = (x.detach() for x in K(theta0))
+    rng = np.random.default_rng(W.seed_for(5, 3))
+    flat = c.reshape(-1)
+    idx = rng.choice(flat.numel(), 20, replace=False)
+    dirs = []
+    for i in idx:
+        d = torch.zeros_like(flat)
+        d[int(i)] = STEP * max(abs(float(flat[int(i)])), 1e-30)
+        dirs.append(d.reshape(c.shape))
+    for r in range(3):
+        v = torch.as_tensor(rng.standard_normal(tuple(c.shape)), device="cuda") * c.abs()
+        dirs.append(STEP * v)
+    fd = _fd_coefficients(plan, cfg, K1d, K2d, c, Ct, s2, dirs).cpu().numpy()
+    an = np.array([float((g_c * d).sum()) for d in dirs])
+    scale = np.abs(fd[20:]).max()
+    err = np.abs(an - fd) / np.maximum(np.abs(fd), 1e-3 * scale)
+    print("coefficient FD check, rel err per coordinate/direction:", np.array2string(err, precision=2), flush=True)
+    assert err[20:].max() < 1e-3
+    assert err[:20].max() < 1e-2
+
+    # every centre and width
+    ths = []
+    for i in range(theta0.size):
+        h = STEP * abs(theta0[i])
+        for sgn in (1, -1):
+            t = theta0.copy()
+            t[i] += sgn * h
+            ths.append(t)
+    Ks = [K(t) for t in ths]
+    K1s = torch.stack([k[0] for k in Ks]).contiguous()
+    K2s = torch.stack([k[1] for k in Ks]).contiguous()
+    Cs = plan.forward(c.expand(len(ths), -1, -1, -1).contiguous(), K1s, K2s, cfg.n_g, cfg.n_s, coef=True)
+    Ls = _chi2(Cs, Ct, s2).cpu().numpy()
+    fd_th = (Ls[0::2] - Ls[1::2]) / (2 * STEP * np.abs(theta0))
+    g = g_th.cpu().numpy()
+    err = np.abs(g - fd_th) / np.maximum(np.abs(fd_th), 1e-3 * np.abs(fd_th).max())
+    print("centre/width FD check, rel err:", np.array2string(err, precision=2), flush=True)
+    assert err.max() < 1e-3
+
+
+@pytest.fixture(scope="module")
+def small():
+    cfg = W.tiny_config(n_ell=9, ell_max=60, n_chi=10, n_R=8, n_cheb=32, k_max=0.8, n_g=3, n_s=2)
+    plan = B.plan_for_config(cfg, precisions=("fp64",))
+    kinds, theta0, theta_t, K, P, Pt, c = _setup(cfg, plan, "cpu")
+    chi, wchi = O.grid_chi(cfg.n_chi, cfg.chi_min, cfg.chi_max)
+    R, wR = O.grid_R(cfg.n_R, cfg.R_min)
+    c1 = np.repeat(chi, cfg.n_R)
+    c2 = (chi[:, None] * R[None, :]).ravel()
+    N = cfg.n_cheb
+
+    def w_of(Pg):
+        return O.w_points(plan.ell, ALL, cfg.k_min, cfg.k_max, c1, c2, nc=N, P=Pg.reshape(-1, N))
+
+    def C_or(theta, w):
+        K1, K2 = (x.numpy() for x in K(theta))
+        return O.sum_rform(chi, wchi, wR, cfg.n_g, cfg.n_s, K1, K2, plan.ell, ALL, w)
+
+    w, wt = w_of(P), w_of(Pt)
+    Ct = C_or(theta_t, wt)
+    s2 = knox_sigma2(Ct, plan.ell, cfg.n_g, cfg.n_s)
+    yield cfg, plan, K, theta0, c, Ct, s2, w, C_or, (chi, R)
+    plan.close()
+
+
+def test_small_fp64_gradient_matches_oracle(small):
+    cfg, plan, K, theta0, c, Ct, s2, w, C_or, (chi, R) = small
+    nb = cfg.n_g + cfg.n_s
+    f = B.cl_function()
+    th = torch.as_tensor(theta0, device="cuda").requires_grad_(True)
+    cd = torch.as_tensor(c).cuda().requires_grad_(True)
+    K1, K2 = W.kernels_torch(["g"] * cfg.n_g + ["s"] * cfg.n_s, th[:nb], th[nb:], *plan.eval_points())
+    C = f.apply(plan, cd[None], K1[None], K2[None], cfg.n_g, cfg.n_s, "fp64", True)[0]
+    Ctd, s2d = torch.as_tensor(Ct).cuda(), torch.as_tensor(s2).cuda()
+    L = _chi2(C, Ctd, s2d)
+    L.backward()
+    g_th = th.grad.cpu().numpy()
+    g_c = cd.grad.cpu().numpy()
+
+    C0 = C_or(theta0, w)
+    assert np.allclose(C.detach().cpu().numpy(), C0, rtol=1e-6, atol=1e-9 * np.abs(C0).max())
+    chi2 = lambda Cx: float(((Cx - Ct) ** 2 / s2).sum())
+    fd = np.empty(theta0.size)
+    for i in range(theta0.size):
+        h = STEP * abs(theta0[i])
+        tp, tm = theta0.copy(), theta0.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd[i] = (chi2(C_or(tp, w)) - chi2(C_or(tm, w))) / (2 * h)
+    err = np.abs(g_th - fd) / np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
+    print("oracle centre/width gradient rel err:", np.array2string(err, precision=2))
+    assert err.max() < 1e-6
+
+    # coefficient gradient: dchi2/dc_n(a, b) = <2 (C - C_tgt)/sigma^2, dC/dc_n(a, b)>, with dC from
+    # the oracle's k-integral of T_n at that single point and its chi-R sum
+    G = 2.0 * (C0 - Ct) / s2
+    N = cfg.n_cheb
+    _, x = O.grid_k(N, cfg.k_min, cfg.k_max)
+    chi_o, wchi = O.grid_chi(cfg.n_chi, cfg.chi_min, cfg.chi_max)
+    Ro, wR = O.grid_R(cfg.n_R, cfg.R_min)
+    K1n, K2n = (v.numpy() for v in K(theta0))
+    rng = np.random.default_rng(6)
+    for trial in range(4):
+        a, b, n = int(rng.integers(cfg.n_chi)), int(rng.integers(cfg.n_R)), int(rng.integers(N))
+        Tn = np.cos(n * np.arccos(x))
+        w1 = O.w_points(plan.ell, ALL, cfg.k_min, cfg.k_max, [chi_o[a]], [Ro[b] * chi_o[a]], nc=N, P=Tn,
+                        shared=True)
+        wp = np.zeros((3, plan.n_ell, cfg.n_chi * cfg.n_R))
+        wp[:, :, a * cfg.n_R + b] = w1[:, :, 0]
+        dC = O.sum_rform(chi_o, wchi, wR, cfg.n_g, cfg.n_s, K1n, K2n, plan.ell, ALL, wp)
+        ref = float((G * dC).sum())
+        assert abs(g_c[a, b, n] - ref) <= 1e-6 * abs(ref) + 1e-9 * np.abs(g_c).max(), (a, b, n, g_c[a, b, n], ref)
