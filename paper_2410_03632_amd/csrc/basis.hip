@@ -259,9 +259,15 @@ __global__ __launch_bounds__(256) void gemm_kernel(Items it, const double *__res
     }
 }
 
-__global__ void to_f32_kernel(const double *__restrict__ src, float *__restrict__ dst, size_t n) {
+// FP32 copy in the tiled layout (src row-major [point][rows_pad][ncp])
+__global__ void to_f32_kernel(const double *__restrict__ src, float *__restrict__ dst, size_t n, int rows_pad,
+                              int ncp) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = (float)src[i];
+    if (i >= n) return;
+    const size_t blk = (size_t)rows_pad * ncp;
+    const size_t pt = i / blk, rem = i % blk;
+    const int row = (int)(rem / ncp), col = (int)(rem % ncp);
+    dst[pt * blk + tiled_off(row, col, ncp / 16, 4)] = (float)src[i];
 }
 
 __device__ inline uint16_t f32_to_bf16_rne(float f) {
@@ -271,9 +277,9 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
 }
 __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-// one wave per basis row: power-of-two scale, BF16 hi and (optionally) lo parts
-__global__ __launch_bounds__(256) void to_bf16_kernel(const double *__restrict__ src, size_t nrows, int ncp,
-                                                      uint16_t *__restrict__ hi, uint16_t *__restrict__ lo,
+// one wave per basis row: power-of-two scale, BF16 hi and (optionally) lo parts, tiled layout
+__global__ __launch_bounds__(256) void to_bf16_kernel(const double *__restrict__ src, size_t nrows, int rows_pad,
+                                                      int ncp, uint16_t *__restrict__ hi, uint16_t *__restrict__ lo,
                                                       float *__restrict__ scale) {
     const size_t row = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -284,11 +290,14 @@ __global__ __launch_bounds__(256) void to_bf16_kernel(const double *__restrict__
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
     const double sc = mx > 0.0 ? ldexp(1.0, ilogb(mx) + 1) : 1.0;  // |value / sc| < 1
     if (lane == 0) scale[row] = (float)sc;
+    const size_t base = (row / rows_pad) * (size_t)rows_pad * ncp;
+    const int rr = (int)(row % rows_pad);
     for (int n = lane; n < ncp; n += 64) {
         const double v = r[n] / sc;
         const uint16_t h = f32_to_bf16_rne((float)v);
-        hi[row * ncp + n] = h;
-        if (lo) lo[row * ncp + n] = f32_to_bf16_rne((float)(v - (double)bf16_to_f32(h)));
+        const size_t o = base + tiled_off(rr, n, ncp / 32, 8);
+        hi[o] = h;
+        if (lo) lo[o] = f32_to_bf16_rne((float)(v - (double)bf16_to_f32(h)));
     }
 }
 
@@ -433,7 +442,7 @@ blast_status derive_precisions(blast_plan *p, hipStream_t s) {
         hipError_t e = hipMalloc(&p->basis.f32, n * sizeof(float));
         if (e != hipSuccess) return p->basis.f32 = nullptr, fail(e, "FP32 basis");
         hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->basis.f64,
-                           p->basis.f32, n);
+                           p->basis.f32, n, p->rows_pad, p->nc_pad);
     }
     const bool want_hi = p->precisions & ((1u << BLAST_BF16) | (1u << BLAST_BF16X3));
     const bool want_lo = p->precisions & (1u << BLAST_BF16X3);
@@ -447,7 +456,7 @@ blast_status derive_precisions(blast_plan *p, hipStream_t s) {
             if (e != hipSuccess) return p->basis.lo = nullptr, fail(e, "BF16 lo basis");
         }
         hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((nrows + 3) / 4)), dim3(256), 0, s, p->basis.f64, nrows,
-                           p->nc_pad, p->basis.hi, p->basis.lo, p->basis.scale);
+                           p->rows_pad, p->nc_pad, p->basis.hi, p->basis.lo, p->basis.scale);
     }
     BLAST_HIP_TRY(hipGetLastError());
     return BLAST_OK;

@@ -196,6 +196,123 @@ __global__ __launch_bounds__(256) void project_mfma_kernel(const PT *__restrict_
         }
 }
 
+// FP32 projection for N % 32 == 0 (then nc_pad == N), with the even/odd split of the DCT-II.
+// With u_j = P_j + P_{N-1-j} and v_j = P_j - P_{N-1-j} (j < N/2), and D[n][N-1-j] = (-1)^n D[n][j],
+//     c_{2m} = sum_{j<N/2} D[2m][j] u_j,      c_{2m+1} = sum_{j<N/2} D[2m+1][j] v_j,
+// two [rows x N/2] x [N/2 x N/2] products: half the MFMA work of the plain product.  Each wave owns
+// kSplitRT row tiles and every even and odd output tile; the P values of step s+1 are loaded
+// while step s runs.  A lane stores (c_{2m}, c_{2m+1}) as one 8-byte pair.
+constexpr int kSplitRT = 2;
+
+template <typename PT, int OUT>
+__global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict__ P, const float *__restrict__ Dn,
+                                                            int N, long nrows, void *__restrict__ c_out,
+                                                            uint16_t *__restrict__ c_lo) {
+    constexpr int RT = kSplitRT, VEC = 4, KSTEP = 16;
+    constexpr int MAXT = kMaxCheb / 32;  // output tiles per parity
+    extern __shared__ __align__(16) unsigned char smem_s[];
+    const int H = N / 2, hs = H + 4;     // LDS row stride: 16 bytes of padding
+    float *De = (float *)smem_s, *Do = De + (size_t)H * hs;
+    for (int i = threadIdx.x; i < H * (H / 4); i += blockDim.x) {
+        const int m = i / (H / 4), q = i % (H / 4);
+        *(float4 *)(De + (size_t)m * hs + 4 * q) = *(const float4 *)(Dn + (size_t)(2 * m) * N + 4 * q);
+        *(float4 *)(Do + (size_t)m * hs + 4 * q) = *(const float4 *)(Dn + (size_t)(2 * m + 1) * N + 4 * q);
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int nt = H >> 4, nsteps = H / KSTEP;
+    const long row0 = (long)blockIdx.x * (64 * RT) + 16 * RT * w;
+    f4 ae[RT][MAXT], ao[RT][MAXT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) ae[r][t] = ao[r][t] = f4{0, 0, 0, 0};
+
+    // raw P values of one step: front[r] = P[j0 .. j0+3], back[r] = P[N-4-j0 .. N-1-j0]
+    auto load = [&](int st, float4 (&front)[RT], float4 (&back)[RT]) {
+        const int j0 = st * KSTEP + lk * VEC;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            const long row = row0 + 16 * r + lr;
+            if (row < nrows) {
+                const PT *pr = P + row * (long)N;
+                if constexpr (sizeof(PT) == 4) {
+                    front[r] = *(const float4 *)(pr + j0);
+                    back[r] = *(const float4 *)(pr + N - 4 - j0);
+                } else {
+                    const double2 f0 = *(const double2 *)(pr + j0), f1 = *(const double2 *)(pr + j0 + 2);
+                    const double2 b0 = *(const double2 *)(pr + N - 4 - j0), b1 = *(const double2 *)(pr + N - 2 - j0);
+                    front[r] = make_float4((float)f0.x, (float)f0.y, (float)f1.x, (float)f1.y);
+                    back[r] = make_float4((float)b0.x, (float)b0.y, (float)b1.x, (float)b1.y);
+                }
+            } else {
+                front[r] = back[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+    };
+    auto compute = [&](int st, const float4 (&front)[RT], const float4 (&back)[RT]) {
+        const int j0 = st * KSTEP + lk * VEC;
+        float u[RT][VEC], v[RT][VEC];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            // mirror of j0 + e is N-1-j0-e = (N-4-j0) + (3-e)
+            u[r][0] = front[r].x + back[r].w, v[r][0] = front[r].x - back[r].w;
+            u[r][1] = front[r].y + back[r].z, v[r][1] = front[r].y - back[r].z;
+            u[r][2] = front[r].z + back[r].y, v[r][2] = front[r].z - back[r].y;
+            u[r][3] = front[r].w + back[r].x, v[r][3] = front[r].w - back[r].x;
+        }
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+            if (t >= nt) break;
+            const float4 de = *(const float4 *)(De + (size_t)(16 * t + lr) * hs + j0);
+            const float4 dd = *(const float4 *)(Do + (size_t)(16 * t + lr) * hs + j0);
+            const float dev[4] = {de.x, de.y, de.z, de.w}, dov[4] = {dd.x, dd.y, dd.z, dd.w};
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+#pragma unroll
+                for (int r = 0; r < RT; ++r) {
+                    ae[r][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(u[r][e], dev[e], ae[r][t], 0, 0, 0);
+                    ao[r][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[r][e], dov[e], ao[r][t], 0, 0, 0);
+                }
+        }
+    };
+    float4 f0[RT], b0[RT], f1[RT], b1[RT];
+    load(0, f0, b0);
+    for (int st = 0; st < nsteps; st += 2) {
+        if (st + 1 < nsteps) load(st + 1, f1, b1);
+        compute(st, f0, b0);
+        if (st + 1 < nsteps) {
+            if (st + 2 < nsteps) load(st + 2, f0, b0);
+            compute(st + 1, f1, b1);
+        }
+    }
+    // lane holds rows 16r + 4lk + q of output m = 16t + lr, i.e. n = 2m and 2m + 1
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+            if (t >= nt) break;
+            const int n = 2 * (16 * t + lr);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const long row = row0 + 16 * r + 4 * lk + q;
+                if (row >= nrows) continue;
+                const size_t o = (size_t)row * N + n;
+                const float ce = ae[r][t][q], co = ao[r][t][q];
+                if (OUT == 1) {
+                    *(float2 *)((float *)c_out + o) = make_float2(ce, co);
+                } else {
+                    const uint16_t he = bf16_rne(ce), ho = bf16_rne(co);
+                    *(uint32_t *)((uint16_t *)c_out + o) = (uint32_t)he | ((uint32_t)ho << 16);
+                    if (c_lo)
+                        *(uint32_t *)(c_lo + o) = (uint32_t)bf16_rne(ce - bf16_val(he)) |
+                                                   ((uint32_t)bf16_rne(co - bf16_val(ho)) << 16);
+                }
+            }
+        }
+}
+
 // ---------------------------------------------------------------------------------------------
 // contraction: per (chi_a, R_b) point a [rows x n] x [n x batch] product on MFMA.
 // Lane layout of the 16x16 tiles: A[i][k] lane = i + 16*(k-group), B[k][j] lane = j + 16*(k-group),
@@ -415,6 +532,164 @@ __global__ __launch_bounds__(256) void contract_kernel(const typename Cfg<PREC>:
     }
 }
 
+// Mixed-precision contraction on the tiled basis copies (FP32, BF16, BF16x3).  One work-group per
+// (point, batch tile of 64 cosmologies); its W = blockDim/64 waves each own kTilesPerWave adjacent
+// 16-row tiles per pass, so that e.g. 18 row tiles split evenly over 6 waves.  Every basis load is
+// a contiguous 1 KB (tiled layout); the c tile sits in LDS; the loads of step s+1 are in flight
+// while step s runs on the MFMA units.
+constexpr int kTilesPerWave = 3;
+
+template <int PREC, int WPE = (PREC == BLAST_BF16X3 ? 2 : 4)>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE))) void contract_tiled_kernel(const typename Cfg<PREC>::E *__restrict__ basis,
+                                                             const uint16_t *__restrict__ basis_lo,
+                                                             const float *__restrict__ scale,
+                                                             const typename Cfg<PREC>::E *__restrict__ c,
+                                                             const uint16_t *__restrict__ c_lo, int batch, int NP,
+                                                             int rows_pad, int ncp, float *__restrict__ w_out) {
+    using C = Cfg<PREC>;
+    using E = typename C::E;
+    constexpr int VEC = C::VEC, BT = C::BT, BTN = BT / 16, TPW = kTilesPerWave;
+    constexpr bool X3 = PREC == BLAST_BF16X3;
+    constexpr int KSTEP = 4 * VEC;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int cst = ncp + 16 / (int)sizeof(E);
+    E *cs = (E *)smem;
+    uint16_t *cls = (uint16_t *)(smem + (size_t)BT * cst * sizeof(E));
+
+    const int ab = blockIdx.x;
+    const int beta0 = blockIdx.y * BT;
+    const int nb = min(BT, batch - beta0);
+    const int vec_per_row = ncp / VEC;
+    for (int i = threadIdx.x; i < BT * vec_per_row; i += blockDim.x) {
+        const int bb = i / vec_per_row, v = i % vec_per_row;
+        U4 val = {0u, 0u, 0u, 0u}, vlo = {0u, 0u, 0u, 0u};
+        if (bb < nb) {
+            const size_t off = ((size_t)(beta0 + bb) * NP + ab) * ncp + (size_t)v * VEC;
+            val = *(const U4 *)(c + off);
+            if (X3) vlo = *(const U4 *)(c_lo + off);
+        }
+        *(U4 *)(cs + (size_t)bb * cst + v * VEC) = val;
+        if (X3) *(U4 *)(cls + (size_t)bb * cst + v * VEC) = vlo;
+    }
+    __syncthreads();
+
+    const int W = blockDim.x >> 6;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int RT = rows_pad / 16;
+    const int nsteps = ncp / KSTEP;
+    const size_t blk = (size_t)ab * rows_pad * ncp;
+    const U4 *bt = (const U4 *)(basis + blk) + lane;
+    const U4 *btl = X3 ? (const U4 *)(basis_lo + blk) + lane : nullptr;
+
+    for (int pass = 0; pass * W * TPW < RT; ++pass) {
+        const int rt0 = (pass * W + w) * TPW;
+        if (rt0 >= RT) break;
+        f4 acc[TPW][BTN];
+#pragma unroll
+        for (int i = 0; i < TPW; ++i)
+#pragma unroll
+            for (int j = 0; j < BTN; ++j) acc[i][j] = f4{0, 0, 0, 0};
+        bool on[TPW];
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) on[i] = rt0 + i < RT;
+
+        auto loadA = [&](int st, U4(&dst)[TPW], U4(&dstl)[TPW]) {
+#pragma unroll
+            for (int i = 0; i < TPW; ++i) {
+                const int r = on[i] ? rt0 + i : rt0;
+                const size_t o = ((size_t)r * nsteps + st) * 64;
+                dst[i] = bt[o];
+                if (X3) dstl[i] = btl[o];
+            }
+        };
+        auto compute = [&](int st, const U4(&av)[TPW], const U4(&avl)[TPW]) {
+            const int kof = st * KSTEP + lk * VEC;
+            U4 bv[BTN], bvl[BTN];
+#pragma unroll
+            for (int j = 0; j < BTN; ++j) {
+                bv[j] = *(const U4 *)(cs + (size_t)(16 * j + lr) * cst + kof);
+                if (X3) bvl[j] = *(const U4 *)(cls + (size_t)(16 * j + lr) * cst + kof);
+            }
+            if constexpr (PREC == BLAST_FP32) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int i = 0; i < TPW; ++i) {
+                        if (!on[i]) continue;
+                        const float a = __builtin_bit_cast(f4v, av[i])[u];
+#pragma unroll
+                        for (int j = 0; j < BTN; ++j) {
+                            if (16 * j >= nb) continue;
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, __builtin_bit_cast(f4v, bv[j])[u],
+                                                                             acc[i][j], 0, 0, 0);
+                        }
+                    }
+            } else {
+#pragma unroll
+                for (int i = 0; i < TPW; ++i) {
+                    if (!on[i]) continue;
+                    const bf8 a = __builtin_bit_cast(bf8, av[i]);
+#pragma unroll
+                    for (int j = 0; j < BTN; ++j) {
+                        if (16 * j >= nb) continue;
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf8, bv[j]),
+                                                                            acc[i][j], 0, 0, 0);
+                    }
+                }
+                if constexpr (X3) {
+#pragma unroll
+                    for (int i = 0; i < TPW; ++i) {
+                        if (!on[i]) continue;
+                        const bf8 a = __builtin_bit_cast(bf8, av[i]), al = __builtin_bit_cast(bf8, avl[i]);
+#pragma unroll
+                        for (int j = 0; j < BTN; ++j) {
+                            if (16 * j >= nb) continue;
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf8, bvl[j]),
+                                                                                acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, __builtin_bit_cast(bf8, bv[j]),
+                                                                                acc[i][j], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        };
+        U4 a0[TPW], a0l[TPW], a1[TPW], a1l[TPW];
+        loadA(0, a0, a0l);
+        for (int st = 0; st < nsteps; st += 2) {
+            if (st + 1 < nsteps) loadA(st + 1, a1, a1l);
+            compute(st, a0, a0l);
+            if (st + 1 < nsteps) {
+                if (st + 2 < nsteps) loadA(st + 2, a0, a0l);
+                compute(st + 1, a1, a1l);
+            }
+        }
+        // lane holds rows 16*rt + 4*lk + r for cosmology 16*j + lr
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+            if (!on[i]) continue;
+            const int row0 = 16 * (rt0 + i) + 4 * lk;
+            float sc[4] = {1.f, 1.f, 1.f, 1.f};
+            if (PREC != BLAST_FP32) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sc[r] = scale[(size_t)ab * rows_pad + row0 + r];
+            }
+#pragma unroll
+            for (int j = 0; j < BTN; ++j) {
+                const int bb = 16 * j + lr;
+                if (bb >= nb) continue;
+                const size_t o = ((size_t)(beta0 + bb) * NP + ab) * rows_pad + row0;
+                float4 v;
+                v.x = acc[i][j][0] * sc[0];
+                v.y = acc[i][j][1] * sc[1];
+                v.z = acc[i][j][2] * sc[2];
+                v.w = acc[i][j][3] * sc[3];
+                *(float4 *)(w_out + o) = v;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // quadrature
 // ---------------------------------------------------------------------------------------------
@@ -491,6 +766,238 @@ __global__ __launch_bounds__(256) void quad_y_kernel(const T *__restrict__ w, co
             for (int e = 0; e < (int)(16 / sizeof(T)); ++e) op[e] = acc[r][q + e];
             *(U4 *)(y + q) = o;
         }
+    }
+}
+
+// Fused contraction and R-quadrature (mixed precisions, no w_save): w never leaves the registers
+// of the wave that makes it.
+//   w[row][beta]          = sum_n Ttilde[a, b][row][n] c[beta][a, b][n]        (MFMA, per b)
+//   Y[beta][row][a][bin] += w[row][beta] * Kt[a, b][beta][bin]               (VALU, per b)
+// with Kt = wR_b K_bin(R_b chi_a).  Work-group = (chi_a, batch tile of 64, group of TR row
+// tiles), 4*TR waves: wave (i, k) makes the 16 x 16 tile (row tile i, cosmologies 16k..16k+15)
+// for every b and keeps Y for its 4 rows x NB bins.  Per b the work-group stages the TR basis
+// tiles (tiled layout: one contiguous block) and the 64 c rows in LDS, shared by the 4 waves of
+// a row tile and the TR waves of a batch sub-tile; the global loads for b+1 are issued before
+// the MFMAs of b and land in the other LDS buffer after them (one barrier per b).
+// Work-groups are numbered so that the row groups and batch tiles of one chi_a run together on
+// one XCD (work-groups go round-robin over the 8 XCDs) and share c rows and basis tiles in its
+// L2.  Y rows are written with stride NBP (zero padding), the layout of the chi-quadrature.
+constexpr int kFusedTR = 3;
+
+template <int PREC, int NB, int NBP, int NS>
+__global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
+    const typename Cfg<PREC>::E *__restrict__ basis, const uint16_t *__restrict__ basis_lo,
+    const float *__restrict__ scale, const typename Cfg<PREC>::E *__restrict__ c, const uint16_t *__restrict__ c_lo,
+    const float *__restrict__ Kt, int batch, int n_chi, int n_R, int rows_pad, int nBT, int units,
+    float *__restrict__ Y) {
+    using E = typename Cfg<PREC>::E;
+    constexpr int TR = kFusedTR, NT = 256 * TR;
+    constexpr int VEC = Cfg<PREC>::VEC, KSTEP = 4 * VEC;
+    constexpr int ncp = NS * KSTEP;
+    constexpr bool X3 = PREC == BLAST_BF16X3;
+    constexpr int NPART = X3 ? 2 : 1;                     // hi (and lo) parts
+    constexpr int A_U4 = TR * NS * 64;                    // U4s of the staged basis tiles (per part)
+    constexpr int CST = ncp + VEC;                        // LDS row stride of c (elements), 16 B pad
+    constexpr int C_U4 = 64 * ncp / VEC;                  // U4s of the 64 c rows (per part)
+    constexpr int ST_A = (A_U4 + NT - 1) / NT, ST_C = (C_U4 + NT - 1) / NT;
+    extern __shared__ __align__(16) unsigned char smem_f[];
+    constexpr size_t A_BYTES = (size_t)A_U4 * 16, C_BYTES = (size_t)64 * CST * sizeof(E);
+    constexpr size_t BUF = NPART * (A_BYTES + C_BYTES);
+
+    const int groups = (rows_pad / 16 + TR - 1) / TR;
+    const int per = (units + 7) / 8;
+    const int unit = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (unit >= units) return;  // uniform over the work-group
+    const int RT = rows_pad / 16;
+    const int g = unit % groups, bt = (unit / groups) % nBT, a = unit / (groups * nBT);
+    const int rt0 = g * TR;
+    const int ntile = min(TR, RT - rt0);                  // row tiles of this group
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int ti = w >> 2, tk = w & 3;                    // row tile, 16-cosmology sub-tile
+    const int beta = bt * 64 + 16 * tk + lr;
+    const bool active = ti < ntile && bt * 64 + 16 * tk < batch;
+    const int bcl = beta < batch ? beta : batch - 1;
+    const int nb = min(64, batch - bt * 64);
+    const size_t NP = (size_t)n_chi * n_R;
+    const size_t pt_u4 = (size_t)RT * NS * 64;             // U4s per point in the tiled layout
+
+    // staging of one b: basis tiles rt0.. (contiguous; rows past the last tile are clamped) and c rows
+    U4 sa[NPART][ST_A], sc_[NPART][ST_C];
+    auto gload = [&](int b) {
+        const size_t ab = (size_t)a * n_R + b;
+        const size_t abase = ab * pt_u4 + (size_t)rt0 * NS * 64;
+        const size_t alim = ab * pt_u4 + pt_u4 - 1;
+#pragma unroll
+        for (int k = 0; k < ST_A; ++k) {
+            const int i = threadIdx.x + k * NT;
+            const size_t o = min(abase + (size_t)(i < A_U4 ? i : 0), alim);
+            sa[0][k] = ((const U4 *)basis)[o];
+            if (X3) sa[NPART - 1][k] = ((const U4 *)basis_lo)[o];
+        }
+#pragma unroll
+        for (int k = 0; k < ST_C; ++k) {
+            const int i = threadIdx.x + k * NT;
+            const int row = (i < C_U4 ? i : 0) / (ncp / VEC), v = (i < C_U4 ? i : 0) % (ncp / VEC);
+            const int bb = row < nb ? bt * 64 + row : bt * 64;
+            const size_t o = ((size_t)bb * NP + ab) * ncp + (size_t)v * VEC;
+            sc_[0][k] = *(const U4 *)(c + o);
+            if (X3) sc_[NPART - 1][k] = *(const U4 *)(c_lo + o);
+        }
+    };
+    auto lstore = [&](int buf) {
+        unsigned char *base = smem_f + (size_t)buf * BUF;
+#pragma unroll
+        for (int part = 0; part < NPART; ++part) {
+            U4 *As = (U4 *)(base + part * A_BYTES);
+            E *Cs = (E *)(base + NPART * A_BYTES + part * C_BYTES);
+#pragma unroll
+            for (int k = 0; k < ST_A; ++k) {
+                const int i = threadIdx.x + k * NT;
+                if (i < A_U4) As[i] = sa[part][k];
+            }
+#pragma unroll
+            for (int k = 0; k < ST_C; ++k) {
+                const int i = threadIdx.x + k * NT;
+                if (i < C_U4) {
+                    const int row = i / (ncp / VEC), v = i % (ncp / VEC);
+                    *(U4 *)(Cs + (size_t)row * CST + v * VEC) = sc_[part][k];
+                }
+            }
+        }
+    };
+
+    float y[4][NB];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) y[r][j] = 0.f;
+
+    // the Y update of b-1 (VALU) is interleaved with the MFMAs of b where the registers allow
+    constexpr bool PIPE = !X3 && NB <= 16;
+    f4 wprev = f4{0, 0, 0, 0};
+    float ktp[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) ktp[j] = 0.f;
+    constexpr int FPS = (4 * NB + NS - 1) / NS;  // Y FMAs per step
+
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int b = 0; b < n_R; ++b) {
+        if (b + 1 < n_R) gload(b + 1);
+        // kernel weights (and BF16 row scales) of this b
+        float kt[NB];
+        {
+            const float4 *kp = (const float4 *)(Kt + (((size_t)a * n_R + b) * batch + bcl) * NB);
+#pragma unroll
+            for (int q = 0; q < NB / 4; ++q) {
+                const float4 v = kp[q];
+                kt[4 * q] = v.x, kt[4 * q + 1] = v.y, kt[4 * q + 2] = v.z, kt[4 * q + 3] = v.w;
+            }
+        }
+        float4 sc = make_float4(1.f, 1.f, 1.f, 1.f);
+        if constexpr (PREC != BLAST_FP32) {
+            const int rsafe = 16 * min(rt0 + ti, RT - 1) + 4 * lk;
+            sc = *(const float4 *)(scale + ((size_t)a * n_R + b) * rows_pad + rsafe);
+        }
+        const unsigned char *base = smem_f + (size_t)(b & 1) * BUF;
+        const U4 *As = (const U4 *)base + (size_t)min(ti, TR - 1) * NS * 64 + lane;
+        const U4 *Asl = X3 ? (const U4 *)(base + A_BYTES) + (size_t)min(ti, TR - 1) * NS * 64 + lane : nullptr;
+        const E *Cs = (const E *)(base + NPART * A_BYTES) + (size_t)(16 * tk + lr) * CST + lk * VEC;
+        const E *Csl = X3 ? (const E *)(base + NPART * A_BYTES + C_BYTES) + (size_t)(16 * tk + lr) * CST + lk * VEC
+                          : nullptr;
+        f4 acc[2] = {f4{0, 0, 0, 0}, f4{0, 0, 0, 0}};
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            const U4 ua = As[st * 64], ub = *(const U4 *)(Cs + st * KSTEP);
+            f4 &ac = acc[st & 1];
+            if constexpr (PREC == BLAST_FP32) {
+                const f4v av = __builtin_bit_cast(f4v, ua), bv = __builtin_bit_cast(f4v, ub);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) ac = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e], bv[e], ac, 0, 0, 0);
+            } else {
+                const bf8 av = __builtin_bit_cast(bf8, ua), bv = __builtin_bit_cast(bf8, ub);
+                ac = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, ac, 0, 0, 0);
+                if constexpr (X3) {
+                    const U4 ual = Asl[st * 64], ubl = *(const U4 *)(Csl + st * KSTEP);
+                    ac = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, ubl), ac, 0, 0, 0);
+                    ac = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ual), bv, ac, 0, 0, 0);
+                }
+            }
+            if constexpr (PIPE) {
+                // a slice of the previous b's Y update
+#pragma unroll
+                for (int f = 0; f < FPS; ++f) {
+                    const int idx = st * FPS + f;
+                    if (idx < 4 * NB) y[idx / NB][idx % NB] += wprev[idx / NB] * ktp[idx % NB];
+                }
+            }
+        }
+        // w tile of this b: lane holds rows 16 (rt0 + ti) + 4 lk + r for cosmology beta
+        wprev = acc[0] + acc[1];
+        wprev[0] *= sc.x, wprev[1] *= sc.y, wprev[2] *= sc.z, wprev[3] *= sc.w;
+        if constexpr (PIPE) {
+#pragma unroll
+            for (int j = 0; j < NB; ++j) ktp[j] = kt[j];
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) y[r][j] += wprev[r] * kt[j];
+            wprev = f4{0, 0, 0, 0};
+        }
+        if (b + 1 < n_R) lstore((b + 1) & 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) y[r][j] += wprev[r] * ktp[j];
+    if (!active || beta >= batch) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        float *yp = Y + (((size_t)beta * rows_pad + 16 * (rt0 + ti) + 4 * lk + r) * n_chi + a) * NBP;
+#pragma unroll
+        for (int q = 0; q < NBP / 4; ++q) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (4 * q < NB) v = make_float4(y[r][4 * q], y[r][4 * q + 1], y[r][4 * q + 2], y[r][4 * q + 3]);
+            ((float4 *)yp)[q] = v;
+        }
+    }
+}
+
+template <int PREC, int NS>
+constexpr size_t fused_lds_bytes() {
+    using E = typename Cfg<PREC>::E;
+    constexpr int VEC = Cfg<PREC>::VEC;
+    constexpr int ncp = NS * 4 * VEC;
+    constexpr int NPART = PREC == BLAST_BF16X3 ? 2 : 1;
+    return 2 * NPART * ((size_t)kFusedTR * NS * 64 * 16 + (size_t)64 * (ncp + VEC) * sizeof(E));
+}
+
+// Kt[a, b][beta][bin] = wR_b K_bin(R_b chi_a) (FP32, NB bins with zero padding) for the fused
+// kernel.  A work-group transposes 32 points x 16 cosmologies through LDS: coalesced reads along
+// the points, 1 KB contiguous writes per point.
+__global__ __launch_bounds__(256) void kt_kernel(const double *__restrict__ Kchi2, const double *__restrict__ wR,
+                                                 int batch, int nbins, int NB, int NP, int n_R,
+                                                 float *__restrict__ Kt) {
+    __shared__ float tile[32][16 * 20 + 1];  // [point][beta_local * NB + bin], NB <= 20
+    const int ab0 = blockIdx.x * 32, b0 = blockIdx.y * 16;
+    const int nbeta = min(16, batch - b0);
+    for (int i = threadIdx.x; i < 16 * NB * 32; i += blockDim.x) {
+        const int p = i % 32, q = i / 32;  // q = beta_local * NB + bin
+        const int bl = q / NB, bin = q % NB, ab = ab0 + p;
+        float v = 0.f;
+        if (bl < nbeta && bin < nbins && ab < NP)
+            v = (float)(wR[ab % n_R] * Kchi2[((size_t)(b0 + bl) * nbins + bin) * NP + ab]);
+        tile[p][q] = v;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 32 * nbeta * NB; i += blockDim.x) {
+        const int p = i / (nbeta * NB), q = i % (nbeta * NB);
+        const int ab = ab0 + p;
+        if (ab < NP) Kt[((size_t)ab * batch + b0) * NB + q] = tile[p][q];
     }
 }
 
@@ -812,7 +1319,7 @@ __global__ __launch_bounds__(256) void contract_t_kernel(const typename std::con
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
     const int NT = ncp >> 4;
-    const T *bp = basis + (size_t)ab * rows_pad * ncp;
+    const T *bp = basis + (size_t)ab * rows_pad * ncp;  // FP64: row-major; FP32: tiled layout
     Acc acc[2][BTN];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -824,7 +1331,8 @@ __global__ __launch_bounds__(256) void contract_t_kernel(const typename std::con
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int nt = wv + 4 * i;
-            av[i] = nt < NT ? bp[(size_t)row * ncp + 16 * nt + lr] : (T)0;
+            const size_t o = F64 ? (size_t)row * ncp + 16 * nt + lr : tiled_off(row, 16 * nt + lr, ncp / 16, 4);
+            av[i] = nt < NT ? bp[o] : (T)0;
         }
 #pragma unroll
         for (int j = 0; j < BTN; ++j) bv[j] = ws[(16 * j + lr) * dst + row];
@@ -885,8 +1393,14 @@ struct Ctx {
 };
 
 struct Layout {
-    size_t c, clo, w, y, dy, sg, dw, dc, total;
+    size_t c, clo, w, kt, y, dy, sg, dw, dc, total;
 };
+
+// bins computed by the fused kernel (multiple of 4), 0 when it does not apply
+int fused_nb(int prec, int nbins) {
+    if (prec == BLAST_FP64 || nbins > 20) return 0;
+    return (nbins + 3) / 4 * 4;
+}
 
 Layout layout_of(const blast_plan *p, int batch, int prec, int nbins, bool need_w, bool adjoint) {
     Layout L{};
@@ -901,7 +1415,12 @@ Layout layout_of(const blast_plan *p, int batch, int prec, int nbins, bool need_
     L.clo = off;
     if (prec == BLAST_BF16X3) off += align256(nc * 2);
     L.w = off;
-    if (need_w) off += align256((size_t)batch * p->NP * p->rows_pad * te);
+    L.kt = off;
+    if (need_w) {
+        const int fnb = adjoint ? 0 : fused_nb(prec, nbins);
+        // the fused path keeps Kt where the unfused one keeps w
+        off += align256(std::max((size_t)batch * p->NP * p->rows_pad * te, (size_t)batch * p->NP * fnb * 4));
+    }
     L.y = off;
     off += align256(ny * te);
     if (adjoint) {
@@ -1052,7 +1571,18 @@ void stage_project(blast_plan *p, const blast_cl_args *a, const Ctx &x, void *c,
 #undef BLAST_CI
         return;
     }
-    if (N % (f64 ? 8 : 16) == 0) {
+    if (!f64 && N % 32 == 0) {
+        dim3 grid((unsigned)((nrows + 64 * kSplitRT - 1) / (64 * kSplitRT)));
+        const size_t shp = (size_t)2 * (N / 2) * (N / 2 + 4) * sizeof(float);
+#define BLAST_PROJ(PT, O) \
+    hipLaunchKernelGGL((project_split_kernel<PT, O>), grid, dim3(256), shp, s, (const PT *)a->P, p->d_dctn32, N, \
+                       nrows, c, clo)
+        if (p64 && out == 1) BLAST_PROJ(double, 1);
+        if (p64 && out == 2) BLAST_PROJ(double, 2);
+        if (!p64 && out == 1) BLAST_PROJ(float, 1);
+        if (!p64 && out == 2) BLAST_PROJ(float, 2);
+#undef BLAST_PROJ
+    } else if (N % (f64 ? 8 : 16) == 0) {
         dim3 grid((unsigned)((nrows + 255) / 256));
         const size_t shp = f64 ? 0 : (size_t)ncp * (N + 4) * sizeof(float);
 #define BLAST_PROJ(PT, F, O, D)                                                                                  \
@@ -1092,8 +1622,15 @@ void stage_contract(blast_plan *p, const blast_cl_args *a, const Ctx &x, const v
         dim3 grid(p->NP, (a->batch + BT - 1) / BT);
         const E *bas = PR == BLAST_FP64 ? (const E *)p->basis.f64
                                         : (PR == BLAST_FP32 ? (const E *)p->basis.f32 : (const E *)p->basis.hi);
-        hipLaunchKernelGGL((contract_kernel<PR>), grid, dim3(256), sh, s, bas, p->basis.lo, p->basis.scale,
-                           (const E *)c, clo, a->batch, p->NP, p->rows_pad, ncp, w);
+        if constexpr (PR == BLAST_FP64) {
+            hipLaunchKernelGGL((contract_kernel<PR>), grid, dim3(256), sh, s, bas, p->basis.lo, p->basis.scale,
+                               (const E *)c, clo, a->batch, p->NP, p->rows_pad, ncp, w);
+        } else {
+            const int RT = p->rows_pad / 16;
+            const int W = std::min((RT + kTilesPerWave - 1) / kTilesPerWave, 8);
+            hipLaunchKernelGGL((contract_tiled_kernel<PR>), grid, dim3(64 * W), sh, s, bas, p->basis.lo,
+                               p->basis.scale, (const E *)c, clo, a->batch, p->NP, p->rows_pad, ncp, (float *)w);
+        }
     };
     if (x.prec == BLAST_FP64) launch(std::integral_constant<int, BLAST_FP64>());
     if (x.prec == BLAST_FP32) launch(std::integral_constant<int, BLAST_FP32>());
@@ -1116,6 +1653,55 @@ void stage_quad_y(blast_plan *p, const blast_cl_args *a, const Ctx &x, const voi
     if (!f64 && x.nbp == 16) BLAST_QY(float, 16);
     if (!f64 && x.nbp == 32) BLAST_QY(float, 32);
 #undef BLAST_QY
+}
+
+// stages 2 + 3 fused (mixed precisions without w_save)
+void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, int nb, const void *c,
+                         const uint16_t *clo, float *Kt, float *Y, hipStream_t s) {
+    dim3 gk((unsigned)((p->NP + 31) / 32), (unsigned)((a->batch + 15) / 16));
+    hipLaunchKernelGGL(kt_kernel, gk, dim3(256), 0, s, a->K_chi2, p->d_wR, a->batch, x.nbins, nb, p->NP, p->n_R, Kt);
+    const int RT = p->rows_pad / 16, nBT = (a->batch + 63) / 64;
+    const int groups = (RT + kFusedTR - 1) / kFusedTR;
+    const int units = p->n_chi * nBT * groups;
+    const unsigned grid = (unsigned)((units + 7) / 8 * 8);
+    auto launch = [&](auto ptag, auto nbtag, auto nbptag, auto nstag) {
+        constexpr int PR = decltype(ptag)::value, NB = decltype(nbtag)::value, NBP = decltype(nbptag)::value;
+        constexpr int NS = decltype(nstag)::value;
+        using E = typename Cfg<PR>::E;
+        constexpr size_t lds = fused_lds_bytes<PR, NS>();
+        static std::once_flag once;
+        std::call_once(once, [] {
+            (void)hipFuncSetAttribute((const void *)contract_quad_kernel<PR, NB, NBP, NS>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        });
+        const E *bas = PR == BLAST_FP32 ? (const E *)p->basis.f32 : (const E *)p->basis.hi;
+        hipLaunchKernelGGL((contract_quad_kernel<PR, NB, NBP, NS>), dim3(grid), dim3(256 * kFusedTR), lds, s, bas,
+                           p->basis.lo, p->basis.scale, (const E *)c, clo, Kt, a->batch, p->n_chi, p->n_R,
+                           p->rows_pad, nBT, units, Y);
+    };
+    // nc_pad is a multiple of 32 up to 128: 1..4 blocks of 32 columns
+    auto by_ns = [&](auto ptag, auto nbtag, auto nbptag) {
+        constexpr int PR = decltype(ptag)::value;
+        constexpr int S32 = PR == BLAST_FP32 ? 2 : 1;  // steps per 32 columns
+        switch (p->nc_pad / 32) {
+            case 1: launch(ptag, nbtag, nbptag, std::integral_constant<int, S32>()); break;
+            case 2: launch(ptag, nbtag, nbptag, std::integral_constant<int, 2 * S32>()); break;
+            case 3: launch(ptag, nbtag, nbptag, std::integral_constant<int, 3 * S32>()); break;
+            default: launch(ptag, nbtag, nbptag, std::integral_constant<int, 4 * S32>()); break;
+        }
+    };
+    auto by_nb = [&](auto ptag) {
+        switch (nb) {
+            case 4: by_ns(ptag, std::integral_constant<int, 4>(), std::integral_constant<int, 16>()); break;
+            case 8: by_ns(ptag, std::integral_constant<int, 8>(), std::integral_constant<int, 16>()); break;
+            case 12: by_ns(ptag, std::integral_constant<int, 12>(), std::integral_constant<int, 16>()); break;
+            case 16: by_ns(ptag, std::integral_constant<int, 16>(), std::integral_constant<int, 16>()); break;
+            default: by_ns(ptag, std::integral_constant<int, 20>(), std::integral_constant<int, 32>()); break;
+        }
+    };
+    if (x.prec == BLAST_FP32) by_nb(std::integral_constant<int, BLAST_FP32>());
+    if (x.prec == BLAST_BF16) by_nb(std::integral_constant<int, BLAST_BF16>());
+    if (x.prec == BLAST_BF16X3) by_nb(std::integral_constant<int, BLAST_BF16X3>());
 }
 
 // stage 4: C = chi-quadrature and pair assembly
@@ -1152,12 +1738,18 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     uint16_t *clo = x.prec == BLAST_BF16X3 ? (uint16_t *)(ws + L.clo) : nullptr;
     void *w = need_w ? (void *)(ws + L.w) : a->w_save;
     void *Y = ws + L.y;
+    const int fnb = need_w ? fused_nb(x.prec, x.nbins) : 0;
     mark(0);
     stage_project(p, a, x, c, clo, s);
     mark(1);
-    stage_contract(p, a, x, c, clo, w, s);
-    mark(2);
-    stage_quad_y(p, a, x, w, Y, s);
+    if (fnb) {
+        stage_contract_quad(p, a, x, fnb, c, clo, (float *)(ws + L.kt), (float *)Y, s);
+        mark(2);
+    } else {
+        stage_contract(p, a, x, c, clo, w, s);
+        mark(2);
+        stage_quad_y(p, a, x, w, Y, s);
+    }
     mark(3);
     stage_quad_c(p, a, x, Y, s);
     mark(4);

@@ -22,6 +22,18 @@ constexpr int kBatchTile = 64;   // cosmologies per contraction work-group pass
 
 inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
+// Reduced-precision basis copies (FP32, BF16 hi/lo) are stored per (chi_a, R_b) point in the
+// register image of the contraction's MFMA A operand: 16-row tiles, steps of KSTEP = 4*VEC
+// columns, and inside one (tile, step) the 16-byte vectors of the 64 lanes in lane order
+// (lane = row % 16 + 16 * ((n % KSTEP) / VEC)), so that each load of a tile is 1 KB contiguous.
+// VEC = 16 bytes / element size; nsteps = nc_pad / KSTEP.  Returns the element offset of
+// (row, n) inside the point's rows_pad * nc_pad block.
+__host__ __device__ inline size_t tiled_off(int row, int n, int nsteps, int VEC) {
+    const int KSTEP = 4 * VEC;
+    const int lane = (row & 15) + 16 * ((n % KSTEP) / VEC);
+    return (((size_t)(row >> 4) * nsteps + n / KSTEP) * 64 + lane) * VEC + n % VEC;
+}
+
 // Power-of-two scale and the BF16 bit pattern helpers shared by host conversions.
 struct BasisBuffers {
     double *f64 = nullptr;     // [NP][rows_pad][nc_pad]
