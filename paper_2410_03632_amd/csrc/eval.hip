@@ -775,14 +775,79 @@ __global__ __launch_bounds__(256) void quad_y_kernel(const T *__restrict__ w, co
 //   Y[beta][row][a][bin] += w[row][beta] * Kt[a, b][beta][bin]               (VALU, per b)
 // with Kt = wR_b K_bin(R_b chi_a).  Work-group = (chi_a, batch tile of 64, group of TR row
 // tiles), 4*TR waves: wave (i, k) makes the 16 x 16 tile (row tile i, cosmologies 16k..16k+15)
-// for every b and keeps Y for its 4 rows x NB bins.  Per b the work-group stages the TR basis
-// tiles (tiled layout: one contiguous block) and the 64 c rows in LDS, shared by the 4 waves of
-// a row tile and the TR waves of a batch sub-tile; the global loads for b+1 are issued before
-// the MFMAs of b and land in the other LDS buffer after them (one barrier per b).
-// Work-groups are numbered so that the row groups and batch tiles of one chi_a run together on
-// one XCD (work-groups go round-robin over the 8 XCDs) and share c rows and basis tiles in its
-// L2.  Y rows are written with stride NBP (zero padding), the layout of the chi-quadrature.
+// for every b and keeps Y for its 4 rows x NB bins.  Per b the TR basis tiles (tiled layout:
+// contiguous 1 KB register images) and the 64 c rows are moved straight from global memory to
+// LDS (global_load_lds_dwordx4, no registers), shared by the 4 waves of a row tile and the TR
+// waves of a cosmology sub-tile.  Basis tiles run two b ahead (3 LDS buffers), c rows one b
+// ahead (2 buffers); one barrier per b.  The c rows sit in LDS with their 16-byte granules
+// permuted (granule v of row r at v ^ (r & 7)) so that the 16 rows read by one instruction
+// spread over the banks.  Work-groups are numbered so that the row groups and batch tiles of
+// one chi_a run together on one XCD (work-groups go round-robin over the 8 XCDs) and share c
+// rows and basis tiles in its L2.  Y rows are written with stride NBP (zero padding), the layout
+// of the chi-quadrature.
 constexpr int kFusedTR = 3;
+
+template <int PREC, int NS>
+struct FusedShape {
+    using E = typename Cfg<PREC>::E;
+    static constexpr int VEC = Cfg<PREC>::VEC, KSTEP = 4 * VEC, ncp = NS * KSTEP;
+    static constexpr int NPART = PREC == BLAST_BF16X3 ? 2 : 1;
+    static constexpr int ROWB = ncp * (int)sizeof(E);                  // bytes of one c row
+    static constexpr int A_CH = kFusedTR * NS * NPART;                 // 1 KB chunks of basis per b
+    static constexpr int C_CH = 64 * ROWB * NPART / 1024;              // 1 KB chunks of c per b
+    static constexpr int NW = 4 * kFusedTR;                            // waves
+    static constexpr int A_PW = (A_CH + NW - 1) / NW, C_PW = (C_CH + NW - 1) / NW;  // per wave
+    static constexpr size_t A_BUF = (size_t)A_CH * 1024, C_BUF = (size_t)C_CH * 1024;
+    // per b also: kernel weights of the 64 cosmologies (<= 20 bins: <= 5 KB) and row scales
+    static constexpr size_t X_BUF = 6 * 1024;
+    static constexpr size_t LDS = 3 * A_BUF + 2 * (C_BUF + X_BUF);
+};
+
+__device__ inline void lds_dma16(const void *g, void *l) {
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)g,
+                                     (void __attribute__((address_space(3))) *)l, 16, 0, 0);
+}
+
+// LDS reads of DMA-filled buffers.  Written as asm so that the compiler, which cannot always tell
+// which buffer an LDS DMA in flight writes, adds no wait for the DMAs (the kernel orders them
+// itself with explicit counts and barriers); each block waits for its own reads before it ends.
+__device__ inline uint32_t lds_addr(const void *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+// f(integral_constant<I>) for I = B..N-1
+template <int I, int N, typename F>
+__device__ inline void static_for(F &f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>());
+        static_for<I + 1, N>(f);
+    }
+}
+
+// two (or four) 16-byte reads at base + compile-time offset, then a wait for them
+template <int O0, int O1>
+__device__ inline void lds_read2(uint32_t b0, uint32_t b1, U4 &r0, U4 &r1) {
+    asm volatile("ds_read_b128 %0, %2 offset:%4\n\tds_read_b128 %1, %3 offset:%5\n\ts_waitcnt lgkmcnt(0)"
+                 : "=&v"(r0), "=&v"(r1)
+                 : "v"(b0), "v"(b1), "i"(O0), "i"(O1)
+                 : "memory");
+}
+template <int O0, int O1, int O2, int O3>
+__device__ inline void lds_read4(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3, U4 &r0, U4 &r1, U4 &r2,
+                                 U4 &r3) {
+    asm volatile(
+        "ds_read_b128 %0, %4 offset:%8\n\tds_read_b128 %1, %5 offset:%9\n\t"
+        "ds_read_b128 %2, %6 offset:%10\n\tds_read_b128 %3, %7 offset:%11\n\ts_waitcnt lgkmcnt(0)"
+        : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)
+        : "v"(b0), "v"(b1), "v"(b2), "v"(b3), "i"(O0), "i"(O1), "i"(O2), "i"(O3)
+        : "memory");
+}
+
+// s_waitcnt with only the vector-memory counter constrained (gfx9 encoding)
+template <int N>
+__device__ inline void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt out of range");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
 
 template <int PREC, int NB, int NBP, int NS>
 __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
@@ -790,19 +855,19 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     const float *__restrict__ scale, const typename Cfg<PREC>::E *__restrict__ c, const uint16_t *__restrict__ c_lo,
     const float *__restrict__ Kt, int batch, int n_chi, int n_R, int rows_pad, int nBT, int units,
     float *__restrict__ Y) {
-    using E = typename Cfg<PREC>::E;
-    constexpr int TR = kFusedTR, NT = 256 * TR;
-    constexpr int VEC = Cfg<PREC>::VEC, KSTEP = 4 * VEC;
-    constexpr int ncp = NS * KSTEP;
+    using S = FusedShape<PREC, NS>;
+    using E = typename S::E;
+    constexpr int TR = kFusedTR, VEC = S::VEC, KSTEP = S::KSTEP, ncp = S::ncp, NPART = S::NPART;
     constexpr bool X3 = PREC == BLAST_BF16X3;
-    constexpr int NPART = X3 ? 2 : 1;                     // hi (and lo) parts
-    constexpr int A_U4 = TR * NS * 64;                    // U4s of the staged basis tiles (per part)
-    constexpr int CST = ncp + VEC;                        // LDS row stride of c (elements), 16 B pad
-    constexpr int C_U4 = 64 * ncp / VEC;                  // U4s of the 64 c rows (per part)
-    constexpr int ST_A = (A_U4 + NT - 1) / NT, ST_C = (C_U4 + NT - 1) / NT;
-    extern __shared__ __align__(16) unsigned char smem_f[];
-    constexpr size_t A_BYTES = (size_t)A_U4 * 16, C_BYTES = (size_t)64 * CST * sizeof(E);
-    constexpr size_t BUF = NPART * (A_BYTES + C_BYTES);
+    constexpr int GPR = S::ROWB / 16;            // granules per c row
+    constexpr int RPC = 1024 / S::ROWB;          // c rows per 1 KB chunk
+    // granule permutation mask: XOR by up to SWZ stays inside the row when SWZ + 1 divides GPR
+    constexpr int SWZ = GPR % 8 == 0 ? 7 : (GPR % 4 == 0 ? 3 : (GPR % 2 == 0 ? 1 : 0));
+    // five distinct LDS objects, so that the compiler can tell the buffer a DMA writes from the
+    // buffers the MFMA loop reads (and does not wait for the DMAs in flight)
+    static_assert(S::LDS <= 160 * 1024, "LDS of the fused kernel");
+    __shared__ __align__(1024) unsigned char A0[S::A_BUF], A1[S::A_BUF], A2[S::A_BUF];
+    __shared__ __align__(1024) unsigned char C0[S::C_BUF + S::X_BUF], C1[S::C_BUF + S::X_BUF];
 
     const int groups = (rows_pad / 16 + TR - 1) / TR;
     const int per = (units + 7) / 8;
@@ -811,59 +876,56 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     const int RT = rows_pad / 16;
     const int g = unit % groups, bt = (unit / groups) % nBT, a = unit / (groups * nBT);
     const int rt0 = g * TR;
-    const int ntile = min(TR, RT - rt0);                  // row tiles of this group
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ntile = min(TR, RT - rt0);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
-    const int ti = w >> 2, tk = w & 3;                    // row tile, 16-cosmology sub-tile
+    const int ti = w >> 2, tk = w & 3;         // row tile, 16-cosmology sub-tile
     const int beta = bt * 64 + 16 * tk + lr;
-    const bool active = ti < ntile && bt * 64 + 16 * tk < batch;
-    const int bcl = beta < batch ? beta : batch - 1;
     const int nb = min(64, batch - bt * 64);
     const size_t NP = (size_t)n_chi * n_R;
-    const size_t pt_u4 = (size_t)RT * NS * 64;             // U4s per point in the tiled layout
+    const size_t pt_u4 = (size_t)RT * NS * 64;  // U4s per point in the tiled layout
 
-    // staging of one b: basis tiles rt0.. (contiguous; rows past the last tile are clamped) and c rows
-    U4 sa[NPART][ST_A], sc_[NPART][ST_C];
-    auto gload = [&](int b) {
-        const size_t ab = (size_t)a * n_R + b;
-        const size_t abase = ab * pt_u4 + (size_t)rt0 * NS * 64;
-        const size_t alim = ab * pt_u4 + pt_u4 - 1;
+    // every wave issues exactly A_PW + C_PW DMA instructions per b (chunk indices past the end are
+    // clamped to the last chunk, which is then written more than once with identical data), so
+    // the wait counts below are constants
+    auto dma_A = [&](int b, unsigned char *__restrict__ buf) {
+        const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
 #pragma unroll
-        for (int k = 0; k < ST_A; ++k) {
-            const int i = threadIdx.x + k * NT;
-            const size_t o = min(abase + (size_t)(i < A_U4 ? i : 0), alim);
-            sa[0][k] = ((const U4 *)basis)[o];
-            if (X3) sa[NPART - 1][k] = ((const U4 *)basis_lo)[o];
-        }
-#pragma unroll
-        for (int k = 0; k < ST_C; ++k) {
-            const int i = threadIdx.x + k * NT;
-            const int row = (i < C_U4 ? i : 0) / (ncp / VEC), v = (i < C_U4 ? i : 0) % (ncp / VEC);
-            const int bb = row < nb ? bt * 64 + row : bt * 64;
-            const size_t o = ((size_t)bb * NP + ab) * ncp + (size_t)v * VEC;
-            sc_[0][k] = *(const U4 *)(c + o);
-            if (X3) sc_[NPART - 1][k] = *(const U4 *)(c_lo + o);
+        for (int k = 0; k < S::A_PW; ++k) {
+            const int ch = min(w + k * S::NW, S::A_CH - 1);
+            const int part = ch / (TR * NS), tl = (ch / NS) % TR, st = ch % NS;
+            const int rt = min(rt0 + tl, RT - 1);
+            const U4 *src = (const U4 *)(part ? (const void *)basis_lo : (const void *)basis) +
+                            ab * pt_u4 + ((size_t)rt * NS + st) * 64 + lane;
+            lds_dma16(src, buf + (size_t)ch * 1024);
         }
     };
-    auto lstore = [&](int buf) {
-        unsigned char *base = smem_f + (size_t)buf * BUF;
+    // kernel weights Kt[ab][64 cosmologies][NB] (contiguous) and the row scales of the group, one
+    // DMA per wave: waves 0..KCH-1 move weight chunks, wave KCH the scales, the others repeat
+    constexpr int KCH = 64 * NB * 4 / 1024;
+    static_assert(KCH + 1 <= S::NW && TR * 16 * 4 <= 1024 && KCH * 1024 + 1024 <= (int)S::X_BUF, "extra region");
+    auto dma_X = [&](int b, unsigned char *__restrict__ buf) {
+        const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
+        const int ch = min(w, KCH);
+        const int f = ch * 256 + lane * 4;                   // float index in the 64 x NB block
+        const int bl = f / NB;
+        // cosmologies past the batch read the tile's first weight instead (never used)
+        const float *kp = Kt + (ab * batch + bt * 64 + (bl < nb ? bl : 0)) * NB + (bl < nb ? f % NB : 0);
+        const int row = min(16 * rt0 + 4 * lane, rows_pad - 4);
+        const float *sp = PREC != BLAST_FP32 ? scale + ab * rows_pad + row : Kt;
+        lds_dma16(ch < KCH ? kp : sp, buf + S::C_BUF + (size_t)ch * 1024);
+    };
+    auto dma_C = [&](int b, unsigned char *__restrict__ buf) {
+        const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
 #pragma unroll
-        for (int part = 0; part < NPART; ++part) {
-            U4 *As = (U4 *)(base + part * A_BYTES);
-            E *Cs = (E *)(base + NPART * A_BYTES + part * C_BYTES);
-#pragma unroll
-            for (int k = 0; k < ST_A; ++k) {
-                const int i = threadIdx.x + k * NT;
-                if (i < A_U4) As[i] = sa[part][k];
-            }
-#pragma unroll
-            for (int k = 0; k < ST_C; ++k) {
-                const int i = threadIdx.x + k * NT;
-                if (i < C_U4) {
-                    const int row = i / (ncp / VEC), v = i % (ncp / VEC);
-                    *(U4 *)(Cs + (size_t)row * CST + v * VEC) = sc_[part][k];
-                }
-            }
+        for (int k = 0; k < S::C_PW; ++k) {
+            const int ch = min(w + k * S::NW, S::C_CH - 1);
+            const int part = ch / (S::C_CH / NPART), chp = ch % (S::C_CH / NPART);
+            const int row = chp * RPC + lane / GPR, gp = lane % GPR;
+            const int v = gp ^ (row & SWZ);          // granule stored at position gp
+            const int bb = bt * 64 + (row < nb ? row : 0);
+            const E *src = (part ? (const E *)c_lo : c) + ((size_t)bb * NP + ab) * ncp + v * VEC;
+            lds_dma16(src, buf + (size_t)ch * 1024);
         }
     };
 
@@ -872,89 +934,106 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int j = 0; j < NB; ++j) y[r][j] = 0.f;
+    const int crow = 16 * tk + lr;
+    const int arow = min(ti, TR - 1) * NS * 64 + lane;  // U4 offset of the wave's basis tile
 
-    // the Y update of b-1 (VALU) is interleaved with the MFMAs of b where the registers allow
-    constexpr bool PIPE = !X3 && NB <= 16;
-    f4 wprev = f4{0, 0, 0, 0};
-    float ktp[NB];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) ktp[j] = 0.f;
-    constexpr int FPS = (4 * NB + NS - 1) / NS;  // Y FMAs per step
-
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int b = 0; b < n_R; ++b) {
-        if (b + 1 < n_R) gload(b + 1);
-        // kernel weights (and BF16 row scales) of this b
+    // one b: buffers fixed at compile time (b mod 3 for the basis, b mod 2 for c)
+    // (restrict: the compiler tags the LDS accesses with alias scopes, which its wait-count logic
+    // needs before it will tell a DMA's target buffer from the buffers being read)
+    auto step = [&](int b, const unsigned char *__restrict__ Ab, const unsigned char *__restrict__ Cb,
+                    unsigned char *__restrict__ Cnext, unsigned char *__restrict__ Anext2) {
+        // c(b), weights(b) and A(b) have landed once only A(b+1) may still be in flight; the
+        // barrier is a plain s_barrier (a fence would drain every outstanding load)
+        wait_vmcnt<S::A_PW>();
+        __builtin_amdgcn_s_barrier();
+        // the DMAs for b+1 and b+2 go out before any LDS read of b: the compiler then sees that
+        // they write other buffers than the ones read here and adds no wait for them
+        __builtin_amdgcn_sched_barrier(0);
+        dma_C(b + 1, Cnext);
+        dma_X(b + 1, Cnext);
+        dma_A(b + 2, Anext2);
+        __builtin_amdgcn_sched_barrier(0);
+        // weights of this b's cosmology and the row scales, from LDS
         float kt[NB];
+        float4 sc = make_float4(1.f, 1.f, 1.f, 1.f);
         {
-            const float4 *kp = (const float4 *)(Kt + (((size_t)a * n_R + b) * batch + bcl) * NB);
+            const uint32_t kb = lds_addr(Cb + S::C_BUF) + (uint32_t)(16 * tk + lr) * (NB * 4);
+            const uint32_t sa = lds_addr(Cb + S::C_BUF + (size_t)KCH * 1024) + (uint32_t)(16 * min(ti, TR - 1) + 4 * lk) * 4;
+            U4 q[6];
+            constexpr int NQ = NB / 4;  // 1..5
+            lds_read4<0, (NQ > 1 ? 16 : 0), (NQ > 2 ? 32 : 0), (NQ > 3 ? 48 : 0)>(kb, kb, kb, kb, q[0], q[1], q[2], q[3]);
+            lds_read2<(NQ > 4 ? 64 : 0), 0>(kb, sa, q[4], q[5]);
 #pragma unroll
-            for (int q = 0; q < NB / 4; ++q) {
-                const float4 v = kp[q];
-                kt[4 * q] = v.x, kt[4 * q + 1] = v.y, kt[4 * q + 2] = v.z, kt[4 * q + 3] = v.w;
+            for (int j = 0; j < NQ; ++j) {
+                const f4v v = __builtin_bit_cast(f4v, q[j]);
+                kt[4 * j] = v[0], kt[4 * j + 1] = v[1], kt[4 * j + 2] = v[2], kt[4 * j + 3] = v[3];
+            }
+            if constexpr (PREC != BLAST_FP32) {
+                const f4v v = __builtin_bit_cast(f4v, q[5]);
+                sc = make_float4(v[0], v[1], v[2], v[3]);
             }
         }
-        float4 sc = make_float4(1.f, 1.f, 1.f, 1.f);
-        if constexpr (PREC != BLAST_FP32) {
-            const int rsafe = 16 * min(rt0 + ti, RT - 1) + 4 * lk;
-            sc = *(const float4 *)(scale + ((size_t)a * n_R + b) * rows_pad + rsafe);
-        }
-        const unsigned char *base = smem_f + (size_t)(b & 1) * BUF;
-        const U4 *As = (const U4 *)base + (size_t)min(ti, TR - 1) * NS * 64 + lane;
-        const U4 *Asl = X3 ? (const U4 *)(base + A_BYTES) + (size_t)min(ti, TR - 1) * NS * 64 + lane : nullptr;
-        const E *Cs = (const E *)(base + NPART * A_BYTES) + (size_t)(16 * tk + lr) * CST + lk * VEC;
-        const E *Csl = X3 ? (const E *)(base + NPART * A_BYTES + C_BYTES) + (size_t)(16 * tk + lr) * CST + lk * VEC
-                          : nullptr;
-        f4 acc[2] = {f4{0, 0, 0, 0}, f4{0, 0, 0, 0}};
-#pragma unroll
-        for (int st = 0; st < NS; ++st) {
-            const U4 ua = As[st * 64], ub = *(const U4 *)(Cs + st * KSTEP);
-            f4 &ac = acc[st & 1];
+        const uint32_t As = lds_addr(Ab) + (uint32_t)arow * 16;
+        const uint32_t Asl = As + TR * NS * 64 * 16;
+        // granule (4 st + lk) of row crow sits at ((4 st + lk) ^ m) with m = crow & SWZ, i.e. at
+        // 4 (st ^ (m >> 2)) + (lk ^ (m & 3)): one base for even and one for odd steps
+        const uint32_t Cr = lds_addr(Cb) + (uint32_t)crow * S::ROWB;
+        const int m = crow & SWZ, h = (m >> 2) & 1, l = lk ^ (m & 3);
+        const uint32_t Ce = Cr + 16 * (4 * h + l), Co = Cr + 16 * (4 * (1 - h) + l);  // st even / odd
+        const uint32_t Cel = Ce + S::C_BUF / NPART, Col = Co + S::C_BUF / NPART;
+        // four accumulators, so that consecutive MFMAs never wait for each other
+        f4 acc[4] = {f4{0, 0, 0, 0}, f4{0, 0, 0, 0}, f4{0, 0, 0, 0}, f4{0, 0, 0, 0}};
+        auto step_k = [&](auto stc) {
+            constexpr int st = decltype(stc)::value;
+            constexpr int coff = 64 * (st & ~1);
+            const uint32_t cb = (st & 1) ? Co : Ce, cbl = (st & 1) ? Col : Cel;
+            U4 ua, ub, ual, ubl;
+            if constexpr (X3)
+                lds_read4<st * 1024, coff, st * 1024, coff>(As, cb, Asl, cbl, ua, ub, ual, ubl);
+            else
+                lds_read2<st * 1024, coff>(As, cb, ua, ub);
             if constexpr (PREC == BLAST_FP32) {
                 const f4v av = __builtin_bit_cast(f4v, ua), bv = __builtin_bit_cast(f4v, ub);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) ac = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e], bv[e], ac, 0, 0, 0);
+                for (int e = 0; e < 4; ++e)
+                    acc[e] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e], bv[e], acc[e], 0, 0, 0);
             } else {
                 const bf8 av = __builtin_bit_cast(bf8, ua), bv = __builtin_bit_cast(bf8, ub);
-                ac = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, ac, 0, 0, 0);
+                f4 &a0 = acc[st & 1];
+                a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, a0, 0, 0, 0);
                 if constexpr (X3) {
-                    const U4 ual = Asl[st * 64], ubl = *(const U4 *)(Csl + st * KSTEP);
-                    ac = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, ubl), ac, 0, 0, 0);
-                    ac = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ual), bv, ac, 0, 0, 0);
+                    f4 &a1 = acc[2 + (st & 1)];
+                    a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, ubl), a1, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ual), bv, a1, 0, 0, 0);
                 }
             }
-            if constexpr (PIPE) {
-                // a slice of the previous b's Y update
-#pragma unroll
-                for (int f = 0; f < FPS; ++f) {
-                    const int idx = st * FPS + f;
-                    if (idx < 4 * NB) y[idx / NB][idx % NB] += wprev[idx / NB] * ktp[idx % NB];
-                }
-            }
-        }
+        };
+        static_for<0, NS>(step_k);
         // w tile of this b: lane holds rows 16 (rt0 + ti) + 4 lk + r for cosmology beta
-        wprev = acc[0] + acc[1];
-        wprev[0] *= sc.x, wprev[1] *= sc.y, wprev[2] *= sc.z, wprev[3] *= sc.w;
-        if constexpr (PIPE) {
+        f4 wv = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        wv[0] *= sc.x, wv[1] *= sc.y, wv[2] *= sc.z, wv[3] *= sc.w;
 #pragma unroll
-            for (int j = 0; j < NB; ++j) ktp[j] = kt[j];
-        } else {
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int j = 0; j < NB; ++j) y[r][j] += wprev[r] * kt[j];
-            wprev = f4{0, 0, 0, 0};
-        }
-        if (b + 1 < n_R) lstore((b + 1) & 1);
-        __syncthreads();
+            for (int j = 0; j < NB; ++j) y[r][j] += wv[r] * kt[j];
+    };
+
+    // issue order: A(0), c(0) + weights(0), A(1); then per b, after its barrier: c(b+1) +
+    // weights(b+1), A(b+2).  Only DMAs are in flight, so the manual counts are exact.
+    dma_A(0, A0);
+    dma_C(0, C0);
+    dma_X(0, C0);
+    dma_A(1, A1);
+    for (int b = 0; b < n_R; b += 6) {
+        step(b, A0, C0, C1, A2);
+        if (b + 1 < n_R) step(b + 1, A1, C1, C0, A0);
+        if (b + 2 < n_R) step(b + 2, A2, C0, C1, A1);
+        if (b + 3 < n_R) step(b + 3, A0, C1, C0, A2);
+        if (b + 4 < n_R) step(b + 4, A1, C0, C1, A0);
+        if (b + 5 < n_R) step(b + 5, A2, C1, C0, A1);
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int j = 0; j < NB; ++j) y[r][j] += wprev[r] * ktp[j];
-    if (!active || beta >= batch) return;
+    wait_vmcnt<0>();  // no DMA may outlive the work-group's LDS
+    if (ti >= ntile || beta >= batch) return;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         float *yp = Y + (((size_t)beta * rows_pad + 16 * (rt0 + ti) + 4 * lk + r) * n_chi + a) * NBP;
@@ -965,15 +1044,6 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
             ((float4 *)yp)[q] = v;
         }
     }
-}
-
-template <int PREC, int NS>
-constexpr size_t fused_lds_bytes() {
-    using E = typename Cfg<PREC>::E;
-    constexpr int VEC = Cfg<PREC>::VEC;
-    constexpr int ncp = NS * 4 * VEC;
-    constexpr int NPART = PREC == BLAST_BF16X3 ? 2 : 1;
-    return 2 * NPART * ((size_t)kFusedTR * NS * 64 * 16 + (size_t)64 * (ncp + VEC) * sizeof(E));
 }
 
 // Kt[a, b][beta][bin] = wR_b K_bin(R_b chi_a) (FP32, NB bins with zero padding) for the fused
@@ -1668,14 +1738,9 @@ void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, in
         constexpr int PR = decltype(ptag)::value, NB = decltype(nbtag)::value, NBP = decltype(nbptag)::value;
         constexpr int NS = decltype(nstag)::value;
         using E = typename Cfg<PR>::E;
-        constexpr size_t lds = fused_lds_bytes<PR, NS>();
-        static std::once_flag once;
-        std::call_once(once, [] {
-            (void)hipFuncSetAttribute((const void *)contract_quad_kernel<PR, NB, NBP, NS>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        });
         const E *bas = PR == BLAST_FP32 ? (const E *)p->basis.f32 : (const E *)p->basis.hi;
-        hipLaunchKernelGGL((contract_quad_kernel<PR, NB, NBP, NS>), dim3(grid), dim3(256 * kFusedTR), lds, s, bas,
+        // all LDS of the fused kernel is static (FusedShape::LDS bytes)
+        hipLaunchKernelGGL((contract_quad_kernel<PR, NB, NBP, NS>), dim3(grid), dim3(256 * kFusedTR), 0, s, bas,
                            p->basis.lo, p->basis.scale, (const E *)c, clo, Kt, a->batch, p->n_chi, p->n_R,
                            p->rows_pad, nBT, units, Y);
     };
