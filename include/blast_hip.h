@@ -275,6 +275,42 @@ blast_status blast_server_destroy(blast_server *srv);
  * and pair assembly.  The events cost a few microseconds per call. */
 blast_status blast_plan_profile(blast_plan *plan, int32_t enable);
 
+/* ------------------------------------------------------------------------ */
+/* Limber approximations (Sec. 2.2) and the non-linear correction (Sec. 3.2) */
+/* ------------------------------------------------------------------------ */
+
+/* Where the Limber approximation samples P: k[l][a] = (ell_l + 1/2) / chi_a at chi1 = chi2 =
+ * chi_a (host [n_ell][n_chi], plan ell order). */
+blast_status blast_plan_limber_k(const blast_plan *plan, double *k);
+
+typedef struct {
+    int32_t batch;
+    int32_t p_dtype;          /* 0: P and P_sub are double, 1: float */
+    const void *P;            /* device [batch][n_ell][n_chi]: P(k[l][a], chi_a, chi_a), plan ell order */
+    const void *P_sub;        /* device, nullable: same layout, subtracted from P */
+    int32_t n_g, n_s;         /* bins as in blast_cl_args */
+    const double *K_chi;      /* device [batch][n_g + n_s][n_chi]: calligraphic kernels at chi_a */
+    uint32_t types;           /* subset of the plan's types */
+    int32_t n_ell_out;        /* 0: all plan multipoles */
+    const int32_t *ell_idx;   /* host [n_ell_out], increasing indices into the plan's ell */
+    int32_t order;            /* 1: Limber, 2: extended Limber (needs n_chi >= 5) */
+    int32_t accumulate;       /* 0: C = C_limb, 1: C += C_limb */
+    double *C;                /* device [batch][n_pairs][n_ell_out], pair order as blast_cl_forward */
+} blast_limber_args;
+
+/* Limber spectra on the plan's chi quadrature, in FP64:
+ *   C_ij(l) = N_t(l) (pi/2) sum_a wchi_a f_t(k)/k^2 (P - P_sub)[l][a] / chi_a^2 E_ij(l, a),
+ * k = (l+1/2)/chi_a; E = K_i K_j for order 1 and, for order 2 (the extended approximation),
+ *   E = K_i K_j - nu^-2 sqrt(chi) [(chi^2/2 Kt_i'' + chi^3/6 Kt_i''') K_j + (i <-> j)],
+ * nu = l + 1/2, Kt = K / sqrt(chi), with the derivatives of the degree-4 polynomial through
+ * the 5 nearest chi nodes.  (The paper prints the bracket with a plus sign; the minus sign
+ * of the underlying Bessel expansion gives the O(nu^-4) error it states.)  With P = the
+ * non-linear and P_sub = the linear spectrum at the Limber points, and accumulate = 1 on
+ * the output of blast_cl_forward for the linear spectrum, C becomes the corrected
+ * C_lin + C_nl^limb - C_lin^limb of Sec. 3.2.  Asynchronous on `stream`.  Errors: INVALID
+ * (shapes, types, order 2 with n_chi < 5), OOM, HIP. */
+blast_status blast_cl_limber(blast_plan *plan, const blast_limber_args *args, void *stream);
+
 /* Waits for the recorded events, writes the summed milliseconds of each stage
  * (host [4]) and the number of recorded calls, and clears the record. */
 blast_status blast_plan_profile_read(blast_plan *plan, double *stage_ms, int64_t *calls);

@@ -50,6 +50,15 @@ class ClArgs(C.Structure):
     ]
 
 
+class LimberArgs(C.Structure):
+    _fields_ = [
+        ("batch", C.c_int32), ("p_dtype", C.c_int32), ("P", C.c_void_p), ("P_sub", C.c_void_p),
+        ("n_g", C.c_int32), ("n_s", C.c_int32), ("K_chi", C.c_void_p), ("types", C.c_uint32),
+        ("n_ell_out", C.c_int32), ("ell_idx", C.POINTER(C.c_int32)), ("order", C.c_int32),
+        ("accumulate", C.c_int32), ("C", C.c_void_p),
+    ]
+
+
 class ServerDesc(C.Structure):
     _fields_ = [("precision", C.c_int32), ("p_dtype", C.c_int32), ("batch", C.c_int32), ("n_sets", C.c_int32),
                 ("max_g", C.c_int32), ("max_s", C.c_int32), ("hbm_budget", C.c_size_t), ("max_queue", C.c_int32),
@@ -74,7 +83,7 @@ EXPORTS = [
     "blast_plan_create", "blast_plan_destroy", "blast_plan_info", "blast_plan_k_nodes", "blast_plan_basis_point",
     "blast_cl_workspace_bytes", "blast_cl_forward", "blast_cl_backward", "blast_plan_profile",
     "blast_plan_profile_read", "blast_plan_save", "blast_plan_load", "blast_plan_eval_points",
-    "blast_plan_grids",
+    "blast_plan_grids", "blast_plan_limber_k", "blast_cl_limber",
     "blast_server_create", "blast_server_submit", "blast_server_wait",
     "blast_server_stats_get", "blast_server_destroy",
 ]
@@ -117,6 +126,8 @@ def lib():
         L.blast_plan_save.argtypes = [C.c_void_p, C.c_char_p]
         L.blast_plan_load.argtypes = [C.c_char_p, C.c_int32, C.c_uint32, C.POINTER(C.c_void_p)]
         L.blast_plan_eval_points.argtypes = [C.c_void_p, dp, dp]
+        L.blast_plan_limber_k.argtypes = [C.c_void_p, dp]
+        L.blast_cl_limber.argtypes = [C.c_void_p, C.POINTER(LimberArgs), C.c_void_p]
         i32p = C.POINTER(C.c_int32)
         L.blast_plan_grids.argtypes = [C.c_void_p, i32p, i32p, i32p, i32p, C.POINTER(C.c_uint32), dp, dp,
                                        i32p, dp, dp, dp, dp]
@@ -327,6 +338,71 @@ class Plan:
                       idx_arr.ctypes.data_as(C.POINTER(C.c_int32)) if idx_arr is not None else None,
                       None, None, None, 0)
         return args, (P, K_chi, K_chi2, idx_arr), (B, npair, n_l), prec
+
+    def limber_k(self):
+        """k[l][a] = (ell_l + 1/2) / chi_a: where the Limber approximation samples P."""
+        k = np.empty((self.n_ell, len(self.chi)))
+        _check(lib().blast_plan_limber_k(self._h, _dptr(k)))
+        return k
+
+    def limber(self, P, K_chi, n_g, n_s, *, P_sub=None, order=1, types=None, ell_idx=None, out=None,
+               accumulate=False, stream=None):
+        """Limber (order 1) or extended Limber (order 2) spectra C[batch][pair][ell] (blast_cl_limber)
+        from P [B, n_ell, n_chi] at the Limber points (minus P_sub if given) and K_chi [B, bins, n_chi].
+        With accumulate=True the result is added to `out` (e.g. the beyond-Limber C of the linear
+        spectrum, for the non-linear correction)."""
+        import torch
+        if P.dim() == 2:
+            P = P.unsqueeze(0)
+        if K_chi.dim() == 2:
+            K_chi = K_chi.unsqueeze(0)
+        B = P.shape[0]
+        if tuple(P.shape) != (B, self.n_ell, len(self.chi)) or not P.is_cuda or not P.is_contiguous():
+            raise ValueError("P must be a contiguous device tensor of shape (batch, n_ell, n_chi)")
+        if P.dtype not in (torch.float64, torch.float32):
+            raise ValueError("P must be float64 or float32")
+        if P_sub is not None and (P_sub.shape != P.shape or P_sub.dtype != P.dtype or not P_sub.is_contiguous()):
+            raise ValueError("P_sub must match P")
+        if K_chi.dtype != torch.float64 or tuple(K_chi.shape) != (B, n_g + n_s, len(self.chi)):
+            raise ValueError("K_chi must be float64 of shape (batch, bins, n_chi)")
+        tmask = self.types if types is None else types_mask(types)
+        npair = n_pairs(n_g, n_s, tmask)
+        if ell_idx is None:
+            n_out, idx_arr, n_l = 0, None, self.n_ell
+        else:
+            idx_arr = np.ascontiguousarray(ell_idx, dtype=np.int32)
+            n_out = n_l = len(idx_arr)
+        shape = (B, npair, n_l)
+        if out is None:
+            if accumulate:
+                raise ValueError("accumulate needs out")
+            out = torch.empty(shape, dtype=torch.float64, device=P.device)
+        elif tuple(out.shape) != shape or out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of shape %s" % (shape,))
+        args = LimberArgs(B, 0 if P.dtype == torch.float64 else 1, P.data_ptr(),
+                          P_sub.data_ptr() if P_sub is not None else None, n_g, n_s, K_chi.data_ptr(), tmask, n_out,
+                          idx_arr.ctypes.data_as(C.POINTER(C.c_int32)) if idx_arr is not None else None,
+                          int(order), 1 if accumulate else 0, out.data_ptr())
+        if stream is None:
+            stream = torch.cuda.current_stream(P.device).cuda_stream
+        _check(lib().blast_cl_limber(self._h, C.byref(args), C.c_void_p(stream)))
+        return out
+
+    def cl_hybrid(self, P, K_chi, K_chi2, P_limber, n_g, n_s, ell_cut, *, order=2, precision="fp64", types=None):
+        """Beyond-Limber spectra below ell_cut and (extended) Limber spectra from ell_cut on: one
+        forward call for the low multipoles, one Limber call for the high ones, assembled into
+        C[batch][pair][ell] over all plan multipoles."""
+        import torch
+        lo = np.nonzero(self.ell < ell_cut)[0].astype(np.int32)
+        hi = np.nonzero(self.ell >= ell_cut)[0].astype(np.int32)
+        Pb = P if P.dim() == 4 else P.unsqueeze(0)
+        tmask = self.types if types is None else types_mask(types)
+        out = torch.empty((Pb.shape[0], n_pairs(n_g, n_s, tmask), self.n_ell), dtype=torch.float64, device=P.device)
+        if len(lo):
+            out[:, :, lo] = self.forward(P, K_chi, K_chi2, n_g, n_s, precision=precision, types=types, ell_idx=lo)
+        if len(hi):
+            out[:, :, hi] = self.limber(P_limber, K_chi, n_g, n_s, order=order, types=types, ell_idx=hi)
+        return out
 
     def _w_ws(self, args, B, prec, w_save, workspace):
         import torch

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libblast_hip.so")
-SOURCES = ["api.cpp", "basis.hip", "eval.hip", "server.cpp"]
+SOURCES = ["api.cpp", "basis.hip", "eval.hip", "limber.hip", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -141,6 +141,9 @@ static void free_plan(blast_plan *p) {
     f(p->d_pref);
     f(p->d_ell);
     f(p->scratch);
+    f(p->d_fd);
+    f(p->d_fds);
+    f(p->limb_ws);
     for (hipEvent_t e : p->prof_events) (void)hipEventDestroy(e);
     delete p;
 }
@@ -172,6 +175,44 @@ static blast_status validate_desc(const blast_plan_desc *d) {
     if (d->kq_panels < 0 || d->kq_panels > 4096) return blast::set_error("kq_panels out of range"), BLAST_E_INVALID;
     if (d->kq_phase < 0 || !std::isfinite(d->kq_phase)) return blast::set_error("kq_phase must be >= 0"), BLAST_E_INVALID;
     return BLAST_OK;
+}
+
+// Second and third derivative at every chi node from the 5 nearest nodes (the first / last
+// five at the two ends): Fornberg's recursion (Math. Comp. 51 (1988) 699) for the weights of
+// the derivatives at z of the polynomial through the stencil.  fd[a][m-2][q], m = 2, 3.
+static void derivative_stencils(const std::vector<double> &x, std::vector<double> &fd, std::vector<int> &fds) {
+    const int n = (int)x.size(), S = 5, M = 3;
+    fd.assign((size_t)n * 2 * S, 0.0);
+    fds.assign(n, 0);
+    for (int a = 0; a < n; ++a) {
+        const int s0 = std::min(std::max(a - 2, 0), n - S);
+        fds[a] = s0;
+        const double z = x[a];
+        double c[S][M + 1] = {};
+        double c1 = 1.0, c4 = x[s0] - z;
+        c[0][0] = 1.0;
+        for (int i = 1; i < S; ++i) {
+            const int mn = std::min(i, M);
+            double c2 = 1.0;
+            const double c5 = c4;
+            c4 = x[s0 + i] - z;
+            for (int j = 0; j < i; ++j) {
+                const double c3 = x[s0 + i] - x[s0 + j];
+                c2 *= c3;
+                if (j == i - 1) {
+                    for (int k = mn; k >= 1; --k) c[i][k] = c1 * (k * c[i - 1][k - 1] - c5 * c[i - 1][k]) / c2;
+                    c[i][0] = -c1 * c5 * c[i - 1][0] / c2;
+                }
+                for (int k = mn; k >= 1; --k) c[j][k] = (c4 * c[j][k] - k * c[j][k - 1]) / c3;
+                c[j][0] = c4 * c[j][0] / c3;
+            }
+            c1 = c2;
+        }
+        for (int q = 0; q < S; ++q) {
+            fd[((size_t)a * 2 + 0) * S + q] = c[q][2];
+            fd[((size_t)a * 2 + 1) * S + q] = c[q][3];
+        }
+    }
 }
 
 // the basis comes either from the device precompute or from a saved file (reader != nullptr)
@@ -262,6 +303,13 @@ static blast_status plan_create_impl(const blast_plan_desc *d, int32_t device, B
         if (e == hipSuccess) e = up((void **)&p->d_wR, p->w_R.data(), p->n_R * sizeof(double));
         if (e == hipSuccess) e = up((void **)&p->d_pref, pref.data(), pref.size() * sizeof(double));
         if (e == hipSuccess) e = up((void **)&p->d_ell, p->ell.data(), p->n_ell * sizeof(int));
+        if (e == hipSuccess && p->n_chi >= 5) {
+            std::vector<double> fd;
+            std::vector<int> fds;
+            derivative_stencils(p->chi, fd, fds);
+            e = up((void **)&p->d_fd, fd.data(), fd.size() * sizeof(double));
+            if (e == hipSuccess) e = up((void **)&p->d_fds, fds.data(), fds.size() * sizeof(int));
+        }
         if (e != hipSuccess) {
             blast::set_error("device tables: %s", hipGetErrorString(e));
             return fail(e == hipErrorOutOfMemory ? BLAST_E_OOM : BLAST_E_HIP);
@@ -483,6 +531,20 @@ extern "C" blast_status blast_plan_eval_points(const blast_plan *p, double *chi,
         for (int a = 0; a < p->n_chi; ++a)
             for (int b = 0; b < p->n_R; ++b) chi2[(size_t)a * p->n_R + b] = p->R[b] * p->chi[a];
     return BLAST_OK;
+}
+
+extern "C" blast_status blast_plan_limber_k(const blast_plan *p, double *k) {
+    if (!p || !k) return blast::set_error("NULL argument"), BLAST_E_INVALID;
+    for (int l = 0; l < p->n_ell; ++l)
+        for (int a = 0; a < p->n_chi; ++a) k[(size_t)l * p->n_chi + a] = (p->ell[l] + 0.5) / p->chi[a];
+    return BLAST_OK;
+}
+
+extern "C" blast_status blast_cl_limber(blast_plan *plan, const blast_limber_args *args, void *stream) {
+    blast::clear_error();
+    if (!plan || !args) return blast::set_error("NULL argument"), BLAST_E_INVALID;
+    DeviceGuard guard(plan->device);
+    return blast::limber(plan, args, (hipStream_t)stream);
 }
 
 extern "C" blast_status blast_plan_destroy(blast_plan *plan) {

@@ -83,6 +83,12 @@ struct blast_plan {
     // plan-owned scratch for calls without a caller workspace
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    // Limber path: 5-node stencils for the second and third derivative at each chi node
+    // (weights [n_chi][2][5], first node [n_chi]; absent when n_chi < 5) and its own scratch
+    double *d_fd = nullptr;
+    int *d_fds = nullptr;
+    void *limb_ws = nullptr;
+    size_t limb_ws_bytes = 0;
     std::mutex mu;
 };
 
@@ -97,6 +103,9 @@ blast_status forward(blast_plan *p, const blast_cl_args *a, hipStream_t s);
 blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, void *dP, double *dK_chi,
                       double *dK_chi2, hipStream_t s);
 size_t workspace_bytes(const blast_plan *p, int batch, int prec, int n_bins);
+
+// limber.hip
+blast_status limber(blast_plan *p, const blast_limber_args *a, hipStream_t s);
 
 }  // namespace blast
 

@@ -379,3 +379,24 @@ def kernels_torch(kinds, centres, sigmas, chi, chi2, panels: int = 32):
     K = torch.stack(out)
     n_chi = np.size(chi)
     return K[:, :n_chi].contiguous(), K[:, n_chi:].reshape((len(kinds),) + tuple(np.shape(chi2))).contiguous()
+
+
+# ----------------------------------------------------------------------------
+# spectra at the Limber points (k = (l+1/2)/chi, chi1 = chi2 = chi) and a non-linear stand-in
+# ----------------------------------------------------------------------------
+
+
+def nl_boost(k, chi):
+    """Synthetic non-linear boost P_nl / P_lin = 1 + (k / k_nl(chi))^1.5 with k_nl = 0.2 (1 + chi/2000)
+    [1/Mpc]: smooth, larger at small scales and late times; a stand-in, not a fit."""
+    k = np.asarray(k, dtype=np.float64)
+    knl = 0.2 * (1.0 + np.asarray(chi, dtype=np.float64) / 2000.0)
+    return 1.0 + (k / knl) ** 1.5
+
+
+def p_limber(k_limb, chi, cosmo: Cosmo, nonlinear: bool = False):
+    """P(k[l][a], chi_a, chi_a) on the Limber points k_limb [n_ell, n_chi] (linear, or with the
+    synthetic non-linear boost)."""
+    chi = np.asarray(chi, dtype=np.float64)
+    P = p0(k_limb, cosmo) * growth(chi, cosmo)[None, :] ** 2
+    return P * nl_boost(k_limb, chi[None, :]) if nonlinear else P
