@@ -34,25 +34,71 @@ def log(*a):
 
 
 def stage_work(plan, cfg, prec, batch):
-    """Algorithmic flops and HBM bytes of each stage for one launch over `batch` sets."""
+    """Algorithmic flops and HBM bytes of each stage for one launch over `batch` sets.
+
+    projection : c = D P as the even/odd split DCT (two [N/2 x N/2] products per point): N^2
+                 flops per (point, set); P read, c written once.
+    contraction: FP64 path: w = Ttilde c, basis read once per launch, c read, w written.
+                 Mixed paths: fused with the R-quadrature (w stays in registers): basis and c
+                 read, weighted kernels Kt written and read (from K_chi2), Y written; flops of
+                 the contraction plus those of the R-sum.
+    quad_R     : FP64 path only: w and K_chi2 read, Y written.
+    quad_chi   : Y read, C written (negligible)."""
     NP = cfg.n_chi * cfg.n_R
     N = cfg.n_cheb
     rows = plan.rows
+    rows_pad = plan.rows_pad
     nb = cfg.n_g + cfg.n_s
+    nbp = 16 if nb <= 16 else 32
     eb = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4}[prec]       # basis bytes per element (hi+lo)
     ec = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4}[prec]       # coefficient bytes
-    ew = 8 if prec == "fp64" else 4                                    # w bytes
+    ew = 8 if prec == "fp64" else 4                                    # w and Y bytes
     ep = 8 if prec == "fp64" else 4                                    # P bytes
     rows_bins = plan.n_ell * (cfg.n_g + nb + cfg.n_s)                 # (row, bin) products in the R-sum
+    proj = dict(flops=(1.0 if N % 32 == 0 and prec != "fp64" else 2.0) * NP * N * N * batch,
+                bytes=float(NP * N * (ep + ec) * batch))
+    quad_chi = dict(flops=4.0 * cfg.n_chi * plan.n_ell * B_pairs(cfg) * batch,
+                    bytes=float(cfg.n_chi * rows_pad * nbp * ew * batch))
+    y_bytes = float(cfg.n_chi * rows_pad * nbp * ew * batch)
+    if prec == "fp64":
+        return {
+            "projection": proj,
+            "contraction": dict(flops=2.0 * rows * N * NP * batch,
+                                bytes=float(NP * rows * N * eb + NP * N * ec * batch + NP * rows_pad * ew * batch)),
+            "quad_R": dict(flops=2.0 * rows_bins * NP * batch,
+                           bytes=float(NP * rows_pad * ew * batch + nb * NP * 8 * batch) + y_bytes),
+            "quad_chi": quad_chi,
+        }
+    nbf = (nb + 3) // 4 * 4
     return {
-        "projection": dict(flops=2.0 * NP * N * N * batch, bytes=float(NP * N * (ep + ec) * batch)),
-        "contraction": dict(flops=2.0 * rows * N * NP * batch,
-                            bytes=float(NP * rows * N * eb + NP * N * ec * batch + NP * rows * ew * batch)),
-        "quad_R": dict(flops=2.0 * rows_bins * NP * batch,
-                       bytes=float((NP * rows * ew + nb * NP * 8 + cfg.n_chi * rows * nb * 8) * batch)),
-        "quad_chi": dict(flops=4.0 * cfg.n_chi * plan.n_ell * 120 * batch,
-                         bytes=float(cfg.n_chi * rows * nb * 8 * batch)),
+        "projection": proj,
+        "contraction": dict(flops=2.0 * rows * N * NP * batch + 2.0 * rows_bins * NP * batch,
+                            bytes=float(NP * rows * N * eb + NP * N * ec * batch + nb * NP * 8 * batch
+                                        + 2 * NP * nbf * 4 * batch) + y_bytes),
+        "quad_chi": quad_chi,
     }
+
+
+def B_pairs(cfg):
+    g, s = cfg.n_g, cfg.n_s
+    return g * (g + 1) // 2 + g * s + s * (s + 1) // 2
+
+
+def counter_traffic(kernel, cfg_name, batch, prec):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, when it
+    was taken on the current kernel source, workload, batch and precision; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2410_03632_amd", "csrc", "eval.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for r in rec.get("records", []):
+        if (r["kernel"] == kernel and r["source_sha256"] == sha and r["workload"] == cfg_name
+                and r["batch"] == batch and r["precision"] == prec):
+            return r["fetch_bytes"] + r["write_bytes"]
+    return None
 
 
 def roofline(work, ms_per_launch, prec):
@@ -171,7 +217,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64", "bf16"])
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -248,10 +294,15 @@ def main():
     work = stage_work(plan, cfg, prec, Bn)
     dom = max(per_launch, key=per_launch.get)
     roof = roofline(work[dom], per_launch[dom], prec)
-    roof["kernel"] = {"projection": "project_kernel", "contraction": "contract_kernel", "quad_R": "quad_y_kernel",
-                      "quad_chi": "quad_c_kernel"}[dom]
+    fused = prec != "fp64"
+    roof["kernel"] = {"projection": "project_split_kernel" if fused else "project_mfma_kernel",
+                      "contraction": "contract_quad_kernel" if fused else "contract_kernel",
+                      "quad_R": "quad_y_kernel", "quad_chi": "quad_c_mfma_kernel"}[dom]
+    roof["traffic"] = counter_traffic(roof["kernel"], cfg.name, Bn, prec)
+    if fused:
+        per_launch.pop("quad_R", None)   # fused into the contraction stage
     roof["stage_ms_per_launch"] = per_launch
-    roof["stage_roofline"] = {k: roofline(work[k], per_launch[k], prec) for k in per_launch}
+    roof["stage_roofline"] = {k: roofline(work[k], per_launch[k], prec) for k in per_launch if k in work}
     for v in roof["stage_roofline"].values():
         v.pop("algorithmic_flops", None)
         v.pop("algorithmic_bytes", None)
@@ -296,6 +347,40 @@ def main():
             if i >= 2:
                 lat.append((time.perf_counter() - ta) * 1e3)
         extras["batch1_latency_ms"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}
+        # sets/s of the timed path over batch sizes (inputs tiled from the timed batch)
+        sweep = {}
+        for nbat in (1, 8, 64, 256):
+            reps = (nbat + Bn - 1) // Bn
+            Pb = P.repeat(reps, 1, 1, 1)[:nbat].contiguous()
+            K1b = K1[:1].expand(nbat, -1, -1).contiguous()
+            K2b = K2[:1].expand(nbat, -1, -1, -1).contiguous()
+            for _ in range(2):
+                plan.forward(Pb, K1b, K2b, cfg.n_g, cfg.n_s, precision=prec)
+            torch.cuda.synchronize()
+            nrep = 3 if nbat >= 64 else 10
+            t0 = time.perf_counter()
+            for _ in range(nrep):
+                plan.forward(Pb, K1b, K2b, cfg.n_g, cfg.n_s, precision=prec)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / nrep
+            sweep[str(nbat)] = {"ms_per_step": ms, "sets_per_s": nbat / (ms * 1e-3)}
+            del Pb, K1b, K2b
+        extras["batch_sweep"] = sweep
+        # Limber correction of the same batch: extended Limber of P_nl - P_lin at the Limber points
+        kl = plan.limber_k()
+        PL = torch.empty((Bn, plan.n_ell, cfg.n_chi), dtype=torch.float64, device=dev)
+        PN = torch.empty_like(PL)
+        for i, cos in enumerate(rng_cos):
+            PL[i] = torch.as_tensor(W.p_limber(kl, chi, cos))
+            PN[i] = torch.as_tensor(W.p_limber(kl, chi, cos, nonlinear=True))
+        for _ in range(2):
+            plan.limber(PN, K1, cfg.n_g, cfg.n_s, P_sub=PL, order=2, out=out, accumulate=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            plan.limber(PN, K1, cfg.n_g, cfg.n_s, P_sub=PL, order=2, out=out, accumulate=True)
+        torch.cuda.synchronize()
+        extras["limber_correction_ms_per_step"] = (time.perf_counter() - t0) * 1e3 / 5
 
     serving = None
     if args.serving_seconds > 0:

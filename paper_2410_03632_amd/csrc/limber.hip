@@ -17,7 +17,7 @@
 namespace blast {
 namespace {
 
-constexpr int kLimbChunk = 1024;  // chi nodes staged in LDS per pass
+constexpr int kLimbChunk = 128;   // chi nodes staged in LDS per pass
 
 struct LimbSel {
     int n_out;
@@ -72,67 +72,91 @@ __device__ inline void pair_decode(int p, int ng, int ns, uint32_t types, int &t
     j = base + r + q;
 }
 
-// one work-group per (output multipole, cosmology); threads over bin pairs, loop over chi in chunks
+// One work-group per (16 output multipoles, cosmology); threads over bin pairs, each keeping the
+// sums of its pair for the 16 multipoles; the chi loop runs over chunks with the weighted
+// spectra of the 16 multipoles and every bin's (K, A) of the chunk staged in LDS (rows padded by
+// one entry so that the bins read at one node fall in different banks).  Per chi node a thread
+// forms K_i K_j and A_i K_j + K_i A_j once and uses them for all 16 multipoles.
+constexpr int kLimbEll = 16;
+
 template <typename PT>
 __global__ __launch_bounds__(256) void limber_kernel(const PT *__restrict__ P, const PT *__restrict__ Psub,
                                                      const double2 *__restrict__ KA, const double *__restrict__ chi,
                                                      const double *__restrict__ wchi, const double *__restrict__ pref,
                                                      const int *__restrict__ ell, int slot_gg, int slot_gs,
-                                                     int slot_ss, int n_chi, int n_ell, int ng, int ns, uint32_t types, int npairs,
-                                                     LimbSel sel, int order, int accumulate, double *__restrict__ C) {
-    __shared__ double u[kLimbChunk], x2[kLimbChunk];
-    const int io = blockIdx.x, beta = blockIdx.y;
-    const int l = sel.idx[io];
-    const double nu = ell[l] + 0.5, inu2 = 1.0 / (nu * nu);
+                                                     int slot_ss, int n_chi, int n_ell, int ng, int ns, uint32_t types,
+                                                     int npairs, LimbSel sel, int order, int accumulate,
+                                                     double *__restrict__ C) {
+    extern __shared__ __align__(16) double smem_l[];
+    constexpr int KST = kLimbChunk + 1, LE = kLimbEll;
+    double *u = smem_l;                                  // [LE][kLimbChunk]: wchi dP / chi^2
+    double *c2 = smem_l + LE * kLimbChunk;               // [kLimbChunk]: chi^2
+    double2 *kas = (double2 *)(c2 + kLimbChunk);         // [nbins][KST]: (K, A)
+    const int io0 = blockIdx.x * LE, beta = blockIdx.y;
+    const int nio = min(LE, sel.n_out - io0);
     const int nbins = ng + ns;
-    const PT *pr = P + ((size_t)beta * n_ell + l) * n_chi;
-    const PT *ps = Psub ? Psub + ((size_t)beta * n_ell + l) * n_chi : nullptr;
     const double2 *ka = KA + (size_t)beta * nbins * n_chi;
-    // each thread keeps the sums of up to 4 pairs (npairs <= 528 for 32 bins)
-    constexpr int PPT = 4;
-    double acc[PPT] = {0.0, 0.0, 0.0, 0.0};
-    int pt[PPT], pi[PPT], pj[PPT];
+    double inu2[LE];
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-        const int p = threadIdx.x + q * blockDim.x;
-        pt[q] = 0, pi[q] = 0, pj[q] = 0;
-        if (p < npairs) pair_decode(p, ng, ns, types, pt[q], pi[q], pj[q]);
+    for (int e = 0; e < LE; ++e) {
+        const double nu = ell[sel.idx[io0 + (e < nio ? e : 0)]] + 0.5;
+        inu2[e] = 1.0 / (nu * nu);
     }
-    for (int a0 = 0; a0 < n_chi; a0 += kLimbChunk) {
-        const int na = min(kLimbChunk, n_chi - a0);
-        __syncthreads();
-        for (int a = threadIdx.x; a < na; a += blockDim.x) {
-            const double x = chi[a0 + a];
-            double d = (double)pr[a0 + a];
-            if (ps) d -= (double)ps[a0 + a];
-            u[a] = wchi[a0 + a] * d / (x * x);
-            x2[a] = x * x * inu2;  // 1/k^2
-        }
-        __syncthreads();
+    for (int p0 = 0; p0 < npairs; p0 += blockDim.x) {
+        const int p = p0 + threadIdx.x;
+        int t = 0, pi = 0, pj = 0;
+        if (p < npairs) pair_decode(p, ng, ns, types, t, pi, pj);
+        double s0[LE], s1[LE];
 #pragma unroll
-        for (int q = 0; q < PPT; ++q) {
-            const int p = threadIdx.x + q * blockDim.x;
+        for (int e = 0; e < LE; ++e) s0[e] = s1[e] = 0.0;
+        for (int a0 = 0; a0 < n_chi; a0 += kLimbChunk) {
+            const int na = min(kLimbChunk, n_chi - a0);
+            __syncthreads();
+            for (int i = threadIdx.x; i < LE * na; i += blockDim.x) {
+                const int e = i / na, a = i % na;
+                double d = 0.0;
+                if (e < nio) {
+                    const size_t o = ((size_t)beta * n_ell + sel.idx[io0 + e]) * n_chi + a0 + a;
+                    d = (double)P[o];
+                    if (Psub) d -= (double)Psub[o];
+                }
+                const double x = chi[a0 + a];
+                u[e * kLimbChunk + a] = wchi[a0 + a] * d / (x * x);
+            }
+            for (int a = threadIdx.x; a < na; a += blockDim.x) c2[a] = chi[a0 + a] * chi[a0 + a];
+            for (int i = threadIdx.x; i < nbins * na; i += blockDim.x) {
+                const int bin = i / na, a = i % na;
+                kas[bin * KST + a] = ka[(size_t)bin * n_chi + a0 + a];
+            }
+            __syncthreads();
             if (p >= npairs) continue;
-            const double2 *ki = ka + (size_t)pi[q] * n_chi + a0, *kj = ka + (size_t)pj[q] * n_chi + a0;
-            double s = 0.0;
+            const double2 *ki = kas + pi * KST, *kj = kas + pj * KST;
             for (int a = 0; a < na; ++a) {
                 const double2 vi = ki[a], vj = kj[a];
-                double e = vi.x * vj.x;
-                if (order == 2) e -= inu2 * (vi.y * vj.x + vi.x * vj.y);
-                const double g = pt[q] == BLAST_GG ? 1.0 : (pt[q] == BLAST_GS ? x2[a] : x2[a] * x2[a]);
-                s += u[a] * g * e;
-            }
-            acc[q] += s;
-        }
-    }
+                const double e0 = vi.x * vj.x, e1 = vi.y * vj.x + vi.x * vj.y;
+                const double x2 = c2[a];
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-        const int p = threadIdx.x + q * blockDim.x;
+                for (int e = 0; e < LE; ++e) {
+                    // f_t / k^2 = 1, 1/k^2, 1/k^4 with 1/k^2 = chi^2 / nu^2
+                    const double k2i = x2 * inu2[e];
+                    const double g = t == BLAST_GG ? 1.0 : (t == BLAST_GS ? k2i : k2i * k2i);
+                    const double wv = u[e * kLimbChunk + a] * g;
+                    s0[e] += wv * e0;
+                    s1[e] += wv * e1;
+                }
+            }
+        }
         if (p >= npairs) continue;
-        const int slot = pt[q] == BLAST_GG ? slot_gg : (pt[q] == BLAST_GS ? slot_gs : slot_ss);
-        const double v = pref[slot * n_ell + l] * (0.5 * M_PI) * acc[q];
-        double *o = C + ((size_t)beta * npairs + p) * sel.n_out + io;
-        *o = accumulate ? *o + v : v;
+        const int slot = t == BLAST_GG ? slot_gg : (t == BLAST_GS ? slot_gs : slot_ss);
+#pragma unroll
+        for (int e = 0; e < LE; ++e) {
+            if (e >= nio) break;
+            const int l = sel.idx[io0 + e];
+            const double sum = order == 2 ? s0[e] - inu2[e] * s1[e] : s0[e];
+            const double v = pref[slot * n_ell + l] * (0.5 * M_PI) * sum;
+            double *o = C + ((size_t)beta * npairs + p) * sel.n_out + io0 + e;
+            *o = accumulate ? *o + v : v;
+        }
     }
 }
 
@@ -157,7 +181,6 @@ blast_status limber(blast_plan *p, const blast_limber_args *a, hipStream_t s) {
         return set_error("types 0x%x not a non-empty subset of the plan's 0x%x", a->types, p->types), BLAST_E_INVALID;
     const int npairs = npairs_for(ng, ns, a->types);
     if (npairs < 1) return set_error("no bin pairs for these types and bins"), BLAST_E_INVALID;
-    if (npairs > 4 * 256) return set_error("too many bin pairs"), BLAST_E_INVALID;
     LimbSel sel{};
     if (a->n_ell_out == 0) {
         sel.n_out = p->n_ell;
@@ -195,14 +218,22 @@ blast_status limber(blast_plan *p, const blast_limber_args *a, hipStream_t s) {
     const long total = (long)a->batch * nbins * p->n_chi;
     hipLaunchKernelGGL(limber_ka_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a->K_chi, p->d_chi,
                        p->d_fd, p->d_fds, p->n_chi, total, a->order, (double2 *)ws);
-    dim3 grid((unsigned)sel.n_out, (unsigned)a->batch);
+    dim3 grid((unsigned)((sel.n_out + kLimbEll - 1) / kLimbEll), (unsigned)a->batch);
+    const size_t lds = ((kLimbEll + 1) * kLimbChunk + 2 * (size_t)nbins * (kLimbChunk + 1)) * sizeof(double);  // <= 83 KB
+    static std::once_flag once;
+    std::call_once(once, [] {
+        (void)hipFuncSetAttribute((const void *)limber_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        (void)hipFuncSetAttribute((const void *)limber_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+    });
     if (a->p_dtype == 0)
-        hipLaunchKernelGGL(limber_kernel<double>, grid, dim3(256), 0, s, (const double *)a->P, (const double *)a->P_sub,
+        hipLaunchKernelGGL(limber_kernel<double>, grid, dim3(256), lds, s, (const double *)a->P, (const double *)a->P_sub,
                            (const double2 *)ws, p->d_chi, p->d_wchi, p->d_pref, p->d_ell, p->slot[0], p->slot[1], p->slot[2],
                            p->n_chi, p->n_ell,
                            ng, ns, a->types, npairs, sel, a->order, a->accumulate, a->C);
     else
-        hipLaunchKernelGGL(limber_kernel<float>, grid, dim3(256), 0, s, (const float *)a->P, (const float *)a->P_sub,
+        hipLaunchKernelGGL(limber_kernel<float>, grid, dim3(256), lds, s, (const float *)a->P, (const float *)a->P_sub,
                            (const double2 *)ws, p->d_chi, p->d_wchi, p->d_pref, p->d_ell, p->slot[0], p->slot[1], p->slot[2],
                            p->n_chi, p->n_ell,
                            ng, ns, a->types, npairs, sel, a->order, a->accumulate, a->C);
