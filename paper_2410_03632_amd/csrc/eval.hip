@@ -861,8 +861,12 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     constexpr bool X3 = PREC == BLAST_BF16X3;
     constexpr int GPR = S::ROWB / 16;            // granules per c row
     constexpr int RPC = 1024 / S::ROWB;          // c rows per 1 KB chunk
-    // granule permutation mask: XOR by up to SWZ stays inside the row when SWZ + 1 divides GPR
-    constexpr int SWZ = GPR % 8 == 0 ? 7 : (GPR % 4 == 0 ? 3 : (GPR % 2 == 0 ? 1 : 0));
+    // granule permutation mask: XOR by up to SWZ stays inside the row when SWZ + 1 divides GPR;
+    // with 16 the 16 rows read by one instruction hit 16 distinct 16-byte bank groups
+    constexpr int SWZ = GPR % 16 == 0 ? 15 : (GPR % 8 == 0 ? 7 : (GPR % 4 == 0 ? 3 : (GPR % 2 == 0 ? 1 : 0)));
+    // the weights block [64 cosmologies][NB] is stored with the 4 granules of each row rotated by
+    // (row >> 2) & 3 when NB = 16, so that the 16 rows read together fall in distinct bank groups
+    constexpr bool KROT = NB == 16;
     // five distinct LDS objects, so that the compiler can tell the buffer a DMA writes from the
     // buffers the MFMA loop reads (and does not wait for the DMAs in flight)
     static_assert(S::LDS <= 160 * 1024, "LDS of the fused kernel");
@@ -907,7 +911,11 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     auto dma_X = [&](int b, unsigned char *__restrict__ buf) {
         const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
         const int ch = min(w, KCH);
-        const int f = ch * 256 + lane * 4;                   // float index in the 64 x NB block
+        int f = ch * 256 + lane * 4;                         // float index of the LDS position
+        if (KROT) {                                          // position 4r + ((q + (r >> 2)) & 3) holds granule q
+            const int r = f / 16, sp = (f / 4) & 3;
+            f = r * 16 + ((sp - (r >> 2)) & 3) * 4;
+        }
         const int bl = f / NB;
         // cosmologies past the batch read the tile's first weight instead (never used)
         const float *kp = Kt + (ab * batch + bt * 64 + (bl < nb ? bl : 0)) * NB + (bl < nb ? f % NB : 0);
@@ -961,7 +969,14 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
             const uint32_t sa = lds_addr(Cb + S::C_BUF + (size_t)KCH * 1024) + (uint32_t)(16 * min(ti, TR - 1) + 4 * lk) * 4;
             U4 q[6];
             constexpr int NQ = NB / 4;  // 1..5
-            lds_read4<0, (NQ > 1 ? 16 : 0), (NQ > 2 ? 32 : 0), (NQ > 3 ? 48 : 0)>(kb, kb, kb, kb, q[0], q[1], q[2], q[3]);
+            if constexpr (KROT) {
+                const int rr = ((16 * tk + lr) >> 2) & 3;
+                lds_read4<0, 0, 0, 0>(kb + 16 * (rr & 3), kb + 16 * ((1 + rr) & 3), kb + 16 * ((2 + rr) & 3),
+                                      kb + 16 * ((3 + rr) & 3), q[0], q[1], q[2], q[3]);
+            } else {
+                lds_read4<0, (NQ > 1 ? 16 : 0), (NQ > 2 ? 32 : 0), (NQ > 3 ? 48 : 0)>(kb, kb, kb, kb, q[0], q[1], q[2],
+                                                                                      q[3]);
+            }
             lds_read2<(NQ > 4 ? 64 : 0), 0>(kb, sa, q[4], q[5]);
 #pragma unroll
             for (int j = 0; j < NQ; ++j) {
@@ -975,18 +990,22 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
         }
         const uint32_t As = lds_addr(Ab) + (uint32_t)arow * 16;
         const uint32_t Asl = As + TR * NS * 64 * 16;
-        // granule (4 st + lk) of row crow sits at ((4 st + lk) ^ m) with m = crow & SWZ, i.e. at
-        // 4 (st ^ (m >> 2)) + (lk ^ (m & 3)): one base for even and one for odd steps
+        // granule (4 st + lk) of row crow sits at ((4 st + lk) ^ m) with m = crow & SWZ < 16, i.e. at
+        // 16 (st >> 2) + 4 ((st & 3) ^ (m >> 2)) + (lk ^ (m & 3)): one base per st & 3
         const uint32_t Cr = lds_addr(Cb) + (uint32_t)crow * S::ROWB;
-        const int m = crow & SWZ, h = (m >> 2) & 1, l = lk ^ (m & 3);
-        const uint32_t Ce = Cr + 16 * (4 * h + l), Co = Cr + 16 * (4 * (1 - h) + l);  // st even / odd
-        const uint32_t Cel = Ce + S::C_BUF / NPART, Col = Co + S::C_BUF / NPART;
+        const int m = crow & SWZ, mh = m >> 2, ml = lk ^ (m & 3);
+        uint32_t Cq[4], Cql[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            Cq[k] = Cr + 16 * (4 * (k ^ mh) + ml);
+            Cql[k] = Cq[k] + S::C_BUF / NPART;
+        }
         // four accumulators, so that consecutive MFMAs never wait for each other
         f4 acc[4] = {f4{0, 0, 0, 0}, f4{0, 0, 0, 0}, f4{0, 0, 0, 0}, f4{0, 0, 0, 0}};
         auto step_k = [&](auto stc) {
             constexpr int st = decltype(stc)::value;
-            constexpr int coff = 64 * (st & ~1);
-            const uint32_t cb = (st & 1) ? Co : Ce, cbl = (st & 1) ? Col : Cel;
+            constexpr int coff = 256 * (st >> 2);
+            const uint32_t cb = Cq[st & 3], cbl = Cql[st & 3];
             U4 ua, ub, ual, ubl;
             if constexpr (X3)
                 lds_read4<st * 1024, coff, st * 1024, coff>(As, cb, Asl, cbl, ua, ub, ual, ubl);
