@@ -72,9 +72,9 @@ def stage_work(plan, cfg, prec, batch):
     nbf = (nb + 3) // 4 * 4
     return {
         "projection": proj,
+        "r_weights": dict(flops=float(nb * NP * batch), bytes=float(nb * NP * 8 * batch + NP * nbf * 4 * batch)),
         "contraction": dict(flops=2.0 * rows * N * NP * batch + 2.0 * rows_bins * NP * batch,
-                            bytes=float(NP * rows * N * eb + NP * N * ec * batch + nb * NP * 8 * batch
-                                        + 2 * NP * nbf * 4 * batch) + y_bytes),
+                            bytes=float(NP * rows * N * eb + NP * N * ec * batch + NP * nbf * 4 * batch) + y_bytes),
         "quad_chi": quad_chi,
     }
 
@@ -290,17 +290,19 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = Bn / (ms_per_step * 1e-3)
     per_launch = {k: v / max(ncalls, 1) for k, v in stage_ms.items()}
+    fused = prec != "fp64"
+    if fused:
+        # intervals of the fused path: R-quadrature weights, then contraction + R-quadrature
+        per_launch = {"projection": per_launch["projection"], "r_weights": per_launch["contraction"],
+                      "contraction": per_launch["quad_R"], "quad_chi": per_launch["quad_chi"]}
     log("ms/step %.3f  sets/s %.1f  stages(ms/launch) %s" % (ms_per_step, value, per_launch))
     work = stage_work(plan, cfg, prec, Bn)
     dom = max(per_launch, key=per_launch.get)
     roof = roofline(work[dom], per_launch[dom], prec)
-    fused = prec != "fp64"
     roof["kernel"] = {"projection": "project_split_kernel" if fused else "project_mfma_kernel",
                       "contraction": "contract_quad_kernel" if fused else "contract_kernel",
-                      "quad_R": "quad_y_kernel", "quad_chi": "quad_c_mfma_kernel"}[dom]
+                      "quad_R": "quad_y_kernel", "quad_chi": "quad_c_mfma_kernel", "r_weights": "kt_kernel"}[dom]
     roof["traffic"] = counter_traffic(roof["kernel"], cfg.name, Bn, prec)
-    if fused:
-        per_launch.pop("quad_R", None)   # fused into the contraction stage
     roof["stage_ms_per_launch"] = per_launch
     roof["stage_roofline"] = {k: roofline(work[k], per_launch[k], prec) for k in per_launch if k in work}
     for v in roof["stage_roofline"].values():

@@ -271,8 +271,10 @@ blast_status blast_server_destroy(blast_server *srv);
 /* ------------------------------------------------------------------------- */
 
 /* While enabled, blast_cl_forward records HIP events on the call's stream around
- * its four stages: 0 projection, 1 contraction, 2 R-quadrature, 3 chi-quadrature
- * and pair assembly.  The events cost a few microseconds per call. */
+ * four intervals: 0 projection, 1 contraction, 2 R-quadrature, 3 chi-quadrature and
+ * pair assembly.  On the mixed-precision paths without w_save, where the contraction
+ * and the R-quadrature run fused, interval 1 holds the R-quadrature weight table and
+ * interval 2 the fused kernel.  The events cost a few microseconds per call. */
 blast_status blast_plan_profile(blast_plan *plan, int32_t enable);
 
 /* ------------------------------------------------------------------------ */

@@ -1745,10 +1745,13 @@ void stage_quad_y(blast_plan *p, const blast_cl_args *a, const Ctx &x, const voi
 }
 
 // stages 2 + 3 fused (mixed precisions without w_save)
-void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, int nb, const void *c,
-                         const uint16_t *clo, float *Kt, float *Y, hipStream_t s) {
+void stage_r_weights(blast_plan *p, const blast_cl_args *a, const Ctx &x, int nb, float *Kt, hipStream_t s) {
     dim3 gk((unsigned)((p->NP + 31) / 32), (unsigned)((a->batch + 15) / 16));
     hipLaunchKernelGGL(kt_kernel, gk, dim3(256), 0, s, a->K_chi2, p->d_wR, a->batch, x.nbins, nb, p->NP, p->n_R, Kt);
+}
+
+void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, int nb, const void *c,
+                         const uint16_t *clo, const float *Kt, float *Y, hipStream_t s) {
     const int RT = p->rows_pad / 16, nBT = (a->batch + 63) / 64;
     const int groups = (RT + kFusedTR - 1) / kFusedTR;
     const int units = p->n_chi * nBT * groups;
@@ -1827,8 +1830,10 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     stage_project(p, a, x, c, clo, s);
     mark(1);
     if (fnb) {
-        stage_contract_quad(p, a, x, fnb, c, clo, (float *)(ws + L.kt), (float *)Y, s);
+        // fused path: interval 1 = the R-weights table, interval 2 = contraction + R-quadrature
+        stage_r_weights(p, a, x, fnb, (float *)(ws + L.kt), s);
         mark(2);
+        stage_contract_quad(p, a, x, fnb, c, clo, (float *)(ws + L.kt), (float *)Y, s);
     } else {
         stage_contract(p, a, x, c, clo, w, s);
         mark(2);
