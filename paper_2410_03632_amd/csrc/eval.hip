@@ -888,6 +888,9 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     const int nb = min(64, batch - bt * 64);
     const size_t NP = (size_t)n_chi * n_R;
     const size_t pt_u4 = (size_t)RT * NS * 64;  // U4s per point in the tiled layout
+    // waves whose row tile or cosmologies lie past the end only move data (small batches,
+    // the last row group)
+    const bool busy = ti < ntile && bt * 64 + 16 * tk < batch;
 
     // every wave issues exactly A_PW + C_PW DMA instructions per b (chunk indices past the end are
     // clamped to the last chunk, which is then written more than once with identical data), so
@@ -961,6 +964,7 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
         dma_X(b + 1, Cnext);
         dma_A(b + 2, Anext2);
         __builtin_amdgcn_sched_barrier(0);
+        if (!busy) return;
         // weights of this b's cosmology and the row scales, from LDS
         float kt[NB];
         float4 sc = make_float4(1.f, 1.f, 1.f, 1.f);
@@ -1485,9 +1489,14 @@ struct Layout {
     size_t c, clo, w, kt, y, dy, sg, dw, dc, total;
 };
 
+// Below this batch the fused kernel, which keeps one work-group per CU busy with a barrier per
+// b, streams the basis more slowly than the unfused contraction (many independent work-groups);
+// there the w round trip through HBM is the cheaper part.
+constexpr int kFusedMinBatch = 32;
+
 // bins computed by the fused kernel (multiple of 4), 0 when it does not apply
-int fused_nb(int prec, int nbins) {
-    if (prec == BLAST_FP64 || nbins > 20) return 0;
+int fused_nb(int prec, int nbins, int batch) {
+    if (prec == BLAST_FP64 || nbins > 20 || batch < kFusedMinBatch) return 0;
     return (nbins + 3) / 4 * 4;
 }
 
@@ -1506,7 +1515,7 @@ Layout layout_of(const blast_plan *p, int batch, int prec, int nbins, bool need_
     L.w = off;
     L.kt = off;
     if (need_w) {
-        const int fnb = adjoint ? 0 : fused_nb(prec, nbins);
+        const int fnb = adjoint ? 0 : fused_nb(prec, nbins, batch);
         // the fused path keeps Kt where the unfused one keeps w
         off += align256(std::max((size_t)batch * p->NP * p->rows_pad * te, (size_t)batch * p->NP * fnb * 4));
     }
@@ -1825,7 +1834,7 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     uint16_t *clo = x.prec == BLAST_BF16X3 ? (uint16_t *)(ws + L.clo) : nullptr;
     void *w = need_w ? (void *)(ws + L.w) : a->w_save;
     void *Y = ws + L.y;
-    const int fnb = need_w ? fused_nb(x.prec, x.nbins) : 0;
+    const int fnb = need_w ? fused_nb(x.prec, x.nbins, a->batch) : 0;
     mark(0);
     stage_project(p, a, x, c, clo, s);
     mark(1);
