@@ -212,6 +212,102 @@ def serving_run(seconds, rate_hz=200.0, batch=16, precision="fp32", pool=32):
                         "through %d seed-drawn ones" % len(Ps)}
 
 
+def sweep_run(steps=5):
+    """Grid sweeps after the paper's discussion section, on the full 3x2pt workload (FP32 path,
+    batch 64): time per set against the number of Chebyshev nodes and the number of bins, and
+    the accuracy (Delta chi^2 of Eq. dchi, with LSST-like noise) against clustering bin width
+    with the default and a refined chi-R grid.  Benchmarks are the FP64 path (its parity with
+    the oracle is pinned separately): for node counts, FP64 at 128 nodes; for bin widths,
+    FP64 on the refined grid."""
+    import dataclasses
+
+    import torch
+    from paper_2410_03632_amd import blast as B
+    from paper_2410_03632_amd import metrics as M
+    from paper_2410_03632_amd import workloads as W
+
+    base = W.CONFIGS[2]
+    Bn = 64
+    dev = torch.device("cuda:0")
+    cos0 = W.draw_cosmo(np.random.default_rng(W.seed_for(2, 0)))
+
+    def run(cfg, plan, prec, bins, n_g, n_s, timed=True):
+        chi, chi2 = plan.eval_points()
+        Kchi, Kchi2 = W.kernels(bins, chi, chi2)
+        pdt = torch.float64 if prec == "fp64" else torch.float32
+        P = torch.as_tensor(W.p_grid(plan.k_nodes, chi, chi2, cos0), dtype=pdt, device=dev)[None]
+        P = P.expand(Bn, -1, -1, -1).contiguous()
+        K1 = torch.as_tensor(Kchi, device=dev)[None].expand(Bn, -1, -1).contiguous()
+        K2 = torch.as_tensor(Kchi2, device=dev)[None].expand(Bn, -1, -1, -1).contiguous()
+        C = plan.forward(P, K1, K2, n_g, n_s, precision=prec)
+        ms = None
+        if timed:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                plan.forward(P, K1, K2, n_g, n_s, precision=prec)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+        return C[0].cpu().numpy(), ms
+
+    out = {"workload": "full 3x2pt shapes, FP32 path, batch 64 (times per set)"}
+    # E5: Chebyshev nodes
+    bins = W.bins_of(base)
+    ref_plan = B.plan_for_config(base, precisions=("fp64", "fp32"))
+    Cref, _ = run(base, ref_plan, "fp64", bins, base.n_g, base.n_s, timed=False)
+    pairs = W.pair_list(base.n_g, base.n_s)
+    ref_plan.close()
+    rows = []
+    for N in (96, 104, 112, 120, 128):
+        cfg = dataclasses.replace(base, n_cheb=N)
+        plan = B.plan_for_config(cfg, precisions=("fp32",))
+        C, ms = run(cfg, plan, "fp32", bins, cfg.n_g, cfg.n_s)
+        rows.append({"n_cheb": N, "us_per_set": 1e3 * ms / Bn,
+                     "delta_chi2_vs_fp64_128_l200": M.delta_chi2(C, Cref, plan.ell, cfg.n_g, cfg.n_s, pairs,
+                                                                 ell_max=200),
+                     "delta_chi2_vs_fp64_128": M.delta_chi2(C, Cref, plan.ell, cfg.n_g, cfg.n_s, pairs)})
+        log("sweep n_cheb", rows[-1])
+        plan.close()
+    out["chebyshev_nodes"] = rows
+    # E6: number of bins (one plan; clustering bins 1..10 with 1 or 5 shear bins)
+    plan = B.plan_for_config(base, precisions=("fp32",))
+    rows = []
+    for n_s in (1, 5):
+        for n_g in (1, 2, 4, 6, 8, 10):
+            bsel = W.bins_of(base)[:n_g] + W.bins_of(base)[base.n_g:base.n_g + n_s]
+            _, ms = run(base, plan, "fp32", bsel, n_g, n_s)
+            rows.append({"n_g": n_g, "n_s": n_s, "pairs": len(W.pair_list(n_g, n_s)), "us_per_set": 1e3 * ms / Bn})
+            log("sweep bins", rows[-1])
+    plan.close()
+    out["bins"] = rows
+    # E7: clustering bin width (sigma 150, 75, 37.5 Mpc), default grid and a refined grid
+    fine = dataclasses.replace(base, n_chi=512, n_R=128)
+    mid = dataclasses.replace(base, n_chi=384, n_R=112)
+    pf = B.plan_for_config(fine, precisions=("fp64",))
+    pm = B.plan_for_config(mid, precisions=("fp64",))
+    pd = B.plan_for_config(base, precisions=("fp64", "fp32"))
+    rows = []
+    for f in (1.0, 0.5, 0.25):
+        cfgw = dataclasses.replace(base, g_sigma=base.g_sigma * f)
+        bw = W.bins_of(cfgw)
+        Cb, _ = run(fine, pf, "fp64", bw, base.n_g, base.n_s, timed=False)
+        Cm, _ = run(mid, pm, "fp64", bw, base.n_g, base.n_s, timed=False)
+        C64, _ = run(base, pd, "fp64", bw, base.n_g, base.n_s, timed=False)
+        C32, _ = run(base, pd, "fp32", bw, base.n_g, base.n_s, timed=False)
+        d = lambda X, Y, lm=200: M.delta_chi2(X, Y, pd.ell, base.n_g, base.n_s, pairs, ell_max=lm)
+        rows.append({"width": f, "benchmark": "FP64, chi 512 x R 128", "l_range": "l < 200 (all l)",
+                     "delta_chi2_fp64_chi256_R96": (d(C64, Cb), d(C64, Cb, None)),
+                     "delta_chi2_fp32_chi256_R96": (d(C32, Cb), d(C32, Cb, None)),
+                     "delta_chi2_fp64_chi384_R112": (d(Cm, Cb), d(Cm, Cb, None)),
+                     "delta_chi2_fp32_vs_fp64_same_grid": (d(C32, C64), d(C32, C64, None))})
+        log("sweep width", rows[-1])
+    pf.close()
+    pm.close()
+    pd.close()
+    out["bin_width"] = rows
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +319,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64-path and batch-1 timings")
     ap.add_argument("--serving-seconds", type=float, default=5.0, help="seconds of Poisson arrivals (0: skip)")
+    ap.add_argument("--sweep", action="store_true", help="only run the grid sweeps (one JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -240,6 +337,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n}))
+        return
+    if args.sweep:
+        print(json.dumps({"sweep": sweep_run()}), flush=True)
         return
     from paper_2410_03632_amd import blast as B
     from paper_2410_03632_amd import workloads as W

@@ -196,32 +196,39 @@ __global__ __launch_bounds__(256) void project_mfma_kernel(const PT *__restrict_
         }
 }
 
-// FP32 projection for N % 32 == 0 (then nc_pad == N), with the even/odd split of the DCT-II.
+// FP32 projection for N % 8 == 0, with the even/odd split of the DCT-II.
 // With u_j = P_j + P_{N-1-j} and v_j = P_j - P_{N-1-j} (j < N/2), and D[n][N-1-j] = (-1)^n D[n][j],
 //     c_{2m} = sum_{j<N/2} D[2m][j] u_j,      c_{2m+1} = sum_{j<N/2} D[2m+1][j] v_j,
-// two [rows x N/2] x [N/2 x N/2] products: half the MFMA work of the plain product.  Each wave owns
-// kSplitRT row tiles and every even and odd output tile; the P values of step s+1 are loaded
-// while step s runs.  A lane stores (c_{2m}, c_{2m+1}) as one 8-byte pair.
+// two [rows x N/2] x [N/2 x N/2] products: half the MFMA work of the plain product.  N/2 is padded
+// to Hp (a multiple of 16) with zero weights, so the nc_pad = 2 Hp outputs of a row come out with
+// exact zeros past N.  Each wave owns kSplitRT row tiles and every even and odd output tile; the
+// P values of step s+1 are loaded while step s runs.  A lane stores (c_{2m}, c_{2m+1}) as one
+// 8-byte pair.
 constexpr int kSplitRT = 2;
 
 template <typename PT, int OUT>
 __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict__ P, const float *__restrict__ Dn,
-                                                            int N, long nrows, void *__restrict__ c_out,
+                                                            int N, int ncp, long nrows, void *__restrict__ c_out,
                                                             uint16_t *__restrict__ c_lo) {
     constexpr int RT = kSplitRT, VEC = 4, KSTEP = 16;
     constexpr int MAXT = kMaxCheb / 32;  // output tiles per parity
     extern __shared__ __align__(16) unsigned char smem_s[];
-    const int H = N / 2, hs = H + 4;     // LDS row stride: 16 bytes of padding
-    float *De = (float *)smem_s, *Do = De + (size_t)H * hs;
-    for (int i = threadIdx.x; i < H * (H / 4); i += blockDim.x) {
-        const int m = i / (H / 4), q = i % (H / 4);
-        *(float4 *)(De + (size_t)m * hs + 4 * q) = *(const float4 *)(Dn + (size_t)(2 * m) * N + 4 * q);
-        *(float4 *)(Do + (size_t)m * hs + 4 * q) = *(const float4 *)(Dn + (size_t)(2 * m + 1) * N + 4 * q);
+    const int H = N / 2, Hp = ncp / 2, hs = Hp + 4;  // LDS row stride: 16 bytes of padding
+    float *De = (float *)smem_s, *Do = De + (size_t)Hp * hs;
+    for (int i = threadIdx.x; i < Hp * (Hp / 4); i += blockDim.x) {
+        const int m = i / (Hp / 4), q = i % (Hp / 4);
+        float4 e = make_float4(0.f, 0.f, 0.f, 0.f), o = e;
+        if (m < H && 4 * q < H) {
+            e = *(const float4 *)(Dn + (size_t)(2 * m) * N + 4 * q);
+            o = *(const float4 *)(Dn + (size_t)(2 * m + 1) * N + 4 * q);
+        }
+        *(float4 *)(De + (size_t)m * hs + 4 * q) = e;
+        *(float4 *)(Do + (size_t)m * hs + 4 * q) = o;
     }
     __syncthreads();
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
-    const int nt = H >> 4, nsteps = H / KSTEP;
+    const int nt = Hp >> 4, nsteps = Hp / KSTEP;
     const long row0 = (long)blockIdx.x * (64 * RT) + 16 * RT * w;
     f4 ae[RT][MAXT], ao[RT][MAXT];
 #pragma unroll
@@ -230,8 +237,10 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
         for (int t = 0; t < MAXT; ++t) ae[r][t] = ao[r][t] = f4{0, 0, 0, 0};
 
     // raw P values of one step: front[r] = P[j0 .. j0+3], back[r] = P[N-4-j0 .. N-1-j0]
+    // past N/2 the weights are zero, so any finite P values will do: the loads are clamped to the
+    // row's last 4-vector below N/2 (H % 4 == 0)
     auto load = [&](int st, float4 (&front)[RT], float4 (&back)[RT]) {
-        const int j0 = st * KSTEP + lk * VEC;
+        const int j0 = min(st * KSTEP + lk * VEC, H - 4);
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
             const long row = row0 + 16 * r + lr;
@@ -298,7 +307,7 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
             for (int q = 0; q < 4; ++q) {
                 const long row = row0 + 16 * r + 4 * lk + q;
                 if (row >= nrows) continue;
-                const size_t o = (size_t)row * N + n;
+                const size_t o = (size_t)row * ncp + n;
                 const float ce = ae[r][t][q], co = ao[r][t][q];
                 if (OUT == 1) {
                     *(float2 *)((float *)c_out + o) = make_float2(ce, co);
@@ -1669,12 +1678,12 @@ void stage_project(blast_plan *p, const blast_cl_args *a, const Ctx &x, void *c,
 #undef BLAST_CI
         return;
     }
-    if (!f64 && N % 32 == 0) {
+    if (!f64 && N % 8 == 0) {
         dim3 grid((unsigned)((nrows + 64 * kSplitRT - 1) / (64 * kSplitRT)));
-        const size_t shp = (size_t)2 * (N / 2) * (N / 2 + 4) * sizeof(float);
+        const size_t shp = (size_t)2 * (ncp / 2) * (ncp / 2 + 4) * sizeof(float);
 #define BLAST_PROJ(PT, O) \
     hipLaunchKernelGGL((project_split_kernel<PT, O>), grid, dim3(256), shp, s, (const PT *)a->P, p->d_dctn32, N, \
-                       nrows, c, clo)
+                       ncp, nrows, c, clo)
         if (p64 && out == 1) BLAST_PROJ(double, 1);
         if (p64 && out == 2) BLAST_PROJ(double, 2);
         if (!p64 && out == 1) BLAST_PROJ(float, 1);

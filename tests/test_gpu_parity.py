@@ -210,3 +210,26 @@ def test_named_config_matches_oracle_golden(config):
             assert e.max() <= tol, (prec, e.max())
     print("config", config, "max errors", res, flush=True)
     plan.close()
+
+
+@pytest.mark.parametrize("config", [1, 2])
+def test_named_config_delta_chi2(config):
+    """The paper's accuracy metric (Eq. dchi, LSST-like noise, f_sky = 0.4) of the FP32 path with
+    the oracle golden as the benchmark: below the challenge's 0.2 (and reported without noise)."""
+    from paper_2410_03632_amd import metrics as M
+    g = _golden(config)
+    cfg = W.CONFIGS[config]
+    plan = B.plan_for_config(cfg, precisions=("fp64", "fp32"))
+    try:
+        inp = W.make_inputs(cfg, g["seed"], plan.k_nodes, plan.chi, plan.R)
+        Cor = np.array(g["C"])
+        pairs = W.pair_list(cfg.n_g, cfg.n_s)
+        out = {}
+        for prec in ("fp64", "fp32"):
+            C = _run(plan, inp, prec, p32=prec == "fp32")
+            out[prec] = (M.delta_chi2(C, Cor, plan.ell, cfg.n_g, cfg.n_s, pairs),
+                         M.delta_chi2(C, Cor, plan.ell, cfg.n_g, cfg.n_s, pairs, N=np.zeros(cfg.n_g + cfg.n_s)))
+        print("config", config, "Delta chi^2 (with noise, without):", out, flush=True)
+        assert out["fp32"][0] < 0.2 and out["fp64"][0] < 1e-6
+    finally:
+        plan.close()
