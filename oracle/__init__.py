@@ -48,20 +48,22 @@ def lib():
         L.or_grid_chi.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp]
         L.or_grid_R.argtypes = [C.c_int, C.c_double, dp, dp]
         L.or_grid_k.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp]
-        L.or_prefactor.argtypes = [C.c_int, C.c_int]
+        L.or_prefactor.argtypes = [C.c_int, C.c_double]
         L.or_prefactor.restype = C.c_double
         L.or_sph_jn.argtypes = [C.c_int, C.c_double, dp]
+        L.or_sph_jnu.argtypes = [C.c_double, C.c_double]
+        L.or_sph_jnu.restype = C.c_double
         L.or_cheb_interp.argtypes = [C.c_int, dp, C.c_double]
         L.or_cheb_interp.restype = C.c_double
-        L.or_w_points.argtypes = [C.c_int, ip, C.c_int, C.c_double, C.c_double, C.c_int, C.c_long,
+        L.or_w_points.argtypes = [C.c_int, dp, C.c_int, C.c_double, C.c_double, C.c_int, C.c_long,
                                   dp, dp, C.c_int, dp, C.c_long, C.c_int, C.c_double, C.c_double,
                                   C.c_double, C.c_int, C.c_double, dp, C.c_int]
-        L.or_sum_rform.argtypes = [C.c_int, C.c_int, dp, dp, dp, C.c_int, C.c_int, dp, dp, C.c_int, ip,
+        L.or_sum_rform.argtypes = [C.c_int, C.c_int, dp, dp, dp, C.c_int, C.c_int, dp, dp, C.c_int, dp,
                                    C.c_int, dp, dp]
-        L.or_sum_points.argtypes = [C.c_long, dp, C.c_int, C.c_int, dp, dp, C.c_int, ip, C.c_int, dp, dp]
-        L.or_limber.argtypes = [C.c_int, dp, dp, C.c_int, C.c_int, dp, C.c_int, ip, C.c_int, C.c_double,
+        L.or_sum_points.argtypes = [C.c_long, dp, C.c_int, C.c_int, dp, dp, C.c_int, dp, C.c_int, dp, dp]
+        L.or_limber.argtypes = [C.c_int, dp, dp, C.c_int, C.c_int, dp, C.c_int, dp, C.c_int, C.c_double,
                                 C.c_double, C.c_int, dp, dp]
-        L.or_cl_grid.argtypes = [C.c_int, ip, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
+        L.or_cl_grid.argtypes = [C.c_int, dp, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                                  dp, dp, dp, dp, dp, C.c_int, C.c_int, dp, dp, C.c_int, C.c_double,
                                  C.c_double, C.c_int, dp, dp, dp, ip, C.c_int]
         L.or_npairs.argtypes = [C.c_int, C.c_int, C.c_int]
@@ -76,9 +78,11 @@ def _d(a):
     return a, a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def _i(a):
-    a = np.ascontiguousarray(a, dtype=np.int32)
-    return a, a.ctypes.data_as(C.POINTER(C.c_int))
+def _ell(a):
+    """Multipoles as FP64 (integer or not); the oracle takes one recurrence for all of them
+    when they are all integers, and a real-order evaluation per multipole otherwise."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
 
 
 def types_mask(types) -> int:
@@ -124,13 +128,18 @@ def grid_k(n, kmin, kmax):
 
 
 def prefactor(t, ell):
-    return lib().or_prefactor(types_mask([t]) if isinstance(t, str) else t, int(ell))
+    return lib().or_prefactor(types_mask([t]) if isinstance(t, str) else t, float(ell))
 
 
 def sph_jn(lmax, x):
     out = np.empty(lmax + 1)
     lib().or_sph_jn(int(lmax), float(x), out.ctypes.data_as(C.POINTER(C.c_double)))
     return out
+
+
+def sph_jnu(nu, x):
+    """j_nu(x) for real order nu >= 0 (Miller's recurrence normalised by Neumann's series)."""
+    return lib().or_sph_jnu(float(nu), float(x))
 
 
 def cheb_interp(f_nodes, x):
@@ -157,7 +166,7 @@ def w_points(ell, types, kmin, kmax, chi1, chi2, *, nc=0, P=None, shared=False, 
     mode P_NODAL: P = interpolant of nodal values (P[m, :nc], or one shared row);
     mode P_CHEB : P = sum a_n T_n(x(k)) with coefficients cheb_coef[m, :d] (or shared);
     mode P_GAUSS: P = amp k^m exp(-(p k)^2), gauss = (p, m, amp)."""
-    ell, ellp = _i(ell)
+    ell, ellp = _ell(ell)
     chi1, c1p = _d(np.atleast_1d(chi1))
     chi2, c2p = _d(np.atleast_1d(chi2))
     npts = len(chi1)
@@ -192,7 +201,7 @@ def sum_rform(chi, wchi, wR, n_g, n_s, Kchi, Kchi2, ell, types, w):
     wR, wrp = _d(wR)
     Kchi, kp = _d(Kchi)
     Kchi2, k2p = _d(Kchi2)
-    ell, ellp = _i(ell)
+    ell, ellp = _ell(ell)
     w, wp = _d(w)
     tm = types_mask(types)
     C_out = np.zeros((npairs(n_g, n_s, tm), len(ell)))
@@ -205,7 +214,7 @@ def sum_points(W, n_g, n_s, K1, K2, ell, types, w):
     W, Wp = _d(W)
     K1, k1p = _d(K1)
     K2, k2p = _d(K2)
-    ell, ellp = _i(ell)
+    ell, ellp = _ell(ell)
     w, wp = _d(w)
     tm = types_mask(types)
     C_out = np.zeros((npairs(n_g, n_s, tm), len(ell)))
@@ -218,7 +227,7 @@ def limber(chi, wchi, n_g, n_s, K, ell, types, kmin, kmax, p_nodal):
     chi, cp = _d(chi)
     wchi, wcp = _d(wchi)
     K, kp = _d(K)
-    ell, ellp = _i(ell)
+    ell, ellp = _ell(ell)
     pn, pnp = _d(p_nodal)
     tm = types_mask(types)
     C_out = np.zeros((npairs(n_g, n_s, tm), len(ell)))
@@ -233,7 +242,7 @@ def cl_grid(ell, types, kmin, kmax, nc, chi, wchi, R, wR, P, n_g, n_s, Kchi, Kch
             M0=None, Phi0=10.0, tol=1e-10, maxlev=4, want_w=False, nthreads=0):
     """The discrete target C[p][il] on the (chi, R) grid with its self-convergence
     estimate.  Returns (C, err, levels, w or None)."""
-    ell, ellp = _i(ell)
+    ell, ellp = _ell(ell)
     chi, cp = _d(chi)
     wchi, wcp = _d(wchi)
     R, rp = _d(R)

@@ -29,6 +29,9 @@
  *     (Berrut & Trefethen, SIAM Review 46 (2004) 501), not by coefficients;
  *   - j_l by three-term recurrence (upward for x > lmax, otherwise Miller's
  *     downward recurrence normalised by j_0 or j_1; Abramowitz & Stegun 10.1);
+ *     non-integer multipoles (the challenge's multipole list is not integer) by
+ *     Miller's downward recurrence to the fractional order, normalised by
+ *     Neumann's series (x/2)^a = sum_k (a+2k) Gamma(a+k)/k! J_{a+2k}(x), DLMF 10.23;
  *   - the k-integral by composite 16-point Gauss-Legendre on panels that resolve
  *     both the Chebyshev structure in ln k and the Bessel oscillation (frequency
  *     chi1 + chi2), refined by doubling until the C_l aggregate stops changing.
@@ -170,9 +173,9 @@ int or_grid_k(int n, double kmin, double kmax, double *k, double *x)
 }
 
 /* N_t(l) of Eqs. gg, gs, ss. */
-double or_prefactor(int type, int ell)
+double or_prefactor(int type, double ell)
 {
-    double l = (double)ell;
+    double l = ell;
     double pi4 = (l + 2.0) * (l + 1.0) * l * (l - 1.0); /* (l+2)!/(l-2)! */
     if (type == OR_GG)
         return 2.0 / OR_PI;
@@ -241,6 +244,60 @@ void or_sph_jn(int lmax, double x, double *j)
     j[0] = y * scale;
     for (int l = 1; l <= lmax; l++)
         j[l] = (l <= hi) ? j[l] * scale : 0.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Spherical Bessel function of real order nu >= 0, x >= 0                    */
+/* ------------------------------------------------------------------------- */
+/* With mu = nu - floor(nu) and y_i an unnormalised solution of the spherical
+ * three-term recurrence j_{b-1} = (2b+1)/x j_b - j_{b+1} on the orders b = mu + i,
+ * started far above max(nu, x) (where the minimal solution j dominates), the
+ * normalisation follows from Neumann's series for the cylindrical order
+ * a = mu + 1/2 (J_{a+2k} = sqrt(2x/pi) j_{mu+2k}):
+ *     (x/2)^a / Gamma(a) = sqrt(2x/pi) sum_k (a+2k) r_k j_{mu+2k}(x),
+ *     r_k = Gamma(a+k) / (Gamma(a) k!)   (r_0 = 1, r_k = r_{k-1} (a+k-1)/k).
+ * The r_k are generated downwards from an arbitrary top value and divided by
+ * the r_0 they reach, so no Gamma ratio of large arguments is formed. */
+double or_sph_jnu(double nu, double x)
+{
+    if (x == 0.0)
+        return nu == 0.0 ? 1.0 : 0.0;
+    int n = (int)floor(nu);
+    double mu = nu - n, a = mu + 0.5;
+    double top = (nu > x ? nu : x);
+    int L = (int)ceil(top - mu) + 20 + (int)sqrt(40.0 * (top > 1.0 ? top : 1.0));
+    if (L % 2)
+        L++; /* even top index: the series terms sit on even i */
+    double inv_x = 1.0 / x;
+    double y_up = 0.0, y = 1e-30; /* y_{i+1}, y_i at i = L */
+    double rk = 1.0;              /* r_{L/2} up to a constant */
+    double sum = 0.0, yn = 0.0;
+    for (int i = L; i >= 0; i--) {
+        if (i == n)
+            yn = y;
+        if (i % 2 == 0) {
+            int k = i / 2;
+            sum += (a + 2.0 * k) * rk * y;
+            if (k > 0)
+                rk *= k / (a + k - 1.0);
+        }
+        if (i > 0) {
+            double b = mu + i;
+            double y_dn = (2.0 * b + 1.0) * inv_x * y - y_up;
+            y_up = y;
+            y = y_dn;
+            if (fabs(y) > 1e250) { /* rescale everything held so far */
+                y *= 1e-250;
+                y_up *= 1e-250;
+                yn *= 1e-250;
+                sum *= 1e-250;
+            }
+        }
+    }
+    /* rk now holds r_0 times the constant; sum / rk = sum_k (a+2k) r_k y_{mu+2k} */
+    double lhs = exp(a * log(0.5 * x) - lgamma(a));
+    double norm = sqrt(2.0 * x / OR_PI) * (sum / rk);
+    return yn * lhs / norm;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -314,7 +371,8 @@ static double cheb_clenshaw(int d, const double *a, double x)
 /* ------------------------------------------------------------------------- */
 typedef struct {
     int nl;
-    const int *ell; /* strictly increasing, >= 0 */
+    const double *ell; /* strictly increasing, >= 0 */
+    int integer;       /* every multipole is an integer: one recurrence for all of them */
     int types;      /* OR_GG | OR_GS | OR_SS */
     double kmin, kmax;
     int nc; /* Chebyshev node count of the interpolant (nodal mode) */
@@ -343,7 +401,7 @@ static void kint_point(const or_spec *sp, const cheb_t *cb, const or_pspec *ps, 
                        double *pacc, double *comp)
 {
     const int nl = sp->nl;
-    const int lmax = sp->ell[nl - 1];
+    const int lmax = (int)sp->ell[nl - 1];
     const double lnkmin = log(sp->kmin), L = log(sp->kmax / sp->kmin);
     const double omega = chi1 + chi2;
     const double *pd = ps->data ? ps->data + (ps->stride ? pt * ps->stride : 0) : NULL;
@@ -374,26 +432,35 @@ static void kint_point(const or_spec *sp, const cheb_t *cb, const or_pspec *ps, 
                     P = cheb_clenshaw(ps->d, pd, x);
                 else
                     P = ps->amp * pow(k, ps->m) * exp(-(ps->p * k) * (ps->p * k));
-                or_sph_jn(lmax, k * chi1, jb1);
-                or_sph_jn(lmax, k * chi2, jb2);
+                /* jj[il] = j_l(k chi1) j_l(k chi2) */
+                double *jj = jb1 + (lmax + 1);
+                if (sp->integer) {
+                    or_sph_jn(lmax, k * chi1, jb1);
+                    or_sph_jn(lmax, k * chi2, jb2);
+                    for (int il = 0; il < nl; il++)
+                        jj[il] = jb1[(int)sp->ell[il]] * jb2[(int)sp->ell[il]];
+                } else {
+                    for (int il = 0; il < nl; il++)
+                        jj[il] = or_sph_jnu(sp->ell[il], k * chi1) * or_sph_jnu(sp->ell[il], k * chi2);
+                }
                 double base = wq * P;
                 if (sp->types & OR_GG) {
                     double cf = base * k * k;
                     double *a = pacc;
                     for (int il = 0; il < nl; il++)
-                        a[il] += cf * jb1[sp->ell[il]] * jb2[sp->ell[il]];
+                        a[il] += cf * jj[il];
                 }
                 if (sp->types & OR_GS) {
                     double cf = base;
                     double *a = pacc + nl;
                     for (int il = 0; il < nl; il++)
-                        a[il] += cf * jb1[sp->ell[il]] * jb2[sp->ell[il]];
+                        a[il] += cf * jj[il];
                 }
                 if (sp->types & OR_SS) {
                     double cf = base / (k * k);
                     double *a = pacc + 2 * nl;
                     for (int il = 0; il < nl; il++)
-                        a[il] += cf * jb1[sp->ell[il]] * jb2[sp->ell[il]];
+                        a[il] += cf * jj[il];
                 }
             }
             for (int q = 0; q < 3 * nl; q++)
@@ -404,10 +471,14 @@ static void kint_point(const or_spec *sp, const cheb_t *cb, const or_pspec *ps, 
         w[q] += comp[q];
 }
 
-static int spec_ok(const or_spec *sp)
+static int spec_ok(or_spec *sp)
 {
-    if (sp->nl < 1 || !sp->ell || sp->ell[0] < 0)
+    if (sp->nl < 1 || !sp->ell || !(sp->ell[0] >= 0.0) || !(sp->ell[sp->nl - 1] <= 1e5))
         return 0;
+    sp->integer = 1;
+    for (int i = 0; i < sp->nl; i++)
+        if (sp->ell[i] != floor(sp->ell[i]))
+            sp->integer = 0;
     for (int i = 1; i < sp->nl; i++)
         if (sp->ell[i] <= sp->ell[i - 1])
             return 0;
@@ -419,11 +490,11 @@ static int spec_ok(const or_spec *sp)
 /* w[t][il][m] for npts points (chi1_m, chi2_m).  P per point per `ps`.
  * M coarse panels uniform in theta (x = -cos theta), each split into
  * ceil((chi1+chi2) dk / Phi) equal sub-panels in k. */
-int or_w_points(int nl, const int *ell, int types, double kmin, double kmax, int nc, long npts,
+int or_w_points(int nl, const double *ell, int types, double kmin, double kmax, int nc, long npts,
                 const double *chi1, const double *chi2, int pmode, const double *pdata, long pstride,
                 int pd, double pp, double pm, double pamp, int M, double Phi, double *w, int nthreads)
 {
-    or_spec sp = {nl, ell, types, kmin, kmax, nc};
+    or_spec sp = {nl, ell, 0, types, kmin, kmax, nc};
     or_pspec ps = {pmode, pdata, pstride, pd, pp, pm, pamp};
     if (!spec_ok(&sp) || npts < 0 || M < 1 || !(Phi > 0.0))
         return 1;
@@ -434,7 +505,7 @@ int or_w_points(int nl, const int *ell, int types, double kmin, double kmax, int
     cheb_t cb = {0, NULL, NULL};
     if (pmode == OR_P_NODAL && cheb_make(&cb, nc))
         return 2;
-    int lmax = ell[nl - 1];
+    int lmax = (int)ell[nl - 1];
     int err = 0;
 #ifdef _OPENMP
     if (nthreads > 0)
@@ -442,7 +513,7 @@ int or_w_points(int nl, const int *ell, int types, double kmin, double kmax, int
 #endif
 #pragma omp parallel
     {
-        double *jb1 = (double *)malloc(sizeof(double) * (lmax + 1));
+        double *jb1 = (double *)malloc(sizeof(double) * (lmax + 1 + nl)); /* + the products j j */
         double *jb2 = (double *)malloc(sizeof(double) * (lmax + 1));
         double *acc = (double *)malloc(sizeof(double) * 3 * nl);
         double *pacc = (double *)malloc(sizeof(double) * 3 * nl);
@@ -526,7 +597,7 @@ static int tidx(int t) { return t == OR_GG ? 0 : (t == OR_GS ? 1 : 2); }
 
 /* R-form sum (Eq. final_cls) over the (chi_a, R_b) grid. */
 int or_sum_rform(int na, int nb, const double *chi, const double *wchi, const double *wR, int ng, int ns,
-                 const double *Kchi, const double *Kchi2, int nl, const int *ell, int types, const double *w,
+                 const double *Kchi, const double *Kchi2, int nl, const double *ell, int types, const double *w,
                  double *C)
 {
     int np = npairs_of(ng, ns, types);
@@ -556,7 +627,7 @@ int or_sum_rform(int na, int nb, const double *chi, const double *wchi, const do
 /* Full-square (chi1-chi2) sum over arbitrary points with weights W_m:
  *   C_ij = N_t sum_m W_m K_i(chi1_m) K_j(chi2_m) w_t(chi1_m, chi2_m)   (Eq. cls-general) */
 int or_sum_points(long npts, const double *W, int ng, int ns, const double *K1, const double *K2, int nl,
-                  const int *ell, int types, const double *w, double *C)
+                  const double *ell, int types, const double *w, double *C)
 {
     int np = npairs_of(ng, ns, types);
     for (int p = 0; p < np; p++) {
@@ -579,7 +650,7 @@ int or_sum_points(long npts, const double *W, int ng, int ns, const double *K1, 
  *   C = N_t (pi/2) sum_a wchi_a K_i K_j f_t(k) P(k) / (k^2 chi_a^2),  k = (l+1/2)/chi_a.
  * P is chi-independent here: nodal values pnodal[nc] (Phat, zero outside [kmin,kmax]). */
 int or_limber(int na, const double *chi, const double *wchi, int ng, int ns, const double *K, int nl,
-              const int *ell, int types, double kmin, double kmax, int nc, const double *pnodal, double *C)
+              const double *ell, int types, double kmin, double kmax, int nc, const double *pnodal, double *C)
 {
     cheb_t cb;
     if (cheb_make(&cb, nc))
@@ -644,7 +715,7 @@ static double rel_change(int ng, int ns, int types, int nl, const double *Cn, co
  * doubling (M -> 2M, Phi -> Phi/2) until the relative change of C is below tol
  * (or maxlev levels).  P nodal values per (a,b): P[(a*nb+b)*nc + j], ascending k.
  * w_out (nullable) receives the last level's w[t][il][a*nb+b]. */
-int or_cl_grid(int nl, const int *ell, int types, double kmin, double kmax, int nc, int na, int nb,
+int or_cl_grid(int nl, const double *ell, int types, double kmin, double kmax, int nc, int na, int nb,
                const double *chi, const double *wchi, const double *R, const double *wR, const double *P, int ng,
                int ns, const double *Kchi, const double *Kchi2, int M0, double Phi0, double tol, int maxlev,
                double *C, double *w_out, double *err, int *levels, int nthreads)

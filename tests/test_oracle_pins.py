@@ -78,6 +78,54 @@ def test_bessel_branch_continuity():
 
 # ----------------------------------------------------------------------------- quadrature rules
 
+@pytest.mark.parametrize("x", [1e-4, 0.37, 2.0, 29.5, 30.5, 111.1, 640.0, 1200.0])
+def test_real_order_bessel_vs_mpmath(x):
+    """Non-integer multipoles: j_nu(x) = sqrt(pi/2x) J_{nu+1/2}(x) for real nu (mpmath, 40 digits)."""
+    for nu in [0.0, 0.25, 0.5, 0.999, 1.5, 2.37, 10.5, 57.75, 211.63, 640.2, 999.5, 1500.01]:
+        xm = mp.mpf(x)
+        ref = float(mp.sqrt(mp.pi / (2 * xm)) * mp.besselj(mp.mpf(nu) + mp.mpf(1) / 2, xm))
+        got = O.sph_jnu(nu, x)
+        if abs(ref) < 1e-280:
+            assert abs(got) < 1e-270
+            continue
+        env = abs(ref) if nu > x else max(abs(ref), 1.0 / x)
+        assert abs(got - ref) <= 1e-12 * env, (nu, x, got, ref)
+
+
+@pytest.mark.parametrize("x", [0.05, 3.0, 77.7, 640.0, 2500.0])
+def test_real_order_bessel_at_integer_orders_equals_integer_recurrence(x):
+    """The fractional-order routine (one sequence per order, Neumann normalisation) and the
+    integer routine (one sequence for all orders, closed-form j_0 / j_1 normalisation) are
+    different computations that must agree at integer orders."""
+    lmax = 800
+    j = O.sph_jn(lmax, x)
+    for l in [0, 1, 2, 5, 33, 200, 799]:
+        got = O.sph_jnu(float(l), x)
+        env = abs(j[l]) if l > x else max(abs(j[l]), 1.0 / x)
+        if abs(j[l]) < 1e-250:
+            continue
+        assert abs(got - j[l]) <= 1e-12 * env, (l, x, got, j[l])
+
+
+def test_real_order_bessel_recurrence_in_order():
+    """j_{nu-1} + j_{nu+1} = (2 nu + 1)/x j_nu for fractional nu (catches an offset of the
+    fractional part or of the cylindrical order)."""
+    for x in [0.8, 9.0, 45.0, 300.0]:
+        for nu in [1.3, 4.61, 25.5, 120.05]:
+            a, b, c = O.sph_jnu(nu - 1, x), O.sph_jnu(nu, x), O.sph_jnu(nu + 1, x)
+            scale = max(abs(a), abs(c), abs(b) * (2 * nu + 1) / x, 1e-300)
+            assert abs(a + c - (2 * nu + 1) / x * b) <= 1e-12 * scale, (x, nu)
+
+
+def test_real_prefactors_against_gamma():
+    """N_t(l) for non-integer l: (l+2)!/(l-2)! continues as Gamma(l+3)/Gamma(l-1)."""
+    for l in [2.0, 2.5, 17.3, 211.63, 999.9]:
+        r = math.exp(math.lgamma(l + 3) - math.lgamma(l - 1))
+        assert abs(O.prefactor("gg", l) - 2 / math.pi) < 1e-16
+        assert abs(O.prefactor("gs", l) / (2 / math.pi * math.sqrt(r)) - 1) < 1e-12
+        assert abs(O.prefactor("ss", l) / (2 / math.pi * r) - 1) < 1e-12
+
+
 def test_gl16_matches_library():
     x, w = O.gl16()
     xr, wr = np.polynomial.legendre.leggauss(16)
@@ -191,6 +239,19 @@ def test_weber_closed_form_all_types(a, b, p):
         w = O.w_points(ell, [t], kmin, kmax, [a], [b], mode=O.P_GAUSS, gauss=(p, m, 1.0), M=64, Phi=10.0)
         got = w[O.types_mask([t]).bit_length() - 1, :, 0]
         scale = np.sqrt(np.pi) / (4 * p ** 3) / max(a * b / (2 * p * p), 1.0)  # size of the integrand
+        assert np.all(np.abs(got - ex) <= 1e-10 * np.maximum(np.abs(ex), 1e-3 * scale)), (t, got, ex)
+
+
+@pytest.mark.parametrize("a,b,p", [(50, 40, 10), (300, 280, 12), (1500, 1500, 40)])
+def test_weber_closed_form_real_ell(a, b, p):
+    """Weber's closed form holds for any real order: the non-integer path of the k-integral."""
+    ell = [2.37, 10.5, 30.9, 100.25, 199.99]
+    ex = np.array([weber(l, a, b, p) for l in ell])
+    kmin, kmax = 1e-7, 12.0
+    for t, m in (("gg", 0.0), ("gs", 2.0), ("ss", 4.0)):
+        w = O.w_points(ell, [t], kmin, kmax, [a], [b], mode=O.P_GAUSS, gauss=(p, m, 1.0), M=64, Phi=10.0)
+        got = w[O.types_mask([t]).bit_length() - 1, :, 0]
+        scale = np.sqrt(np.pi) / (4 * p ** 3) / max(a * b / (2 * p * p), 1.0)
         assert np.all(np.abs(got - ex) <= 1e-10 * np.maximum(np.abs(ex), 1e-3 * scale)), (t, got, ex)
 
 
