@@ -94,7 +94,10 @@ typedef struct blast_plan blast_plan;
 
 typedef struct {
     int32_t n_ell;
-    const int32_t *ell;   /* host [n_ell], strictly increasing, >= 2, <= 4096        */
+    const double *ell;    /* host [n_ell] multipoles, strictly increasing, in [2, 4096];
+                             they need not be integers (the challenge's list is not):
+                             an all-integer list takes one Bessel recurrence for all
+                             orders, any other list one per distinct fractional part  */
     int32_t n_chi;
     const double *chi;    /* host [n_chi] chi nodes (> 0)                            */
     const double *w_chi;  /* host [n_chi] outer chi weights                          */
@@ -131,7 +134,7 @@ blast_status blast_plan_k_nodes(const blast_plan *plan, double *k);
  * written to the non-NULL pointers; the arrays (host, caller-owned, sized n_ell, n_chi,
  * n_chi, n_R, n_R) are filled when non-NULL. */
 blast_status blast_plan_grids(const blast_plan *plan, int32_t *n_ell, int32_t *n_chi, int32_t *n_R,
-                              int32_t *n_cheb, uint32_t *types, double *k_min, double *k_max, int32_t *ell,
+                              int32_t *n_cheb, uint32_t *types, double *k_min, double *k_max, double *ell,
                               double *chi, double *w_chi, double *R, double *w_R);
 
 /* Where to evaluate the kernels and P: chi_a (host [n_chi]) and R_b chi_a (host

@@ -30,7 +30,7 @@ class BlastError(RuntimeError):
 
 class PlanDesc(C.Structure):
     _fields_ = [
-        ("n_ell", C.c_int32), ("ell", C.POINTER(C.c_int32)),
+        ("n_ell", C.c_int32), ("ell", C.POINTER(C.c_double)),
         ("n_chi", C.c_int32), ("chi", C.POINTER(C.c_double)), ("w_chi", C.POINTER(C.c_double)),
         ("n_R", C.c_int32), ("R", C.POINTER(C.c_double)), ("w_R", C.POINTER(C.c_double)),
         ("k_min", C.c_double), ("k_max", C.c_double),
@@ -130,7 +130,7 @@ def lib():
         L.blast_cl_limber.argtypes = [C.c_void_p, C.POINTER(LimberArgs), C.c_void_p]
         i32p = C.POINTER(C.c_int32)
         L.blast_plan_grids.argtypes = [C.c_void_p, i32p, i32p, i32p, i32p, C.POINTER(C.c_uint32), dp, dp,
-                                       i32p, dp, dp, dp, dp]
+                                       dp, dp, dp, dp, dp]
         L.blast_plan_profile_read.argtypes = [C.c_void_p, dp, C.POINTER(C.c_int64)]
         for name in EXPORTS:
             if name not in ("blast_last_error", "blast_version"):
@@ -202,12 +202,12 @@ class Plan:
     def __init__(self, ell, chi, w_chi, R, w_R, k_min, k_max, n_cheb, *, types=7,
                  precisions=("fp64",), kq_panels=0, kq_phase=0.0, device=0):
         self.device = int(device)
-        ell = np.ascontiguousarray(ell, dtype=np.int32)
+        ell = np.ascontiguousarray(ell, dtype=np.float64)   # integer or not
         chi = np.ascontiguousarray(chi, dtype=np.float64)
         w_chi = np.ascontiguousarray(w_chi, dtype=np.float64)
         R = np.ascontiguousarray(R, dtype=np.float64)
         w_R = np.ascontiguousarray(w_R, dtype=np.float64)
-        d = PlanDesc(len(ell), ell.ctypes.data_as(C.POINTER(C.c_int32)),
+        d = PlanDesc(len(ell), _dptr(ell),
                      len(chi), _dptr(chi), _dptr(w_chi), len(R), _dptr(R), _dptr(w_R),
                      float(k_min), float(k_max), int(n_cheb), types_mask(types), _pmask(precisions),
                      int(kq_panels), float(kq_phase))
@@ -238,11 +238,11 @@ class Plan:
         kmin, kmax = C.c_double(), C.c_double()
         _check(L.blast_plan_grids(h, C.byref(ne), C.byref(nc), C.byref(nr), C.byref(nch), C.byref(ty),
                                   C.byref(kmin), C.byref(kmax), None, None, None, None, None))
-        self.ell = np.empty(ne.value, np.int32)
+        self.ell = np.empty(ne.value)
         self.chi, self.w_chi = np.empty(nc.value), np.empty(nc.value)
         self.R, self.w_R = np.empty(nr.value), np.empty(nr.value)
         _check(L.blast_plan_grids(h, None, None, None, None, None, None, None,
-                                  self.ell.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(self.chi),
+                                  _dptr(self.ell), _dptr(self.chi),
                                   _dptr(self.w_chi), _dptr(self.R), _dptr(self.w_R)))
         self.k_min, self.k_max, self.n_cheb, self.types = kmin.value, kmax.value, nch.value, ty.value
         rows, ncp = C.c_int32(), C.c_int32()
@@ -575,9 +575,10 @@ class Server:
             pass
 
 
-def plan_for_config(cfg, precisions=("fp64",), device=0, **kw):
-    """Plan with the default grids of a workloads.Config (Simpson chi, Fejer R, Chebyshev k)."""
+def plan_for_config(cfg, precisions=("fp64",), device=0, ell=None, **kw):
+    """Plan with the default grids of a workloads.Config (Simpson chi, Fejer R, Chebyshev k);
+    `ell` replaces the configuration's multipole list (for instance by non-integer values)."""
     chi, wchi = grid_chi_simpson(cfg.n_chi, cfg.chi_min, cfg.chi_max)
     R, wR = grid_R_fejer(cfg.n_R, cfg.R_min)
-    return Plan(cfg.ells(), chi, wchi, R, wR, cfg.k_min, cfg.k_max, cfg.n_cheb, precisions=precisions,
+    return Plan(cfg.ells() if ell is None else ell, chi, wchi, R, wR, cfg.k_min, cfg.k_max, cfg.n_cheb, precisions=precisions,
                 device=device, **kw)

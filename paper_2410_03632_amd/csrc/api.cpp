@@ -113,7 +113,8 @@ extern "C" blast_status blast_grid_k_cheb(int32_t n, double k_min, double k_max,
 // plan
 // --------------------------------------------------------------------------------------------
 
-static double prefactor(int type_bit, int l) {
+// N_t(l) for real l (the factorial ratio continues as Gamma(l+3)/Gamma(l-1) = (l+2)(l+1)l(l-1))
+static double prefactor(int type_bit, double l) {
     const double L = l;
     const double r = (L + 2.0) * (L + 1.0) * L * (L - 1.0);  // (l+2)!/(l-2)!
     if (type_bit == BLAST_GG) return 2.0 / kPi;
@@ -140,6 +141,7 @@ static void free_plan(blast_plan *p) {
     f(p->d_wR);
     f(p->d_pref);
     f(p->d_ell);
+    f(p->d_elli);
     f(p->scratch);
     f(p->d_fd);
     f(p->d_fds);
@@ -153,8 +155,8 @@ static blast_status validate_desc(const blast_plan_desc *d) {
     if (d->n_ell < 1 || d->n_ell > blast::kMaxEll || !d->ell)
         return blast::set_error("n_ell must be in [1, %d]", blast::kMaxEll), BLAST_E_INVALID;
     for (int i = 0; i < d->n_ell; ++i) {
-        if (d->ell[i] < 2 || d->ell[i] > 4096)
-            return blast::set_error("ell[%d] = %d outside [2, 4096]", i, d->ell[i]), BLAST_E_INVALID;
+        if (!(d->ell[i] >= 2.0 && d->ell[i] <= 4096.0))
+            return blast::set_error("ell[%d] = %g outside [2, 4096]", i, d->ell[i]), BLAST_E_INVALID;
         if (i && d->ell[i] <= d->ell[i - 1])
             return blast::set_error("ell must be strictly increasing (index %d)", i), BLAST_E_INVALID;
     }
@@ -233,7 +235,7 @@ static blast_status plan_create_impl(const blast_plan_desc *d, int32_t device, B
     p->device = device;
     p->n_ell = d->n_ell;
     p->ell.assign(d->ell, d->ell + d->n_ell);
-    p->lmax = p->ell.back();
+    for (double l : p->ell) p->int_ell = p->int_ell && l == std::floor(l);
     p->types = d->types;
     const int bits[3] = {BLAST_GG, BLAST_GS, BLAST_SS};
     for (int t = 0; t < 3; ++t)
@@ -302,7 +304,11 @@ static blast_status plan_create_impl(const blast_plan_desc *d, int32_t device, B
         if (e == hipSuccess) e = up((void **)&p->d_wchi, p->w_chi.data(), p->n_chi * sizeof(double));
         if (e == hipSuccess) e = up((void **)&p->d_wR, p->w_R.data(), p->n_R * sizeof(double));
         if (e == hipSuccess) e = up((void **)&p->d_pref, pref.data(), pref.size() * sizeof(double));
-        if (e == hipSuccess) e = up((void **)&p->d_ell, p->ell.data(), p->n_ell * sizeof(int));
+        if (e == hipSuccess) e = up((void **)&p->d_ell, p->ell.data(), p->n_ell * sizeof(double));
+        if (e == hipSuccess && p->int_ell) {
+            std::vector<int> li(p->ell.begin(), p->ell.end());
+            e = up((void **)&p->d_elli, li.data(), li.size() * sizeof(int));
+        }
         if (e == hipSuccess && p->n_chi >= 5) {
             std::vector<double> fd;
             std::vector<int> fds;
@@ -341,7 +347,7 @@ extern "C" blast_status blast_plan_create(const blast_plan_desc *d, int32_t devi
 
 namespace {
 const char kMagic[8] = {'B', 'L', 'A', 'S', 'T', 'P', 'L', '1'};
-const uint32_t kFileVersion = 1;
+const uint32_t kFileVersion = 2;  // 2: multipoles stored as FP64
 
 // 64-bit word-wise FNV-1a style hash (tail bytes folded one by one)
 struct Hash64 {
@@ -416,7 +422,7 @@ extern "C" blast_status blast_plan_save(const blast_plan *p, const char *path) {
     w.put(hdr, sizeof(hdr));
     const double hd[3] = {p->kmin, p->kmax, p->kq_phase};
     w.put(hd, sizeof(hd));
-    w.put(p->ell.data(), sizeof(int) * p->n_ell);
+    w.put(p->ell.data(), sizeof(double) * p->n_ell);
     w.put(p->chi.data(), sizeof(double) * p->n_chi);
     w.put(p->w_chi.data(), sizeof(double) * p->n_chi);
     w.put(p->R.data(), sizeof(double) * p->n_R);
@@ -473,9 +479,9 @@ extern "C" blast_status blast_plan_load(const char *path, int32_t device, uint32
         std::fclose(f);
         return st;
     }
-    std::vector<int32_t> ell(hdr[1]);
+    std::vector<double> ell(hdr[1]);
     std::vector<double> chi(hdr[2]), wchi(hdr[2]), R(hdr[3]), wR(hdr[3]);
-    r.get(ell.data(), sizeof(int32_t) * ell.size());
+    r.get(ell.data(), sizeof(double) * ell.size());
     r.get(chi.data(), sizeof(double) * chi.size());
     r.get(wchi.data(), sizeof(double) * wchi.size());
     r.get(R.data(), sizeof(double) * R.size());
@@ -507,7 +513,7 @@ extern "C" blast_status blast_plan_load(const char *path, int32_t device, uint32
 
 extern "C" blast_status blast_plan_grids(const blast_plan *p, int32_t *n_ell, int32_t *n_chi, int32_t *n_R,
                                          int32_t *n_cheb, uint32_t *types, double *k_min, double *k_max,
-                                         int32_t *ell, double *chi, double *w_chi, double *R, double *w_R) {
+                                         double *ell, double *chi, double *w_chi, double *R, double *w_R) {
     if (!p) return blast::set_error("plan is NULL"), BLAST_E_INVALID;
     if (n_ell) *n_ell = p->n_ell;
     if (n_chi) *n_chi = p->n_chi;
@@ -516,7 +522,7 @@ extern "C" blast_status blast_plan_grids(const blast_plan *p, int32_t *n_ell, in
     if (types) *types = p->types;
     if (k_min) *k_min = p->kmin;
     if (k_max) *k_max = p->kmax;
-    if (ell) std::memcpy(ell, p->ell.data(), sizeof(int32_t) * p->n_ell);
+    if (ell) std::memcpy(ell, p->ell.data(), sizeof(double) * p->n_ell);
     if (chi) std::memcpy(chi, p->chi.data(), sizeof(double) * p->n_chi);
     if (w_chi) std::memcpy(w_chi, p->w_chi.data(), sizeof(double) * p->n_chi);
     if (R) std::memcpy(R, p->R.data(), sizeof(double) * p->n_R);

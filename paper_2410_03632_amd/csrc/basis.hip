@@ -50,6 +50,23 @@ struct Items {
 //              normalised to the upward value j_m(x) > 0 (x < m+1 lies before j_m's first zero).
 // Orders above L are set to zero (they are below e^-70 of the turning-point amplitude).
 // ---------------------------------------------------------------------------------------------
+// Order nu > x at which the Debye exponent nu (alpha - tanh alpha), cosh alpha = nu / x, reaches
+// 100: Newton from above (the exponent is convex in nu with derivative alpha).
+__device__ double miller_start(double x) {
+    double nu = x + 10.0 + 25.0 * cbrt(x + 8.0);
+    for (int it = 0; it < 12; ++it) {
+        const double al = acosh(nu / x);
+        const double a2 = al * al;
+        const double E = al < 0.1 ? nu * al * a2 * (1.0 / 3.0 - a2 * (2.0 / 15.0 - a2 * (17.0 / 315.0)))
+                                  : nu * (al - tanh(al));
+        const double d = (E - 100.0) / al;
+        nu -= d;
+        if (nu < x + 1e-3) nu = x + 1e-3;
+        if (fabs(d) < 0.25) break;
+    }
+    return nu;
+}
+
 __device__ void bessel_list(double x, const int *__restrict__ ell, int nl, double *__restrict__ out) {
     const int lmax = ell[nl - 1];
     double sx, cx;
@@ -91,19 +108,7 @@ __device__ void bessel_list(double x, const int *__restrict__ ell, int nl, doubl
         }
         jmv = a1;
     }
-    // start of the downward recurrence: Newton from above on E(nu) = 100 (E convex, dE/dnu = alpha)
-    double nu = x + 10.0 + 25.0 * cbrt(x + 8.0);
-    for (int it = 0; it < 12; ++it) {
-        const double al = acosh(nu / x);
-        const double a2 = al * al;
-        const double E = al < 0.1 ? nu * al * a2 * (1.0 / 3.0 - a2 * (2.0 / 15.0 - a2 * (17.0 / 315.0)))
-                                  : nu * (al - tanh(al));
-        const double d = (E - 100.0) / al;
-        nu -= d;
-        if (nu < x + 1e-3) nu = x + 1e-3;
-        if (fabs(d) < 0.25) break;
-    }
-    int L = (int)ceil(nu) + 2;
+    int L = (int)ceil(miller_start(x)) + 2;
     if (L < m + 2) L = m + 2;
     int ih = nl - 1;
     while (ih >= il && ell[ih] > L) {
@@ -124,6 +129,148 @@ __device__ void bessel_list(double x, const int *__restrict__ ell, int nl, doubl
     }
     const double scale = jmv / y;  // y = y_m
     for (int q = il; q < nl && ell[q] <= L; ++q) out[q] *= scale;
+}
+
+// ---------------------------------------------------------------------------------------------
+// j_nu(x) for real multipoles nu (not all integers), x > 0.  The multipoles are taken in runs of
+// equal fractional part mu, members mu + n with increasing n (run r: ell[perm[runs[r] ..
+// runs[r+1])]); one run is one recurrence over the orders mu + i, as for integer orders:
+//  x >= kHankelX : j_mu and j_{mu+1} from Hankel's expansion for large argument (DLMF 10.17.3,
+//                  cylindrical order a = mu + 1/2), then upward to m = floor(x - mu) and, for
+//                  members above m, Miller's downward recurrence from the Debye start,
+//                  normalised to the upward value at m (positive: x < mu + m + 1 lies before the
+//                  first zero of j_{mu+m}).
+//  x <  kHankelX : Miller's downward recurrence from the Debye start to order mu, normalised by
+//                  Neumann's series (x/2)^a / Gamma(a) = sqrt(2x/pi) sum_k (a+2k) r_k j_{mu+2k}(x),
+//                  r_k = Gamma(a+k) / (Gamma(a) k!) (DLMF 10.23), with the r_k generated downwards
+//                  from an arbitrary top value and divided by the r_0 they reach.
+// Orders above the Debye start are set to zero, as on the integer path.
+// ---------------------------------------------------------------------------------------------
+constexpr double kHankelX = 30.0;
+
+// P and Q of Hankel's expansion of J_a(x): t_k = t_{k-1} (4a^2 - (2k-1)^2) / (8 k x),
+// P = t_0 - t_2 + t_4 - ..., Q = t_1 - t_3 + ...; for x >= 30 and a < 2 the terms fall below
+// 1e-17 before k = 40, well ahead of the smallest term (k ~ 2x).
+__device__ void hankel_pq(double a, double x, double &P, double &Q) {
+    const double a4 = 4.0 * a * a, i8x = 1.0 / (8.0 * x);
+    double t = 1.0;
+    P = 1.0;
+    Q = 0.0;
+    for (int k = 1; k < 48; ++k) {
+        t *= (a4 - (2.0 * k - 1.0) * (2.0 * k - 1.0)) * i8x / k;
+        const double s = ((k >> 1) & 1) ? -t : t;  // sign (-1)^floor(k/2)
+        if (k & 1)
+            Q += s;
+        else
+            P += s;
+        if (fabs(t) < 1e-17) break;
+    }
+}
+
+__device__ void bessel_run(double x, double sx, double cx, double Lnu, double mu, const double *__restrict__ ell,
+                           const int *__restrict__ perm, int r0, int r1, double *__restrict__ out) {
+    const double inv = 1.0 / x;
+    const int itop0 = (int)ceil(Lnu - mu) + 2;
+    int hi = r1 - 1;  // members above the start are zero
+    while (hi >= r0 && (int)floor(ell[perm[hi]]) > itop0) {
+        out[perm[hi]] = 0.0;
+        --hi;
+    }
+    if (hi < r0) return;
+    if (x < kHankelX) {
+        const double a = mu + 0.5;
+        int itop = itop0 + (itop0 & 1);  // even: the series terms sit on even i
+        double yp = 0.0, y = 1.0, rk = 1.0, sum = 0.0;
+        int q = hi;
+        for (int i = itop; i >= 0; --i) {
+            if (q >= r0 && (int)floor(ell[perm[q]]) == i) {
+                out[perm[q]] = y;
+                --q;
+            }
+            if (!(i & 1)) {
+                const int k = i >> 1;
+                sum += (a + 2.0 * k) * rk * y;
+                if (k) rk *= k / (a + k - 1.0);
+            }
+            if (i) {
+                const double yn = (2.0 * (mu + i) + 1.0) * inv * y - yp;
+                yp = y;
+                y = yn;
+            }
+        }
+        const double scale = exp(a * log(0.5 * x) - lgamma(a)) / (sqrt(2.0 * x / M_PI) * (sum / rk));
+        for (int u = r0; u <= hi; ++u) out[perm[u]] *= scale;
+        return;
+    }
+    // seeds from Hankel's expansion: w = x - (mu + 1) pi / 2
+    double sph, cph;
+    sincos(0.5 * M_PI * (mu + 1.0), &sph, &cph);
+    const double cw = cx * cph + sx * sph, sw = sx * cph - cx * sph;
+    double P0, Q0, P1, Q1;
+    hankel_pq(mu + 0.5, x, P0, Q0);
+    hankel_pq(mu + 1.5, x, P1, Q1);
+    double a0 = (P0 * cw - Q0 * sw) * inv;  // j_mu
+    double a1 = (P1 * sw + Q1 * cw) * inv;  // j_{mu+1}
+    const int m = (int)floor(x - mu);
+    int q = r0;
+    auto take = [&](int i, double v) {
+        while (q <= hi && (int)floor(ell[perm[q]]) == i) {
+            out[perm[q]] = v;
+            ++q;
+        }
+    };
+    take(0, a0);
+    take(1, a1);
+    const int nup = min((int)floor(ell[perm[hi]]), m);
+    for (int i = 1; i < nup; ++i) {
+        const double an = (2.0 * (mu + i) + 1.0) * inv * a1 - a0;
+        a0 = a1;
+        a1 = an;
+        take(i + 1, a1);
+    }
+    if (q > hi) return;
+    // members above m: Miller from the start down to m, normalised to j_{mu+m} from above
+    const double jm = nup >= 1 ? a1 : a0;  // nup = m here (m >= 29)
+    const int itop = max(itop0, m + 2);
+    double yp = 0.0, y = 1.0;
+    int u = hi;
+    for (int i = itop; i > m; --i) {
+        if (u >= q && (int)floor(ell[perm[u]]) == i) {
+            out[perm[u]] = y;
+            --u;
+        }
+        const double yn = (2.0 * (mu + i) + 1.0) * inv * y - yp;
+        yp = y;
+        y = yn;
+    }
+    const double scale = jm / y;
+    for (int v = q; v <= hi; ++v) out[perm[v]] *= scale;
+}
+
+// J[g][s][q][ilp] for a plan with non-integer multipoles (layout as bessel_kernel)
+__global__ __launch_bounds__(256) void bessel_real_kernel(Items it, const double *__restrict__ Kq,
+                                                          const double *__restrict__ chi, const double *__restrict__ R,
+                                                          int S, const double *__restrict__ ell,
+                                                          const int *__restrict__ perm, const int *__restrict__ runs,
+                                                          int nruns, int nl, int ilp, double *__restrict__ J) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y, g = blockIdx.z;
+    if (q >= kQc || g >= it.n) return;
+    double *out = J + (((size_t)g * S + s) * kQc + q) * ilp;
+    const double k = Kq[(size_t)g * kQc + q];
+    if (q >= it.nq[g] || k <= 0.0) {
+        for (int il = 0; il < ilp; ++il) out[il] = 0.0;
+        return;
+    }
+    const double x = k * chi[it.a[g]] * (s == 0 ? 1.0 : R[s - 1]);
+    double sx, cx;
+    sincos(x, &sx, &cx);
+    const double Lnu = miller_start(x);
+    for (int r = 0; r < nruns; ++r) {
+        const double l0 = ell[perm[runs[r]]];
+        bessel_run(x, sx, cx, Lnu, l0 - floor(l0), ell, perm, runs[r], runs[r + 1], out);
+    }
+    for (int il = nl; il < ilp; ++il) out[il] = 0.0;
 }
 
 // node tables of one launch: Tq[g][q][n], Fq[g][q][3], Kq[g][q]
@@ -367,6 +514,7 @@ blast_status build_basis(blast_plan *p, hipStream_t s) {
 
     double2 *d_panels = nullptr;
     double *d_Tq = nullptr, *d_Fq = nullptr, *d_Kq = nullptr, *d_J = nullptr, *d_R = nullptr;
+    int *d_perm = nullptr, *d_runs = nullptr;
     auto cleanup = [&]() {
         (void)hipStreamSynchronize(s);
         if (d_panels) (void)hipFree(d_panels);
@@ -375,6 +523,8 @@ blast_status build_basis(blast_plan *p, hipStream_t s) {
         if (d_Kq) (void)hipFree(d_Kq);
         if (d_J) (void)hipFree(d_J);
         if (d_R) (void)hipFree(d_R);
+        if (d_perm) (void)hipFree(d_perm);
+        if (d_runs) (void)hipFree(d_runs);
     };
     auto alloc = [&](void **q, size_t bytes) {
         hipError_t r = hipMalloc(q, bytes);
@@ -389,6 +539,29 @@ blast_status build_basis(blast_plan *p, hipStream_t s) {
     if (e == hipSuccess) e = alloc((void **)&d_R, p->n_R * sizeof(double));
     if (e == hipSuccess) e = hipMemcpy(d_panels, panels.data(), panels.size() * sizeof(double2), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_R, p->R.data(), p->n_R * sizeof(double), hipMemcpyHostToDevice);
+    // non-integer multipoles: runs of equal fractional part (each in increasing order)
+    int nruns = 0;
+    if (e == hipSuccess && !p->int_ell) {
+        std::vector<int> perm(p->n_ell), runs;
+        std::vector<char> done(p->n_ell, 0);
+        int np = 0;
+        for (int i = 0; i < p->n_ell; ++i) {
+            if (done[i]) continue;
+            const double mu = p->ell[i] - std::floor(p->ell[i]);
+            runs.push_back(np);
+            for (int j = i; j < p->n_ell; ++j)
+                if (!done[j] && p->ell[j] - std::floor(p->ell[j]) == mu) {
+                    done[j] = 1;
+                    perm[np++] = j;
+                }
+        }
+        runs.push_back(np);
+        nruns = (int)runs.size() - 1;
+        e = alloc((void **)&d_perm, perm.size() * sizeof(int));
+        if (e == hipSuccess) e = alloc((void **)&d_runs, runs.size() * sizeof(int));
+        if (e == hipSuccess) e = hipMemcpy(d_perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_runs, runs.data(), runs.size() * sizeof(int), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         set_error("basis workspace: %s", hipGetErrorString(e));
         cleanup();
@@ -415,8 +588,12 @@ blast_status build_basis(blast_plan *p, hipStream_t s) {
             if (!it.n) continue;
             hipLaunchKernelGGL(tq_kernel, dim3(kQc / 256, it.n), dim3(256), 0, s, it, d_panels, lnkmin, span,
                                p->n_cheb, ncp, p->nt, t0, t1, t2, d_Tq, d_Fq, d_Kq);
-            hipLaunchKernelGGL(bessel_kernel, dim3(kQc / 256, S, it.n), dim3(256), 0, s, it, d_Kq, p->d_chi, d_R, S,
-                               p->d_ell, p->n_ell, ilp, d_J);
+            if (p->int_ell)
+                hipLaunchKernelGGL(bessel_kernel, dim3(kQc / 256, S, it.n), dim3(256), 0, s, it, d_Kq, p->d_chi, d_R,
+                                   S, p->d_elli, p->n_ell, ilp, d_J);
+            else
+                hipLaunchKernelGGL(bessel_real_kernel, dim3(kQc / 256, S, it.n), dim3(256), 0, s, it, d_Kq, p->d_chi,
+                                   d_R, S, p->d_ell, d_perm, d_runs, nruns, p->n_ell, ilp, d_J);
             hipLaunchKernelGGL(gemm_kernel, dim3(ilp / 32, p->n_R, it.n), dim3(256), 0, s, it, d_J, d_Tq, d_Fq, S, ilp,
                                ncp, p->n_ell, p->nt, p->n_R, p->rows_pad, p->basis.f64);
             e = hipGetLastError();

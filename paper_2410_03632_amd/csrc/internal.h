@@ -49,8 +49,8 @@ struct blast_plan {
     int device = 0;
     // multipoles and types
     int n_ell = 0;
-    std::vector<int> ell;
-    int lmax = 0;
+    std::vector<double> ell;   // multipoles (any real values >= 2)
+    bool int_ell = true;       // every multipole is an integer
     uint32_t types = 0;
     int nt = 0;              // number of resident types
     int slot[3] = {-1, -1, -1};  // slot of gg, gs, ss rows (or -1)
@@ -76,7 +76,8 @@ struct blast_plan {
     float *d_dctn32 = nullptr;
     double *d_chi = nullptr, *d_wchi = nullptr, *d_wR = nullptr;
     double *d_pref = nullptr;   // [rows] N_t(l)
-    int *d_ell = nullptr;
+    double *d_ell = nullptr;    // [n_ell] multipoles
+    int *d_elli = nullptr;      // [n_ell] the same as integers (integer plans only)
     // stage timing: 5 events per recorded forward call
     bool profile = false;
     std::vector<hipEvent_t> prof_events;

@@ -83,7 +83,7 @@ template <typename PT>
 __global__ __launch_bounds__(256) void limber_kernel(const PT *__restrict__ P, const PT *__restrict__ Psub,
                                                      const double2 *__restrict__ KA, const double *__restrict__ chi,
                                                      const double *__restrict__ wchi, const double *__restrict__ pref,
-                                                     const int *__restrict__ ell, int slot_gg, int slot_gs,
+                                                     const double *__restrict__ ell, int slot_gg, int slot_gs,
                                                      int slot_ss, int n_chi, int n_ell, int ng, int ns, uint32_t types,
                                                      int npairs, LimbSel sel, int order, int accumulate,
                                                      double *__restrict__ C) {

@@ -42,8 +42,8 @@ OMEGA_M = 0.3
 def ell_list(n: int, lmin: int, lmax: int) -> np.ndarray:
     """n integer multipoles, log-spaced on [lmin, lmax], strictly increasing.
 
-    round(geomspace) and then every duplicate is bumped to previous + 1 (the paper
-    uses non-integer ell; integer ell is the reading taken here)."""
+    round(geomspace) and then every duplicate is bumped to previous + 1 (the default
+    workloads use integer ell; real_ell_list gives the challenge's kind of list)."""
     raw = np.rint(np.geomspace(lmin, lmax, n)).astype(np.int64)
     out = raw.copy()
     for i in range(1, n):
@@ -52,6 +52,12 @@ def ell_list(n: int, lmin: int, lmax: int) -> np.ndarray:
     if out[-1] > lmax:
         raise ValueError("cannot fit %d distinct integer ells in [%d, %d]" % (n, lmin, lmax))
     return out.astype(np.int32)
+
+
+def real_ell_list(n: int, lmin: float, lmax: float) -> np.ndarray:
+    """n log-spaced multipoles on [lmin, lmax], not rounded: the kind of multipole list the
+    paper's challenge evaluates (its values are not integers)."""
+    return np.geomspace(lmin, lmax, n)
 
 
 # ----------------------------------------------------------------------------

@@ -63,13 +63,13 @@ def test_grid_helpers_reject_bad_input():
 
 
 def _desc(**kw):
-    ell = np.array(kw.get("ell", [2, 5, 9]), dtype=np.int32)
+    ell = np.array(kw.get("ell", [2, 5, 9]), dtype=np.float64)
     chi = np.array(kw.get("chi", [100.0, 200.0, 300.0, 400.0]))
     w = np.ones_like(chi)
     R = np.array(kw.get("R", [0.5, 0.9]))
     wR = np.ones_like(R)
     keep = (ell, chi, w, R, wR)
-    d = B.PlanDesc(len(ell), ell.ctypes.data_as(C.POINTER(C.c_int32)), len(chi),
+    d = B.PlanDesc(len(ell), ell.ctypes.data_as(C.POINTER(C.c_double)), len(chi),
                    chi.ctypes.data_as(C.POINTER(C.c_double)), w.ctypes.data_as(C.POINTER(C.c_double)),
                    len(R), R.ctypes.data_as(C.POINTER(C.c_double)), wR.ctypes.data_as(C.POINTER(C.c_double)),
                    kw.get("kmin", 1e-4), kw.get("kmax", 1.0), kw.get("n_cheb", 16), kw.get("types", 7),
@@ -77,7 +77,8 @@ def _desc(**kw):
     return d, keep
 
 
-@pytest.mark.parametrize("bad", [dict(ell=[2, 2, 5]), dict(ell=[1, 4]), dict(chi=[0.0, 1.0, 2.0, 3.0]),
+@pytest.mark.parametrize("bad", [dict(ell=[2, 2, 5]), dict(ell=[1, 4]), dict(ell=[2.5, 2.5]), dict(ell=[1.99, 3.0]),
+                                 dict(ell=[2.0, float("nan")]), dict(ell=[2.0, 4096.5]), dict(chi=[0.0, 1.0, 2.0, 3.0]),
                                  dict(R=[0.5, 1.2]), dict(kmin=2.0, kmax=1.0), dict(n_cheb=1),
                                  dict(n_cheb=300), dict(types=0), dict(types=8), dict(prec=32)])
 def test_plan_create_rejects_bad_descriptor(bad):
