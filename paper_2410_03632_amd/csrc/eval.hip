@@ -851,6 +851,68 @@ __device__ inline void lds_read4(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t
         : "memory");
 }
 
+// FP32 contraction steps of the fused kernel, software-pipelined.  Each block issues the LDS reads
+// of the next step, then the four v_mfma_f32_16x16x4_f32 of the current step (operand a[e], b[e]
+// holds the K slice e of the step), and waits for its own reads before it ends, so no read is in
+// flight outside the block.  The leading s_nop keeps the MFMAs two wait states clear of any VALU
+// write of their operands.  The first block also reads the four 16-byte groups of kernel weights
+// and starts the accumulators from zero; the last one reads nothing and ends with 32 wait states,
+// so that the VALU may read the accumulators right after it.
+#define BLAST_MFMA4_ACC                                                                               \
+    "v_mfma_f32_16x16x4_f32 %[c0], %[a0], %[b0], %[c0]\n\t"                                        \
+    "v_mfma_f32_16x16x4_f32 %[c1], %[a1], %[b1], %[c1]\n\t"                                        \
+    "v_mfma_f32_16x16x4_f32 %[c2], %[a2], %[b2], %[c2]\n\t"                                        \
+    "v_mfma_f32_16x16x4_f32 %[c3], %[a3], %[b3], %[c3]\n\t"
+#define BLAST_AB_IN(av, bv)                                                                           \
+    [a0] "v"(av[0]), [a1] "v"(av[1]), [a2] "v"(av[2]), [a3] "v"(av[3]), [b0] "v"(bv[0]), [b1] "v"(bv[1]), \
+        [b2] "v"(bv[2]), [b3] "v"(bv[3])
+
+template <int AO, int CO>
+__device__ inline void mfma_first(uint32_t an, uint32_t cn, const uint32_t (&kq)[4], f4v av, f4v bv, U4 &ua, U4 &ub,
+                                  U4 (&q)[4], f4 &c0, f4 &c1, f4 &c2, f4 &c3) {
+    asm volatile(
+        "ds_read_b128 %[na], %[ab] offset:%[ao]\n\t"
+        "ds_read_b128 %[nb], %[cb] offset:%[co]\n\t"
+        "ds_read_b128 %[q0], %[k0]\n\t"
+        "ds_read_b128 %[q1], %[k1]\n\t"
+        "ds_read_b128 %[q2], %[k2]\n\t"
+        "ds_read_b128 %[q3], %[k3]\n\t"
+        "s_nop 1\n\t"
+        "v_mfma_f32_16x16x4_f32 %[c0], %[a0], %[b0], 0\n\t"
+        "v_mfma_f32_16x16x4_f32 %[c1], %[a1], %[b1], 0\n\t"
+        "v_mfma_f32_16x16x4_f32 %[c2], %[a2], %[b2], 0\n\t"
+        "v_mfma_f32_16x16x4_f32 %[c3], %[a3], %[b3], 0\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : [na] "=&v"(ua), [nb] "=&v"(ub), [q0] "=&v"(q[0]), [q1] "=&v"(q[1]), [q2] "=&v"(q[2]), [q3] "=&v"(q[3]),
+          [c0] "=&v"(c0), [c1] "=&v"(c1), [c2] "=&v"(c2), [c3] "=&v"(c3)
+        : [ab] "v"(an), [cb] "v"(cn), [ao] "i"(AO), [co] "i"(CO), [k0] "v"(kq[0]), [k1] "v"(kq[1]), [k2] "v"(kq[2]),
+          [k3] "v"(kq[3]), BLAST_AB_IN(av, bv)
+        : "memory");
+}
+template <int AO, int CO>
+__device__ inline void mfma_mid(uint32_t an, uint32_t cn, f4v av, f4v bv, U4 &ua, U4 &ub, f4 &c0, f4 &c1, f4 &c2,
+                                f4 &c3) {
+    asm volatile(
+        "ds_read_b128 %[na], %[ab] offset:%[ao]\n\t"
+        "ds_read_b128 %[nb], %[cb] offset:%[co]\n\t"
+        "s_nop 1\n\t"
+        BLAST_MFMA4_ACC
+        "s_waitcnt lgkmcnt(0)"
+        : [na] "=&v"(ua), [nb] "=&v"(ub), [c0] "+v"(c0), [c1] "+v"(c1), [c2] "+v"(c2), [c3] "+v"(c3)
+        : [ab] "v"(an), [cb] "v"(cn), [ao] "i"(AO), [co] "i"(CO), BLAST_AB_IN(av, bv)
+        : "memory");
+}
+__device__ inline void mfma_last(f4v av, f4v bv, f4 &c0, f4 &c1, f4 &c2, f4 &c3) {
+    asm volatile(
+        "s_nop 1\n\t"
+        BLAST_MFMA4_ACC
+        "s_nop 15\n\t"
+        "s_nop 15"
+        : [c0] "+v"(c0), [c1] "+v"(c1), [c2] "+v"(c2), [c3] "+v"(c3)
+        : BLAST_AB_IN(av, bv)
+        : "memory");
+}
+
 // s_waitcnt with only the vector-memory counter constrained (gfx9 encoding)
 template <int N>
 __device__ inline void wait_vmcnt() {
@@ -869,7 +931,6 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     constexpr int TR = kFusedTR, VEC = S::VEC, KSTEP = S::KSTEP, ncp = S::ncp, NPART = S::NPART;
     constexpr bool X3 = PREC == BLAST_BF16X3;
     constexpr int GPR = S::ROWB / 16;            // granules per c row
-    constexpr int RPC = 1024 / S::ROWB;          // c rows per 1 KB chunk
     // granule permutation mask: XOR by up to SWZ stays inside the row when SWZ + 1 divides GPR;
     // with 16 the 16 rows read by one instruction hit 16 distinct 16-byte bank groups
     constexpr int SWZ = GPR % 16 == 0 ? 15 : (GPR % 8 == 0 ? 7 : (GPR % 4 == 0 ? 3 : (GPR % 2 == 0 ? 1 : 0)));
@@ -941,7 +1002,9 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
         for (int k = 0; k < S::C_PW; ++k) {
             const int ch = min(w + k * S::NW, S::C_CH - 1);
             const int part = ch / (S::C_CH / NPART), chp = ch % (S::C_CH / NPART);
-            const int row = chp * RPC + lane / GPR, gp = lane % GPR;
+            // the lane's 16 bytes land at byte pos of the part's rows (a row need not divide 1 KB)
+            const int pos = chp * 1024 + lane * 16;
+            const int row = pos / S::ROWB, gp = (pos % S::ROWB) / 16;
             const int v = gp ^ (row & SWZ);          // granule stored at position gp
             const int bb = bt * 64 + (row < nb ? row : 0);
             const E *src = (part ? (const E *)c_lo : c) + ((size_t)bb * NP + ab) * ncp + v * VEC;
@@ -974,62 +1037,98 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
         dma_A(b + 2, Anext2);
         __builtin_amdgcn_sched_barrier(0);
         if (!busy) return;
-        // weights of this b's cosmology and the row scales, from LDS
         float kt[NB];
-        float4 sc = make_float4(1.f, 1.f, 1.f, 1.f);
-        {
-            const uint32_t kb = lds_addr(Cb + S::C_BUF) + (uint32_t)(16 * tk + lr) * (NB * 4);
-            const uint32_t sa = lds_addr(Cb + S::C_BUF + (size_t)KCH * 1024) + (uint32_t)(16 * min(ti, TR - 1) + 4 * lk) * 4;
-            U4 q[6];
-            constexpr int NQ = NB / 4;  // 1..5
-            if constexpr (KROT) {
-                const int rr = ((16 * tk + lr) >> 2) & 3;
-                lds_read4<0, 0, 0, 0>(kb + 16 * (rr & 3), kb + 16 * ((1 + rr) & 3), kb + 16 * ((2 + rr) & 3),
-                                      kb + 16 * ((3 + rr) & 3), q[0], q[1], q[2], q[3]);
-            } else {
-                lds_read4<0, (NQ > 1 ? 16 : 0), (NQ > 2 ? 32 : 0), (NQ > 3 ? 48 : 0)>(kb, kb, kb, kb, q[0], q[1], q[2],
-                                                                                      q[3]);
-            }
-            lds_read2<(NQ > 4 ? 64 : 0), 0>(kb, sa, q[4], q[5]);
-#pragma unroll
-            for (int j = 0; j < NQ; ++j) {
-                const f4v v = __builtin_bit_cast(f4v, q[j]);
-                kt[4 * j] = v[0], kt[4 * j + 1] = v[1], kt[4 * j + 2] = v[2], kt[4 * j + 3] = v[3];
-            }
-            if constexpr (PREC != BLAST_FP32) {
-                const f4v v = __builtin_bit_cast(f4v, q[5]);
-                sc = make_float4(v[0], v[1], v[2], v[3]);
-            }
-        }
+        f4 wv;
         const uint32_t As = lds_addr(Ab) + (uint32_t)arow * 16;
-        const uint32_t Asl = As + TR * NS * 64 * 16;
         // granule (4 st + lk) of row crow sits at ((4 st + lk) ^ m) with m = crow & SWZ < 16, i.e. at
         // 16 (st >> 2) + 4 ((st & 3) ^ (m >> 2)) + (lk ^ (m & 3)): one base per st & 3
         const uint32_t Cr = lds_addr(Cb) + (uint32_t)crow * S::ROWB;
         const int m = crow & SWZ, mh = m >> 2, ml = lk ^ (m & 3);
-        uint32_t Cq[4], Cql[4];
+        uint32_t Cq[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            Cq[k] = Cr + 16 * (4 * (k ^ mh) + ml);
-            Cql[k] = Cq[k] + S::C_BUF / NPART;
-        }
-        // four accumulators, so that consecutive MFMAs never wait for each other
-        f4 acc[4] = {f4{0, 0, 0, 0}, f4{0, 0, 0, 0}, f4{0, 0, 0, 0}, f4{0, 0, 0, 0}};
-        auto step_k = [&](auto stc) {
-            constexpr int st = decltype(stc)::value;
-            constexpr int coff = 256 * (st >> 2);
-            const uint32_t cb = Cq[st & 3], cbl = Cql[st & 3];
-            U4 ua, ub, ual, ubl;
-            if constexpr (X3)
-                lds_read4<st * 1024, coff, st * 1024, coff>(As, cb, Asl, cbl, ua, ub, ual, ubl);
-            else
-                lds_read2<st * 1024, coff>(As, cb, ua, ub);
-            if constexpr (PREC == BLAST_FP32) {
+        for (int k = 0; k < 4; ++k) Cq[k] = Cr + 16 * (4 * (k ^ mh) + ml);
+        constexpr int NQ = NB / 4;  // 16-byte groups of weights per cosmology, 1..5
+        const uint32_t kb = lds_addr(Cb + S::C_BUF) + (uint32_t)(16 * tk + lr) * (NB * 4);
+        if constexpr (PREC == BLAST_FP32) {
+            static_assert(NS >= 2, "pipelined FP32 steps");
+            // weight groups of this b's cosmology (granules rotated when KROT); groups past NQ repeat
+            // the last one
+            uint32_t kq[4];
+            const int rr = ((16 * tk + lr) >> 2) & 3;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) kq[j] = KROT ? kb + 16 * ((j + rr) & 3) : kb + 16 * (j < NQ ? j : NQ - 1);
+            U4 q[4], ua, ub;
+            lds_read2<0, 0>(As, Cq[0], ua, ub);  // operands of step 0
+            f4 c0, c1, c2, c3;
+            // step st: basis at As + 1024 st, c at Cq[st & 3] + 256 (st >> 2)
+            auto pipe = [&](auto stc) {
+                constexpr int st = decltype(stc)::value;
                 const f4v av = __builtin_bit_cast(f4v, ua), bv = __builtin_bit_cast(f4v, ub);
+                if constexpr (st + 1 < NS) {
+                    U4 na, nb;
+                    if constexpr (st == 0)
+                        mfma_first<1024, 0>(As, Cq[1], kq, av, bv, na, nb, q, c0, c1, c2, c3);
+                    else
+                        mfma_mid<(st + 1) * 1024, 256 * ((st + 1) >> 2)>(As, Cq[(st + 1) & 3], av, bv, na, nb, c0,
+                                                                         c1, c2, c3);
+                    ua = na;
+                    ub = nb;
+                } else {
+                    mfma_last(av, bv, c0, c1, c2, c3);
+                }
+            };
+            static_for<0, NS>(pipe);
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    acc[e] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e], bv[e], acc[e], 0, 0, 0);
-            } else {
+            for (int j = 0; j < (NQ < 4 ? NQ : 4); ++j) {
+                const f4v v = __builtin_bit_cast(f4v, q[j]);
+                kt[4 * j] = v[0], kt[4 * j + 1] = v[1], kt[4 * j + 2] = v[2], kt[4 * j + 3] = v[3];
+            }
+            if constexpr (NQ > 4) {
+                U4 q4, qd;
+                lds_read2<64, 64>(kb, kb, q4, qd);
+                const f4v v = __builtin_bit_cast(f4v, q4);
+                kt[16] = v[0], kt[17] = v[1], kt[18] = v[2], kt[19] = v[3];
+            }
+            wv = (c0 + c1) + (c2 + c3);
+        } else {
+            // weights of this b's cosmology and the row scales, from LDS
+            float4 sc;
+            {
+                const uint32_t sa =
+                    lds_addr(Cb + S::C_BUF + (size_t)KCH * 1024) + (uint32_t)(16 * min(ti, TR - 1) + 4 * lk) * 4;
+                U4 q[6];
+                if constexpr (KROT) {
+                    const int rr = ((16 * tk + lr) >> 2) & 3;
+                    lds_read4<0, 0, 0, 0>(kb + 16 * (rr & 3), kb + 16 * ((1 + rr) & 3), kb + 16 * ((2 + rr) & 3),
+                                          kb + 16 * ((3 + rr) & 3), q[0], q[1], q[2], q[3]);
+                } else {
+                    lds_read4<0, (NQ > 1 ? 16 : 0), (NQ > 2 ? 32 : 0), (NQ > 3 ? 48 : 0)>(kb, kb, kb, kb, q[0], q[1],
+                                                                                          q[2], q[3]);
+                }
+                lds_read2<(NQ > 4 ? 64 : 0), 0>(kb, sa, q[4], q[5]);
+#pragma unroll
+                for (int j = 0; j < NQ; ++j) {
+                    const f4v v = __builtin_bit_cast(f4v, q[j]);
+                    kt[4 * j] = v[0], kt[4 * j + 1] = v[1], kt[4 * j + 2] = v[2], kt[4 * j + 3] = v[3];
+                }
+                const f4v v = __builtin_bit_cast(f4v, q[5]);
+                sc = make_float4(v[0], v[1], v[2], v[3]);
+            }
+            const uint32_t Asl = As + TR * NS * 64 * 16;
+            uint32_t Cql[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Cql[k] = Cq[k] + S::C_BUF / NPART;
+            // four accumulators, so that consecutive MFMAs never wait for each other
+            f4 acc[4] = {f4{0, 0, 0, 0}, f4{0, 0, 0, 0}, f4{0, 0, 0, 0}, f4{0, 0, 0, 0}};
+            auto step_k = [&](auto stc) {
+                constexpr int st = decltype(stc)::value;
+                constexpr int coff = 256 * (st >> 2);
+                const uint32_t cb = Cq[st & 3], cbl = Cql[st & 3];
+                U4 ua, ub, ual, ubl;
+                if constexpr (X3)
+                    lds_read4<st * 1024, coff, st * 1024, coff>(As, cb, Asl, cbl, ua, ub, ual, ubl);
+                else
+                    lds_read2<st * 1024, coff>(As, cb, ua, ub);
                 const bf8 av = __builtin_bit_cast(bf8, ua), bv = __builtin_bit_cast(bf8, ub);
                 f4 &a0 = acc[st & 1];
                 a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, a0, 0, 0, 0);
@@ -1038,12 +1137,12 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
                     a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, ubl), a1, 0, 0, 0);
                     a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ual), bv, a1, 0, 0, 0);
                 }
-            }
-        };
-        static_for<0, NS>(step_k);
+            };
+            static_for<0, NS>(step_k);
+            wv = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+            wv[0] *= sc.x, wv[1] *= sc.y, wv[2] *= sc.z, wv[3] *= sc.w;
+        }
         // w tile of this b: lane holds rows 16 (rt0 + ti) + 4 lk + r for cosmology beta
-        f4 wv = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-        wv[0] *= sc.x, wv[1] *= sc.y, wv[2] *= sc.z, wv[3] *= sc.w;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll

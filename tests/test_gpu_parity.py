@@ -233,3 +233,44 @@ def test_named_config_delta_chi2(config):
         assert out["fp32"][0] < 0.2 and out["fp64"][0] < 1e-6
     finally:
         plan.close()
+
+
+FUSED = [  # (n_g, n_s, n_cheb): weight groups NB = 4, 16 (rotated granules), 20 (five groups), 8;
+    (2, 2, 24),     # and 2, 4, 6, 8 steps of 16 Chebyshev columns
+    (10, 5, 40),
+    (12, 6, 96),
+    (3, 5, 128),
+]
+
+
+@pytest.mark.parametrize("n_g,n_s,n_cheb", FUSED)
+@pytest.mark.parametrize("batch", [40, 70])
+def test_fused_batch_matches_single_calls_and_oracle(n_g, n_s, n_cheb, batch):
+    """From 32 cosmologies on, the mixed paths fuse the contraction with the R-quadrature (w stays
+    in registers); a single cosmology takes the unfused kernels.  Every cosmology of a fused call
+    must agree with its own single call, and the first with the oracle.  The two paths sum in
+    different orders; each carries a rounding error of 1e-5..1e-4 of the spectra (FP32, BF16x3)
+    against the oracle, so they may differ by a few times that, far inside the 1e-3 bar."""
+    cfg = W.tiny_config(n_ell=7, ell_max=50, n_chi=10, n_R=9, n_cheb=n_cheb, k_max=0.6, n_g=n_g, n_s=n_s)
+    print("fused case", n_g, n_s, n_cheb, batch, flush=True)
+    plan = B.plan_for_config(cfg, precisions=("fp64", "fp32", "bf16", "bf16x3"))
+    try:
+        inps = [W.make_inputs(cfg, W.seed_for(12, i), plan.k_nodes, plan.chi, plan.R, vary=True) for i in range(batch)]
+        P = _dev(np.stack([x.P for x in inps]), torch.float32)
+        K1 = _dev(np.stack([x.Kchi for x in inps]))
+        K2 = _dev(np.stack([x.Kchi2 for x in inps]))
+        Cor = _oracle(cfg, inps[0])
+        # plain BF16 (8-bit products) is a reported mode only: its error against the oracle grows
+        # with the Chebyshev order (0.55 at 96 columns here), the same in both paths
+        for prec, tol_single, tol_oracle in (("fp32", 3e-4, 1e-3), ("bf16x3", 4e-4, 1e-3), ("bf16", 1e-3, None)):
+            Cb = plan.forward(P, K1, K2, n_g, n_s, precision=prec).cpu().numpy()
+            worst = 0.0
+            for i in list(range(0, batch, 7)) + [batch - 1]:
+                Ci = plan.forward(P[i:i + 1].contiguous(), K1[i:i + 1].contiguous(), K2[i:i + 1].contiguous(), n_g,
+                                  n_s, precision=prec).cpu().numpy()[0]
+                worst = max(worst, g16_err(Cb[i], Ci, n_g, n_s).max())
+            eo = g16_err(Cb[0], Cor, n_g, n_s).max()
+            print(prec, "fused vs single", worst, "vs oracle", eo, flush=True)
+            assert worst <= tol_single and (tol_oracle is None or eo <= tol_oracle), (prec, worst, eo)
+    finally:
+        plan.close()
