@@ -857,7 +857,9 @@ __device__ inline void lds_read4(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t
 // flight outside the block.  The leading s_nop keeps the MFMAs two wait states clear of any VALU
 // write of their operands.  The first block also reads the four 16-byte groups of kernel weights
 // and starts the accumulators from zero; the last one reads nothing and ends with 32 wait states,
-// so that the VALU may read the accumulators right after it.
+// so that the VALU may read the accumulators right after it.  From the first block's MFMAs to the
+// end of the last one the wave runs at raised priority (s_setprio 3), so that the waves feeding
+// the MFMA unit issue ahead of those doing address arithmetic or the R-sum.
 #define BLAST_MFMA4_ACC                                                                               \
     "v_mfma_f32_16x16x4_f32 %[c0], %[a0], %[b0], %[c0]\n\t"                                        \
     "v_mfma_f32_16x16x4_f32 %[c1], %[a1], %[b1], %[c1]\n\t"                                        \
@@ -877,6 +879,7 @@ __device__ inline void mfma_first(uint32_t an, uint32_t cn, const uint32_t (&kq)
         "ds_read_b128 %[q1], %[k1]\n\t"
         "ds_read_b128 %[q2], %[k2]\n\t"
         "ds_read_b128 %[q3], %[k3]\n\t"
+        "s_setprio 3\n\t"
         "s_nop 1\n\t"
         "v_mfma_f32_16x16x4_f32 %[c0], %[a0], %[b0], 0\n\t"
         "v_mfma_f32_16x16x4_f32 %[c1], %[a1], %[b1], 0\n\t"
@@ -906,6 +909,7 @@ __device__ inline void mfma_last(f4v av, f4v bv, f4 &c0, f4 &c1, f4 &c2, f4 &c3)
     asm volatile(
         "s_nop 1\n\t"
         BLAST_MFMA4_ACC
+        "s_setprio 0\n\t"
         "s_nop 15\n\t"
         "s_nop 15"
         : [c0] "+v"(c0), [c1] "+v"(c1), [c2] "+v"(c2), [c3] "+v"(c3)
@@ -1186,19 +1190,35 @@ __global__ __launch_bounds__(256) void kt_kernel(const double *__restrict__ Kchi
     __shared__ float tile[32][16 * 20 + 1];  // [point][beta_local * NB + bin], NB <= 20
     const int ab0 = blockIdx.x * 32, b0 = blockIdx.y * 16;
     const int nbeta = min(16, batch - b0);
-    for (int i = threadIdx.x; i < 16 * NB * 32; i += blockDim.x) {
-        const int p = i % 32, q = i / 32;  // q = beta_local * NB + bin
-        const int bl = q / NB, bin = q % NB, ab = ab0 + p;
-        float v = 0.f;
-        if (bl < nbeta && bin < nbins && ab < NP)
-            v = (float)(wR[ab % n_R] * Kchi2[((size_t)(b0 + bl) * nbins + bin) * NP + ab]);
-        tile[p][q] = v;
+    // eight loads in flight per thread: clamped addresses, values masked afterwards
+    constexpr int U = 8;
+    const int total = 16 * NB * 32;
+    for (int i0 = threadIdx.x; i0 < total; i0 += U * blockDim.x) {
+        double kv[U], wv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = min(i0 + u * (int)blockDim.x, total - 1);
+            const int q = i / 32;  // q = beta_local * NB + bin
+            const int bl = min(q / NB, nbeta - 1), bin = min(q % NB, nbins - 1), ab = min(ab0 + i % 32, NP - 1);
+            kv[u] = Kchi2[((size_t)(b0 + bl) * nbins + bin) * NP + ab];
+            wv[u] = wR[ab % n_R];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            const int p = i % 32, q = i / 32;
+            if (i < total)
+                tile[p][q] = (q / NB < nbeta && q % NB < nbins && ab0 + p < NP) ? (float)(wv[u] * kv[u]) : 0.f;
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < 32 * nbeta * NB; i += blockDim.x) {
-        const int p = i / (nbeta * NB), q = i % (nbeta * NB);
-        const int ab = ab0 + p;
-        if (ab < NP) Kt[((size_t)ab * batch + b0) * NB + q] = tile[p][q];
+    // each point's nbeta * NB weights are contiguous in Kt: 16-byte stores (NB % 4 == 0)
+    const int rq = nbeta * NB / 4;
+    for (int i = threadIdx.x; i < 32 * rq; i += blockDim.x) {
+        const int p = i / rq, q = 4 * (i % rq);
+        if (ab0 + p < NP)
+            *(float4 *)(Kt + ((size_t)(ab0 + p) * batch + b0) * NB + q) =
+                make_float4(tile[p][q], tile[p][q + 1], tile[p][q + 2], tile[p][q + 3]);
     }
 }
 
@@ -1230,16 +1250,33 @@ __global__ __launch_bounds__(256) void quad_c_mfma_kernel(const YT *__restrict__
     extern __shared__ __align__(16) double smem_c[];
     const int nbins = ng + ns;
     const int nc4 = (n_chi + 3) & ~3;
-    double *Kt = smem_c;                           // [NBP][nc4]
+    // [nc4][NBP]: the 16 lanes of a K-step read 16 consecutive bins of one chi node (a bin-major
+    // table would put all 16 in one bank)
+    double *Kt = smem_c;
     double *Zs = smem_c + (size_t)NBP * nc4;       // [4 waves][NBP][NBP]
     const int nblk = (sel.n_out + kChiRows - 1) / kChiRows;
     const int slot = blockIdx.x / nblk, io0 = (blockIdx.x % nblk) * kChiRows;
     const int beta = blockIdx.y;
     const int t = slot_type.s[slot];
     if (!(t & types)) return;
-    for (int i = threadIdx.x; i < NBP * nc4; i += blockDim.x) {
-        const int bin = i / nc4, a = i % nc4;
-        Kt[i] = (bin < nbins && a < n_chi) ? wchi[a] * chi[a] * Kchi[((size_t)beta * nbins + bin) * n_chi + a] : 0.0;
+    {
+        // four loads in flight per thread (clamped addresses, masked values)
+        const int tot = NBP * nc4;
+        for (int i0 = threadIdx.x; i0 < tot; i0 += 4 * blockDim.x) {
+            double kv[4], wc[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = min(i0 + u * (int)blockDim.x, tot - 1);
+                const int bin = min(i % NBP, nbins - 1), a = min(i / NBP, n_chi - 1);
+                kv[u] = Kchi[((size_t)beta * nbins + bin) * n_chi + a];
+                wc[u] = wchi[a] * chi[a];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * (int)blockDim.x;
+                if (i < tot) Kt[i] = (i % NBP < nbins && i / NBP < n_chi) ? wc[u] * kv[u] : 0.0;
+            }
+        }
     }
     __syncthreads();
     int off, ntp;
@@ -1264,39 +1301,41 @@ __global__ __launch_bounds__(256) void quad_c_mfma_kernel(const YT *__restrict__
         for (int i = 0; i < NBT; ++i)
 #pragma unroll
             for (int j = 0; j < NBT; ++j) acc[i][j] = d4{0, 0, 0, 0};
-        // full blocks of KB K-steps: all loads first (clamped addresses, masked values), then MFMAs
+        // full blocks of KB K-steps: the raw loads of the block go out first (clamped addresses; the
+        // scheduling barrier keeps the compiler from pairing each load with its use), then the
+        // conversions, masks and MFMAs
         constexpr int KB = 16;
         const int nsteps = nc4 / 4;
-        auto kstep = [&](int st, const double(&b)[NBT]) {
+        auto kstep = [&](int st, const YT(&raw)[NBT]) {
             const int a = 4 * st + lk;
-            double av[NBT];
+            double av[NBT], b[NBT];
 #pragma unroll
-            for (int i = 0; i < NBT; ++i) av[i] = Kt[(size_t)(16 * i + lr) * nc4 + a];
+            for (int i = 0; i < NBT; ++i) {
+                av[i] = Kt[(size_t)a * NBP + 16 * i + lr];
+                b[i] = a < n_chi ? (double)raw[i] : 0.0;
+            }
 #pragma unroll
             for (int i = 0; i < NBT; ++i)
 #pragma unroll
                 for (int j = 0; j < NBT; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], b[j], acc[i][j], 0, 0, 0);
         };
-        auto loadB = [&](int st, double(&b)[NBT]) {
-            const int a = 4 * st + lk;
-            const int ac = a < n_chi ? a : n_chi - 1;
+        auto loadB = [&](int st, YT(&raw)[NBT]) {
+            const int ac = min(4 * st + lk, n_chi - 1);
 #pragma unroll
-            for (int i = 0; i < NBT; ++i) {
-                const double v = (double)yr[(size_t)ac * NBP + 16 * i + lr];
-                b[i] = a < n_chi ? v : 0.0;
-            }
+            for (int i = 0; i < NBT; ++i) raw[i] = yr[(size_t)ac * NBP + 16 * i + lr];
         };
         int s0 = 0;
         for (; s0 + KB <= nsteps; s0 += KB) {
-            double bv[KB][NBT];
+            YT bv[KB][NBT];
 #pragma unroll
             for (int u = 0; u < KB; ++u) loadB(s0 + u, bv[u]);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < KB; ++u) kstep(s0 + u, bv[u]);
         }
         for (; s0 < nsteps; ++s0) {
-            double bv[NBT];
+            YT bv[NBT];
             loadB(s0, bv);
             kstep(s0, bv);
         }
