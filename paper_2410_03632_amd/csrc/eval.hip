@@ -26,6 +26,11 @@ typedef uint32_t U4 __attribute__((ext_vector_type(4)));
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
+template <typename T>
+struct TypeTag {
+    using type = T;
+};
+
 // ---------------------------------------------------------------------------------------------
 // projection
 // ---------------------------------------------------------------------------------------------
@@ -206,14 +211,18 @@ __global__ __launch_bounds__(256) void project_mfma_kernel(const PT *__restrict_
 // 8-byte pair.
 constexpr int kSplitRT = 2;
 
-template <typename PT, int OUT>
+// NT = Hp / 16 output tiles per parity (1..4) and as many K steps: with both known at compile time
+// the step loop unrolls and every load is unconditional (rows past the end read the last row and
+// are never stored), so the compiler can wait for exactly the loads a step needs and the next
+// step's loads stay in flight under the current step's MFMAs.
+template <typename PT, int OUT, int NT>
 __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict__ P, const float *__restrict__ Dn,
                                                             int N, int ncp, long nrows, void *__restrict__ c_out,
                                                             uint16_t *__restrict__ c_lo) {
     constexpr int RT = kSplitRT, VEC = 4, KSTEP = 16;
-    constexpr int MAXT = kMaxCheb / 32;  // output tiles per parity
     extern __shared__ __align__(16) unsigned char smem_s[];
-    const int H = N / 2, Hp = ncp / 2, hs = Hp + 4;  // LDS row stride: 16 bytes of padding
+    const int H = N / 2;
+    constexpr int Hp = 16 * NT, hs = Hp + 4;  // LDS row stride: 16 bytes of padding
     float *De = (float *)smem_s, *Do = De + (size_t)Hp * hs;
     for (int i = threadIdx.x; i < Hp * (Hp / 4); i += blockDim.x) {
         const int m = i / (Hp / 4), q = i % (Hp / 4);
@@ -228,13 +237,15 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
     __syncthreads();
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
-    const int nt = Hp >> 4, nsteps = Hp / KSTEP;
     const long row0 = (long)blockIdx.x * (64 * RT) + 16 * RT * w;
-    f4 ae[RT][MAXT], ao[RT][MAXT];
+    const PT *prow[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) prow[r] = P + min(row0 + 16 * r + lr, nrows - 1) * (long)N;
+    f4 ae[RT][NT], ao[RT][NT];
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
-        for (int t = 0; t < MAXT; ++t) ae[r][t] = ao[r][t] = f4{0, 0, 0, 0};
+        for (int t = 0; t < NT; ++t) ae[r][t] = ao[r][t] = f4{0, 0, 0, 0};
 
     // raw P values of one step: front[r] = P[j0 .. j0+3], back[r] = P[N-4-j0 .. N-1-j0]
     // past N/2 the weights are zero, so any finite P values will do: the loads are clamped to the
@@ -243,20 +254,15 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
         const int j0 = min(st * KSTEP + lk * VEC, H - 4);
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
-            const long row = row0 + 16 * r + lr;
-            if (row < nrows) {
-                const PT *pr = P + row * (long)N;
-                if constexpr (sizeof(PT) == 4) {
-                    front[r] = *(const float4 *)(pr + j0);
-                    back[r] = *(const float4 *)(pr + N - 4 - j0);
-                } else {
-                    const double2 f0 = *(const double2 *)(pr + j0), f1 = *(const double2 *)(pr + j0 + 2);
-                    const double2 b0 = *(const double2 *)(pr + N - 4 - j0), b1 = *(const double2 *)(pr + N - 2 - j0);
-                    front[r] = make_float4((float)f0.x, (float)f0.y, (float)f1.x, (float)f1.y);
-                    back[r] = make_float4((float)b0.x, (float)b0.y, (float)b1.x, (float)b1.y);
-                }
+            const PT *pr = prow[r];
+            if constexpr (sizeof(PT) == 4) {
+                front[r] = *(const float4 *)(pr + j0);
+                back[r] = *(const float4 *)(pr + N - 4 - j0);
             } else {
-                front[r] = back[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+                const double2 f0 = *(const double2 *)(pr + j0), f1 = *(const double2 *)(pr + j0 + 2);
+                const double2 b0 = *(const double2 *)(pr + N - 4 - j0), b1 = *(const double2 *)(pr + N - 2 - j0);
+                front[r] = make_float4((float)f0.x, (float)f0.y, (float)f1.x, (float)f1.y);
+                back[r] = make_float4((float)b0.x, (float)b0.y, (float)b1.x, (float)b1.y);
             }
         }
     };
@@ -272,8 +278,7 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
             u[r][3] = front[r].w + back[r].x, v[r][3] = front[r].w - back[r].x;
         }
 #pragma unroll
-        for (int t = 0; t < MAXT; ++t) {
-            if (t >= nt) break;
+        for (int t = 0; t < NT; ++t) {
             const float4 de = *(const float4 *)(De + (size_t)(16 * t + lr) * hs + j0);
             const float4 dd = *(const float4 *)(Do + (size_t)(16 * t + lr) * hs + j0);
             const float dev[4] = {de.x, de.y, de.z, de.w}, dov[4] = {dd.x, dd.y, dd.z, dd.w};
@@ -286,22 +291,18 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
                 }
         }
     };
-    float4 f0[RT], b0[RT], f1[RT], b1[RT];
-    load(0, f0, b0);
-    for (int st = 0; st < nsteps; st += 2) {
-        if (st + 1 < nsteps) load(st + 1, f1, b1);
-        compute(st, f0, b0);
-        if (st + 1 < nsteps) {
-            if (st + 2 < nsteps) load(st + 2, f0, b0);
-            compute(st + 1, f1, b1);
-        }
+    float4 fr[2][RT], bk[2][RT];
+    load(0, fr[0], bk[0]);
+#pragma unroll
+    for (int st = 0; st < NT; ++st) {
+        if (st + 1 < NT) load(st + 1, fr[(st + 1) & 1], bk[(st + 1) & 1]);
+        compute(st, fr[st & 1], bk[st & 1]);
     }
     // lane holds rows 16r + 4lk + q of output m = 16t + lr, i.e. n = 2m and 2m + 1
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
-        for (int t = 0; t < MAXT; ++t) {
-            if (t >= nt) break;
+        for (int t = 0; t < NT; ++t) {
             const int n = 2 * (16 * t + lr);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -1819,14 +1820,26 @@ void stage_project(blast_plan *p, const blast_cl_args *a, const Ctx &x, void *c,
     if (!f64 && N % 8 == 0) {
         dim3 grid((unsigned)((nrows + 64 * kSplitRT - 1) / (64 * kSplitRT)));
         const size_t shp = (size_t)2 * (ncp / 2) * (ncp / 2 + 4) * sizeof(float);
-#define BLAST_PROJ(PT, O) \
-    hipLaunchKernelGGL((project_split_kernel<PT, O>), grid, dim3(256), shp, s, (const PT *)a->P, p->d_dctn32, N, \
-                       ncp, nrows, c, clo)
-        if (p64 && out == 1) BLAST_PROJ(double, 1);
-        if (p64 && out == 2) BLAST_PROJ(double, 2);
-        if (!p64 && out == 1) BLAST_PROJ(float, 1);
-        if (!p64 && out == 2) BLAST_PROJ(float, 2);
-#undef BLAST_PROJ
+        auto launch = [&](auto ptag, auto otag, auto nttag) {
+            using PT = typename decltype(ptag)::type;
+            constexpr int O = decltype(otag)::value, NT = decltype(nttag)::value;
+            hipLaunchKernelGGL((project_split_kernel<PT, O, NT>), grid, dim3(256), shp, s, (const PT *)a->P,
+                               p->d_dctn32, N, ncp, nrows, c, clo);
+        };
+        auto by_nt = [&](auto ptag, auto otag) {
+            switch (ncp / 32) {  // Hp / 16 = ncp / 32, ncp a multiple of 32 up to 128
+                case 1: launch(ptag, otag, std::integral_constant<int, 1>()); break;
+                case 2: launch(ptag, otag, std::integral_constant<int, 2>()); break;
+                case 3: launch(ptag, otag, std::integral_constant<int, 3>()); break;
+                default: launch(ptag, otag, std::integral_constant<int, 4>()); break;
+            }
+        };
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        if (p64 && out == 1) by_nt(TypeTag<double>(), I1());
+        if (p64 && out == 2) by_nt(TypeTag<double>(), I2());
+        if (!p64 && out == 1) by_nt(TypeTag<float>(), I1());
+        if (!p64 && out == 2) by_nt(TypeTag<float>(), I2());
     } else if (N % (f64 ? 8 : 16) == 0) {
         dim3 grid((unsigned)((nrows + 255) / 256));
         const size_t shp = f64 ? 0 : (size_t)ncp * (N + 4) * sizeof(float);
