@@ -854,8 +854,9 @@ __device__ inline void lds_read4(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t
 
 // FP32 contraction steps of the fused kernel, software-pipelined.  Each block issues the LDS reads
 // of the next step, then the four v_mfma_f32_16x16x4_f32 of the current step (operand a[e], b[e]
-// holds the K slice e of the step), and waits for its own reads before it ends, so no read is in
-// flight outside the block.  The leading s_nop keeps the MFMAs two wait states clear of any VALU
+// holds the K slice e of the step) into two accumulator chains (each MFMA one instruction behind
+// the one it depends on, an exact overlap of SrcC and the previous result, which the hardware
+// orders), and waits for its own reads before it ends, so no read is in flight outside the block.  The leading s_nop keeps the MFMAs two wait states clear of any VALU
 // write of their operands.  The first block also reads the four 16-byte groups of kernel weights
 // and starts the accumulators from zero; the last one reads nothing and ends with 32 wait states,
 // so that the VALU may read the accumulators right after it.  From the first block's MFMAs to the
@@ -864,15 +865,15 @@ __device__ inline void lds_read4(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t
 #define BLAST_MFMA4_ACC                                                                               \
     "v_mfma_f32_16x16x4_f32 %[c0], %[a0], %[b0], %[c0]\n\t"                                        \
     "v_mfma_f32_16x16x4_f32 %[c1], %[a1], %[b1], %[c1]\n\t"                                        \
-    "v_mfma_f32_16x16x4_f32 %[c2], %[a2], %[b2], %[c2]\n\t"                                        \
-    "v_mfma_f32_16x16x4_f32 %[c3], %[a3], %[b3], %[c3]\n\t"
+    "v_mfma_f32_16x16x4_f32 %[c0], %[a2], %[b2], %[c0]\n\t"                                        \
+    "v_mfma_f32_16x16x4_f32 %[c1], %[a3], %[b3], %[c1]\n\t"
 #define BLAST_AB_IN(av, bv)                                                                           \
     [a0] "v"(av[0]), [a1] "v"(av[1]), [a2] "v"(av[2]), [a3] "v"(av[3]), [b0] "v"(bv[0]), [b1] "v"(bv[1]), \
         [b2] "v"(bv[2]), [b3] "v"(bv[3])
 
 template <int AO, int CO>
 __device__ inline void mfma_first(uint32_t an, uint32_t cn, const uint32_t (&kq)[4], f4v av, f4v bv, U4 &ua, U4 &ub,
-                                  U4 (&q)[4], f4 &c0, f4 &c1, f4 &c2, f4 &c3) {
+                                  U4 (&q)[4], f4 &c0, f4 &c1) {
     asm volatile(
         "ds_read_b128 %[na], %[ab] offset:%[ao]\n\t"
         "ds_read_b128 %[nb], %[cb] offset:%[co]\n\t"
@@ -884,36 +885,35 @@ __device__ inline void mfma_first(uint32_t an, uint32_t cn, const uint32_t (&kq)
         "s_nop 1\n\t"
         "v_mfma_f32_16x16x4_f32 %[c0], %[a0], %[b0], 0\n\t"
         "v_mfma_f32_16x16x4_f32 %[c1], %[a1], %[b1], 0\n\t"
-        "v_mfma_f32_16x16x4_f32 %[c2], %[a2], %[b2], 0\n\t"
-        "v_mfma_f32_16x16x4_f32 %[c3], %[a3], %[b3], 0\n\t"
+        "v_mfma_f32_16x16x4_f32 %[c0], %[a2], %[b2], %[c0]\n\t"
+        "v_mfma_f32_16x16x4_f32 %[c1], %[a3], %[b3], %[c1]\n\t"
         "s_waitcnt lgkmcnt(0)"
         : [na] "=&v"(ua), [nb] "=&v"(ub), [q0] "=&v"(q[0]), [q1] "=&v"(q[1]), [q2] "=&v"(q[2]), [q3] "=&v"(q[3]),
-          [c0] "=&v"(c0), [c1] "=&v"(c1), [c2] "=&v"(c2), [c3] "=&v"(c3)
+          [c0] "=&v"(c0), [c1] "=&v"(c1)
         : [ab] "v"(an), [cb] "v"(cn), [ao] "i"(AO), [co] "i"(CO), [k0] "v"(kq[0]), [k1] "v"(kq[1]), [k2] "v"(kq[2]),
           [k3] "v"(kq[3]), BLAST_AB_IN(av, bv)
         : "memory");
 }
 template <int AO, int CO>
-__device__ inline void mfma_mid(uint32_t an, uint32_t cn, f4v av, f4v bv, U4 &ua, U4 &ub, f4 &c0, f4 &c1, f4 &c2,
-                                f4 &c3) {
+__device__ inline void mfma_mid(uint32_t an, uint32_t cn, f4v av, f4v bv, U4 &ua, U4 &ub, f4 &c0, f4 &c1) {
     asm volatile(
         "ds_read_b128 %[na], %[ab] offset:%[ao]\n\t"
         "ds_read_b128 %[nb], %[cb] offset:%[co]\n\t"
         "s_nop 1\n\t"
         BLAST_MFMA4_ACC
         "s_waitcnt lgkmcnt(0)"
-        : [na] "=&v"(ua), [nb] "=&v"(ub), [c0] "+v"(c0), [c1] "+v"(c1), [c2] "+v"(c2), [c3] "+v"(c3)
+        : [na] "=&v"(ua), [nb] "=&v"(ub), [c0] "+v"(c0), [c1] "+v"(c1)
         : [ab] "v"(an), [cb] "v"(cn), [ao] "i"(AO), [co] "i"(CO), BLAST_AB_IN(av, bv)
         : "memory");
 }
-__device__ inline void mfma_last(f4v av, f4v bv, f4 &c0, f4 &c1, f4 &c2, f4 &c3) {
+__device__ inline void mfma_last(f4v av, f4v bv, f4 &c0, f4 &c1) {
     asm volatile(
         "s_nop 1\n\t"
         BLAST_MFMA4_ACC
         "s_setprio 0\n\t"
         "s_nop 15\n\t"
         "s_nop 15"
-        : [c0] "+v"(c0), [c1] "+v"(c1), [c2] "+v"(c2), [c3] "+v"(c3)
+        : [c0] "+v"(c0), [c1] "+v"(c1)
         : BLAST_AB_IN(av, bv)
         : "memory");
 }
@@ -970,51 +970,62 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     // every wave issues exactly A_PW + C_PW DMA instructions per b (chunk indices past the end are
     // clamped to the last chunk, which is then written more than once with identical data), so
     // the wait counts below are constants
+    // Source addresses: a part that depends on b only (uniform, scalar registers) plus a per-lane
+    // part that does not depend on b (computed once, before the loop).
+    const U4 *srcA[S::A_PW];
+#pragma unroll
+    for (int k = 0; k < S::A_PW; ++k) {
+        const int ch = min(w + k * S::NW, S::A_CH - 1);
+        const int part = ch / (TR * NS), tl = (ch / NS) % TR, st = ch % NS;
+        const int rt = min(rt0 + tl, RT - 1);
+        srcA[k] = (const U4 *)(part ? (const void *)basis_lo : (const void *)basis) + ((size_t)rt * NS + st) * 64 + lane;
+    }
     auto dma_A = [&](int b, unsigned char *__restrict__ buf) {
         const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
 #pragma unroll
-        for (int k = 0; k < S::A_PW; ++k) {
-            const int ch = min(w + k * S::NW, S::A_CH - 1);
-            const int part = ch / (TR * NS), tl = (ch / NS) % TR, st = ch % NS;
-            const int rt = min(rt0 + tl, RT - 1);
-            const U4 *src = (const U4 *)(part ? (const void *)basis_lo : (const void *)basis) +
-                            ab * pt_u4 + ((size_t)rt * NS + st) * 64 + lane;
-            lds_dma16(src, buf + (size_t)ch * 1024);
-        }
+        for (int k = 0; k < S::A_PW; ++k)
+            lds_dma16(srcA[k] + ab * pt_u4, buf + (size_t)min(w + k * S::NW, S::A_CH - 1) * 1024);
     };
     // kernel weights Kt[ab][64 cosmologies][NB] (contiguous) and the row scales of the group, one
     // DMA per wave: waves 0..KCH-1 move weight chunks, wave KCH the scales, the others repeat
     constexpr int KCH = 64 * NB * 4 / 1024;
     static_assert(KCH + 1 <= S::NW && TR * 16 * 4 <= 1024 && KCH * 1024 + 1024 <= (int)S::X_BUF, "extra region");
-    auto dma_X = [&](int b, unsigned char *__restrict__ buf) {
-        const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
-        const int ch = min(w, KCH);
-        int f = ch * 256 + lane * 4;                         // float index of the LDS position
+    const int chX = min(w, KCH);
+    const float *srcX;  // b-independent part: weights of (tile cosmology, bin), or the scales of the group's rows
+    {
+        int f = chX * 256 + lane * 4;                        // float index of the LDS position
         if (KROT) {                                          // position 4r + ((q + (r >> 2)) & 3) holds granule q
             const int r = f / 16, sp = (f / 4) & 3;
             f = r * 16 + ((sp - (r >> 2)) & 3) * 4;
         }
         const int bl = f / NB;
         // cosmologies past the batch read the tile's first weight instead (never used)
-        const float *kp = Kt + (ab * batch + bt * 64 + (bl < nb ? bl : 0)) * NB + (bl < nb ? f % NB : 0);
-        const int row = min(16 * rt0 + 4 * lane, rows_pad - 4);
-        const float *sp = PREC != BLAST_FP32 ? scale + ab * rows_pad + row : Kt;
-        lds_dma16(ch < KCH ? kp : sp, buf + S::C_BUF + (size_t)ch * 1024);
+        srcX = chX < KCH ? Kt + (size_t)(bt * 64 + (bl < nb ? bl : 0)) * NB + (bl < nb ? f % NB : 0)
+                         : (PREC != BLAST_FP32 ? scale + min(16 * rt0 + 4 * lane, rows_pad - 4) : Kt);
+    }
+    // per b: the weights advance by batch * NB floats per point, the scales by rows_pad
+    const size_t strideX = chX < KCH ? (size_t)batch * NB : (PREC != BLAST_FP32 ? (size_t)rows_pad : 0);
+    auto dma_X = [&](int b, unsigned char *__restrict__ buf) {
+        const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
+        lds_dma16(srcX + ab * strideX, buf + S::C_BUF + (size_t)chX * 1024);
     };
+    const void *srcC[S::C_PW];
+#pragma unroll
+    for (int k = 0; k < S::C_PW; ++k) {
+        const int ch = min(w + k * S::NW, S::C_CH - 1);
+        const int part = ch / (S::C_CH / NPART), chp = ch % (S::C_CH / NPART);
+        // the lane's 16 bytes land at byte pos of the part's rows (a row need not divide 1 KB)
+        const int pos = chp * 1024 + lane * 16;
+        const int row = pos / S::ROWB, gp = (pos % S::ROWB) / 16;
+        const int v = gp ^ (row & SWZ);          // granule stored at position gp
+        const int bb = bt * 64 + (row < nb ? row : 0);
+        srcC[k] = (part ? (const E *)c_lo : c) + (size_t)bb * NP * ncp + v * VEC;
+    }
     auto dma_C = [&](int b, unsigned char *__restrict__ buf) {
         const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
 #pragma unroll
-        for (int k = 0; k < S::C_PW; ++k) {
-            const int ch = min(w + k * S::NW, S::C_CH - 1);
-            const int part = ch / (S::C_CH / NPART), chp = ch % (S::C_CH / NPART);
-            // the lane's 16 bytes land at byte pos of the part's rows (a row need not divide 1 KB)
-            const int pos = chp * 1024 + lane * 16;
-            const int row = pos / S::ROWB, gp = (pos % S::ROWB) / 16;
-            const int v = gp ^ (row & SWZ);          // granule stored at position gp
-            const int bb = bt * 64 + (row < nb ? row : 0);
-            const E *src = (part ? (const E *)c_lo : c) + ((size_t)bb * NP + ab) * ncp + v * VEC;
-            lds_dma16(src, buf + (size_t)ch * 1024);
-        }
+        for (int k = 0; k < S::C_PW; ++k)
+            lds_dma16((const E *)srcC[k] + ab * ncp, buf + (size_t)min(w + k * S::NW, S::C_CH - 1) * 1024);
     };
 
     float y[4][NB];
@@ -1064,7 +1075,7 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
             for (int j = 0; j < 4; ++j) kq[j] = KROT ? kb + 16 * ((j + rr) & 3) : kb + 16 * (j < NQ ? j : NQ - 1);
             U4 q[4], ua, ub;
             lds_read2<0, 0>(As, Cq[0], ua, ub);  // operands of step 0
-            f4 c0, c1, c2, c3;
+            f4 c0, c1;
             // step st: basis at As + 1024 st, c at Cq[st & 3] + 256 (st >> 2)
             auto pipe = [&](auto stc) {
                 constexpr int st = decltype(stc)::value;
@@ -1072,14 +1083,14 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
                 if constexpr (st + 1 < NS) {
                     U4 na, nb;
                     if constexpr (st == 0)
-                        mfma_first<1024, 0>(As, Cq[1], kq, av, bv, na, nb, q, c0, c1, c2, c3);
+                        mfma_first<1024, 0>(As, Cq[1], kq, av, bv, na, nb, q, c0, c1);
                     else
                         mfma_mid<(st + 1) * 1024, 256 * ((st + 1) >> 2)>(As, Cq[(st + 1) & 3], av, bv, na, nb, c0,
-                                                                         c1, c2, c3);
+                                                                         c1);
                     ua = na;
                     ub = nb;
                 } else {
-                    mfma_last(av, bv, c0, c1, c2, c3);
+                    mfma_last(av, bv, c0, c1);
                 }
             };
             static_for<0, NS>(pipe);
@@ -1094,7 +1105,7 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
                 const f4v v = __builtin_bit_cast(f4v, q4);
                 kt[16] = v[0], kt[17] = v[1], kt[18] = v[2], kt[19] = v[3];
             }
-            wv = (c0 + c1) + (c2 + c3);
+            wv = c0 + c1;
         } else {
             // weights of this b's cosmology and the row scales, from LDS
             float4 sc;
