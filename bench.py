@@ -483,6 +483,23 @@ def main():
             plan.limber(PN, K1, cfg.n_g, cfg.n_s, P_sub=PL, order=2, out=out, accumulate=True)
         torch.cuda.synchronize()
         extras["limber_correction_ms_per_step"] = (time.perf_counter() - t0) * 1e3 / 5
+        # one GPU's share of an 8-way split over multipoles (basis rows are independent, so G GPUs
+        # would each hold 1/G of the rows): every 8th multipole, same grids, same batch
+        ells = cfg.ells()[::8]
+        tb = time.time()
+        ps = B.Plan(ells, plan.chi, plan.w_chi, plan.R, plan.w_R, cfg.k_min, cfg.k_max, cfg.n_cheb, precisions=(prec,))
+        tb = time.time() - tb
+        for _ in range(2):
+            ps.forward(P, K1, K2, cfg.n_g, cfg.n_s, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            ps.forward(P, K1, K2, cfg.n_g, cfg.n_s, precision=prec)
+        torch.cuda.synchronize()
+        ms_s = (time.perf_counter() - t0) * 1e3 / 10
+        extras["multipole_slice_of_8"] = {"n_ell": len(ells), "batch": Bn, "ms_per_step": ms_s,
+                                          "sets_per_s_of_the_slice": Bn / (ms_s * 1e-3), "plan_build_s": tb}
+        ps.close()
 
     serving = None
     if args.serving_seconds > 0:

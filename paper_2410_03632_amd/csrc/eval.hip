@@ -1734,6 +1734,18 @@ hipError_t allow_large_lds() {
     return err;
 }
 
+// Threads per work-group of quad_y_kernel: a work-group of T threads spans at most
+// (T - 1) / RQ + 2 chi nodes, whose R weights [node][n_R][NB] it keeps in LDS; the largest of
+// 256, 192, 128, 64 whose table fits in 160 KB (0: none fits).
+int quad_y_threads(const blast_plan *p, bool f64, int nbp) {
+    const int rq = p->rows_pad / (f64 ? 2 : 4);
+    const size_t el = f64 ? 8 : 4;
+    for (int t = 256; t >= 64; t -= 64)
+        if ((size_t)((t - 1) / rq + 2) * p->n_R * nbp * el <= 160 * 1024) return t;
+    return 0;
+}
+
+
 blast_status check_args(const blast_plan *p, const blast_cl_args *a, Ctx &x) {
     if (a->batch < 1) return set_error("batch must be >= 1"), BLAST_E_INVALID;
     if (a->precision < 0 || a->precision > 3) return set_error("unknown precision %d", a->precision), BLAST_E_INVALID;
@@ -1774,7 +1786,7 @@ blast_status check_args(const blast_plan *p, const blast_cl_args *a, Ctx &x) {
     for (int i = 0; i < x.sel.n_out; ++i) x.inv.io[x.sel.idx[i]] = (int16_t)i;
     if (((size_t)x.nbp * (p->n_chi + 4) + 4 * 32 * 32) * sizeof(double) > 160 * 1024)
         return set_error("n_chi too large for the chi-quadrature tile"), BLAST_E_UNSUPPORTED;
-    if ((size_t)(256 / (p->rows_pad / 4) + 2) * p->n_R * x.nbp * 8 > 160 * 1024)
+    if (!quad_y_threads(p, x.prec == BLAST_FP64, x.nbp))
         return set_error("n_R too large for the R-quadrature tile"), BLAST_E_UNSUPPORTED;
     return BLAST_OK;
 }
@@ -1912,11 +1924,12 @@ void stage_quad_y(blast_plan *p, const blast_cl_args *a, const Ctx &x, const voi
     const bool f64 = x.prec == BLAST_FP64;
     const int rq = p->rows_pad / (f64 ? 2 : 4);
     const long total = (long)p->n_chi * rq;
-    dim3 gq((unsigned)((total + 255) / 256), a->batch);
-    const int na_max = 256 / rq + 2;
-#define BLAST_QY(T, NB)                                                                                      \
-    hipLaunchKernelGGL((quad_y_kernel<T, NB>), gq, dim3(256), (size_t)na_max * p->n_R * NB * sizeof(T), s, \
-                       (const T *)w, a->K_chi2, p->d_wR, p->NP, p->n_R, p->n_chi, p->rows_pad, x.nbins, (T *)Y)
+    const int T = quad_y_threads(p, f64, x.nbp);  // > 0: checked when the call was prepared
+    dim3 gq((unsigned)((total + T - 1) / T), a->batch);
+    const int na_max = (T - 1) / rq + 2;
+#define BLAST_QY(TY, NB)                                                                                        \
+    hipLaunchKernelGGL((quad_y_kernel<TY, NB>), gq, dim3(T), (size_t)na_max * p->n_R * NB * sizeof(TY), s,   \
+                       (const TY *)w, a->K_chi2, p->d_wR, p->NP, p->n_R, p->n_chi, p->rows_pad, x.nbins, (TY *)Y)
     if (f64 && x.nbp == 16) BLAST_QY(double, 16);
     if (f64 && x.nbp == 32) BLAST_QY(double, 32);
     if (!f64 && x.nbp == 16) BLAST_QY(float, 16);

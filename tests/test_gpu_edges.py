@@ -130,3 +130,22 @@ def test_empty_batch_is_refused():
         assert e.value.status == B.E_INVALID
     finally:
         plan.close()
+
+
+def test_few_multipoles_many_R_nodes():
+    """Three multipoles (16 basis rows) on a 96-node R grid: the unfused R-quadrature spans many
+    chi nodes per work-group, whose R weights must still fit in LDS (smaller work-groups)."""
+    cfg = W.tiny_config(n_ell=3, ell_max=30, n_chi=8, n_R=96, n_cheb=24, k_max=0.3)
+    plan = B.plan_for_config(cfg, precisions=("fp64", "fp32"))
+    try:
+        inps = [W.make_inputs(cfg, W.seed_for(17, i), plan.k_nodes, plan.chi, plan.R, vary=True) for i in range(40)]
+        Cor = _oracle(plan, cfg, inps[0], cfg.n_g, cfg.n_s)
+        for prec, tol in (("fp64", 1e-6), ("fp32", 1e-3)):
+            for nb in (1, 40):  # one cosmology: unfused kernels; 40: the fused path on FP32
+                P, K1, K2 = _batch(inps[:nb], p32=prec == "fp32")
+                C = plan.forward(P, K1, K2, cfg.n_g, cfg.n_s, precision=prec).cpu().numpy()
+                e = g16_err(C[0], Cor, cfg.n_g, cfg.n_s).max()
+                print(prec, nb, "max err", e, flush=True)
+                assert e <= tol, (prec, nb, e)
+    finally:
+        plan.close()
