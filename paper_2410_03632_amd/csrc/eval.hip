@@ -929,8 +929,8 @@ template <int PREC, int NB, int NBP, int NS>
 __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     const typename Cfg<PREC>::E *__restrict__ basis, const uint16_t *__restrict__ basis_lo,
     const float *__restrict__ scale, const typename Cfg<PREC>::E *__restrict__ c, const uint16_t *__restrict__ c_lo,
-    const float *__restrict__ Kt, int batch, int n_chi, int n_R, int rows_pad, int nBT, int units,
-    float *__restrict__ Y) {
+    const float *__restrict__ Kt, int batch, int n_chi, int n_R, int rows_pad, int nBT, int units, int n_ell,
+    int nslots, int granges, float *__restrict__ Y) {
     using S = FusedShape<PREC, NS>;
     using E = typename S::E;
     constexpr int TR = kFusedTR, VEC = S::VEC, KSTEP = S::KSTEP, ncp = S::ncp, NPART = S::NPART;
@@ -966,6 +966,21 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     // waves whose row tile or cosmologies lie past the end only move data (small batches,
     // the last row group)
     const bool busy = ti < ntile && bt * 64 + 16 * tk < batch;
+    // 4-bin groups the R-sum keeps for this wave's rows: a gg row pairs clustering bins only and
+    // an ss row shear bins only (granges: per type slot s, first group in bits 6s..6s+2 and end in
+    // bits 6s+3..6s+5); a tile that straddles slots keeps the union.  The other columns of Y stay
+    // zero and are never read by the chi-quadrature.
+    int gq0 = NB / 4, gq1 = 0;
+    {
+        const int r0 = 16 * (rt0 + min(ti, TR - 1));
+        const int s0 = min(r0 / n_ell, nslots - 1), s1 = min((r0 + 15) / n_ell, nslots - 1);
+        for (int sl = s0; sl <= s1; ++sl) {
+            gq0 = min(gq0, (granges >> (6 * sl)) & 7);
+            gq1 = max(gq1, (granges >> (6 * sl + 3)) & 7);
+        }
+        gq0 = __builtin_amdgcn_readfirstlane(gq0);
+        gq1 = __builtin_amdgcn_readfirstlane(gq1);
+    }
 
     // every wave issues exactly A_PW + C_PW DMA instructions per b (chunk indices past the end are
     // clamped to the last chunk, which is then written more than once with identical data), so
@@ -1160,9 +1175,12 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
         }
         // w tile of this b: lane holds rows 16 (rt0 + ti) + 4 lk + r for cosmology beta
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int g = 0; g < NB / 4; ++g)
+            if (g >= gq0 && g < gq1)  // uniform over the wave
 #pragma unroll
-            for (int j = 0; j < NB; ++j) y[r][j] += wv[r] * kt[j];
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int j = 4 * g; j < 4 * g + 4; ++j) y[r][j] += wv[r] * kt[j];
     };
 
     // issue order: A(0), c(0) + weights(0), A(1); then per b, after its barrier: c(b+1) +
@@ -1949,6 +1967,15 @@ void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, in
     const int groups = (RT + kFusedTR - 1) / kFusedTR;
     const int units = p->n_chi * nBT * groups;
     const unsigned grid = (unsigned)((units + 7) / 8 * 8);
+    // 4-bin groups the R-sum needs per type slot (clustering bins first): gg [0, ng), gs all,
+    // ss [ng, nbins); 3 bits per bound
+    int granges = 0;
+    for (int sl = 0; sl < p->nt; ++sl) {
+        const int t = p->tslot_type[sl];
+        const int b0 = t == BLAST_SS ? x.ng : 0, b1 = t == BLAST_GG ? x.ng : x.nbins;
+        const int q0 = b1 > b0 ? b0 / 4 : 0, q1 = b1 > b0 ? (b1 + 3) / 4 : 0;
+        granges |= (q0 | (q1 << 3)) << (6 * sl);
+    }
     auto launch = [&](auto ptag, auto nbtag, auto nbptag, auto nstag) {
         constexpr int PR = decltype(ptag)::value, NB = decltype(nbtag)::value, NBP = decltype(nbptag)::value;
         constexpr int NS = decltype(nstag)::value;
@@ -1957,7 +1984,7 @@ void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, in
         // all LDS of the fused kernel is static (FusedShape::LDS bytes)
         hipLaunchKernelGGL((contract_quad_kernel<PR, NB, NBP, NS>), dim3(grid), dim3(256 * kFusedTR), 0, s, bas,
                            p->basis.lo, p->basis.scale, (const E *)c, clo, Kt, a->batch, p->n_chi, p->n_R,
-                           p->rows_pad, nBT, units, Y);
+                           p->rows_pad, nBT, units, p->n_ell, p->nt, granges, Y);
     };
     // nc_pad is a multiple of 32 up to 128: 1..4 blocks of 32 columns
     auto by_ns = [&](auto ptag, auto nbtag, auto nbptag) {

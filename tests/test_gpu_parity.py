@@ -274,3 +274,26 @@ def test_fused_batch_matches_single_calls_and_oracle(n_g, n_s, n_cheb, batch):
             assert worst <= tol_single and (tol_oracle is None or eo <= tol_oracle), (prec, worst, eo)
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("config", [1, 2])
+def test_named_config_fused_batch_matches_oracle_golden(config):
+    """The fused path (a batch of 32 copies of the golden cosmology) at the named shapes: config 1
+    has 20 multipoles, so row tiles straddle the gg / gs / ss slots; config 2 has 96, so every
+    tile holds one type and the R-sum keeps only that type's bins."""
+    g = _golden(config)
+    cfg = W.CONFIGS[config]
+    plan = B.plan_for_config(cfg, precisions=("fp32",))
+    try:
+        inp = W.make_inputs(cfg, g["seed"], plan.k_nodes, plan.chi, plan.R)
+        nb = 32
+        P = _dev(np.repeat(inp.P[None], nb, axis=0), torch.float32)
+        K1 = _dev(np.repeat(inp.Kchi[None], nb, axis=0))
+        K2 = _dev(np.repeat(inp.Kchi2[None], nb, axis=0))
+        C = plan.forward(P, K1, K2, cfg.n_g, cfg.n_s, precision="fp32").cpu().numpy()
+        Cor = np.array(g["C"])
+        e = max(g16_err(C[i], Cor, cfg.n_g, cfg.n_s).max() for i in (0, nb - 1))
+        print("config", config, "fused FP32 batch: max err", e, flush=True)
+        assert e <= 1e-3
+    finally:
+        plan.close()
