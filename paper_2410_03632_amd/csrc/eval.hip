@@ -978,9 +978,9 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
             gq0 = min(gq0, (granges >> (6 * sl)) & 7);
             gq1 = max(gq1, (granges >> (6 * sl + 3)) & 7);
         }
-        gq0 = __builtin_amdgcn_readfirstlane(gq0);
-        gq1 = __builtin_amdgcn_readfirstlane(gq1);
     }
+    // bit g set: group g is kept (a scalar mask, so the per-group tests stay off the VALU)
+    const int gmask = __builtin_amdgcn_readfirstlane(gq1 > gq0 ? ((1 << gq1) - 1) & ~((1 << gq0) - 1) : 0);
 
     // every wave issues exactly A_PW + C_PW DMA instructions per b (chunk indices past the end are
     // clamped to the last chunk, which is then written more than once with identical data), so
@@ -1176,7 +1176,7 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
         // w tile of this b: lane holds rows 16 (rt0 + ti) + 4 lk + r for cosmology beta
 #pragma unroll
         for (int g = 0; g < NB / 4; ++g)
-            if (g >= gq0 && g < gq1)  // uniform over the wave
+            if ((gmask >> g) & 1)  // uniform over the wave
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
 #pragma unroll
