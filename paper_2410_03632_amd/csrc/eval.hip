@@ -332,6 +332,21 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
 // ---------------------------------------------------------------------------------------------
 constexpr int kRowTilesPerWave = 5;
 
+// Work-group -> (point ab, cosmology tile bt) for the per-point contractions over a 1-D grid of
+// point_tile_grid(NP, nBT) work-groups.  Work-groups are dealt round-robin over the 8 XCDs; the
+// numbering gives each XCD a contiguous range of points with all their tiles in a row, so that a
+// point's basis rows come from HBM once and from that XCD's L2 for its other tiles.  Spare
+// work-groups (the grid is rounded up to a multiple of 8) return false.
+__device__ inline bool point_tile(int NP, int nBT, int &ab, int &bt) {
+    const int units = NP * nBT, per = (units + 7) / 8;
+    const int u = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (u >= units) return false;
+    ab = u / nBT;
+    bt = u % nBT;
+    return true;
+}
+inline dim3 point_tile_grid(int NP, int nBT) { return dim3((unsigned)((NP * nBT + 7) / 8 * 8)); }
+
 template <int PREC>
 struct Cfg;
 template <>
@@ -379,8 +394,9 @@ __global__ __launch_bounds__(256) void contract_kernel(const typename Cfg<PREC>:
     E *cs = (E *)smem;
     uint16_t *cls = (uint16_t *)(smem + (size_t)BT * cst * sizeof(E));
 
-    const int ab = blockIdx.x;
-    const int beta0 = blockIdx.y * BT;
+    int ab, tile;
+    if (!point_tile(NP, (batch + BT - 1) / BT, ab, tile)) return;  // uniform over the work-group
+    const int beta0 = tile * BT;
     const int nb = min(BT, batch - beta0);
     const int vec_per_row = ncp / VEC;
     for (int i = threadIdx.x; i < BT * vec_per_row; i += blockDim.x) {
@@ -566,8 +582,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE))) void
     E *cs = (E *)smem;
     uint16_t *cls = (uint16_t *)(smem + (size_t)BT * cst * sizeof(E));
 
-    const int ab = blockIdx.x;
-    const int beta0 = blockIdx.y * BT;
+    int ab, tile;
+    if (!point_tile(NP, (batch + BT - 1) / BT, ab, tile)) return;  // uniform over the work-group
+    const int beta0 = tile * BT;
     const int nb = min(BT, batch - beta0);
     const int vec_per_row = ncp / VEC;
     for (int i = threadIdx.x; i < BT * vec_per_row; i += blockDim.x) {
@@ -1579,7 +1596,9 @@ __global__ __launch_bounds__(256) void contract_t_kernel(const typename std::con
     extern __shared__ __align__(16) unsigned char smem_t[];
     const int dst = rows_pad + 1;
     T *ws = (T *)smem_t;  // [BT][rows_pad + 1]
-    const int ab = blockIdx.x, beta0 = blockIdx.y * BT;
+    int ab, tile;
+    if (!point_tile(NP, (batch + BT - 1) / BT, ab, tile)) return;  // uniform over the work-group
+    const int beta0 = tile * BT;
     const int nb = min(BT, batch - beta0);
     for (int i = threadIdx.x; i < BT * rows_pad; i += blockDim.x) {
         const int bb = i / rows_pad, row = i % rows_pad;
@@ -1918,7 +1937,7 @@ void stage_contract(blast_plan *p, const blast_cl_args *a, const Ctx &x, const v
         const int BT = Cfg<PR>::BT;
         const size_t cst = ncp + 16 / sizeof(E);
         const size_t sh = (size_t)BT * cst * sizeof(E) + (PR == BLAST_BF16X3 ? (size_t)BT * cst * 2 : 0);
-        dim3 grid(p->NP, (a->batch + BT - 1) / BT);
+        const dim3 grid = point_tile_grid(p->NP, (a->batch + BT - 1) / BT);
         const E *bas = PR == BLAST_FP64 ? (const E *)p->basis.f64
                                         : (PR == BLAST_FP32 ? (const E *)p->basis.f32 : (const E *)p->basis.hi);
         if constexpr (PR == BLAST_FP64) {
@@ -2148,7 +2167,7 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
 #undef BLAST_ADJ
     if (dP) {
         const int BT = f64 ? 32 : 64;
-        dim3 gt(p->NP, (a->batch + BT - 1) / BT);
+        const dim3 gt = point_tile_grid(p->NP, (a->batch + BT - 1) / BT);
         const size_t sht = (size_t)BT * (p->rows_pad + 1) * (f64 ? 8 : 4);
         if (f64)
             hipLaunchKernelGGL((contract_t_kernel<true>), gt, dim3(256), sht, s, p->basis.f64, (const double *)dw,
