@@ -323,6 +323,104 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
         }
 }
 
+// FP64 projection for N % 8 == 0 with the same even/odd split (FP64 path): v_mfma_f64_16x16x4f64,
+// one 16-row tile per wave, the D halves in LDS as doubles.  The f64 result layout puts row
+// 4 r + lk of the tile in register r of lane (m % 16) + 16 lk, so a lane stores rows 4 r + lk.
+template <typename PT, int NT>
+__global__ __launch_bounds__(256) void project_split64_kernel(const PT *__restrict__ P, const double *__restrict__ Dn,
+                                                              int N, int ncp, long nrows, double *__restrict__ c_out) {
+    constexpr int KSTEP = 16;
+    extern __shared__ __align__(16) unsigned char smem_d[];
+    const int H = N / 2;
+    constexpr int Hp = 16 * NT, hs = Hp + 2;  // doubles per LDS row: 16 bytes of padding
+    double *De = (double *)smem_d, *Do = De + (size_t)Hp * hs;
+    {
+        // the halves of D in pairs of doubles: all loads of a thread first (clamped, masked)
+        constexpr int TOT = Hp * (Hp / 2), PER = (TOT + 255) / 256;
+        double2 e[PER], o[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = min((int)threadIdx.x + 256 * u, TOT - 1);
+            const int m = min(i / (Hp / 2), H - 1), q = min(i % (Hp / 2), H / 2 - 1);
+            e[u] = *(const double2 *)(Dn + (size_t)(2 * m) * N + 2 * q);
+            o[u] = *(const double2 *)(Dn + (size_t)(2 * m + 1) * N + 2 * q);
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + 256 * u;
+            const int m = i / (Hp / 2), q = i % (Hp / 2);
+            if (i < TOT) {
+                const bool in = m < H && 2 * q < H;  // per component: a struct select went through scratch
+                *(double2 *)(De + (size_t)m * hs + 2 * q) = make_double2(in ? e[u].x : 0.0, in ? e[u].y : 0.0);
+                *(double2 *)(Do + (size_t)m * hs + 2 * q) = make_double2(in ? o[u].x : 0.0, in ? o[u].y : 0.0);
+            }
+        }
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const long row0 = (long)blockIdx.x * 64 + 16 * w;
+    const PT *pr = P + min(row0 + lr, nrows - 1) * (long)N;
+    d4 ae[NT], ao[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) ae[t] = ao[t] = d4{0, 0, 0, 0};
+    // raw P values of one step: front = P[j0 .. j0+3], back = P[N-4-j0 .. N-1-j0] (clamped as in
+    // the FP32 kernel: past N/2 the weights are zero)
+    auto load = [&](int st, double (&front)[4], double (&back)[4]) {
+        const int j0 = min(st * KSTEP + lk * 4, H - 4);
+        if constexpr (sizeof(PT) == 8) {
+            const double2 f0 = *(const double2 *)(pr + j0), f1 = *(const double2 *)(pr + j0 + 2);
+            const double2 b0 = *(const double2 *)(pr + N - 4 - j0), b1 = *(const double2 *)(pr + N - 2 - j0);
+            front[0] = f0.x, front[1] = f0.y, front[2] = f1.x, front[3] = f1.y;
+            back[0] = b0.x, back[1] = b0.y, back[2] = b1.x, back[3] = b1.y;
+        } else {
+            const float4 f = *(const float4 *)(pr + j0), b = *(const float4 *)(pr + N - 4 - j0);
+            front[0] = f.x, front[1] = f.y, front[2] = f.z, front[3] = f.w;
+            back[0] = b.x, back[1] = b.y, back[2] = b.z, back[3] = b.w;
+        }
+    };
+    auto compute = [&](int st, const double (&front)[4], const double (&back)[4]) {
+        const int j0 = st * KSTEP + lk * 4;
+        double u[4], v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {  // mirror of j0 + e is (N-4-j0) + (3-e)
+            u[e] = front[e] + back[3 - e];
+            v[e] = front[e] - back[3 - e];
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const double *de = De + (size_t)(16 * t + lr) * hs + j0, *dd = Do + (size_t)(16 * t + lr) * hs + j0;
+            const double2 e0 = *(const double2 *)de, e1 = *(const double2 *)(de + 2);
+            const double2 o0 = *(const double2 *)dd, o1 = *(const double2 *)(dd + 2);
+            const double dev[4] = {e0.x, e0.y, e1.x, e1.y}, dov[4] = {o0.x, o0.y, o1.x, o1.y};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                ae[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(u[e], dev[e], ae[t], 0, 0, 0);
+                ao[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[e], dov[e], ao[t], 0, 0, 0);
+            }
+        }
+    };
+    double fr[2][4], bk[2][4];
+    load(0, fr[0], bk[0]);
+#pragma unroll
+    for (int st = 0; st < NT; ++st) {
+        if (st + 1 < NT) {
+            load(st + 1, fr[(st + 1) & 1], bk[(st + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);  // keep the next step's loads ahead of these MFMAs
+        }
+        compute(st, fr[st & 1], bk[st & 1]);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int n = 2 * (16 * t + lr);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const long row = row0 + 4 * r + lk;
+            if (row < nrows) *(double2 *)(c_out + (size_t)row * ncp + n) = make_double2(ae[t][r], ao[t][r]);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // contraction: per (chi_a, R_b) point a [rows x n] x [n x batch] product on MFMA.
 // Lane layout of the 16x16 tiles: A[i][k] lane = i + 16*(k-group), B[k][j] lane = j + 16*(k-group),
@@ -1877,7 +1975,26 @@ void stage_project(blast_plan *p, const blast_cl_args *a, const Ctx &x, void *c,
 #undef BLAST_CI
         return;
     }
-    if (!f64 && N % 8 == 0) {
+    if (f64 && N % 8 == 0) {
+        dim3 grid((unsigned)((nrows + 63) / 64));
+        const size_t shp = (size_t)2 * (ncp / 2) * (ncp / 2 + 2) * sizeof(double);
+        auto launch = [&](auto ptag, auto nttag) {
+            using PT = typename decltype(ptag)::type;
+            constexpr int NT = decltype(nttag)::value;
+            hipLaunchKernelGGL((project_split64_kernel<PT, NT>), grid, dim3(256), shp, s, (const PT *)a->P,
+                               p->d_dctn64, N, ncp, nrows, (double *)c);
+        };
+        auto by_nt = [&](auto ptag) {
+            switch (ncp / 32) {  // Hp / 16 = ncp / 32
+                case 1: launch(ptag, std::integral_constant<int, 1>()); break;
+                case 2: launch(ptag, std::integral_constant<int, 2>()); break;
+                case 3: launch(ptag, std::integral_constant<int, 3>()); break;
+                default: launch(ptag, std::integral_constant<int, 4>()); break;
+            }
+        };
+        if (p64) by_nt(TypeTag<double>());
+        else by_nt(TypeTag<float>());
+    } else if (!f64 && N % 8 == 0) {
         dim3 grid((unsigned)((nrows + 64 * kSplitRT - 1) / (64 * kSplitRT)));
         const size_t shp = (size_t)2 * (ncp / 2) * (ncp / 2 + 4) * sizeof(float);
         auto launch = [&](auto ptag, auto otag, auto nttag) {
