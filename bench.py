@@ -55,7 +55,7 @@ def stage_work(plan, cfg, prec, batch):
     ew = 8 if prec == "fp64" else 4                                    # w and Y bytes
     ep = 8 if prec == "fp64" else 4                                    # P bytes
     rows_bins = plan.n_ell * (cfg.n_g + nb + cfg.n_s)                 # (row, bin) products in the R-sum
-    proj = dict(flops=(1.0 if N % 32 == 0 and prec != "fp64" else 2.0) * NP * N * N * batch,
+    proj = dict(flops=(1.0 if N % 8 == 0 else 2.0) * NP * N * N * batch,
                 bytes=float(NP * N * (ep + ec) * batch))
     quad_chi = dict(flops=4.0 * cfg.n_chi * plan.n_ell * B_pairs(cfg) * batch,
                     bytes=float(cfg.n_chi * rows_pad * nbp * ew * batch))
@@ -399,7 +399,8 @@ def main():
     work = stage_work(plan, cfg, prec, Bn)
     dom = max(per_launch, key=per_launch.get)
     roof = roofline(work[dom], per_launch[dom], prec)
-    roof["kernel"] = {"projection": "project_split_kernel" if fused else "project_mfma_kernel",
+    split = "project_split64_kernel" if prec == "fp64" else "project_split_kernel"
+    roof["kernel"] = {"projection": split if cfg.n_cheb % 8 == 0 else "project_mfma_kernel",
                       "contraction": "contract_quad_kernel" if fused else "contract_kernel",
                       "quad_R": "quad_y_kernel", "quad_chi": "quad_c_mfma_kernel", "r_weights": "kt_kernel"}[dom]
     roof["traffic"] = counter_traffic(roof["kernel"], cfg.name, Bn, prec)
