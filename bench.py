@@ -6,7 +6,7 @@ synthetic cosmologies whose inputs are already resident in HBM.  The basis
 precompute is done once before timing (as in the paper, where it is excluded from
 the timings) and reported separately.
 
-    python bench.py [--steps K] [--warmup W] [--batch B] [--precision fp32|bf16x3|fp64]
+    python bench.py [--steps K] [--warmup W] [--batch B] [--precision fp32|fp16x3|bf16x3|fp64]
 
 Prints ONE JSON line (see the keys at the bottom).
 """
@@ -25,8 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "3x2pt C_ell sets/sec at ≤1e-3 rel err vs FP64 oracle; p50/p99 latency"
-PEAK = {"hbm": 8.0e12, "fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
-DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16": "bf16"}
+PEAK = {"hbm": 8.0e12, "fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16": "bf16", "fp16x3": "f16x3"}
 
 
 def log(*a):
@@ -50,13 +50,14 @@ def stage_work(plan, cfg, prec, batch):
     rows_pad = plan.rows_pad
     nb = cfg.n_g + cfg.n_s
     nbp = 16 if nb <= 16 else 32
-    eb = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4}[prec]       # basis bytes per element (hi+lo)
-    ec = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4}[prec]       # coefficient bytes
+    eb = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4, "fp16x3": 4}[prec]  # basis bytes per element (hi+lo)
+    ec = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4, "fp16x3": 4}[prec]  # coefficient bytes
+    es = 4 if prec == "fp16x3" else 0  # coefficient row scale, written by the projection, read for Kt
     ew = 8 if prec == "fp64" else 4                                    # w and Y bytes
     ep = 8 if prec == "fp64" else 4                                    # P bytes
     rows_bins = plan.n_ell * (cfg.n_g + nb + cfg.n_s)                 # (row, bin) products in the R-sum
     proj = dict(flops=(1.0 if N % 8 == 0 else 2.0) * NP * N * N * batch,
-                bytes=float(NP * N * (ep + ec) * batch))
+                bytes=float(NP * (N * (ep + ec) + es) * batch))
     quad_chi = dict(flops=4.0 * cfg.n_chi * plan.n_ell * B_pairs(cfg) * batch,
                     bytes=float(cfg.n_chi * rows_pad * nbp * ew * batch))
     y_bytes = float(cfg.n_chi * rows_pad * nbp * ew * batch)
@@ -72,7 +73,8 @@ def stage_work(plan, cfg, prec, batch):
     nbf = (nb + 3) // 4 * 4
     return {
         "projection": proj,
-        "r_weights": dict(flops=float(nb * NP * batch), bytes=float(nb * NP * 8 * batch + NP * nbf * 4 * batch)),
+        "r_weights": dict(flops=float(nb * NP * batch),
+                          bytes=float(nb * NP * 8 * batch + NP * nbf * 4 * batch + NP * es * batch)),
         "contraction": dict(flops=2.0 * rows * N * NP * batch + 2.0 * rows_bins * NP * batch,
                             bytes=float(NP * rows * N * eb + NP * N * ec * batch + NP * nbf * 4 * batch) + y_bytes),
         "quad_chi": quad_chi,
@@ -104,7 +106,8 @@ def counter_traffic(kernel, cfg_name, batch, prec):
 def roofline(work, ms_per_launch, prec):
     flops, nbytes = work["flops"], work["bytes"]
     t = ms_per_launch * 1e-3
-    peak_f = PEAK["fp64" if prec == "fp64" else ("bf16" if prec.startswith("bf16") else "fp32")]
+    peak_f = PEAK["fp64" if prec == "fp64" else ("bf16" if prec.startswith("bf16") else
+                                                 ("fp16" if prec == "fp16x3" else "fp32"))]
     ridge = peak_f / PEAK["hbm"]
     if flops / nbytes >= ridge:
         a = flops / t / 1e12
@@ -314,7 +317,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=256)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64", "bf16"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16x3", "bf16x3", "fp64", "bf16"])
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64-path and batch-1 timings")
@@ -349,7 +352,7 @@ def main():
     prec = args.precision
     log("building plan for config", args.config, cfg.name)
     t0 = time.time()
-    precs = ("fp64", "fp32", "bf16x3") if prec != "bf16" else ("fp64", "bf16")
+    precs = ("fp64", "fp32", "bf16x3", "fp16x3") if prec != "bf16" else ("fp64", "bf16")
     plan = B.plan_for_config(cfg, precisions=precs)
     build_s = time.time() - t0
     log("plan built in %.1f s (%d k-nodes, basis %s bytes)" % (build_s, plan.kq_nodes, plan.basis_bytes))

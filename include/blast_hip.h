@@ -59,9 +59,21 @@ typedef enum {
  * FP32: FP32 basis and coefficients, FP32 MFMA.  BF16: BF16 basis and
  * coefficients (per-row power-of-two scales), FP32 accumulate.  BF16X3: basis and
  * coefficients split into BF16 hi + lo parts, hi*hi + hi*lo + lo*hi, FP32
- * accumulate.  The basis precompute is always FP64; the quadrature always
- * accumulates in FP64. */
-typedef enum { BLAST_FP64 = 0, BLAST_FP32 = 1, BLAST_BF16 = 2, BLAST_BF16X3 = 3 } blast_precision;
+ * accumulate.  FP16X3: the same three products with FP16 hi + lo parts (about 22
+ * significant bits per operand); every basis row and every coefficient row
+ * (one cosmology, one point) carries its own power-of-two scale that puts its
+ * largest magnitude in [2^14, 2^15), inside FP16's normal range.  FP16X3 runs the
+ * fused contraction + R-quadrature only: it needs nodal P with n_cheb % 8 == 0
+ * (or P given as coefficients), n_g + n_s <= 20 and no w_save, and is not
+ * available to the adjoint; other requests are refused with BLAST_E_UNSUPPORTED.
+ * The basis precompute is always FP64; the quadrature always accumulates in FP64. */
+typedef enum {
+    BLAST_FP64 = 0,
+    BLAST_FP32 = 1,
+    BLAST_BF16 = 2,
+    BLAST_BF16X3 = 3,
+    BLAST_FP16X3 = 4
+} blast_precision;
 
 enum { BLAST_GG = 1, BLAST_GS = 2, BLAST_SS = 4 };
 
@@ -122,7 +134,7 @@ blast_status blast_plan_create(const blast_plan_desc *desc, int32_t device, blas
 blast_status blast_plan_destroy(blast_plan *plan);
 
 /* Sizes: number of basis rows (types x ell), padded Chebyshev length, bytes of
- * resident basis per precision (host [4]), k-quadrature node count, basis build
+ * resident basis per precision (host [5], indexed by blast_precision), k-quadrature node count, basis build
  * time in milliseconds.  Any output pointer may be NULL. */
 blast_status blast_plan_info(const blast_plan *plan, int32_t *rows, int32_t *n_cheb_pad, size_t *basis_bytes,
                              int64_t *kq_nodes, double *build_ms);

@@ -16,9 +16,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libblast_hip.so")
 
 OK, E_INVALID, E_OOM, E_HIP, E_UNSUPPORTED, E_BUSY, E_CANCELLED = range(7)
-FP64, FP32, BF16, BF16X3 = range(4)
+FP64, FP32, BF16, BF16X3, FP16X3 = range(5)
 GG, GS, SS = 1, 2, 4
-PRECISION = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "bf16x3": BF16X3}
+PRECISION = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "bf16x3": BF16X3, "fp16x3": FP16X3}
 TYPE_BITS = {"gg": GG, "gs": GS, "ss": SS}
 
 
@@ -246,7 +246,7 @@ class Plan:
                                   _dptr(self.w_chi), _dptr(self.R), _dptr(self.w_R)))
         self.k_min, self.k_max, self.n_cheb, self.types = kmin.value, kmax.value, nch.value, ty.value
         rows, ncp = C.c_int32(), C.c_int32()
-        bb = (C.c_size_t * 4)()
+        bb = (C.c_size_t * 5)()
         kq = C.c_int64()
         ms = C.c_double()
         _check(L.blast_plan_info(h, C.byref(rows), C.byref(ncp), bb, C.byref(kq), C.byref(ms)))

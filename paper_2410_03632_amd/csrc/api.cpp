@@ -132,6 +132,9 @@ static void free_plan(blast_plan *p) {
     f(p->basis.hi);
     f(p->basis.lo);
     f(p->basis.scale);
+    f(p->basis.h16);
+    f(p->basis.l16);
+    f(p->basis.scale16);
     f(p->d_dct64);
     f(p->d_dct32);
     f(p->d_dctn64);
@@ -173,7 +176,7 @@ static blast_status validate_desc(const blast_plan_desc *d) {
     if (d->n_cheb < 2 || d->n_cheb > blast::kMaxCheb)
         return blast::set_error("n_cheb must be in [2, %d]", blast::kMaxCheb), BLAST_E_INVALID;
     if (d->types == 0 || (d->types & ~7u)) return blast::set_error("types must be a non-empty subset of 7"), BLAST_E_INVALID;
-    if (d->precisions & ~15u) return blast::set_error("unknown precision bits"), BLAST_E_INVALID;
+    if (d->precisions & ~31u) return blast::set_error("unknown precision bits"), BLAST_E_INVALID;
     if (d->kq_panels < 0 || d->kq_panels > 4096) return blast::set_error("kq_panels out of range"), BLAST_E_INVALID;
     if (d->kq_phase < 0 || !std::isfinite(d->kq_phase)) return blast::set_error("kq_phase must be >= 0"), BLAST_E_INVALID;
     return BLAST_OK;
@@ -572,6 +575,7 @@ extern "C" blast_status blast_plan_info(const blast_plan *p, int32_t *rows, int3
         basis_bytes[1] = p->basis.f32 ? n * 4 : 0;
         basis_bytes[2] = p->basis.hi ? n * 2 + (size_t)p->NP * p->rows_pad * 4 : 0;
         basis_bytes[3] = p->basis.lo ? n * 4 + (size_t)p->NP * p->rows_pad * 4 : 0;
+        basis_bytes[4] = p->basis.l16 ? n * 4 + (size_t)p->NP * p->rows_pad * 4 : 0;
     }
     if (kq_nodes) *kq_nodes = p->kq_nodes;
     if (build_ms) *build_ms = p->build_ms;
@@ -602,7 +606,7 @@ extern "C" blast_status blast_plan_basis_point(const blast_plan *p, int32_t a, i
 
 extern "C" blast_status blast_cl_workspace_bytes(const blast_plan *p, int32_t batch, int32_t precision, int32_t n_bins,
                                                  size_t *bytes) {
-    if (!p || !bytes || batch < 1 || precision < 0 || precision > 3 || n_bins < 1 || n_bins > blast::kMaxBins)
+    if (!p || !bytes || batch < 1 || precision < 0 || precision > 4 || n_bins < 1 || n_bins > blast::kMaxBins)
         return blast::set_error("blast_cl_workspace_bytes: bad argument"), BLAST_E_INVALID;
     *bytes = blast::workspace_bytes(p, batch, precision, n_bins);
     return BLAST_OK;

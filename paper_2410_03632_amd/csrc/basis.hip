@@ -448,6 +448,32 @@ __global__ __launch_bounds__(256) void to_bf16_kernel(const double *__restrict__
     }
 }
 
+// one wave per basis row: a power-of-two scale that puts the row's largest magnitude in
+// [2^14, 2^15) (FP16's normal range, below its largest finite value), then FP16 hi = fp16(v) and
+// lo = fp16(v - hi) of v = value / scale, tiled layout
+__global__ __launch_bounds__(256) void to_fp16_kernel(const double *__restrict__ src, size_t nrows, int rows_pad,
+                                                      int ncp, uint16_t *__restrict__ hi, uint16_t *__restrict__ lo,
+                                                      float *__restrict__ scale) {
+    const size_t row = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= nrows) return;
+    const double *r = src + row * ncp;
+    double mx = 0.0;
+    for (int n = lane; n < ncp; n += 64) mx = fmax(mx, fabs(r[n]));
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    const double sc = mx > 0.0 ? ldexp(1.0, ilogb(mx) - 14) : 1.0;
+    if (lane == 0) scale[row] = (float)sc;
+    const size_t base = (row / rows_pad) * (size_t)rows_pad * ncp;
+    const int rr = (int)(row % rows_pad);
+    for (int n = lane; n < ncp; n += 64) {
+        const double v = r[n] / sc;
+        const _Float16 h = (_Float16)(float)v;
+        const size_t o = base + tiled_off(rr, n, ncp / 32, 8);
+        hi[o] = __builtin_bit_cast(uint16_t, h);
+        lo[o] = __builtin_bit_cast(uint16_t, (_Float16)(float)(v - (double)(float)h));
+    }
+}
+
 void gauss_legendre16(double *x, double *w) {
     const int n = 16;
     for (int i = 0; i < n; ++i) {
@@ -634,6 +660,16 @@ blast_status derive_precisions(blast_plan *p, hipStream_t s) {
         }
         hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((nrows + 3) / 4)), dim3(256), 0, s, p->basis.f64, nrows,
                            p->rows_pad, p->nc_pad, p->basis.hi, p->basis.lo, p->basis.scale);
+    }
+    if (p->precisions & (1u << BLAST_FP16X3)) {
+        hipError_t e = hipMalloc(&p->basis.h16, n * sizeof(uint16_t));
+        if (e != hipSuccess) return p->basis.h16 = nullptr, fail(e, "FP16 basis");
+        e = hipMalloc(&p->basis.l16, n * sizeof(uint16_t));
+        if (e != hipSuccess) return p->basis.l16 = nullptr, fail(e, "FP16 lo basis");
+        e = hipMalloc(&p->basis.scale16, nrows * sizeof(float));
+        if (e != hipSuccess) return p->basis.scale16 = nullptr, fail(e, "FP16 basis scales");
+        hipLaunchKernelGGL(to_fp16_kernel, dim3((unsigned)((nrows + 3) / 4)), dim3(256), 0, s, p->basis.f64, nrows,
+                           p->rows_pad, p->nc_pad, p->basis.h16, p->basis.l16, p->basis.scale16);
     }
     BLAST_HIP_TRY(hipGetLastError());
     return BLAST_OK;

@@ -21,6 +21,7 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 
 typedef uint32_t U4 __attribute__((ext_vector_type(4)));
 typedef double d2v __attribute__((ext_vector_type(2)));
@@ -215,10 +216,12 @@ constexpr int kSplitRT = 2;
 // the step loop unrolls and every load is unconditional (rows past the end read the last row and
 // are never stored), so the compiler can wait for exactly the loads a step needs and the next
 // step's loads stay in flight under the current step's MFMAs.
+// OUT: 1 -> float c, 2 -> BF16 hi (+ lo when c_lo != nullptr), 3 -> FP16 hi and lo of c / s with a
+// power-of-two s per row that puts the row's largest |c_n| in [2^14, 2^15); cs[row] = s.
 template <typename PT, int OUT, int NT>
 __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict__ P, const float *__restrict__ Dn,
                                                             int N, int ncp, long nrows, void *__restrict__ c_out,
-                                                            uint16_t *__restrict__ c_lo) {
+                                                            uint16_t *__restrict__ c_lo, float *__restrict__ cs) {
     constexpr int RT = kSplitRT, VEC = 4, KSTEP = 16;
     extern __shared__ __align__(16) unsigned char smem_s[];
     const int H = N / 2;
@@ -299,6 +302,25 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
         compute(st, fr[st & 1], bk[st & 1]);
     }
     // lane holds rows 16r + 4lk + q of output m = 16t + lr, i.e. n = 2m and 2m + 1
+    // FP16 output: the scale of each row from the largest |c_n| over its 16 lanes (same lk)
+    float mul[RT][4];
+    if constexpr (OUT == 3) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float mx = 0.f;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) mx = fmaxf(mx, fmaxf(fabsf(ae[r][t][q]), fabsf(ao[r][t][q])));
+#pragma unroll
+                for (int off = 1; off < 16; off <<= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+                // e = floor(log2 mx), kept where 2^(14 - e) is a finite float; rows of zeros get s = 1
+                const int e = mx > 0.f ? min(max(ilogbf(mx), -100), 127) : 14;
+                mul[r][q] = ldexpf(1.f, 14 - e);
+                const long row = row0 + 16 * r + 4 * lk + q;
+                if (lr == 0 && row < nrows) cs[row] = ldexpf(1.f, e - 14);
+            }
+    }
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
@@ -312,6 +334,14 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
                 const float ce = ae[r][t][q], co = ao[r][t][q];
                 if (OUT == 1) {
                     *(float2 *)((float *)c_out + o) = make_float2(ce, co);
+                } else if (OUT == 3) {
+                    const float ve = ce * mul[r][q], vo = co * mul[r][q];  // exact: powers of two
+                    const _Float16 he = (_Float16)ve, ho = (_Float16)vo;
+                    const _Float16 le = (_Float16)(ve - (float)he), lo = (_Float16)(vo - (float)ho);
+                    *(uint32_t *)((uint16_t *)c_out + o) = (uint32_t)__builtin_bit_cast(uint16_t, he) |
+                                                           ((uint32_t)__builtin_bit_cast(uint16_t, ho) << 16);
+                    *(uint32_t *)(c_lo + o) = (uint32_t)__builtin_bit_cast(uint16_t, le) |
+                                              ((uint32_t)__builtin_bit_cast(uint16_t, lo) << 16);
                 } else {
                     const uint16_t he = bf16_rne(ce), ho = bf16_rne(co);
                     *(uint32_t *)((uint16_t *)c_out + o) = (uint32_t)he | ((uint32_t)ho << 16);
@@ -471,6 +501,22 @@ struct Cfg<BLAST_BF16X3> {
     using Acc = f4;
     static constexpr int VEC = 8, BT = 64;
 };
+template <>
+struct Cfg<BLAST_FP16X3> {
+    using E = uint16_t;
+    using Acc = f4;
+    static constexpr int VEC = 8, BT = 64;
+};
+
+// one 16x16x32 MFMA on 16-bit operands held as bit patterns: FP16 for FP16X3, BF16 otherwise
+template <int PREC>
+__device__ inline f4 mfma16(U4 a, U4 b, f4 c) {
+    if constexpr (PREC == BLAST_FP16X3)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0,
+                                                       0);
+}
 
 template <int PREC>
 __global__ __launch_bounds__(256) void contract_kernel(const typename Cfg<PREC>::E *__restrict__ basis,
@@ -916,7 +962,7 @@ template <int PREC, int NS>
 struct FusedShape {
     using E = typename Cfg<PREC>::E;
     static constexpr int VEC = Cfg<PREC>::VEC, KSTEP = 4 * VEC, ncp = NS * KSTEP;
-    static constexpr int NPART = PREC == BLAST_BF16X3 ? 2 : 1;
+    static constexpr int NPART = PREC == BLAST_BF16X3 || PREC == BLAST_FP16X3 ? 2 : 1;
     static constexpr int ROWB = ncp * (int)sizeof(E);                  // bytes of one c row
     static constexpr int A_CH = kFusedTR * NS * NPART;                 // 1 KB chunks of basis per b
     static constexpr int C_CH = 64 * ROWB * NPART / 1024;              // 1 KB chunks of c per b
@@ -1033,6 +1079,76 @@ __device__ inline void mfma_last(f4v av, f4v bv, f4 &c0, f4 &c1) {
         : "memory");
 }
 
+// Split 16-bit contraction steps of the fused kernel (FP16X3, BF16X3), pipelined like the FP32
+// steps: a block issues the four LDS reads of the next step (basis hi and lo, c hi and lo), runs the
+// current step's hi*hi, hi*lo and lo*hi products into three accumulator chains (consecutive MFMAs
+// never depend on each other) and waits for its reads.  The first block also reads the weight
+// groups and the row scales and starts the accumulators from zero; the last one reads nothing and
+// ends with 32 wait states before the VALU reads the accumulators.
+#define BLAST_X3_STEP(OP, Z0, Z1, Z2)                                                                 \
+    OP " %[c0], %[a], %[b], " Z0 "\n\t" OP " %[c1], %[a], %[bl], " Z1 "\n\t" OP " %[c2], %[al], %[b], " Z2 "\n\t"
+#define BLAST_X3_READ4                                                                                \
+    "ds_read_b128 %[na], %[ab] offset:%[ao]\n\t"                                                      \
+    "ds_read_b128 %[nb], %[cb] offset:%[co]\n\t"                                                      \
+    "ds_read_b128 %[nal], %[ab] offset:%[alo]\n\t"                                                    \
+    "ds_read_b128 %[nbl], %[cb] offset:%[clo]\n\t"
+template <int PREC, int AO, int ALO, int CO, int CLO>
+__device__ inline void x3_first(uint32_t an, uint32_t cn, const uint32_t (&kq)[4], uint32_t sa, U4 a, U4 al, U4 b,
+                                U4 bl, U4 &na, U4 &nb, U4 &nal, U4 &nbl, U4 (&q)[4], U4 &qs, f4 &c0, f4 &c1, f4 &c2) {
+#define BLAST_X3_FIRST(OP)                                                                               \
+    asm volatile(BLAST_X3_READ4                                                                          \
+                 "ds_read_b128 %[q0], %[k0]\n\t"                                                         \
+                 "ds_read_b128 %[q1], %[k1]\n\t"                                                         \
+                 "ds_read_b128 %[q2], %[k2]\n\t"                                                         \
+                 "ds_read_b128 %[q3], %[k3]\n\t"                                                         \
+                 "ds_read_b128 %[qs], %[sa]\n\t"                                                         \
+                 "s_setprio 3\n\t"                                                                      \
+                 "s_nop 1\n\t" BLAST_X3_STEP(OP, "0", "0", "0") "s_waitcnt lgkmcnt(0)"                    \
+                 : [na] "=&v"(na), [nb] "=&v"(nb), [nal] "=&v"(nal), [nbl] "=&v"(nbl), [q0] "=&v"(q[0]),       \
+                   [q1] "=&v"(q[1]), [q2] "=&v"(q[2]), [q3] "=&v"(q[3]), [qs] "=&v"(qs), [c0] "=&v"(c0),       \
+                   [c1] "=&v"(c1), [c2] "=&v"(c2)                                                        \
+                 : [ab] "v"(an), [cb] "v"(cn), [ao] "i"(AO), [alo] "i"(ALO), [co] "i"(CO), [clo] "i"(CLO),     \
+                   [k0] "v"(kq[0]), [k1] "v"(kq[1]), [k2] "v"(kq[2]), [k3] "v"(kq[3]), [sa] "v"(sa), [a] "v"(a), \
+                   [al] "v"(al), [b] "v"(b), [bl] "v"(bl)                                                \
+                 : "memory")
+    if constexpr (PREC == BLAST_FP16X3)
+        BLAST_X3_FIRST("v_mfma_f32_16x16x32_f16");
+    else
+        BLAST_X3_FIRST("v_mfma_f32_16x16x32_bf16");
+#undef BLAST_X3_FIRST
+}
+template <int PREC, int AO, int ALO, int CO, int CLO>
+__device__ inline void x3_mid(uint32_t an, uint32_t cn, U4 a, U4 al, U4 b, U4 bl, U4 &na, U4 &nb, U4 &nal, U4 &nbl,
+                              f4 &c0, f4 &c1, f4 &c2) {
+#define BLAST_X3_MID(OP)                                                                                 \
+    asm volatile(BLAST_X3_READ4 "s_nop 1\n\t" BLAST_X3_STEP(OP, "%[c0]", "%[c1]", "%[c2]") "s_waitcnt lgkmcnt(0)" \
+                 : [na] "=&v"(na), [nb] "=&v"(nb), [nal] "=&v"(nal), [nbl] "=&v"(nbl), [c0] "+v"(c0),         \
+                   [c1] "+v"(c1), [c2] "+v"(c2)                                                          \
+                 : [ab] "v"(an), [cb] "v"(cn), [ao] "i"(AO), [alo] "i"(ALO), [co] "i"(CO), [clo] "i"(CLO),     \
+                   [a] "v"(a), [al] "v"(al), [b] "v"(b), [bl] "v"(bl)                                     \
+                 : "memory")
+    if constexpr (PREC == BLAST_FP16X3)
+        BLAST_X3_MID("v_mfma_f32_16x16x32_f16");
+    else
+        BLAST_X3_MID("v_mfma_f32_16x16x32_bf16");
+#undef BLAST_X3_MID
+}
+template <int PREC>
+__device__ inline void x3_last(U4 a, U4 al, U4 b, U4 bl, f4 &c0, f4 &c1, f4 &c2) {
+#define BLAST_X3_LAST(OP)                                                                                \
+    asm volatile("s_nop 1\n\t" BLAST_X3_STEP(OP, "%[c0]", "%[c1]", "%[c2]") "s_setprio 0\n\t"            \
+                 "s_nop 15\n\t"                                                                          \
+                 "s_nop 15"                                                                              \
+                 : [c0] "+v"(c0), [c1] "+v"(c1), [c2] "+v"(c2)                                           \
+                 : [a] "v"(a), [al] "v"(al), [b] "v"(b), [bl] "v"(bl)                                    \
+                 : "memory")
+    if constexpr (PREC == BLAST_FP16X3)
+        BLAST_X3_LAST("v_mfma_f32_16x16x32_f16");
+    else
+        BLAST_X3_LAST("v_mfma_f32_16x16x32_bf16");
+#undef BLAST_X3_LAST
+}
+
 // s_waitcnt with only the vector-memory counter constrained (gfx9 encoding)
 template <int N>
 __device__ inline void wait_vmcnt() {
@@ -1049,7 +1165,7 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     using S = FusedShape<PREC, NS>;
     using E = typename S::E;
     constexpr int TR = kFusedTR, VEC = S::VEC, KSTEP = S::KSTEP, ncp = S::ncp, NPART = S::NPART;
-    constexpr bool X3 = PREC == BLAST_BF16X3;
+    constexpr bool X3 = PREC == BLAST_BF16X3 || PREC == BLAST_FP16X3;
     constexpr int GPR = S::ROWB / 16;            // granules per c row
     // granule permutation mask: XOR by up to SWZ stays inside the row when SWZ + 1 divides GPR;
     // with 16 the 16 rows read by one instruction hit 16 distinct 16-byte bank groups
@@ -1236,6 +1352,50 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
                 kt[16] = v[0], kt[17] = v[1], kt[18] = v[2], kt[19] = v[3];
             }
             wv = c0 + c1;
+        } else if constexpr (X3 && NS >= 2 && NB <= 16) {  // (20 bins: registers run out, steps below)
+            constexpr int ALO = TR * NS * 1024;          // lo parts of the basis tiles
+            constexpr int CLO = (int)(S::C_BUF / NPART);  // lo parts of the c rows
+            uint32_t kq[4];
+            const int rr = ((16 * tk + lr) >> 2) & 3;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) kq[j] = KROT ? kb + 16 * ((j + rr) & 3) : kb + 16 * (j < NQ ? j : NQ - 1);
+            const uint32_t sa =
+                lds_addr(Cb + S::C_BUF + (size_t)KCH * 1024) + (uint32_t)(16 * min(ti, TR - 1) + 4 * lk) * 4;
+            U4 q[4], qs, ua, ub, ual, ubl;
+            lds_read4<0, 0, ALO, CLO>(As, Cq[0], As, Cq[0], ua, ub, ual, ubl);  // operands of step 0
+            f4 c0, c1, c2;
+            // step st: basis at As + 1024 st (+ ALO), c at Cq[st & 3] + 256 (st >> 2) (+ CLO)
+            auto pipe = [&](auto stc) {
+                constexpr int st = decltype(stc)::value;
+                if constexpr (st + 1 < NS) {
+                    constexpr int AO = (st + 1) * 1024, CO = 256 * ((st + 1) >> 2);
+                    U4 na, nb, nal, nbl;
+                    if constexpr (st == 0)
+                        x3_first<PREC, AO, AO + ALO, CO, CO + CLO>(As, Cq[1], kq, sa, ua, ual, ub, ubl, na, nb, nal,
+                                                                   nbl, q, qs, c0, c1, c2);
+                    else
+                        x3_mid<PREC, AO, AO + ALO, CO, CO + CLO>(As, Cq[(st + 1) & 3], ua, ual, ub, ubl, na, nb, nal,
+                                                                 nbl, c0, c1, c2);
+                    ua = na, ub = nb, ual = nal, ubl = nbl;
+                } else {
+                    x3_last<PREC>(ua, ual, ub, ubl, c0, c1, c2);
+                }
+            };
+            static_for<0, NS>(pipe);
+#pragma unroll
+            for (int j = 0; j < (NQ < 4 ? NQ : 4); ++j) {
+                const f4v v = __builtin_bit_cast(f4v, q[j]);
+                kt[4 * j] = v[0], kt[4 * j + 1] = v[1], kt[4 * j + 2] = v[2], kt[4 * j + 3] = v[3];
+            }
+            if constexpr (NQ > 4) {
+                U4 q4, qd;
+                lds_read2<64, 64>(kb, kb, q4, qd);
+                const f4v v = __builtin_bit_cast(f4v, q4);
+                kt[16] = v[0], kt[17] = v[1], kt[18] = v[2], kt[19] = v[3];
+            }
+            const f4v sv = __builtin_bit_cast(f4v, qs);
+            wv = c0 + (c1 + c2);
+            wv[0] *= sv[0], wv[1] *= sv[1], wv[2] *= sv[2], wv[3] *= sv[3];
         } else {
             // weights of this b's cosmology and the row scales, from LDS
             float4 sc;
@@ -1275,13 +1435,12 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
                     lds_read4<st * 1024, coff, st * 1024, coff>(As, cb, Asl, cbl, ua, ub, ual, ubl);
                 else
                     lds_read2<st * 1024, coff>(As, cb, ua, ub);
-                const bf8 av = __builtin_bit_cast(bf8, ua), bv = __builtin_bit_cast(bf8, ub);
                 f4 &a0 = acc[st & 1];
-                a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, a0, 0, 0, 0);
+                a0 = mfma16<PREC>(ua, ub, a0);
                 if constexpr (X3) {
                     f4 &a1 = acc[2 + (st & 1)];
-                    a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, ubl), a1, 0, 0, 0);
-                    a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ual), bv, a1, 0, 0, 0);
+                    a1 = mfma16<PREC>(ua, ubl, a1);
+                    a1 = mfma16<PREC>(ual, ub, a1);
                 }
             };
             static_for<0, NS>(step_k);
@@ -1329,9 +1488,11 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
 // Kt[a, b][beta][bin] = wR_b K_bin(R_b chi_a) (FP32, NB bins with zero padding) for the fused
 // kernel.  A work-group transposes 32 points x 16 cosmologies through LDS: coalesced reads along
 // the points, 1 KB contiguous writes per point.
+// With cs (FP16 coefficients) the weights also carry the coefficient row scale cs[beta][a, b], which
+// the contraction of the scaled coefficients leaves out.
 __global__ __launch_bounds__(256) void kt_kernel(const double *__restrict__ Kchi2, const double *__restrict__ wR,
-                                                 int batch, int nbins, int NB, int NP, int n_R,
-                                                 float *__restrict__ Kt) {
+                                                 const float *__restrict__ cs, int batch, int nbins, int NB, int NP,
+                                                 int n_R, float *__restrict__ Kt) {
     __shared__ float tile[32][16 * 20 + 1];  // [point][beta_local * NB + bin], NB <= 20
     const int ab0 = blockIdx.x * 32, b0 = blockIdx.y * 16;
     const int nbeta = min(16, batch - b0);
@@ -1347,6 +1508,7 @@ __global__ __launch_bounds__(256) void kt_kernel(const double *__restrict__ Kchi
             const int bl = min(q / NB, nbeta - 1), bin = min(q % NB, nbins - 1), ab = min(ab0 + i % 32, NP - 1);
             kv[u] = Kchi2[((size_t)(b0 + bl) * nbins + bin) * NP + ab];
             wv[u] = wR[ab % n_R];
+            if (cs) wv[u] *= (double)cs[(size_t)(b0 + bl) * NP + ab];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1537,6 +1699,38 @@ __global__ __launch_bounds__(256) void coef_in_kernel(const PT *__restrict__ cin
         const uint16_t h = bf16_rne(f);
         ((uint16_t *)c_out)[i] = h;
         if (c_lo) c_lo[i] = bf16_rne(f - bf16_val(h));
+    }
+}
+
+// FP16 hi and lo parts of coefficients given as input, one wave per row: the same power-of-two
+// row scale as the projection's FP16 output (largest |c_n| in [2^14, 2^15), cs[row] = scale)
+template <typename PT>
+__global__ __launch_bounds__(256) void coef_in16_kernel(const PT *__restrict__ cin, int N, int ncp, long nrows,
+                                                        uint16_t *__restrict__ c_hi, uint16_t *__restrict__ c_lo,
+                                                        float *__restrict__ cs) {
+    const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= nrows) return;  // uniform over the wave
+    float v[kMaxCheb / 64];
+    float mx = 0.f;
+#pragma unroll
+    for (int i = 0; i < kMaxCheb / 64; ++i) {
+        const int n = lane + 64 * i;
+        v[i] = n < N ? (float)cin[row * N + n] : 0.f;
+        mx = fmaxf(mx, fabsf(v[i]));
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    const int e = mx > 0.f ? min(max(ilogbf(mx), -100), 127) : 14;
+    const float mul = ldexpf(1.f, 14 - e);
+    if (lane == 0) cs[row] = ldexpf(1.f, e - 14);
+#pragma unroll
+    for (int i = 0; i < kMaxCheb / 64; ++i) {
+        const int n = lane + 64 * i;
+        if (n >= ncp) break;
+        const float x = v[i] * mul;
+        const _Float16 h = (_Float16)x;
+        c_hi[row * ncp + n] = __builtin_bit_cast(uint16_t, h);
+        c_lo[row * ncp + n] = __builtin_bit_cast(uint16_t, (_Float16)(x - (float)h));
     }
 }
 
@@ -1780,7 +1974,7 @@ struct Ctx {
 };
 
 struct Layout {
-    size_t c, clo, w, kt, y, dy, sg, dw, dc, total;
+    size_t c, clo, cs, w, kt, y, dy, sg, dw, dc, total;
 };
 
 // Below this batch the fused kernel, which keeps one work-group per CU busy with a barrier per
@@ -1790,7 +1984,7 @@ constexpr int kFusedMinBatch = 32;
 
 // bins computed by the fused kernel (multiple of 4), 0 when it does not apply
 int fused_nb(int prec, int nbins, int batch) {
-    if (prec == BLAST_FP64 || nbins > 20 || batch < kFusedMinBatch) return 0;
+    if (prec == BLAST_FP64 || nbins > 20 || (batch < kFusedMinBatch && prec != BLAST_FP16X3)) return 0;
     return (nbins + 3) / 4 * 4;
 }
 
@@ -1805,7 +1999,9 @@ Layout layout_of(const blast_plan *p, int batch, int prec, int nbins, bool need_
     L.c = off;
     off += align256(nc * ce);
     L.clo = off;
-    if (prec == BLAST_BF16X3) off += align256(nc * 2);
+    if (prec == BLAST_BF16X3 || prec == BLAST_FP16X3) off += align256(nc * 2);
+    L.cs = off;
+    if (prec == BLAST_FP16X3) off += align256((size_t)batch * p->NP * 4);
     L.w = off;
     L.kt = off;
     if (need_w) {
@@ -1883,11 +2079,12 @@ int quad_y_threads(const blast_plan *p, bool f64, int nbp) {
 
 blast_status check_args(const blast_plan *p, const blast_cl_args *a, Ctx &x) {
     if (a->batch < 1) return set_error("batch must be >= 1"), BLAST_E_INVALID;
-    if (a->precision < 0 || a->precision > 3) return set_error("unknown precision %d", a->precision), BLAST_E_INVALID;
+    if (a->precision < 0 || a->precision > 4) return set_error("unknown precision %d", a->precision), BLAST_E_INVALID;
     x.prec = a->precision;
     const int prec = x.prec;
     const bool resident = (prec == BLAST_FP64 && p->basis.f64) || (prec == BLAST_FP32 && p->basis.f32) ||
-                          (prec == BLAST_BF16 && p->basis.hi) || (prec == BLAST_BF16X3 && p->basis.lo);
+                          (prec == BLAST_BF16 && p->basis.hi) || (prec == BLAST_BF16X3 && p->basis.lo) ||
+                          (prec == BLAST_FP16X3 && p->basis.l16);
     if (!resident) return set_error("precision %d is not resident in this plan", prec), BLAST_E_INVALID;
     if (a->p_dtype != 0 && a->p_dtype != 1) return set_error("p_dtype must be 0 (FP64) or 1 (FP32)"), BLAST_E_INVALID;
     if (a->p_kind != 0 && a->p_kind != 1) return set_error("p_kind must be 0 (nodal) or 1 (coefficients)"), BLAST_E_INVALID;
@@ -1955,13 +2152,24 @@ unsigned char *get_workspace(blast_plan *p, const blast_cl_args *a, size_t need,
 }
 
 // stage 1: P (nodal values or coefficients) -> c in the contraction's layout
-void stage_project(blast_plan *p, const blast_cl_args *a, const Ctx &x, void *c, uint16_t *clo, hipStream_t s) {
+void stage_project(blast_plan *p, const blast_cl_args *a, const Ctx &x, void *c, uint16_t *clo, float *cs,
+                   hipStream_t s) {
     const int prec = x.prec;
     const long nrows = (long)a->batch * p->NP;
     const int N = p->n_cheb, ncp = p->nc_pad;
     const bool f64 = prec == BLAST_FP64;
     const bool p64 = a->p_dtype == 0;
-    const int out = f64 ? 0 : (prec == BLAST_FP32 ? 1 : 2);
+    const int out = f64 ? 0 : (prec == BLAST_FP32 ? 1 : (prec == BLAST_FP16X3 ? 3 : 2));
+    if (a->p_kind == 1 && out == 3) {
+        dim3 grid((unsigned)((nrows + 3) / 4));
+        if (p64)
+            hipLaunchKernelGGL((coef_in16_kernel<double>), grid, dim3(256), 0, s, (const double *)a->P, N, ncp, nrows,
+                               (uint16_t *)c, clo, cs);
+        else
+            hipLaunchKernelGGL((coef_in16_kernel<float>), grid, dim3(256), 0, s, (const float *)a->P, N, ncp, nrows,
+                               (uint16_t *)c, clo, cs);
+        return;
+    }
     if (a->p_kind == 1) {
         dim3 grid((unsigned)((nrows * ncp + 255) / 256));
 #define BLAST_CI(PT, O) \
@@ -2001,7 +2209,7 @@ void stage_project(blast_plan *p, const blast_cl_args *a, const Ctx &x, void *c,
             using PT = typename decltype(ptag)::type;
             constexpr int O = decltype(otag)::value, NT = decltype(nttag)::value;
             hipLaunchKernelGGL((project_split_kernel<PT, O, NT>), grid, dim3(256), shp, s, (const PT *)a->P,
-                               p->d_dctn32, N, ncp, nrows, c, clo);
+                               p->d_dctn32, N, ncp, nrows, c, clo, cs);
         };
         auto by_nt = [&](auto ptag, auto otag) {
             switch (ncp / 32) {  // Hp / 16 = ncp / 32, ncp a multiple of 32 up to 128
@@ -2013,10 +2221,13 @@ void stage_project(blast_plan *p, const blast_cl_args *a, const Ctx &x, void *c,
         };
         using I1 = std::integral_constant<int, 1>;
         using I2 = std::integral_constant<int, 2>;
+        using I3 = std::integral_constant<int, 3>;
         if (p64 && out == 1) by_nt(TypeTag<double>(), I1());
         if (p64 && out == 2) by_nt(TypeTag<double>(), I2());
+        if (p64 && out == 3) by_nt(TypeTag<double>(), I3());
         if (!p64 && out == 1) by_nt(TypeTag<float>(), I1());
         if (!p64 && out == 2) by_nt(TypeTag<float>(), I2());
+        if (!p64 && out == 3) by_nt(TypeTag<float>(), I3());
     } else if (N % (f64 ? 8 : 16) == 0) {
         dim3 grid((unsigned)((nrows + 255) / 256));
         const size_t shp = f64 ? 0 : (size_t)ncp * (N + 4) * sizeof(float);
@@ -2092,9 +2303,11 @@ void stage_quad_y(blast_plan *p, const blast_cl_args *a, const Ctx &x, const voi
 }
 
 // stages 2 + 3 fused (mixed precisions without w_save)
-void stage_r_weights(blast_plan *p, const blast_cl_args *a, const Ctx &x, int nb, float *Kt, hipStream_t s) {
+void stage_r_weights(blast_plan *p, const blast_cl_args *a, const Ctx &x, int nb, const float *cs, float *Kt,
+                     hipStream_t s) {
     dim3 gk((unsigned)((p->NP + 31) / 32), (unsigned)((a->batch + 15) / 16));
-    hipLaunchKernelGGL(kt_kernel, gk, dim3(256), 0, s, a->K_chi2, p->d_wR, a->batch, x.nbins, nb, p->NP, p->n_R, Kt);
+    hipLaunchKernelGGL(kt_kernel, gk, dim3(256), 0, s, a->K_chi2, p->d_wR, cs, a->batch, x.nbins, nb, p->NP, p->n_R,
+                       Kt);
 }
 
 void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, int nb, const void *c,
@@ -2116,11 +2329,12 @@ void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, in
         constexpr int PR = decltype(ptag)::value, NB = decltype(nbtag)::value, NBP = decltype(nbptag)::value;
         constexpr int NS = decltype(nstag)::value;
         using E = typename Cfg<PR>::E;
-        const E *bas = PR == BLAST_FP32 ? (const E *)p->basis.f32 : (const E *)p->basis.hi;
+        constexpr bool H = PR == BLAST_FP16X3;
+        const E *bas = PR == BLAST_FP32 ? (const E *)p->basis.f32 : (const E *)(H ? p->basis.h16 : p->basis.hi);
         // all LDS of the fused kernel is static (FusedShape::LDS bytes)
         hipLaunchKernelGGL((contract_quad_kernel<PR, NB, NBP, NS>), dim3(grid), dim3(256 * kFusedTR), 0, s, bas,
-                           p->basis.lo, p->basis.scale, (const E *)c, clo, Kt, a->batch, p->n_chi, p->n_R,
-                           p->rows_pad, nBT, units, p->n_ell, p->nt, granges, Y);
+                           H ? p->basis.l16 : p->basis.lo, H ? p->basis.scale16 : p->basis.scale, (const E *)c, clo,
+                           Kt, a->batch, p->n_chi, p->n_R, p->rows_pad, nBT, units, p->n_ell, p->nt, granges, Y);
     };
     // nc_pad is a multiple of 32 up to 128: 1..4 blocks of 32 columns
     auto by_ns = [&](auto ptag, auto nbtag, auto nbptag) {
@@ -2145,6 +2359,7 @@ void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, in
     if (x.prec == BLAST_FP32) by_nb(std::integral_constant<int, BLAST_FP32>());
     if (x.prec == BLAST_BF16) by_nb(std::integral_constant<int, BLAST_BF16>());
     if (x.prec == BLAST_BF16X3) by_nb(std::integral_constant<int, BLAST_BF16X3>());
+    if (x.prec == BLAST_FP16X3) by_nb(std::integral_constant<int, BLAST_FP16X3>());
 }
 
 // stage 4: C = chi-quadrature and pair assembly
@@ -2172,22 +2387,28 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     blast_status st = check_args(p, a, x);
     if (st != BLAST_OK) return st;
     if (!a->C) return set_error("C is required"), BLAST_E_INVALID;
+    if (x.prec == BLAST_FP16X3) {
+        if (a->w_save) return set_error("FP16X3 runs the fused path only and cannot keep w"), BLAST_E_UNSUPPORTED;
+        if (x.nbins > 20) return set_error("FP16X3 takes at most 20 bins"), BLAST_E_UNSUPPORTED;
+        if (a->p_kind == 0 && p->n_cheb % 8) return set_error("FP16X3 needs n_cheb % 8 == 0"), BLAST_E_UNSUPPORTED;
+    }
     BLAST_HIP_TRY(allow_large_lds());
     const bool need_w = a->w_save == nullptr;
     const Layout L = layout_of(p, a->batch, x.prec, x.nbins, need_w, false);
     unsigned char *ws = get_workspace(p, a, L.total, st);
     if (!ws) return st;
     void *c = ws + L.c;
-    uint16_t *clo = x.prec == BLAST_BF16X3 ? (uint16_t *)(ws + L.clo) : nullptr;
+    uint16_t *clo = x.prec == BLAST_BF16X3 || x.prec == BLAST_FP16X3 ? (uint16_t *)(ws + L.clo) : nullptr;
+    float *cs = x.prec == BLAST_FP16X3 ? (float *)(ws + L.cs) : nullptr;
     void *w = need_w ? (void *)(ws + L.w) : a->w_save;
     void *Y = ws + L.y;
     const int fnb = need_w ? fused_nb(x.prec, x.nbins, a->batch) : 0;
     mark(0);
-    stage_project(p, a, x, c, clo, s);
+    stage_project(p, a, x, c, clo, cs, s);
     mark(1);
     if (fnb) {
         // fused path: interval 1 = the R-weights table, interval 2 = contraction + R-quadrature
-        stage_r_weights(p, a, x, fnb, (float *)(ws + L.kt), s);
+        stage_r_weights(p, a, x, fnb, cs, (float *)(ws + L.kt), s);
         mark(2);
         stage_contract_quad(p, a, x, fnb, c, clo, (float *)(ws + L.kt), (float *)Y, s);
     } else {
@@ -2256,7 +2477,7 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
     void *Y = ws + L.y, *dY = ws + L.dy, *dw = ws + L.dw, *dc = ws + L.dc;
     double *Sg = (double *)(ws + L.sg);
     if (need_w) {
-        stage_project(p, a, x, c, nullptr, s);
+        stage_project(p, a, x, c, nullptr, nullptr, s);
         stage_contract(p, a, x, c, nullptr, w, s);
     }
     if (dK_chi) stage_quad_y(p, a, x, w, Y, s);

@@ -41,6 +41,9 @@ struct BasisBuffers {
     uint16_t *hi = nullptr;    // BF16 bits of (value / scale), same layout
     uint16_t *lo = nullptr;    // BF16 bits of the remainder
     float *scale = nullptr;    // [NP][rows_pad] power-of-two row scales
+    uint16_t *h16 = nullptr;   // FP16 bits of (value / scale16), tiled layout
+    uint16_t *l16 = nullptr;   // FP16 bits of the remainder
+    float *scale16 = nullptr;  // [NP][rows_pad] power-of-two row scales of the FP16 parts
 };
 
 }  // namespace blast

@@ -310,6 +310,10 @@ extern "C" blast_status blast_server_create(blast_plan *plan, const blast_server
     if (!S->d.max_queue) S->d.max_queue = 4096;
     const size_t budget = d->hbm_budget ? d->hbm_budget : (size_t)8 << 30;
     S->bins = d->max_g + d->max_s;
+    if (d->precision == BLAST_FP16X3 && S->bins > 20) {
+        delete S;
+        return blast::set_error("FP16X3 takes at most 20 bins"), BLAST_E_UNSUPPORTED;
+    }
     S->npairs_pad = npairs(d->max_g, d->max_s, plan->types);
     S->p_elem = d->p_dtype == 0 ? 8 : 4;
     S->P_slot = (size_t)plan->NP * plan->n_cheb * S->p_elem;
