@@ -317,7 +317,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=256)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16x3", "bf16x3", "fp64", "bf16"])
+    ap.add_argument("--precision", default="fp16x3", choices=["fp16x3", "fp32", "bf16x3", "fp64", "bf16"])
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64-path and batch-1 timings")
@@ -444,6 +444,38 @@ def main():
         ms64 = (time.perf_counter() - t0) * 1e3 / 5
         extras["fp64_path"] = {"batch": nb64, "ms_per_step": ms64, "sets_per_s": nb64 / (ms64 * 1e-3)}
         extras["mixed_vs_fp64_speedup"] = value / extras["fp64_path"]["sets_per_s"]
+        if prec != "fp32":
+            # the FP32 path on the same batch: throughput, its fused kernel's roofline, its error
+            P32 = P if P.dtype == torch.float32 else P.float()
+            for _ in range(2):
+                plan.forward(P32, K1, K2, cfg.n_g, cfg.n_s, precision="fp32", out=out)
+            torch.cuda.synchronize()
+            plan.profile(True)
+            plan.profile_read()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                plan.forward(P32, K1, K2, cfg.n_g, cfg.n_s, precision="fp32", out=out)
+            torch.cuda.synchronize()
+            ms32 = (time.perf_counter() - t0) * 1e3 / 5
+            plan.profile(False)
+            st32, n32 = plan.profile_read()
+            pl32 = {k: v / max(n32, 1) for k, v in st32.items()}
+            pl32 = {"projection": pl32["projection"], "r_weights": pl32["contraction"],
+                    "contraction": pl32["quad_R"], "quad_chi": pl32["quad_chi"]}
+            r32 = roofline(stage_work(plan, cfg, "fp32", Bn)["contraction"], pl32["contraction"], "fp32")
+            r32.pop("algorithmic_bytes", None)
+            r32["traffic"] = counter_traffic("contract_quad_kernel", cfg.name, Bn, "fp32")
+            f32 = {"batch": Bn, "ms_per_step": ms32, "sets_per_s": Bn / (ms32 * 1e-3), "stage_ms_per_launch": pl32,
+                   "fused_kernel_roofline": r32}
+            gpath = os.path.join(ROOT, "tests", "golden", "c%d_oracle.json" % args.config)
+            if os.path.exists(gpath):
+                g = json.load(open(gpath))
+                if g["seed"] == W.seed_for(args.config, 0):
+                    f32["max_rel_err_vs_oracle"] = float(g16_err(out[0].cpu().numpy(), np.array(g["C"]), cfg.n_g,
+                                                                 cfg.n_s).max())
+            extras["fp32_path"] = f32
+            step()  # out holds the timed path's result again
+            torch.cuda.synchronize()
         P1, K11, K21 = P[:1].contiguous(), K1[:1].contiguous(), K2[:1].contiguous()
         lat = []
         for i in range(12):
@@ -510,7 +542,8 @@ def main():
     if args.serving_seconds > 0:
         log("serving run: %.1f s of arrivals at 200 requests/s" % args.serving_seconds)
         plan.close()
-        serving = serving_run(args.serving_seconds)
+        # the server runs the FP32 path: at its small batches the unfused kernels are faster
+        serving = serving_run(args.serving_seconds, precision="fp32")
         log("serving: %s" % serving)
 
     cpu = None
