@@ -61,8 +61,10 @@ typedef enum {
  * coefficients split into BF16 hi + lo parts, hi*hi + hi*lo + lo*hi, FP32
  * accumulate.  FP16X3: the same three products with FP16 hi + lo parts (about 22
  * significant bits per operand); every basis row and every coefficient row
- * (one cosmology, one point) carries its own power-of-two scale that puts its
- * largest magnitude in [2^14, 2^15), inside FP16's normal range.  FP16X3 runs the
+ * (one cosmology, one point) carries its own power-of-two scale that keeps its
+ * magnitudes below 2^15, inside FP16's range (basis rows and coefficients given
+ * as input: largest magnitude in [2^14, 2^15); coefficients projected from nodal
+ * P: from the row's largest |P_j|, which bounds |c_n| / 2).  FP16X3 runs the
  * fused contraction + R-quadrature only: it needs nodal P with n_cheb % 8 == 0
  * (or P given as coefficients), n_g + n_s <= 20 and no w_save, and is not
  * available to the adjoint; other requests are refused with BLAST_E_UNSUPPORTED.
