@@ -1506,6 +1506,245 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     }
 }
 
+// Split 16-bit fused kernel with wider wave tiles (FP16X3 and BF16X3, NB <= 16).  The 12-wave kernel
+// above is bound by the bytes it moves from L2 into LDS per (row, cosmology) pair; here a work-group
+// is (chi_a, 64 cosmologies, 4 row tiles) with 8 waves, and wave (i, k) makes two 16 x 16 tiles per b
+// (row tile i, cosmologies 32k..32k+15 and 32k+16..32k+31), keeping Y for 4 rows x NB bins of both
+// (two waves per SIMD).  Per b it moves 32 KB of basis and 32 KB of c rows for 4096 pairs, against
+// 24 + 32 KB for 3072.  Basis and c one b ahead (two LDS buffers each, 138 KB); one barrier per b.
+// Steps are not software-pipelined (the registers hold both tiles' accumulators and Y).
+constexpr int kWideTR = 4;
+
+template <int PREC, int NS>
+struct WideShape {
+    using E = uint16_t;
+    static constexpr int VEC = 8, KSTEP = 32, ncp = NS * KSTEP, NPART = 2;
+    static constexpr int ROWB = ncp * 2;
+    static constexpr int A_CH = kWideTR * NS * NPART, C_CH = 64 * ROWB * NPART / 1024;
+    static constexpr int NW = 8;
+    static constexpr int A_PW = (A_CH + NW - 1) / NW, C_PW = (C_CH + NW - 1) / NW;
+    static constexpr size_t A_BUF = (size_t)A_CH * 1024, C_BUF = (size_t)C_CH * 1024;
+    static constexpr size_t X_BUF = 5 * 1024;  // weights (NB <= 16: <= 4 KB) and the row scales
+    static constexpr size_t LDS = 2 * A_BUF + 2 * (C_BUF + X_BUF);
+};
+
+template <int PREC, int NB, int NBP, int NS>
+__global__ __launch_bounds__(512) void contract_quad_wide_kernel(
+    const uint16_t *__restrict__ basis, const uint16_t *__restrict__ basis_lo, const float *__restrict__ scale,
+    const uint16_t *__restrict__ c, const uint16_t *__restrict__ c_lo, const float *__restrict__ Kt, int batch,
+    int n_chi, int n_R, int rows_pad, int nBT, int units, int n_ell, int nslots, int granges, float *__restrict__ Y) {
+    using S = WideShape<PREC, NS>;
+    using E = typename S::E;
+    constexpr int TR = kWideTR, VEC = S::VEC, ncp = S::ncp, NPART = S::NPART;
+    constexpr int GPR = S::ROWB / 16;
+    constexpr int SWZ = GPR % 16 == 0 ? 15 : (GPR % 8 == 0 ? 7 : (GPR % 4 == 0 ? 3 : (GPR % 2 == 0 ? 1 : 0)));
+    constexpr bool KROT = NB == 16;
+    static_assert(NB <= 16 && S::LDS <= 160 * 1024, "LDS of the wide fused kernel");
+    __shared__ __align__(1024) unsigned char A0[S::A_BUF], A1[S::A_BUF];
+    __shared__ __align__(1024) unsigned char C0[S::C_BUF + S::X_BUF], C1[S::C_BUF + S::X_BUF];
+
+    const int groups = (rows_pad / 16 + TR - 1) / TR;
+    const int per = (units + 7) / 8;
+    const int unit = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (unit >= units) return;  // uniform over the work-group
+    const int RT = rows_pad / 16;
+    const int g = unit % groups, bt = (unit / groups) % nBT, a = unit / (groups * nBT);
+    const int rt0 = g * TR;
+    const int ntile = min(TR, RT - rt0);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int ti = w >> 1, tk = w & 1;  // row tile, 32-cosmology half
+    const int nb = min(64, batch - bt * 64);
+    const size_t NP = (size_t)n_chi * n_R;
+    const size_t pt_u4 = (size_t)RT * NS * 64;
+    const bool busy = ti < ntile && bt * 64 + 32 * tk < batch;
+    int gq0 = NB / 4, gq1 = 0;
+    {
+        const int r0 = 16 * (rt0 + min(ti, TR - 1));
+        const int s0 = min(r0 / n_ell, nslots - 1), s1 = min((r0 + 15) / n_ell, nslots - 1);
+        for (int sl = s0; sl <= s1; ++sl) {
+            gq0 = min(gq0, (granges >> (6 * sl)) & 7);
+            gq1 = max(gq1, (granges >> (6 * sl + 3)) & 7);
+        }
+    }
+    const int gmask = __builtin_amdgcn_readfirstlane(gq1 > gq0 ? ((1 << gq1) - 1) & ~((1 << gq0) - 1) : 0);
+
+    // a wave issues up to A_PW basis and C_PW c DMAs per b (chunk indices past the end clamped: the
+    // last chunk is written more than once with identical data); basis chunks of row tiles past the
+    // end of the last group are skipped (each b waits for all DMAs, so the counts may differ)
+    const U4 *srcA[S::A_PW];
+    bool useA[S::A_PW];
+#pragma unroll
+    for (int k = 0; k < S::A_PW; ++k) {
+        const int ch = min(w + k * S::NW, S::A_CH - 1);
+        const int part = ch / (TR * NS), tl = (ch / NS) % TR, st = ch % NS;
+        const int rt = min(rt0 + tl, RT - 1);
+        srcA[k] = (const U4 *)(part ? basis_lo : basis) + ((size_t)rt * NS + st) * 64 + lane;
+        useA[k] = tl < ntile;  // uniform over the wave
+    }
+    auto dma_A = [&](int b, unsigned char *__restrict__ buf) {
+        const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
+#pragma unroll
+        for (int k = 0; k < S::A_PW; ++k)
+            if (useA[k]) lds_dma16(srcA[k] + ab * pt_u4, buf + (size_t)min(w + k * S::NW, S::A_CH - 1) * 1024);
+    };
+    // weights Kt[ab][64 cosmologies][NB] and the row scales of the group: waves 0..KCH-1 move weight
+    // chunks, wave KCH the scales, the others nothing
+    constexpr int KCH = 64 * NB * 4 / 1024;
+    static_assert(KCH + 1 <= S::NW && TR * 16 * 4 <= 1024 && KCH * 1024 + 1024 <= (int)S::X_BUF, "extra region");
+    const int chX = min(w, KCH);
+    const float *srcX;
+    {
+        int f = chX * 256 + lane * 4;
+        if (KROT) {
+            const int r = f / 16, sp = (f / 4) & 3;
+            f = r * 16 + ((sp - (r >> 2)) & 3) * 4;
+        }
+        const int bl = f / NB;
+        srcX = chX < KCH ? Kt + (size_t)(bt * 64 + (bl < nb ? bl : 0)) * NB + (bl < nb ? f % NB : 0)
+                         : scale + min(16 * rt0 + 4 * lane, rows_pad - 4);
+    }
+    const size_t strideX = chX < KCH ? (size_t)batch * NB : (size_t)rows_pad;
+    auto dma_X = [&](int b, unsigned char *__restrict__ buf) {
+        if (w > KCH) return;
+        const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
+        lds_dma16(srcX + ab * strideX, buf + S::C_BUF + (size_t)chX * 1024);
+    };
+    const E *srcC[S::C_PW];
+#pragma unroll
+    for (int k = 0; k < S::C_PW; ++k) {
+        const int ch = min(w + k * S::NW, S::C_CH - 1);
+        const int part = ch / (S::C_CH / NPART), chp = ch % (S::C_CH / NPART);
+        const int pos = chp * 1024 + lane * 16;
+        const int row = pos / S::ROWB, gp = (pos % S::ROWB) / 16;
+        const int v = gp ^ (row & SWZ);
+        const int bb = bt * 64 + (row < nb ? row : 0);
+        srcC[k] = (part ? c_lo : c) + (size_t)bb * NP * ncp + v * VEC;
+    }
+    auto dma_C = [&](int b, unsigned char *__restrict__ buf) {
+        const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
+#pragma unroll
+        for (int k = 0; k < S::C_PW; ++k)
+            lds_dma16(srcC[k] + ab * ncp, buf + (size_t)min(w + k * S::NW, S::C_CH - 1) * 1024);
+    };
+
+    float y[2][4][NB];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int q = 0; q < NB; ++q) y[j][r][q] = 0.f;
+    const int arow = min(ti, TR - 1) * NS * 64 + lane;
+
+    auto step = [&](int b, const unsigned char *__restrict__ Ab, const unsigned char *__restrict__ Cb,
+                    unsigned char *__restrict__ Cnext, unsigned char *__restrict__ Anext) {
+        // everything issued one b ago has landed (this wave's DMAs), then all waves' (barrier)
+        wait_vmcnt<0>();
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        dma_C(b + 1, Cnext);
+        dma_X(b + 1, Cnext);
+        dma_A(b + 1, Anext);
+        __builtin_amdgcn_sched_barrier(0);
+        if (!busy) return;
+        constexpr int NQ = NB / 4;
+        constexpr int ALO = TR * NS * 1024, CLO = (int)(S::C_BUF / NPART);
+        // the second half's rows are 16 rows further on with the same granule permutation and the
+        // same weight rotation (16 is a multiple of SWZ + 1 and of 16): fixed offsets
+        constexpr int C16 = 16 * S::ROWB, K16 = 16 * NB * 4;
+        const uint32_t As = lds_addr(Ab) + (uint32_t)arow * 16;
+        const int crow = 32 * tk + lr;
+        uint32_t Cq[4], kq[4];
+        {
+            const uint32_t Cr = lds_addr(Cb) + (uint32_t)crow * S::ROWB;
+            const int m = crow & SWZ, mh = m >> 2, ml = lk ^ (m & 3);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Cq[k] = Cr + 16 * (4 * (k ^ mh) + ml);
+            const uint32_t kb = lds_addr(Cb + S::C_BUF) + (uint32_t)crow * (NB * 4);
+            const int rr = (crow >> 2) & 3;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) kq[q] = KROT ? kb + 16 * ((q + rr) & 3) : kb + 16 * (q < NQ ? q : NQ - 1);
+        }
+        const uint32_t sa = lds_addr(Cb + S::C_BUF + (size_t)KCH * 1024) + (uint32_t)(16 * min(ti, TR - 1) + 4 * lk) * 4;
+        f4 acc[2][3];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int u = 0; u < 3; ++u) acc[j][u] = f4{0, 0, 0, 0};
+        auto step_k = [&](auto stc) {
+            constexpr int st = decltype(stc)::value;
+            constexpr int coff = 256 * (st >> 2);
+            U4 ua, ual, ub0, ub0l, ub1, ub1l;
+            const uint32_t cq = Cq[st & 3];
+            lds_read4<st * 1024, st * 1024 + ALO, coff, coff + CLO>(As, As, cq, cq, ua, ual, ub0, ub0l);
+            lds_read2<coff + C16, coff + C16 + CLO>(cq, cq, ub1, ub1l);
+            acc[0][0] = mfma16<PREC>(ua, ub0, acc[0][0]);
+            acc[1][0] = mfma16<PREC>(ua, ub1, acc[1][0]);
+            acc[0][1] = mfma16<PREC>(ua, ub0l, acc[0][1]);
+            acc[1][1] = mfma16<PREC>(ua, ub1l, acc[1][1]);
+            acc[0][2] = mfma16<PREC>(ual, ub0, acc[0][2]);
+            acc[1][2] = mfma16<PREC>(ual, ub1, acc[1][2]);
+        };
+        static_for<0, NS>(step_k);
+        float4 sc;
+        {
+            U4 qs, qd;
+            lds_read2<0, 0>(sa, sa, qs, qd);
+            const f4v v = __builtin_bit_cast(f4v, qs);
+            sc = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        // R-sum, one half at a time (its weights read just before)
+        auto rsum = [&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            U4 q[4];
+            lds_read4<j * K16, j * K16, j * K16, j * K16>(kq[0], kq[1], kq[2], kq[3], q[0], q[1], q[2], q[3]);
+            float kt[NB];
+#pragma unroll
+            for (int g4 = 0; g4 < NQ; ++g4) {
+                const f4v v = __builtin_bit_cast(f4v, q[g4]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) kt[4 * g4 + e] = v[e];
+            }
+            f4 wv = acc[j][0] + (acc[j][1] + acc[j][2]);
+            wv[0] *= sc.x, wv[1] *= sc.y, wv[2] *= sc.z, wv[3] *= sc.w;
+#pragma unroll
+            for (int gq = 0; gq < NB / 4; ++gq)
+                if ((gmask >> gq) & 1)  // uniform over the wave
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int qq = 4 * gq; qq < 4 * gq + 4; ++qq) y[j][r][qq] += wv[r] * kt[qq];
+        };
+        static_for<0, 2>(rsum);
+    };
+
+    // issue order: A(0), c(0) + weights(0); then per b, after its barrier: c(b+1) + weights(b+1), A(b+1)
+    dma_C(0, C0);
+    dma_X(0, C0);
+    dma_A(0, A0);
+    for (int b = 0; b < n_R; b += 2) {
+        step(b, A0, C0, C1, A1);
+        if (b + 1 < n_R) step(b + 1, A1, C1, C0, A0);
+    }
+    wait_vmcnt<0>();  // no DMA may outlive the work-group's LDS
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int beta = bt * 64 + 32 * tk + 16 * j + lr;
+        if (ti >= ntile || beta >= batch) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float *yp = Y + (((size_t)beta * rows_pad + 16 * (rt0 + ti) + 4 * lk + r) * n_chi + a) * NBP;
+#pragma unroll
+            for (int q = 0; q < NBP / 4; ++q) {
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (4 * q < NB) v = make_float4(y[j][r][4 * q], y[j][r][4 * q + 1], y[j][r][4 * q + 2], y[j][r][4 * q + 3]);
+                ((float4 *)yp)[q] = v;
+            }
+        }
+    }
+}
+
 // Kt[a, b][beta][bin] = wR_b K_bin(R_b chi_a) (FP32, NB bins with zero padding) for the fused
 // kernel.  A work-group transposes 32 points x 16 cosmologies through LDS: coalesced reads along
 // the points, 1 KB contiguous writes per point.
@@ -2361,6 +2600,16 @@ void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, in
         constexpr int NS = decltype(nstag)::value;
         using E = typename Cfg<PR>::E;
         constexpr bool H = PR == BLAST_FP16X3;
+        if constexpr (H && NB <= 16) {
+            // wide wave tiles (8 waves, 4 row tiles, 64 cosmologies per work-group)
+            const int wgroups = (RT + kWideTR - 1) / kWideTR;
+            const int wunits = p->n_chi * nBT * wgroups;
+            hipLaunchKernelGGL((contract_quad_wide_kernel<PR, NB, NBP, NS>), dim3((unsigned)((wunits + 7) / 8 * 8)),
+                               dim3(512), 0, s, (const uint16_t *)p->basis.h16, p->basis.l16, p->basis.scale16,
+                               (const uint16_t *)c, clo, Kt, a->batch, p->n_chi, p->n_R, p->rows_pad, nBT, wunits,
+                               p->n_ell, p->nt, granges, Y);
+            return;
+        }
         const E *bas = PR == BLAST_FP32 ? (const E *)p->basis.f32 : (const E *)(H ? p->basis.h16 : p->basis.hi);
         // all LDS of the fused kernel is static (FusedShape::LDS bytes)
         hipLaunchKernelGGL((contract_quad_kernel<PR, NB, NBP, NS>), dim3(grid), dim3(256 * kFusedTR), 0, s, bas,
