@@ -404,7 +404,8 @@ def main():
     roof = roofline(work[dom], per_launch[dom], prec)
     split = "project_split64_kernel" if prec == "fp64" else "project_split_kernel"
     roof["kernel"] = {"projection": split if cfg.n_cheb % 8 == 0 else "project_mfma_kernel",
-                      "contraction": "contract_quad_kernel" if fused else "contract_kernel",
+                      "contraction": ("contract_quad_wide_kernel" if prec == "fp16x3" and cfg.n_g + cfg.n_s <= 16
+                                      else "contract_quad_kernel") if fused else "contract_kernel",
                       "quad_R": "quad_y_kernel", "quad_chi": "quad_c_mfma_kernel", "r_weights": "kt_kernel"}[dom]
     roof["traffic"] = counter_traffic(roof["kernel"], cfg.name, Bn, prec)
     roof["stage_ms_per_launch"] = per_launch
