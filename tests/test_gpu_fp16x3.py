@@ -45,13 +45,14 @@ CASES = [  # (n_g, n_s, n_cheb): weight groups NB = 4, 16, 20, 8; 1, 2, 3, 4 blo
 
 @pytest.mark.parametrize("n_g,n_s,n_cheb", CASES)
 def test_fp16x3_matches_oracle_at_any_batch(n_g, n_s, n_cheb):
-    """Batches of 1, 5 and 40 (FP16X3 is fused at every batch) against the oracle, and every
-    cosmology of the batched call against its own single call."""
+    """Batches of 1, 5 and 70 (FP16X3 is fused at every batch; 70 = one full tile of 64
+    cosmologies and a ragged one) against the oracle, and every cosmology of the batched call
+    against its own call in a small batch."""
     cfg = W.tiny_config(n_ell=7, ell_max=50, n_chi=10, n_R=9, n_cheb=n_cheb, k_max=0.6, n_g=n_g, n_s=n_s)
     print("fp16x3 case", n_g, n_s, n_cheb, flush=True)
     plan = B.plan_for_config(cfg, precisions=("fp64", "fp16x3"))
     try:
-        inps = [W.make_inputs(cfg, W.seed_for(21, i), plan.k_nodes, plan.chi, plan.R, vary=True) for i in range(40)]
+        inps = [W.make_inputs(cfg, W.seed_for(21, i), plan.k_nodes, plan.chi, plan.R, vary=True) for i in range(70)]
         P = _dev(np.stack([x.P for x in inps]), torch.float32)
         K1 = _dev(np.stack([x.Kchi for x in inps]))
         K2 = _dev(np.stack([x.Kchi2 for x in inps]))
@@ -59,13 +60,39 @@ def test_fp16x3_matches_oracle_at_any_batch(n_g, n_s, n_cheb):
         Cb = plan.forward(P, K1, K2, n_g, n_s, precision="fp16x3").cpu().numpy()
         eo = g16_err(Cb[0], Cor, n_g, n_s).max()
         worst = 0.0
-        for nb in (1, 5):
-            Cs = plan.forward(P[:nb].contiguous(), K1[:nb].contiguous(), K2[:nb].contiguous(), n_g, n_s,
+        for lo, nb in ((0, 1), (0, 5), (64, 6)):
+            sl = slice(lo, lo + nb)
+            Cs = plan.forward(P[sl].contiguous(), K1[sl].contiguous(), K2[sl].contiguous(), n_g, n_s,
                               precision="fp16x3").cpu().numpy()
             for i in range(nb):
-                worst = max(worst, g16_err(Cs[i], Cb[i], n_g, n_s).max())
-        print("fp16x3 vs oracle", eo, "batch 1/5 vs 40", worst, flush=True)
+                worst = max(worst, g16_err(Cs[i], Cb[lo + i], n_g, n_s).max())
+        print("fp16x3 vs oracle", eo, "small batches vs 70", worst, flush=True)
         assert eo <= 1e-3 and worst <= 1e-6, (eo, worst)
+    finally:
+        plan.close()
+
+
+def test_fp16x3_row_groups_with_a_short_last_group():
+    """30 multipoles: 90 basis rows in 6 tiles of 16, two work-group row groups (4 and 2 tiles) of
+    the wide fused kernel, with gg, gs and ss rows inside one group."""
+    cfg = W.tiny_config(n_ell=30, ell_max=60, n_chi=10, n_R=9, n_cheb=64, k_max=0.6, n_g=4, n_s=3)
+    plan = B.plan_for_config(cfg, precisions=("fp64", "fp16x3"))
+    try:
+        assert plan.rows_pad // 16 == 6
+        inps = [W.make_inputs(cfg, W.seed_for(25, i), plan.k_nodes, plan.chi, plan.R, vary=True) for i in range(40)]
+        P = _dev(np.stack([x.P for x in inps]), torch.float32)
+        K1 = _dev(np.stack([x.Kchi for x in inps]))
+        K2 = _dev(np.stack([x.Kchi2 for x in inps]))
+        Cb = plan.forward(P, K1, K2, cfg.n_g, cfg.n_s, precision="fp16x3").cpu().numpy()
+        # the FP64 path on the FP64 inputs (P rounded to FP32 moves the cancelling cross spectra by ~1e-5)
+        C64 = plan.forward(_dev(np.stack([inps[0].P, inps[39].P])), K1[[0, 39]].contiguous(),
+                           K2[[0, 39]].contiguous(), cfg.n_g, cfg.n_s, precision="fp64").cpu().numpy()
+        Cor = _oracle(plan, cfg, inps[0])
+        e64 = g16_err(C64[0], Cor, cfg.n_g, cfg.n_s).max()
+        eo = g16_err(Cb[0], Cor, cfg.n_g, cfg.n_s).max()
+        el = g16_err(Cb[39], C64[1], cfg.n_g, cfg.n_s).max()
+        print("30 ell: FP64 vs oracle", e64, "FP16X3 vs oracle", eo, "last cosmology vs FP64", el, flush=True)
+        assert e64 <= 1e-6 and eo <= 1e-3 and el <= 1e-3
     finally:
         plan.close()
 
