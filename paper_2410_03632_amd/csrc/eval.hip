@@ -1030,6 +1030,18 @@ __device__ inline void lds_read4(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t
         : "memory");
 }
 
+// six 16-byte reads (three at base a, three at base c, compile-time offsets), then a wait for them
+template <int A0, int A1, int C0, int C1, int C2, int C3>
+__device__ inline void lds_read6(uint32_t a, uint32_t c, U4 &r0, U4 &r1, U4 &r2, U4 &r3, U4 &r4, U4 &r5) {
+    asm volatile(
+        "ds_read_b128 %0, %6 offset:%8\n\tds_read_b128 %1, %6 offset:%9\n\t"
+        "ds_read_b128 %2, %7 offset:%10\n\tds_read_b128 %3, %7 offset:%11\n\t"
+        "ds_read_b128 %4, %7 offset:%12\n\tds_read_b128 %5, %7 offset:%13\n\ts_waitcnt lgkmcnt(0)"
+        : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3), "=&v"(r4), "=&v"(r5)
+        : "v"(a), "v"(c), "i"(A0), "i"(A1), "i"(C0), "i"(C1), "i"(C2), "i"(C3)
+        : "memory");
+}
+
 // FP32 contraction steps of the fused kernel, software-pipelined.  Each block issues the LDS reads
 // of the next step, then the four v_mfma_f32_16x16x4_f32 of the current step (operand a[e], b[e]
 // holds the K slice e of the step) into two accumulator chains (each MFMA one instruction behind
@@ -1677,8 +1689,8 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
             constexpr int coff = 256 * (st >> 2);
             U4 ua, ual, ub0, ub0l, ub1, ub1l;
             const uint32_t cq = Cq[st & 3];
-            lds_read4<st * 1024, st * 1024 + ALO, coff, coff + CLO>(As, As, cq, cq, ua, ual, ub0, ub0l);
-            lds_read2<coff + C16, coff + C16 + CLO>(cq, cq, ub1, ub1l);
+            lds_read6<st * 1024, st * 1024 + ALO, coff, coff + CLO, coff + C16, coff + C16 + CLO>(As, cq, ua, ual, ub0,
+                                                                                                ub0l, ub1, ub1l);
             acc[0][0] = mfma16<PREC>(ua, ub0, acc[0][0]);
             acc[1][0] = mfma16<PREC>(ua, ub1, acc[1][0]);
             acc[0][1] = mfma16<PREC>(ua, ub0l, acc[0][1]);
@@ -1746,50 +1758,55 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
 }
 
 // Kt[a, b][beta][bin] = wR_b K_bin(R_b chi_a) (FP32, NB bins with zero padding) for the fused
-// kernel.  A work-group transposes 32 points x 16 cosmologies through LDS: coalesced reads along
-// the points, 1 KB contiguous writes per point.
+// kernel.  A work-group transposes 64 points x 8 cosmologies through LDS: coalesced 512-byte reads
+// along the points, 512-byte contiguous writes per point.
 // With cs (FP16 coefficients) the weights also carry the coefficient row scale cs[beta][a, b], which
 // the contraction of the scaled coefficients leaves out.
+constexpr int kKtP = 64, kKtB = 8;  // points x cosmologies per work-group of kt_kernel
 __global__ __launch_bounds__(256) void kt_kernel(const double *__restrict__ Kchi2, const double *__restrict__ wR,
                                                  const float *__restrict__ cs, int batch, int nbins, int NB, int NP,
                                                  int n_R, float *__restrict__ Kt) {
-    __shared__ float tile[32][16 * 20 + 1];  // [point][beta_local * NB + bin], NB <= 20
-    __shared__ float csl[16][32];            // coefficient row scales [beta_local][point]
-    const int ab0 = blockIdx.x * 32, b0 = blockIdx.y * 16;
-    const int nbeta = min(16, batch - b0);
+    constexpr int KP = kKtP, KB = kKtB;
+    __shared__ float tile[KP][KB * 20 + 1];  // [point][beta_local * NB + bin], NB <= 20
+    __shared__ float csl[KB][KP];            // coefficient row scales [beta_local][point]
+    const int ab0 = blockIdx.x * KP, b0 = blockIdx.y * KB;
+    const int nbeta = min(KB, batch - b0);
     if (cs) {
-        for (int i = threadIdx.x; i < 16 * 32; i += blockDim.x) {
-            const int bl = i / 32, p = i % 32;
+        for (int i = threadIdx.x; i < KB * KP; i += blockDim.x) {
+            const int bl = i / KP, p = i % KP;
             csl[bl][p] = (bl < nbeta && ab0 + p < NP) ? cs[(size_t)(b0 + bl) * NP + ab0 + p] : 0.f;
         }
         __syncthreads();
     }
-    // eight loads in flight per thread: clamped addresses, values masked afterwards
+    // a thread always handles point ab0 + threadIdx.x % KP (blockDim is a multiple of KP), so its R
+    // weight is loaded once; eight K_chi2 loads in flight per thread (clamped addresses, values masked)
+    static_assert(256 % KP == 0, "point of a thread");
+    const int pt = threadIdx.x % KP, ab = min(ab0 + pt, NP - 1);
+    const double wv = wR[ab % n_R];
     constexpr int U = 8;
-    const int total = 16 * NB * 32;
+    const int total = KB * NB * KP;
     for (int i0 = threadIdx.x; i0 < total; i0 += U * blockDim.x) {
-        double kv[U], wv[U];
+        double kv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int i = min(i0 + u * (int)blockDim.x, total - 1);
-            const int q = i / 32;  // q = beta_local * NB + bin
-            const int bl = min(q / NB, nbeta - 1), bin = min(q % NB, nbins - 1), ab = min(ab0 + i % 32, NP - 1);
-            kv[u] = Kchi2[((size_t)(b0 + bl) * nbins + bin) * NP + ab];
-            wv[u] = wR[ab % n_R];
+            const int q = i / KP;  // q = beta_local * NB + bin
+            const int bl = min(q / NB, nbeta - 1), bin = min(q % NB, nbins - 1);
+            kv[u] = Kchi2[((size_t)(b0 + bl) * nbins + bin) * NP + min(ab0 + i % KP, NP - 1)];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int i = i0 + u * (int)blockDim.x;
-            const int p = i % 32, q = i / 32;
+            const int q = i / KP;
             if (i < total)
-                tile[p][q] = (q / NB < nbeta && q % NB < nbins && ab0 + p < NP) ? (float)(wv[u] * kv[u]) : 0.f;
+                tile[pt][q] = (q / NB < nbeta && q % NB < nbins && ab0 + pt < NP) ? (float)(wv * kv[u]) : 0.f;
         }
     }
     __syncthreads();
     // each point's nbeta * NB weights are contiguous in Kt: 16-byte stores (NB % 4 == 0, so the four
     // values share one cosmology and its power-of-two coefficient scale: exact in FP32)
     const int rq = nbeta * NB / 4;
-    for (int i = threadIdx.x; i < 32 * rq; i += blockDim.x) {
+    for (int i = threadIdx.x; i < KP * rq; i += blockDim.x) {
         const int p = i / rq, q = 4 * (i % rq);
         const float sc = cs ? csl[q / NB][p] : 1.f;
         if (ab0 + p < NP)
@@ -2575,7 +2592,7 @@ void stage_quad_y(blast_plan *p, const blast_cl_args *a, const Ctx &x, const voi
 // stages 2 + 3 fused (mixed precisions without w_save)
 void stage_r_weights(blast_plan *p, const blast_cl_args *a, const Ctx &x, int nb, const float *cs, float *Kt,
                      hipStream_t s) {
-    dim3 gk((unsigned)((p->NP + 31) / 32), (unsigned)((a->batch + 15) / 16));
+    dim3 gk((unsigned)((p->NP + kKtP - 1) / kKtP), (unsigned)((a->batch + kKtB - 1) / kKtB));
     hipLaunchKernelGGL(kt_kernel, gk, dim3(256), 0, s, a->K_chi2, p->d_wR, cs, a->batch, x.nbins, nb, p->NP, p->n_R,
                        Kt);
 }
