@@ -403,7 +403,7 @@ def main():
     dom = max(per_launch, key=per_launch.get)
     roof = roofline(work[dom], per_launch[dom], prec)
     split = "project_split64_kernel" if prec == "fp64" else "project_split_kernel"
-    roof["kernel"] = {"projection": split if cfg.n_cheb % 8 == 0 else "project_mfma_kernel",
+    roof["kernel"] = {"projection": split if cfg.n_cheb % 8 == 0 else "project_kernel",
                       "contraction": ("contract_quad_wide_kernel" if prec == "fp16x3" and cfg.n_g + cfg.n_s <= 16
                                       else "contract_quad_kernel") if fused else "contract_kernel",
                       "quad_R": "quad_y_kernel", "quad_chi": "quad_c_mfma_kernel", "r_weights": "kt_kernel"}[dom]

@@ -89,119 +89,6 @@ __global__ __launch_bounds__(256) void project_kernel(const PT *__restrict__ P, 
     }
 }
 
-// MFMA projection: c[row][n] = sum_j P[row][j] D[n][j], 256 rows per work-group (wave w owns row
-// tiles 4w..4w+3) and every n tile.  FP32: D staged in LDS (rows padded by 16 bytes so the 16
-// rows of one ds_read_b128 fall in distinct banks).  FP64: D read through L1/L2.  The k order
-// inside a tile is a permutation shared by A and B (lane group g supplies j = KSTEP*s + VEC*g + u).
-// Needs N % (4*VEC) == 0.
-template <typename PT, bool F64, int OUT>
-__global__ __launch_bounds__(256) void project_mfma_kernel(const PT *__restrict__ P,
-                                                           const typename std::conditional<F64, double, float>::type
-                                                               *__restrict__ Dn,
-                                                           int N, int ncp, long nrows, void *__restrict__ c_out,
-                                                           uint16_t *__restrict__ c_lo) {
-    using T = typename std::conditional<F64, double, float>::type;
-    using Acc = typename std::conditional<F64, d4, f4>::type;
-    constexpr int VEC = F64 ? 2 : 4;
-    constexpr int KSTEP = 4 * VEC;
-    constexpr int MAXNT = kMaxCheb / 16;
-    constexpr int RT = 4;
-    extern __shared__ __align__(16) unsigned char smem_p[];
-    const int dst = N + 16 / (int)sizeof(T);
-    const T *D = Dn;
-    if constexpr (!F64) {
-        T *Ds = (T *)smem_p;
-        for (int i = threadIdx.x; i < ncp * (N / 4); i += blockDim.x) {
-            const int n = i / (N / 4), q = i % (N / 4);
-            *(float4 *)(Ds + (size_t)n * dst + 4 * q) = *(const float4 *)(Dn + (size_t)n * N + 4 * q);
-        }
-        __syncthreads();
-        D = Ds;
-    }
-    const int ldd = F64 ? N : dst;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int nt = ncp >> 4;
-    const long row0 = (long)blockIdx.x * 256 + 64 * w;
-    Acc acc[RT][MAXNT];
-#pragma unroll
-    for (int r = 0; r < RT; ++r)
-#pragma unroll
-        for (int t = 0; t < MAXNT; ++t) acc[r][t] = Acc{0, 0, 0, 0};
-    for (int s = 0; s < N / KSTEP; ++s) {
-        const int j0 = s * KSTEP + lk * VEC;
-        T av[RT][VEC];
-#pragma unroll
-        for (int r = 0; r < RT; ++r) {
-            const long row = row0 + 16 * r + lr;
-            if (row < nrows) {
-                const PT *pr = P + row * (long)N + j0;
-                if constexpr (sizeof(PT) == 4 && VEC == 4) {
-                    const float4 v = *(const float4 *)pr;
-                    av[r][0] = v.x, av[r][1] = v.y, av[r][2] = v.z, av[r][3] = v.w;
-                } else if constexpr (sizeof(PT) == 8 && VEC == 4) {
-                    const double2 v0 = *(const double2 *)pr, v1 = *(const double2 *)(pr + 2);
-                    av[r][0] = (T)v0.x, av[r][1] = (T)v0.y, av[r][2] = (T)v1.x, av[r][3] = (T)v1.y;
-                } else if constexpr (sizeof(PT) == 8) {
-                    const double2 v = *(const double2 *)pr;
-                    av[r][0] = v.x, av[r][1] = v.y;
-                } else {
-                    const float2 v = *(const float2 *)pr;
-                    av[r][0] = v.x, av[r][1] = v.y;
-                }
-            } else {
-#pragma unroll
-                for (int u = 0; u < VEC; ++u) av[r][u] = (T)0;
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < MAXNT; ++t) {
-            if (t >= nt) break;
-            T bv[VEC];
-            const T *dr = D + (size_t)(16 * t + lr) * ldd + j0;
-            if constexpr (VEC == 4) {
-                const float4 v = *(const float4 *)dr;
-                bv[0] = v.x, bv[1] = v.y, bv[2] = v.z, bv[3] = v.w;
-            } else {
-                const double2 v = *(const double2 *)dr;
-                bv[0] = v.x, bv[1] = v.y;
-            }
-#pragma unroll
-            for (int r = 0; r < RT; ++r)
-#pragma unroll
-                for (int u = 0; u < VEC; ++u) {
-                    if constexpr (F64)
-                        acc[r][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][u], bv[u], acc[r][t], 0, 0, 0);
-                    else
-                        acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][u], bv[u], acc[r][t], 0, 0, 0);
-                }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < RT; ++r)
-#pragma unroll
-        for (int t = 0; t < MAXNT; ++t) {
-            if (t >= nt) break;
-            const int n = 16 * t + lr;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const long row = row0 + 16 * r + (F64 ? lk + 4 * q : 4 * lk + q);
-                if (row >= nrows) continue;
-                const size_t o = (size_t)row * ncp + n;
-                if (OUT == 0) {
-                    ((double *)c_out)[o] = (double)acc[r][t][q];
-                } else if (OUT == 1) {
-                    ((float *)c_out)[o] = (float)acc[r][t][q];
-                } else {
-                    const float v = (float)acc[r][t][q];
-                    const uint16_t h = bf16_rne(v);
-                    ((uint16_t *)c_out)[o] = h;
-                    if (c_lo) c_lo[o] = bf16_rne(v - bf16_val(h));
-                }
-            }
-        }
-}
-
 // FP32 projection for N % 8 == 0, with the even/odd split of the DCT-II.
 // With u_j = P_j + P_{N-1-j} and v_j = P_j - P_{N-1-j} (j < N/2), and D[n][N-1-j] = (-1)^n D[n][j],
 //     c_{2m} = sum_{j<N/2} D[2m][j] u_j,      c_{2m+1} = sum_{j<N/2} D[2m+1][j] v_j,
@@ -2333,8 +2220,6 @@ hipError_t allow_large_lds() {
     std::call_once(once, [] {
         const int lim = 160 * 1024;
         const void *fns[] = {
-            (const void *)project_mfma_kernel<float, false, 1>, (const void *)project_mfma_kernel<float, false, 2>,
-            (const void *)project_mfma_kernel<double, false, 1>, (const void *)project_mfma_kernel<double, false, 2>,
             (const void *)quad_y_kernel<double, 16>, (const void *)quad_y_kernel<double, 32>,
             (const void *)quad_y_kernel<float, 16>, (const void *)quad_y_kernel<float, 32>,
             (const void *)quad_c_mfma_kernel<double, 1>, (const void *)quad_c_mfma_kernel<double, 2>,
@@ -2515,19 +2400,6 @@ void stage_project(blast_plan *p, const blast_cl_args *a, const Ctx &x, void *c,
         if (!p64 && out == 1) by_nt(TypeTag<float>(), I1());
         if (!p64 && out == 2) by_nt(TypeTag<float>(), I2());
         if (!p64 && out == 3) by_nt(TypeTag<float>(), I3());
-    } else if (N % (f64 ? 8 : 16) == 0) {
-        dim3 grid((unsigned)((nrows + 255) / 256));
-        const size_t shp = f64 ? 0 : (size_t)ncp * (N + 4) * sizeof(float);
-#define BLAST_PROJ(PT, F, O, D)                                                                                  \
-    hipLaunchKernelGGL((project_mfma_kernel<PT, F, O>), grid, dim3(256), shp, s, (const PT *)a->P, D, N, ncp, nrows, \
-                       c, clo)
-        if (f64 && p64) BLAST_PROJ(double, true, 0, p->d_dctn64);
-        if (f64 && !p64) BLAST_PROJ(float, true, 0, p->d_dctn64);
-        if (!f64 && p64 && out == 1) BLAST_PROJ(double, false, 1, p->d_dctn32);
-        if (!f64 && p64 && out == 2) BLAST_PROJ(double, false, 2, p->d_dctn32);
-        if (!f64 && !p64 && out == 1) BLAST_PROJ(float, false, 1, p->d_dctn32);
-        if (!f64 && !p64 && out == 2) BLAST_PROJ(float, false, 2, p->d_dctn32);
-#undef BLAST_PROJ
     } else {
         dim3 grid((unsigned)((nrows + kProjRows - 1) / kProjRows));
 #define BLAST_PROJ(PT, AT, O, D) \
