@@ -197,7 +197,11 @@ def _pmask(precisions):
 
 
 class Plan:
-    """Grids plus the resident basis of Eq. t_tilde on one GPU."""
+    """Grids plus the resident basis of Eq. t_tilde on one GPU.
+
+    `precisions` lists the contraction arithmetics kept resident ("fp64" is always built):
+    "fp64"; "fp32"; "fp16x3" (FP16 hi + lo parts with power-of-two row scales, the fastest path
+    inside 1e-3; fused path only: at most 20 bins, no w_save, no adjoint); "bf16x3"; "bf16"."""
 
     def __init__(self, ell, chi, w_chi, R, w_R, k_min, k_max, n_cheb, *, types=7,
                  precisions=("fp64",), kq_panels=0, kq_phase=0.0, device=0):
