@@ -573,6 +573,9 @@ def main():
                    "batch": Bn, "precision": prec, "basis_build_s": build_s, "kq_nodes": plan.kq_nodes},
         "roofline": roof,
         "cpu_baseline": cpu,
+        # the paper's own timing, as context only: another grid (N5K fiducial), another machine
+        "paper_context": {"ms_per_set": 3.60, "sets_per_s": 278, "precision": "f64",
+                          "hardware": "2x AMD EPYC 7532, 32 threads (CPU)", "grid": "N5K fiducial, not config 2"},
     }
     line.update(err)
     line.update(extras)
