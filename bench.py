@@ -327,7 +327,7 @@ def main():
                     help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (asked for %d)" % args.gpus,
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (asked for %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 

@@ -50,7 +50,7 @@ typedef enum {
     BLAST_E_INVALID = 1,     /* bad argument, shape or grid                      */
     BLAST_E_OOM = 2,         /* device or host allocation failed / over budget   */
     BLAST_E_HIP = 3,         /* a HIP runtime call failed                        */
-    BLAST_E_UNSUPPORTED = 4, /* valid request this build does not implement      */
+    BLAST_E_UNSUPPORTED = 4, /* valid request the library does not implement   */
     BLAST_E_BUSY = 5,        /* server queue full                                */
     BLAST_E_CANCELLED = 6    /* request cancelled                                */
 } blast_status;
