@@ -19,7 +19,7 @@ MAXG, MAXS = 4, 3
 @pytest.fixture(scope="module")
 def env():
     cfg = W.tiny_config(n_ell=24, ell_max=120, n_chi=16, n_R=12, n_cheb=32, k_max=0.8, n_g=MAXG, n_s=MAXS)
-    plan = B.plan_for_config(cfg, precisions=("fp64", "fp32"))
+    plan = B.plan_for_config(cfg, precisions=("fp64", "fp32", "fp16x3"))
     chi, chi2 = plan.eval_points()
     Kchi, Kchi2 = W.kernels(W.bins_of(cfg), chi, chi2)
     rng = np.random.default_rng(12)
@@ -46,7 +46,7 @@ def _direct(plan, req, precision, pdt):
 
 
 @pytest.mark.parametrize("precision,pdt,graphs", [("fp64", "fp64", True), ("fp32", "fp32", True),
-                                                  ("fp32", "fp32", False)])
+                                                  ("fp32", "fp32", False), ("fp16x3", "fp32", True)])
 def test_server_results_equal_direct_forward(env, precision, pdt, graphs):
     cfg, plan, reqs = env
     npdt = np.float64 if pdt == "fp64" else np.float32
@@ -66,7 +66,7 @@ def test_server_results_equal_direct_forward(env, precision, pdt, graphs):
         assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max()), np.abs(got - ref).max()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16x3"])
 def test_result_same_alone_and_in_the_mix(env, precision):
     cfg, plan, reqs = env
     pdt = np.float64 if precision == "fp64" else np.float32
