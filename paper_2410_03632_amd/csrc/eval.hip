@@ -803,7 +803,8 @@ __global__ __launch_bounds__(256) void quad_y_kernel(const T *__restrict__ w, co
     for (int r = 0; r < V; ++r)
 #pragma unroll
         for (int q = 0; q < NB; ++q) acc[r][q] = (T)0;
-    constexpr int UB = 4;
+    // UB loads of w in flight; the weights of a b read 16 bytes at a time (NB is a multiple of 4)
+    constexpr int UB = sizeof(T) == 8 ? 8 : 4, KV = 16 / sizeof(T);
     int b = 0;
     for (; b + UB <= nR; b += UB) {
         U4 v[UB];
@@ -813,10 +814,13 @@ __global__ __launch_bounds__(256) void quad_y_kernel(const T *__restrict__ w, co
         for (int u = 0; u < UB; ++u) {
             const T *wv = (const T *)&v[u];
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                const T k = kh[(b + u) * NB + q];
+            for (int q0 = 0; q0 < NB; q0 += KV) {
+                const U4 kk = *(const U4 *)(kh + (b + u) * NB + q0);
+                const T *k = (const T *)&kk;
 #pragma unroll
-                for (int r = 0; r < V; ++r) acc[r][q] += wv[r] * k;
+                for (int q = 0; q < KV; ++q)
+#pragma unroll
+                    for (int r = 0; r < V; ++r) acc[r][q0 + q] += wv[r] * k[q];
             }
         }
     }
