@@ -38,11 +38,13 @@ def stage_work(plan, cfg, prec, batch):
 
     projection : c = D P as the even/odd split DCT (two [N/2 x N/2] products per point): N^2
                  flops per (point, set); P read, c written once.
-    contraction: FP64 path: w = Ttilde c, basis read once per launch, c read, w written.
-                 Mixed paths: fused with the R-quadrature (w stays in registers): basis and c
-                 read, weighted kernels Kt written and read (from K_chi2), Y written; flops of
-                 the contraction plus those of the R-sum.
-    quad_R     : FP64 path only: w and K_chi2 read, Y written.
+    contraction: fused with the R-quadrature (w stays in registers; mixed paths, and the FP64
+                 path at batches of 32 or more with at most 16 bins): basis and c read, weighted
+                 kernels Kt written and read (from K_chi2; FP32 with the bins rounded up to a
+                 multiple of 4, FP64 16 wide), Y written; flops of the contraction plus those of
+                 the R-sum.  Unfused FP64: w = Ttilde c, basis read once per launch, c read, w
+                 written.
+    quad_R     : unfused FP64 only: w and K_chi2 read, Y written.
     quad_chi   : Y read, C written (negligible)."""
     NP = cfg.n_chi * cfg.n_R
     N = cfg.n_cheb
@@ -61,7 +63,7 @@ def stage_work(plan, cfg, prec, batch):
     quad_chi = dict(flops=4.0 * cfg.n_chi * plan.n_ell * B_pairs(cfg) * batch,
                     bytes=float(cfg.n_chi * rows_pad * nbp * ew * batch))
     y_bytes = float(cfg.n_chi * rows_pad * nbp * ew * batch)
-    if prec == "fp64":
+    if prec == "fp64" and not fused_path(prec, nb, batch):
         return {
             "projection": proj,
             "contraction": dict(flops=2.0 * rows * N * NP * batch,
@@ -71,14 +73,26 @@ def stage_work(plan, cfg, prec, batch):
             "quad_chi": quad_chi,
         }
     nbf = (nb + 3) // 4 * 4
+    ek = 4  # weights table bytes per element
+    if prec == "fp64":
+        nbf, ek = 16, 8
     return {
         "projection": proj,
         "r_weights": dict(flops=float(nb * NP * batch),
-                          bytes=float(nb * NP * 8 * batch + NP * nbf * 4 * batch + NP * es * batch)),
+                          bytes=float(nb * NP * 8 * batch + NP * nbf * ek * batch + NP * es * batch)),
         "contraction": dict(flops=2.0 * rows * N * NP * batch + 2.0 * rows_bins * NP * batch,
-                            bytes=float(NP * rows * N * eb + NP * N * ec * batch + NP * nbf * 4 * batch) + y_bytes),
+                            bytes=float(NP * rows * N * eb + NP * N * ec * batch + NP * nbf * ek * batch) + y_bytes),
         "quad_chi": quad_chi,
     }
+
+
+def fused_path(prec, nbins, batch):
+    """Whether the library runs the contraction fused with the R-quadrature (no w_save): the
+    mixed paths with at most 20 bins (FP16X3 at any batch, the others from batch 32), the FP64
+    path with at most 16 bins from batch 32."""
+    if prec == "fp64":
+        return nbins <= 16 and batch >= 32
+    return nbins <= 20 and (batch >= 32 or prec == "fp16x3")
 
 
 def B_pairs(cfg):
@@ -393,7 +407,7 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = Bn / (ms_per_step * 1e-3)
     per_launch = {k: v / max(ncalls, 1) for k, v in stage_ms.items()}
-    fused = prec != "fp64"
+    fused = fused_path(prec, cfg.n_g + cfg.n_s, Bn)
     if fused:
         # intervals of the fused path: R-quadrature weights, then contraction + R-quadrature
         per_launch = {"projection": per_launch["projection"], "r_weights": per_launch["contraction"],
@@ -404,8 +418,9 @@ def main():
     roof = roofline(work[dom], per_launch[dom], prec)
     split = "project_split64_kernel" if prec == "fp64" else "project_split_kernel"
     roof["kernel"] = {"projection": split if cfg.n_cheb % 8 == 0 else "project_kernel",
-                      "contraction": ("contract_quad_wide_kernel" if prec == "fp16x3" and cfg.n_g + cfg.n_s <= 16
-                                      else "contract_quad_kernel") if fused else "contract_kernel",
+                      "contraction": (("contract_quad_f64_kernel" if prec == "fp64" else
+                                       "contract_quad_wide_kernel" if prec == "fp16x3" and cfg.n_g + cfg.n_s <= 16
+                                       else "contract_quad_kernel") if fused else "contract_kernel"),
                       "quad_R": "quad_y_kernel", "quad_chi": "quad_c_mfma_kernel", "r_weights": "kt_kernel"}[dom]
     roof["traffic"] = counter_traffic(roof["kernel"], cfg.name, Bn, prec)
     roof["stage_ms_per_launch"] = per_launch

@@ -1648,18 +1648,204 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
     }
 }
 
-// Kt[a, b][beta][bin] = wR_b K_bin(R_b chi_a) (FP32, NB bins with zero padding) for the fused
-// kernel.  A work-group transposes 64 points x 8 cosmologies through LDS: coalesced 512-byte reads
-// along the points, 512-byte contiguous writes per point.
-// With cs (FP16 coefficients) the weights also carry the coefficient row scale cs[beta][a, b], which
-// the contraction of the scaled coefficients leaves out.
-constexpr int kKtP = 64, kKtB = 8;  // points x cosmologies per work-group of kt_kernel
+// FP64 fused contraction and R-quadrature (no w_save, at most 16 bins): the FP64 path's w, like
+// the mixed paths', never leaves the registers of the wave that makes it.
+//   w[row][beta]          = sum_n Ttilde[a, b][row][n] c[beta][a, b][n]     (v_mfma_f64_16x16x4_f64)
+//   Y[beta][row][a][bin] += w[row][beta] * Kt[a, b][beta][bin]            (FP64 FMA, per b)
+// Work-group = (chi_a, 64 cosmologies, 2 row tiles), 8 waves: wave (i, j) makes the 16 x 16 tile
+// (row tile i, cosmologies 16j..16j+15) and keeps Y for its 4 rows x NB bins in FP64.  Each b is
+// taken in NSTG stages of KS Chebyshev columns; a stage's 32 basis row slices and 64 c row slices
+// go from global memory straight to LDS (two buffers, one stage ahead, one barrier per stage), the
+// weights of b (16 bins, zero padded) with b's first stage.  Rows sit in LDS with their 16-byte
+// granules permuted (granule g of row r at g ^ (r & 15)) so that the 16 rows one instruction reads
+// fall in distinct banks.  A lane reads two consecutive columns at once and feeds them to two
+// MFMAs (two accumulator chains): lane group lk takes columns 8p + 2lk and 8p + 2lk + 1 of each
+// group p of 8, so the two MFMAs of p together cover its 8 columns once.
+constexpr int kF64TR = 2;
+
+template <int KS>
+struct F64Shape {
+    static constexpr int ROWB = KS * 8;   // bytes of one row's slice in a stage
+    static constexpr int GR = ROWB / 16;  // 16-byte granules per slice
+    static constexpr int RPC = 1024 / ROWB;  // slices per 1 KB chunk
+    static constexpr int NW = 8;
+    static constexpr int A_CH = kF64TR * 16 / RPC, C_CH = 64 / RPC;
+    static constexpr int A_PW = A_CH / NW, C_PW = C_CH / NW;
+    static constexpr size_t A_BUF = (size_t)A_CH * 1024, C_BUF = (size_t)C_CH * 1024, K_BUF = 8 * 1024;
+    static_assert(A_PW * NW == A_CH && C_PW * NW == C_CH, "whole chunks per wave");
+};
+
+// eight 16-byte reads (four at bases a[k], four at c[k], one compile-time offset), then a wait
+template <int O>
+__device__ inline void lds_read8(const uint32_t (&a)[4], const uint32_t (&c)[4], U4 (&ra)[4], U4 (&rc)[4]) {
+    asm volatile(
+        "ds_read_b128 %0, %8 offset:%16\n\tds_read_b128 %1, %9 offset:%16\n\t"
+        "ds_read_b128 %2, %10 offset:%16\n\tds_read_b128 %3, %11 offset:%16\n\t"
+        "ds_read_b128 %4, %12 offset:%16\n\tds_read_b128 %5, %13 offset:%16\n\t"
+        "ds_read_b128 %6, %14 offset:%16\n\tds_read_b128 %7, %15 offset:%16\n\ts_waitcnt lgkmcnt(0)"
+        : "=&v"(ra[0]), "=&v"(ra[1]), "=&v"(ra[2]), "=&v"(ra[3]), "=&v"(rc[0]), "=&v"(rc[1]), "=&v"(rc[2]),
+          "=&v"(rc[3])
+        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "i"(O)
+        : "memory");
+}
+
+template <int NB, int KS, int NSTG>
+__global__ __launch_bounds__(512) void contract_quad_f64_kernel(const double *__restrict__ basis,
+                                                                const double *__restrict__ c,
+                                                                const double *__restrict__ Kt, int batch, int n_chi,
+                                                                int n_R, int rows_pad, int nBT, int units,
+                                                                double *__restrict__ Y) {
+    using S = F64Shape<KS>;
+    constexpr int ncp = KS * NSTG, NBK = 16, TR = kF64TR;
+    static_assert(NB % 4 == 0 && NB <= NBK && KS % 32 == 0, "shape of the FP64 fused kernel");
+    __shared__ __align__(1024) unsigned char A0[S::A_BUF], A1[S::A_BUF], C0[S::C_BUF], C1[S::C_BUF];
+    __shared__ __align__(1024) unsigned char K0[S::K_BUF], K1[S::K_BUF];
+
+    const int RT = rows_pad / 16;
+    const int groups = (RT + TR - 1) / TR;
+    const int per = (units + 7) / 8;
+    const int unit = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (unit >= units) return;  // uniform over the work-group
+    const int g = unit % groups, bt = (unit / groups) % nBT, a = unit / (groups * nBT);
+    const int rt0 = g * TR;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int ti = w >> 2, tj = w & 3;  // row tile, 16-cosmology tile
+    const int nb = min(64, batch - bt * 64);
+    const size_t NP = (size_t)n_chi * n_R;
+    const bool busy = rt0 + ti < RT && 16 * tj < nb;
+
+    // DMA sources at b = 0, stage 0 (element offsets); rows past the end read the last valid row
+    size_t srcA[S::A_PW], srcC[S::C_PW];
+#pragma unroll
+    for (int k = 0; k < S::A_PW; ++k) {
+        const int row = (w + k * S::NW) * S::RPC + lane / S::GR, gr = (lane % S::GR) ^ (row & 15);
+        const int rt = min(rt0 + row / 16, RT - 1);
+        srcA[k] = ((size_t)a * n_R * rows_pad + 16 * rt + row % 16) * ncp + 2 * gr;
+    }
+#pragma unroll
+    for (int k = 0; k < S::C_PW; ++k) {
+        const int row = (w + k * S::NW) * S::RPC + lane / S::GR, gr = (lane % S::GR) ^ (row & 15);
+        const size_t beta = (size_t)bt * 64 + min(row, nb - 1);
+        srcC[k] = (beta * NP + (size_t)a * n_R) * ncp + 2 * gr;
+    }
+    // weights: chunk w holds cosmologies 8w..8w+7 (128 bytes each), granule gk of cosmology cr in
+    // slot (gk + cr / 2) % 8, so that the 16 cosmologies of a read fall in distinct banks
+    size_t srcK;
+    {
+        const int cr = w * 8 + lane / 8, gk = (lane % 8 - (cr >> 1)) & 7;
+        srcK = ((size_t)a * n_R * batch + (size_t)bt * 64 + min(cr, nb - 1)) * NBK + 2 * gk;
+    }
+    auto dma = [&](int idx) {
+        const int b = idx / NSTG, s = idx % NSTG;
+        unsigned char *Ab = (idx & 1) ? A1 : A0, *Cb = (idx & 1) ? C1 : C0;
+        const size_t offA = (size_t)b * rows_pad * ncp + (size_t)s * KS, offC = (size_t)b * ncp + (size_t)s * KS;
+#pragma unroll
+        for (int k = 0; k < S::A_PW; ++k) lds_dma16(basis + srcA[k] + offA, Ab + (size_t)(w + k * S::NW) * 1024);
+#pragma unroll
+        for (int k = 0; k < S::C_PW; ++k) lds_dma16(c + srcC[k] + offC, Cb + (size_t)(w + k * S::NW) * 1024);
+        if (s == 0) lds_dma16(Kt + srcK + (size_t)b * batch * NBK, ((b & 1) ? K1 : K0) + (size_t)w * 1024);
+    };
+
+    // LDS read offsets of the lane: pair p of a group of 4 (32 columns) at granule 4p + lk
+    uint32_t offA[4], offC[4], offK[NB / 2];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const uint32_t gp = 16u * (4u * (uint32_t)(p ^ (lr >> 2)) + (uint32_t)((lk ^ lr) & 3));
+        offA[p] = (uint32_t)(16 * ti + lr) * S::ROWB + gp;
+        offC[p] = (uint32_t)(16 * tj + lr) * S::ROWB + gp;
+    }
+    {
+        const int cr = 16 * tj + lr;
+#pragma unroll
+        for (int q = 0; q < NB / 2; ++q) offK[q] = (uint32_t)cr * (NBK * 8) + 16u * (uint32_t)((q + (cr >> 1)) & 7);
+    }
+
+    double y[4][NB];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) y[r][q] = 0.0;
+    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+
+    const int total = n_R * NSTG;
+    dma(0);
+    for (int idx = 0; idx < total; ++idx) {
+        // this wave's DMAs of stage idx have landed, then every wave's (barrier)
+        wait_vmcnt<0>();
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        if (idx + 1 < total) dma(idx + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        if (!busy) continue;
+        const uint32_t ab = lds_addr((idx & 1) ? A1 : A0), cb = lds_addr((idx & 1) ? C1 : C0);
+        uint32_t ra[4], rc[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) ra[p] = ab + offA[p], rc[p] = cb + offC[p];
+        auto group = [&](auto gc) {
+            constexpr int G = decltype(gc)::value;
+            U4 xa[4], xc[4];
+            lds_read8<256 * G>(ra, rc, xa, xc);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const d2v av = __builtin_bit_cast(d2v, xa[p]), cv = __builtin_bit_cast(d2v, xc[p]);
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], cv[0], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], cv[1], acc1, 0, 0, 0);
+            }
+        };
+        static_for<0, KS / 32>(group);
+        if (idx % NSTG == NSTG - 1) {
+            // R-sum of b: lane holds w of rows lk + 4r of its row tile for cosmology 16 tj + lr
+            const uint32_t kb = lds_addr(((idx / NSTG) & 1) ? K1 : K0);
+            double kt[NB];
+#pragma unroll
+            for (int q0 = 0; q0 < NB / 2; q0 += 2) {
+                U4 k0, k1;
+                lds_read2<0, 0>(kb + offK[q0], kb + offK[q0 + 1], k0, k1);
+                const d2v v0 = __builtin_bit_cast(d2v, k0), v1 = __builtin_bit_cast(d2v, k1);
+                kt[2 * q0] = v0[0], kt[2 * q0 + 1] = v0[1], kt[2 * q0 + 2] = v1[0], kt[2 * q0 + 3] = v1[1];
+            }
+            const d4 wv = acc0 + acc1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int q = 0; q < NB; ++q) y[r][q] = fma(wv[r], kt[q], y[r][q]);
+            acc0 = d4{0, 0, 0, 0};
+            acc1 = d4{0, 0, 0, 0};
+        }
+    }
+    wait_vmcnt<0>();  // no DMA may outlive the work-group's LDS
+    const int beta = bt * 64 + 16 * tj + lr;
+    if (!busy || beta >= batch) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (rt0 + ti) + lk + 4 * r;
+        double *yp = Y + (((size_t)beta * rows_pad + row) * n_chi + a) * NBK;
+#pragma unroll
+        for (int q = 0; q < NBK; q += 2) {
+            double2 v = make_double2(0.0, 0.0);
+            if (q < NB) v = make_double2(y[r][q], y[r][q + 1]);
+            *(double2 *)(yp + q) = v;
+        }
+    }
+}
+
+// Kt[a, b][beta][bin] = wR_b K_bin(R_b chi_a) (T = float or double, NB bins with zero padding) for
+// the fused kernels.  A work-group transposes 64 points x KB cosmologies through LDS: coalesced
+// 512-byte reads along the points, contiguous writes per point.
+// With cs (FP16 coefficients, T = float) the weights also carry the coefficient row scale
+// cs[beta][a, b], which the contraction of the scaled coefficients leaves out.
+constexpr int kKtP = 64;  // points per work-group of kt_kernel
+template <typename T>
+constexpr int kt_cosmologies() { return sizeof(T) == 8 ? 4 : 8; }  // cosmologies per work-group
+
+template <typename T>
 __global__ __launch_bounds__(256) void kt_kernel(const double *__restrict__ Kchi2, const double *__restrict__ wR,
                                                  const float *__restrict__ cs, int batch, int nbins, int NB, int NP,
-                                                 int n_R, float *__restrict__ Kt) {
-    constexpr int KP = kKtP, KB = kKtB;
-    __shared__ float tile[KP][KB * 20 + 1];  // [point][beta_local * NB + bin], NB <= 20
-    __shared__ float csl[KB][KP];            // coefficient row scales [beta_local][point]
+                                                 int n_R, T *__restrict__ Kt) {
+    constexpr int KP = kKtP, KB = kt_cosmologies<T>();
+    __shared__ T tile[KP][KB * 20 + 1];  // [point][beta_local * NB + bin], NB <= 20
+    __shared__ float csl[KB][KP];        // coefficient row scales [beta_local][point]
     const int ab0 = blockIdx.x * KP, b0 = blockIdx.y * KB;
     const int nbeta = min(KB, batch - b0);
     if (cs) {
@@ -1690,19 +1876,25 @@ __global__ __launch_bounds__(256) void kt_kernel(const double *__restrict__ Kchi
             const int i = i0 + u * (int)blockDim.x;
             const int q = i / KP;
             if (i < total)
-                tile[pt][q] = (q / NB < nbeta && q % NB < nbins && ab0 + pt < NP) ? (float)(wv * kv[u]) : 0.f;
+                tile[pt][q] = (q / NB < nbeta && q % NB < nbins && ab0 + pt < NP) ? (T)(wv * kv[u]) : (T)0;
         }
     }
     __syncthreads();
-    // each point's nbeta * NB weights are contiguous in Kt: 16-byte stores (NB % 4 == 0, so the four
-    // values share one cosmology and its power-of-two coefficient scale: exact in FP32)
+    // each point's nbeta * NB weights are contiguous in Kt: four values per thread (NB % 4 == 0, so
+    // the four share one cosmology and its power-of-two coefficient scale: exact in FP32)
     const int rq = nbeta * NB / 4;
     for (int i = threadIdx.x; i < KP * rq; i += blockDim.x) {
         const int p = i / rq, q = 4 * (i % rq);
-        const float sc = cs ? csl[q / NB][p] : 1.f;
-        if (ab0 + p < NP)
-            *(float4 *)(Kt + ((size_t)(ab0 + p) * batch + b0) * NB + q) =
+        if (ab0 + p >= NP) continue;
+        T *o = Kt + ((size_t)(ab0 + p) * batch + b0) * NB + q;
+        if constexpr (sizeof(T) == 8) {
+            *(double2 *)o = make_double2(tile[p][q], tile[p][q + 1]);
+            *(double2 *)(o + 2) = make_double2(tile[p][q + 2], tile[p][q + 3]);
+        } else {
+            const float sc = cs ? csl[q / NB][p] : 1.f;
+            *(float4 *)o =
                 make_float4(tile[p][q] * sc, tile[p][q + 1] * sc, tile[p][q + 2] * sc, tile[p][q + 3] * sc);
+        }
     }
 }
 
@@ -2468,9 +2660,10 @@ void stage_quad_y(blast_plan *p, const blast_cl_args *a, const Ctx &x, const voi
 // stages 2 + 3 fused (mixed precisions without w_save)
 void stage_r_weights(blast_plan *p, const blast_cl_args *a, const Ctx &x, int nb, const float *cs, float *Kt,
                      hipStream_t s) {
-    dim3 gk((unsigned)((p->NP + kKtP - 1) / kKtP), (unsigned)((a->batch + kKtB - 1) / kKtB));
-    hipLaunchKernelGGL(kt_kernel, gk, dim3(256), 0, s, a->K_chi2, p->d_wR, cs, a->batch, x.nbins, nb, p->NP, p->n_R,
-                       Kt);
+    constexpr int KB = kt_cosmologies<float>();
+    dim3 gk((unsigned)((p->NP + kKtP - 1) / kKtP), (unsigned)((a->batch + KB - 1) / KB));
+    hipLaunchKernelGGL(kt_kernel<float>, gk, dim3(256), 0, s, a->K_chi2, p->d_wR, cs, a->batch, x.nbins, nb, p->NP,
+                       p->n_R, Kt);
 }
 
 void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, int nb, const void *c,
@@ -2535,6 +2728,47 @@ void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, in
     if (x.prec == BLAST_FP16X3) by_nb(std::integral_constant<int, BLAST_FP16X3>());
 }
 
+// FP64 stages 2 + 3 fused: without w_save, at most 16 bins, batches of kFusedMinBatch or more
+bool fused_f64(int nbins, int batch) { return nbins <= 16 && batch >= kFusedMinBatch; }
+
+// the FP64 weights table Kt[a, b][beta][16] (bins past nbins zero)
+void stage_r_weights64(blast_plan *p, const blast_cl_args *a, const Ctx &x, double *Kt, hipStream_t s) {
+    constexpr int KB = kt_cosmologies<double>();
+    dim3 gk((unsigned)((p->NP + kKtP - 1) / kKtP), (unsigned)((a->batch + KB - 1) / KB));
+    hipLaunchKernelGGL(kt_kernel<double>, gk, dim3(256), 0, s, a->K_chi2, p->d_wR, (const float *)nullptr,
+                       a->batch, x.nbins, 16, p->NP, p->n_R, Kt);
+}
+
+void stage_contract_quad_f64(blast_plan *p, const blast_cl_args *a, const Ctx &x, const void *c, const double *Kt,
+                             double *Y, hipStream_t s) {
+    const int RT = p->rows_pad / 16, nBT = (a->batch + 63) / 64;
+    const int units = p->n_chi * nBT * ((RT + kF64TR - 1) / kF64TR);
+    const unsigned grid = (unsigned)((units + 7) / 8 * 8);
+    auto launch = [&](auto nbtag, auto kstag, auto nstag) {
+        constexpr int NB = decltype(nbtag)::value, KS = decltype(kstag)::value, NSTG = decltype(nstag)::value;
+        hipLaunchKernelGGL((contract_quad_f64_kernel<NB, KS, NSTG>), dim3(grid), dim3(512), 0, s, p->basis.f64,
+                           (const double *)c, Kt, a->batch, p->n_chi, p->n_R, p->rows_pad, nBT, units, Y);
+    };
+    using I32 = std::integral_constant<int, 32>;
+    using I64 = std::integral_constant<int, 64>;
+    using S1 = std::integral_constant<int, 1>;
+    // nc_pad is a multiple of 32 up to 128: stages of 64 columns where they divide it, else 32
+    auto by_ncp = [&](auto nbtag) {
+        switch (p->nc_pad / 32) {
+            case 1: launch(nbtag, I32(), S1()); break;
+            case 2: launch(nbtag, I64(), S1()); break;
+            case 3: launch(nbtag, I32(), std::integral_constant<int, 3>()); break;
+            default: launch(nbtag, I64(), std::integral_constant<int, 2>()); break;
+        }
+    };
+    switch ((x.nbins + 3) / 4) {
+        case 1: by_ncp(std::integral_constant<int, 4>()); break;
+        case 2: by_ncp(std::integral_constant<int, 8>()); break;
+        case 3: by_ncp(std::integral_constant<int, 12>()); break;
+        default: by_ncp(std::integral_constant<int, 16>()); break;
+    }
+}
+
 // stage 4: C = chi-quadrature and pair assembly
 void stage_quad_c(blast_plan *p, const blast_cl_args *a, const Ctx &x, const void *Y, hipStream_t s) {
     Slots st{{p->tslot_type[0], p->tslot_type[1], p->tslot_type[2]}};
@@ -2576,6 +2810,7 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     void *w = need_w ? (void *)(ws + L.w) : a->w_save;
     void *Y = ws + L.y;
     const int fnb = need_w ? fused_nb(x.prec, x.nbins, a->batch) : 0;
+    const bool f64f = need_w && x.prec == BLAST_FP64 && fused_f64(x.nbins, a->batch);
     mark(0);
     stage_project(p, a, x, c, clo, cs, s);
     mark(1);
@@ -2584,6 +2819,10 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
         stage_r_weights(p, a, x, fnb, cs, (float *)(ws + L.kt), s);
         mark(2);
         stage_contract_quad(p, a, x, fnb, c, clo, (float *)(ws + L.kt), (float *)Y, s);
+    } else if (f64f) {
+        stage_r_weights64(p, a, x, (double *)(ws + L.kt), s);
+        mark(2);
+        stage_contract_quad_f64(p, a, x, c, (const double *)(ws + L.kt), (double *)Y, s);
     } else {
         stage_contract(p, a, x, c, clo, w, s);
         mark(2);

@@ -1,5 +1,5 @@
 """Host logic of bench.py (no GPU): the one-GPU refusal, the roofline's choice of roof, the
-per-stage algorithmic bytes and flops of the precisions, and the rule that counter traffic is
+per-stage algorithmic bytes and flops of the precisions and paths, and the rule that counter traffic is
 reported only for the kernel source it was measured on."""
 import hashlib
 import json
@@ -56,9 +56,20 @@ def test_stage_work_of_the_precisions():
     assert w16["contraction"]["flops"] == w32["contraction"]["flops"]
     assert w16["projection"]["bytes"] - w32["projection"]["bytes"] == NP * 4 * B
     assert w16["r_weights"]["bytes"] - w32["r_weights"]["bytes"] == NP * 4 * B
-    # contraction: 2 flops per (row, Chebyshev node, point, set); basis read once per launch
-    assert w64["contraction"]["flops"] == 2.0 * 288 * N * NP * B
+    # contraction: 2 flops per (row, Chebyshev node, point, set), plus the R-sum's where it is
+    # fused; basis read once per launch
+    rows_bins = 96 * (10 + 15 + 5)
+    assert w64["contraction"]["flops"] == 2.0 * 288 * N * NP * B + 2.0 * rows_bins * NP * B
+    assert w32["contraction"]["flops"] == w64["contraction"]["flops"]
     assert w32["contraction"]["bytes"] > NP * 288 * N * 4
+    # the FP64 weights table is 16 wide in FP64, the FP32 one 16 wide (15 bins rounded up) in FP32
+    assert w64["r_weights"]["bytes"] - w32["r_weights"]["bytes"] == NP * 16 * 4 * B
+    # below batch 32 the FP64 path keeps w in memory and sums it in a separate stage
+    u64 = bench.stage_work(plan, cfg, "fp64", 16)
+    assert "r_weights" not in u64 and u64["contraction"]["flops"] == 2.0 * 288 * N * NP * 16
+    assert u64["quad_R"]["flops"] == 2.0 * rows_bins * NP * 16
+    assert bench.fused_path("fp64", 16, 32) and not bench.fused_path("fp64", 17, 256)
+    assert bench.fused_path("fp16x3", 20, 1) and not bench.fused_path("fp32", 20, 31)
     # the even/odd split halves the projection's products when N % 8 == 0
     plan, cfg7 = _shapes(n_cheb=100)
     assert bench.stage_work(plan, cfg, "fp32", B)["projection"]["flops"] * 2 == pytest.approx(
