@@ -1698,8 +1698,13 @@ __global__ __launch_bounds__(512) void contract_quad_f64_kernel(const double *__
     using S = F64Shape<KS>;
     constexpr int ncp = KS * NSTG, NBK = 16, TR = kF64TR;
     static_assert(NB % 4 == 0 && NB <= NBK && KS % 32 == 0, "shape of the FP64 fused kernel");
-    __shared__ __align__(1024) unsigned char A0[S::A_BUF], A1[S::A_BUF], C0[S::C_BUF], C1[S::C_BUF];
-    __shared__ __align__(1024) unsigned char K0[S::K_BUF], K1[S::K_BUF];
+    // two stage buffers of basis and c slices, two of weights; after the last stage the first
+    // 64 KB hold the Y tiles on their way out (8 KB per wave)
+    __shared__ __align__(1024) unsigned char lds[2 * (S::A_BUF + S::C_BUF + S::K_BUF)];
+    static_assert(2 * (S::A_BUF + S::C_BUF + S::K_BUF) >= 64 * 1024, "room for the Y tiles");
+    unsigned char *const A0 = lds, *const A1 = lds + S::A_BUF;
+    unsigned char *const C0 = lds + 2 * S::A_BUF, *const C1 = C0 + S::C_BUF;
+    unsigned char *const K0 = C1 + S::C_BUF, *const K1 = K0 + S::K_BUF;
 
     const int RT = rows_pad / 16;
     const int groups = (RT + TR - 1) / TR;
@@ -1815,18 +1820,31 @@ __global__ __launch_bounds__(512) void contract_quad_f64_kernel(const double *__
         }
     }
     wait_vmcnt<0>();  // no DMA may outlive the work-group's LDS
-    const int beta = bt * 64 + 16 * tj + lr;
-    if (!busy || beta >= batch) return;
+    // Y rows are 128 bytes ([beta][row][a][16 bins]) and a lane holds 4 of them: they go out
+    // through LDS so that each store instruction writes 8 whole rows (16 bytes per lane) rather
+    // than 16 bytes of 64 rows.  Every wave has finished its last stage's reads past this barrier.
+    __syncthreads();
+    if (!busy) return;
+    double *tile = (double *)(lds + (size_t)w * 8192);  // [cosmology lr][row lk][16 bins]
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int row = 16 * (rt0 + ti) + lk + 4 * r;
-        double *yp = Y + (((size_t)beta * rows_pad + row) * n_chi + a) * NBK;
 #pragma unroll
         for (int q = 0; q < NBK; q += 2) {
             double2 v = make_double2(0.0, 0.0);
             if (q < NB) v = make_double2(y[r][q], y[r][q + 1]);
-            *(double2 *)(yp + q) = v;
+            *(double2 *)(tile + (lr * 4 + lk) * NBK + q) = v;
         }
+        // LDS accesses of a wave complete in order; the asm keeps the compiler from moving the
+        // reads of other lanes' rows above these writes (and the next pass's writes above them)
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int line = 8 * i + lane / 8, ch = lane % 8;  // line = 4 * cosmology + row
+            const int beta = bt * 64 + 16 * tj + line / 4, row = 16 * (rt0 + ti) + line % 4 + 4 * r;
+            const double2 v = *(const double2 *)(tile + line * NBK + 2 * ch);
+            if (beta < batch) *(double2 *)(Y + (((size_t)beta * rows_pad + row) * n_chi + a) * NBK + 2 * ch) = v;
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     }
 }
 
