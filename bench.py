@@ -492,6 +492,29 @@ def main():
             extras["fp32_path"] = f32
             step()  # out holds the timed path's result again
             torch.cuda.synchronize()
+        # differentiation at the same batch (FP32): a forward that keeps w, then the adjoint from
+        # dC = dL/dC to the gradients with respect to P at the nodes, K_chi and K_chi2
+        P32 = P if P.dtype == torch.float32 else P.float()
+        wg = torch.empty(Bn * cfg.n_chi * cfg.n_R * plan.rows_pad, dtype=torch.float32, device=dev)
+        outg = torch.empty_like(out)
+        dC = torch.ones_like(out)
+
+        def grad_step():
+            plan.forward(P32, K1, K2, cfg.n_g, cfg.n_s, precision="fp32", out=outg, w_save=wg)
+            return plan.backward(P32, K1, K2, cfg.n_g, cfg.n_s, dC, precision="fp32", w_save=wg)
+
+        for _ in range(2):
+            grad_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            grads = grad_step()
+        torch.cuda.synchronize()
+        msg = (time.perf_counter() - t0) * 1e3 / 5
+        extras["gradient_fp32"] = {"batch": Bn, "ms_per_step": msg, "sets_per_s": Bn / (msg * 1e-3),
+                                   "finite": bool(all(torch.isfinite(g).all().item() for g in grads)),
+                                   "what": "forward keeping w + adjoint: dC -> dP (nodal), dK_chi, dK_chi2"}
+        del wg, outg, dC, grads
         P1, K11, K21 = P[:1].contiguous(), K1[:1].contiguous(), K2[:1].contiguous()
         lat = []
         for i in range(12):

@@ -2332,23 +2332,43 @@ __global__ __launch_bounds__(256) void contract_t_kernel(const typename std::con
 }
 
 // dP[row][j] = sum_{n < N} D[n][j] dc[row][n] (nodal input) or dP[row][n] = dc[row][n]
-// (coefficient input), written in P's dtype.
+// (coefficient input), written in P's dtype; N <= 128.  Work-group = kAdjRows rows, whose dc rows
+// sit in LDS in FP64; thread (j, h) makes column j of the rows of parity h, so each D[n][j] it
+// reads serves 32 independent FP64 accumulators (LDS reads of dc are broadcasts: every lane of a
+// wave reads the same row).
+constexpr int kAdjRows = 64;
 template <typename T, typename PT>
 __global__ __launch_bounds__(256) void adj_project_kernel(const T *__restrict__ dc, const double *__restrict__ Dn,
                                                           int N, int ncp, long nrows, int coef, PT *__restrict__ dP) {
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nrows * N) return;
-    const long row = i / N;
-    const int j = (int)(i % N);
-    const T *c = dc + row * ncp;
-    double v;
-    if (coef) {
-        v = (double)c[j];
-    } else {
-        v = 0.0;
-        for (int n = 0; n < N; ++n) v += Dn[(size_t)n * N + j] * (double)c[n];
+    constexpr int RH = kAdjRows / 2;
+    static_assert(kMaxCheb <= 128, "one thread column per Chebyshev node");
+    __shared__ double cs[kAdjRows][128 + 1];
+    const long row0 = (long)blockIdx.x * kAdjRows;
+    for (int i = threadIdx.x; i < kAdjRows * N; i += blockDim.x) {
+        const int r = i / N, n = i % N;
+        cs[r][n] = row0 + r < nrows ? (double)dc[(row0 + r) * ncp + n] : 0.0;
     }
-    dP[i] = (PT)v;
+    __syncthreads();
+    const int j = threadIdx.x % 128, h = threadIdx.x / 128;
+    if (j >= N) return;
+    double acc[RH];
+    if (coef) {
+#pragma unroll
+        for (int k = 0; k < RH; ++k) acc[k] = cs[2 * k + h][j];
+    } else {
+#pragma unroll
+        for (int k = 0; k < RH; ++k) acc[k] = 0.0;
+        for (int n = 0; n < N; ++n) {
+            const double d = Dn[(size_t)n * N + j];
+#pragma unroll
+            for (int k = 0; k < RH; ++k) acc[k] = fma(d, cs[2 * k + h][n], acc[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < RH; ++k) {
+        const long row = row0 + 2 * k + h;
+        if (row < nrows) dP[row * N + j] = (PT)acc[k];
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -2944,7 +2964,7 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
             hipLaunchKernelGGL((contract_t_kernel<false>), gt, dim3(256), sht, s, p->basis.f32, (const float *)dw,
                                a->batch, p->NP, p->rows_pad, p->nc_pad, (float *)dc);
         const long nrows = (long)a->batch * p->NP;
-        dim3 gp((unsigned)((nrows * p->n_cheb + 255) / 256));
+        dim3 gp((unsigned)((nrows + kAdjRows - 1) / kAdjRows));
 #define BLAST_AP(T, PT)                                                                                        \
     hipLaunchKernelGGL((adj_project_kernel<T, PT>), gp, dim3(256), 0, s, (const T *)dc, p->d_dctn64, p->n_cheb, \
                        p->nc_pad, nrows, a->p_kind, (PT *)dP)
