@@ -2221,14 +2221,21 @@ __global__ __launch_bounds__(256) void adj_kchi_kernel(const T *__restrict__ Y, 
 
 // per (chi_a, cosmology):  dw[b][row] = wR_b sum_m K2_m(a, b) dY[row][a][m]
 //                          dK2[m][a][b] = wR_b sum_row dY[row][a][m] w[b][row]
+// dY of the work-group's chi_a sits in LDS with rows NB + 1 doubles apart, so that the dw loop's
+// lanes (consecutive rows) read distinct banks.  (dK2 with one wave per R node, lanes over rows and
+// a shuffle reduction of the NB sums measured slower than this loop.)
+template <int NB>
+constexpr int adj_w_stride() { return NB + 1; }
+
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void adj_w_kernel(const T *__restrict__ dY, const T *__restrict__ w,
                                                     const double *__restrict__ Kchi2, const double *__restrict__ wR,
                                                     int NP, int nR, int n_chi, int rows, int rows_pad, int nbins,
                                                     T *__restrict__ dw, double *__restrict__ dK2) {
+    constexpr int DS = adj_w_stride<NB>();
     extern __shared__ __align__(16) unsigned char smem_a[];
     double *Kh = (double *)smem_a;                   // [nR][NB]
-    double *dYa = Kh + (size_t)nR * NB;              // [rows_pad][NB]
+    double *dYa = Kh + (size_t)nR * NB;              // [rows_pad][DS]
     const int a = blockIdx.x, beta = blockIdx.y;
     for (int i = threadIdx.x; i < nR * NB; i += blockDim.x) {
         const int b = i / NB, m = i % NB;
@@ -2236,7 +2243,7 @@ __global__ __launch_bounds__(256) void adj_w_kernel(const T *__restrict__ dY, co
     }
     for (int i = threadIdx.x; i < rows_pad * NB; i += blockDim.x) {
         const int row = i / NB, m = i % NB;
-        dYa[i] = row < rows ? (double)dY[(((size_t)beta * rows_pad + row) * n_chi + a) * NB + m] : 0.0;
+        dYa[row * DS + m] = row < rows ? (double)dY[(((size_t)beta * rows_pad + row) * n_chi + a) * NB + m] : 0.0;
     }
     __syncthreads();
     const size_t base = ((size_t)beta * NP + (size_t)a * nR) * rows_pad;
@@ -2244,7 +2251,7 @@ __global__ __launch_bounds__(256) void adj_w_kernel(const T *__restrict__ dY, co
         const int b = i / rows_pad, row = i % rows_pad;
         double v = 0.0;
 #pragma unroll
-        for (int m = 0; m < NB; ++m) v += Kh[b * NB + m] * dYa[row * NB + m];
+        for (int m = 0; m < NB; ++m) v += Kh[b * NB + m] * dYa[row * DS + m];
         dw[base + i] = (T)v;
     }
     if (dK2) {
@@ -2253,7 +2260,7 @@ __global__ __launch_bounds__(256) void adj_w_kernel(const T *__restrict__ dY, co
             if (m >= nbins) continue;
             const T *wr = w + base + (size_t)b * rows_pad;
             double v = 0.0;
-            for (int row = 0; row < rows; ++row) v += dYa[row * NB + m] * (double)wr[row];
+            for (int row = 0; row < rows; ++row) v += dYa[row * DS + m] * (double)wr[row];
             dK2[(((size_t)beta * nbins + m) * n_chi + a) * nR + b] = wR[b] * v;
         }
     }
@@ -2915,6 +2922,9 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
     if (st != BLAST_OK) return st;
     if (x.prec != BLAST_FP64 && x.prec != BLAST_FP32)
         return set_error("the adjoint runs in FP64 or FP32"), BLAST_E_UNSUPPORTED;
+    // adj_w_kernel keeps the R weights and dY of one chi node in LDS
+    if (((size_t)p->n_R * x.nbp + (size_t)p->rows_pad * (x.nbp + 1)) * sizeof(double) > 160 * 1024)
+        return set_error("n_R and the multipoles too large for the adjoint's R tile"), BLAST_E_UNSUPPORTED;
     if (!dC) return set_error("dC is required"), BLAST_E_INVALID;
     BLAST_HIP_TRY(allow_large_lds());
     const bool f64 = x.prec == BLAST_FP64;
@@ -2944,7 +2954,7 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
                                p->d_chi, p->n_chi, p->rows, p->rows_pad, x.nbins, dK_chi);                        \
         }                                                                                                         \
         dim3 gw(p->n_chi, a->batch);                                                                              \
-        const size_t shw = ((size_t)p->n_R * NB + (size_t)p->rows_pad * NB) * sizeof(double);                     \
+        const size_t shw = ((size_t)p->n_R * NB + (size_t)p->rows_pad * adj_w_stride<NB>()) * sizeof(double);      \
         hipLaunchKernelGGL((adj_w_kernel<T, NB>), gw, dim3(256), shw, s, (const T *)dY, (const T *)w, a->K_chi2, \
                            p->d_wR, p->NP, p->n_R, p->n_chi, p->rows, p->rows_pad, x.nbins, (T *)dw, dK_chi2);   \
     } while (0)
