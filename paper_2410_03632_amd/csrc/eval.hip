@@ -2201,22 +2201,60 @@ __global__ __launch_bounds__(256) void adj_dy_kernel(const double *__restrict__ 
 }
 
 // dK_chi[beta][l][a] = wchi_a chi_a sum_{row, m} S[row][m][l] Y[row][a][m]
+// Work-group = (64 chi nodes, cosmology), 4 waves: lane = chi node, wave w takes rows w, w + 4, ...
+// and keeps NB sums (one per l).  A wave copies its row's S (NB x NB) into its own LDS slot with
+// coalesced loads and reads it back as broadcasts (every lane the same address); the row's Y
+// entries are 16-byte loads per lane.  The waves' sums are added in LDS in a fixed order.
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void adj_kchi_kernel(const T *__restrict__ Y, const double *__restrict__ Sg,
                                                        const double *__restrict__ wchi,
                                                        const double *__restrict__ chi, int n_chi, int rows,
                                                        int rows_pad, int nbins, double *__restrict__ dK) {
-    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int KV = 16 / sizeof(T), SV = NB * NB / 2;  // 16-byte pieces of one S
+    __shared__ __align__(16) double Ss[4][NB * NB];
+    __shared__ double part[3][64][NB + 1];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int beta = blockIdx.y;
-    if (gid >= (long)nbins * n_chi) return;
-    const int l = (int)(gid / n_chi), a = (int)(gid % n_chi);
-    double acc = 0.0;
-    for (int row = 0; row < rows; ++row) {
+    const int a = blockIdx.x * 64 + lane, ac = min(a, n_chi - 1);
+    double *sw = Ss[w];
+    double acc[NB];
+#pragma unroll
+    for (int l = 0; l < NB; ++l) acc[l] = 0.0;
+    for (int row = w; row < rows; row += 4) {
         const double *sg = Sg + ((size_t)beta * rows_pad + row) * NB * NB;
-        const T *y = Y + (((size_t)beta * rows_pad + row) * n_chi + a) * NB;
-        for (int m = 0; m < nbins; ++m) acc += sg[m * NB + l] * (double)y[m];
+        const T *y = Y + (((size_t)beta * rows_pad + row) * n_chi + ac) * NB;
+        T yv[NB];
+#pragma unroll
+        for (int q = 0; q < NB; q += KV) *(U4 *)(yv + q) = *(const U4 *)(y + q);
+#pragma unroll
+        for (int q = lane; q < SV; q += 64) *(U4 *)(sw + 2 * q) = *(const U4 *)(sg + 2 * q);
+        // the slot's writes are done before any lane reads them (LDS accesses of a wave complete
+        // in order; the asm also keeps the compiler from moving accesses across it)
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+        for (int m = 0; m < NB; ++m) {
+            const double ym = (double)yv[m];
+#pragma unroll
+            for (int l = 0; l < NB; l += 2) {
+                const double2 sv = *(const double2 *)(sw + m * NB + l);
+                acc[l] = fma(sv.x, ym, acc[l]);
+                acc[l + 1] = fma(sv.y, ym, acc[l + 1]);
+            }
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // reads done before the next row's writes
     }
-    dK[((size_t)beta * nbins + l) * n_chi + a] = wchi[a] * chi[a] * acc;
+    if (w > 0)
+#pragma unroll
+        for (int l = 0; l < NB; ++l) part[w - 1][lane][l] = acc[l];
+    __syncthreads();
+    if (w == 0 && a < n_chi) {
+        const double f = wchi[a] * chi[a];
+#pragma unroll
+        for (int l = 0; l < NB; ++l)
+            if (l < nbins)
+                dK[((size_t)beta * nbins + l) * n_chi + a] =
+                    f * (((acc[l] + part[0][lane][l]) + part[1][lane][l]) + part[2][lane][l]);
+    }
 }
 
 // per (chi_a, cosmology):  dw[b][row] = wR_b sum_m K2_m(a, b) dY[row][a][m]
@@ -2949,7 +2987,7 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
                            p->d_pref, p->n_chi, p->rows_pad, p->n_ell, sl, x.ng, x.ns, a->types, x.npairs,        \
                            x.sel.n_out, x.inv, (T *)dY, Sg);                                                      \
         if (dK_chi) {                                                                                             \
-            dim3 gk((unsigned)(((long)x.nbins * p->n_chi + 255) / 256), a->batch);                                \
+            dim3 gk((unsigned)((p->n_chi + 63) / 64), a->batch);                                                  \
             hipLaunchKernelGGL((adj_kchi_kernel<T, NB>), gk, dim3(256), 0, s, (const T *)Y, Sg, p->d_wchi,        \
                                p->d_chi, p->n_chi, p->rows, p->rows_pad, x.nbins, dK_chi);                        \
         }                                                                                                         \

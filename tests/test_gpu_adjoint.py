@@ -24,9 +24,11 @@ def _dev(x, dtype=torch.float64):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).cuda()
 
 
-@pytest.fixture(scope="module", params=[0, 1])
+@pytest.fixture(scope="module", params=[0, 1, 2])
 def setup(request):
-    kw = [dict(), dict(n_ell=11, ell_max=70, n_chi=9, n_R=7, n_cheb=32, k_max=0.9, n_g=3, n_s=2)][request.param]
+    # the third set has 18 bins: the kernels' 32-wide bin tiles
+    kw = [dict(), dict(n_ell=11, ell_max=70, n_chi=9, n_R=7, n_cheb=32, k_max=0.9, n_g=3, n_s=2),
+          dict(n_ell=5, ell_max=40, n_chi=8, n_R=6, n_cheb=24, k_max=0.6, n_g=12, n_s=6)][request.param]
     cfg = W.tiny_config(**kw)
     plan = B.plan_for_config(cfg, precisions=("fp64", "fp32"))
     inps = [W.make_inputs(cfg, W.seed_for(5, request.param * 10 + i), plan.k_nodes, plan.chi, plan.R)
