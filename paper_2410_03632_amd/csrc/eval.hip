@@ -2338,26 +2338,48 @@ __global__ __launch_bounds__(256) void contract_t_kernel(const typename std::con
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < BTN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
-    for (int st = 0; st < rows_pad / 4; ++st) {
-        const int row = 4 * st + lk;
-        T av[2], bv[BTN];
+    // K steps of 4 rows in groups of 4 (rows_pad / 4 is a multiple of 4); the basis values of the
+    // next group are loaded while the current one runs on the MFMA units
+    const int S4 = rows_pad / 4;
+    auto loadA = [&](int st0, T(&av)[4][2]) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int nt = wv + 4 * i;
-            const size_t o = F64 ? (size_t)row * ncp + 16 * nt + lr : tiled_off(row, 16 * nt + lr, ncp / 16, 4);
-            av[i] = nt < NT ? bp[o] : (T)0;
-        }
+        for (int u = 0; u < 4; ++u) {
+            const int row = 4 * (st0 + u) + lk;
 #pragma unroll
-        for (int j = 0; j < BTN; ++j) bv[j] = ws[(16 * j + lr) * dst + row];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < BTN; ++j) {
-                if constexpr (F64)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
-                else
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 2; ++i) {
+                const int nt = wv + 4 * i;
+                const size_t o = F64 ? (size_t)row * ncp + 16 * nt + lr : tiled_off(row, 16 * nt + lr, ncp / 16, 4);
+                av[u][i] = nt < NT ? bp[o] : (T)0;
             }
+        }
+    };
+    auto compute = [&](int st0, const T(&av)[4][2]) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int row = 4 * (st0 + u) + lk;
+            T bv[BTN];
+#pragma unroll
+            for (int j = 0; j < BTN; ++j) bv[j] = ws[(16 * j + lr) * dst + row];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < BTN; ++j) {
+                    if constexpr (F64)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][i], bv[j], acc[i][j], 0, 0, 0);
+                    else
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][i], bv[j], acc[i][j], 0, 0, 0);
+                }
+        }
+    };
+    T a0[4][2], a1[4][2];
+    loadA(0, a0);
+    for (int st0 = 0; st0 < S4; st0 += 8) {
+        if (st0 + 4 < S4) loadA(st0 + 4, a1);
+        compute(st0, a0);
+        if (st0 + 4 < S4) {
+            if (st0 + 8 < S4) loadA(st0 + 8, a0);
+            compute(st0 + 4, a1);
+        }
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
