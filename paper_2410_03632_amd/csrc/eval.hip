@@ -2259,8 +2259,8 @@ __global__ __launch_bounds__(256) void adj_kchi_kernel(const T *__restrict__ Y, 
 
 // per (chi_a, cosmology):  dw[b][row] = wR_b sum_m K2_m(a, b) dY[row][a][m]
 //                          dK2[m][a][b] = wR_b sum_row dY[row][a][m] w[b][row]
-// dY of the work-group's chi_a sits in LDS with rows NB + 1 doubles apart, so that the dw loop's
-// lanes (consecutive rows) read distinct banks.  (dK2 with one wave per R node, lanes over rows and
+// dY of the work-group's chi_a sits in LDS with rows NB + 1 doubles apart, so that lanes reading
+// consecutive rows hit distinct banks.  (dK2 with one wave per R node, lanes over rows and
 // a shuffle reduction of the NB sums measured slower than this loop.)
 template <int NB>
 constexpr int adj_w_stride() { return NB + 1; }
@@ -2285,12 +2285,19 @@ __global__ __launch_bounds__(256) void adj_w_kernel(const T *__restrict__ dY, co
     }
     __syncthreads();
     const size_t base = ((size_t)beta * NP + (size_t)a * nR) * rows_pad;
-    for (int i = threadIdx.x; i < nR * rows_pad; i += blockDim.x) {
-        const int b = i / rows_pad, row = i % rows_pad;
-        double v = 0.0;
+    // dw: item = (row, quarter of the R nodes); the row's dY stays in registers and the weights of
+    // a node are the same address for the whole wave (broadcast reads)
+    for (int i = threadIdx.x; i < 4 * rows_pad; i += blockDim.x) {
+        const int row = i % rows_pad, q = i / rows_pad;
+        double yr[NB];
 #pragma unroll
-        for (int m = 0; m < NB; ++m) v += Kh[b * NB + m] * dYa[row * DS + m];
-        dw[base + i] = (T)v;
+        for (int m = 0; m < NB; ++m) yr[m] = dYa[row * DS + m];
+        for (int b = q * nR / 4; b < (q + 1) * nR / 4; ++b) {
+            double v = 0.0;
+#pragma unroll
+            for (int m = 0; m < NB; ++m) v += Kh[b * NB + m] * yr[m];
+            dw[base + (size_t)b * rows_pad + row] = (T)v;
+        }
     }
     if (dK2) {
         for (int i = threadIdx.x; i < nR * NB; i += blockDim.x) {
