@@ -360,7 +360,7 @@ def main():
         return
     from paper_2410_03632_amd import blast as B
     from paper_2410_03632_amd import workloads as W
-    from tests._util import g16_err
+    from paper_2410_03632_amd.metrics import g16_err, error_by_pair
 
     cfg = W.CONFIGS[args.config]
     prec = args.precision

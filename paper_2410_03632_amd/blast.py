@@ -531,6 +531,20 @@ class Server:
             return x.data_ptr()
         return x.ctypes.data
 
+    @staticmethod
+    def _host_f64(x, shape, name):
+        """A kernel table the server reads as host memory until completion: a float64,
+        C-contiguous host array (numpy, or a torch CPU tensor, e.g. pinned) of exactly `shape`."""
+        if hasattr(x, "data_ptr"):
+            import torch
+            ok = x.dtype == torch.float64 and x.is_contiguous() and not x.is_cuda
+        else:
+            x = np.ascontiguousarray(x, dtype=np.float64)
+            ok = True
+        if not ok or tuple(x.shape) != tuple(shape):
+            raise ValueError("%s must be a contiguous float64 host array of shape %s" % (name, tuple(shape)))
+        return x
+
     def submit(self, P, K_chi, K_chi2, n_g, n_s, ell_idx, out=None):
         plan = self.plan
         want = np.float64 if self.p_dtype == "fp64" else np.float32
@@ -542,11 +556,16 @@ class Server:
             ok = P.dtype == want and P.flags.c_contiguous
         if not ok or tuple(P.shape) != (len(plan.chi), len(plan.R), plan.n_cheb):
             raise ValueError("P must be a contiguous host array [n_chi, n_R, n_cheb] of the server's dtype")
-        K_chi = np.ascontiguousarray(K_chi, dtype=np.float64) if not hasattr(K_chi, "data_ptr") else K_chi
-        K_chi2 = np.ascontiguousarray(K_chi2, dtype=np.float64) if not hasattr(K_chi2, "data_ptr") else K_chi2
+        nb = n_g + n_s
+        K_chi = self._host_f64(K_chi, (nb, len(plan.chi)), "K_chi")
+        K_chi2 = self._host_f64(K_chi2, (nb, len(plan.chi), len(plan.R)), "K_chi2")
         idx = np.ascontiguousarray(ell_idx, dtype=np.int32)
+        shape = (n_pairs(n_g, n_s, plan.types), len(idx))
         if out is None:
-            out = np.empty((n_pairs(n_g, n_s, plan.types), len(idx)))
+            out = np.empty(shape)
+        elif not (isinstance(out, np.ndarray) and out.dtype == np.float64 and out.flags.c_contiguous
+                  and out.flags.writeable and tuple(out.shape) == shape):
+            raise ValueError("out must be a writeable C-contiguous float64 numpy array of shape %s" % (shape,))
         r = Request(self._ptr(P), n_g, n_s, self._ptr(K_chi), self._ptr(K_chi2), len(idx),
                     idx.ctypes.data_as(C.POINTER(C.c_int32)), out.ctypes.data)
         t = C.c_uint64()

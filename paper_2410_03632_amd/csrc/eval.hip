@@ -2993,8 +2993,12 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
     if (((size_t)p->n_R * x.nbp + (size_t)p->rows_pad * (x.nbp + 1)) * sizeof(double) > 160 * 1024)
         return set_error("n_R and the multipoles too large for the adjoint's R tile"), BLAST_E_UNSUPPORTED;
     if (!dC) return set_error("dC is required"), BLAST_E_INVALID;
-    BLAST_HIP_TRY(allow_large_lds());
     const bool f64 = x.prec == BLAST_FP64;
+    // contract_t_kernel keeps the dw rows of one cosmology tile (32 on FP64, 64 on FP32) in LDS
+    if (dP && (size_t)(f64 ? 32 : 64) * (p->rows_pad + 1) * (f64 ? 8 : 4) > 160 * 1024)
+        return set_error("the multipoles are too many for the transposed contraction's tile (dP)"),
+               BLAST_E_UNSUPPORTED;
+    BLAST_HIP_TRY(allow_large_lds());
     const bool need_w = a->w_save == nullptr;
     const Layout L = layout_of(p, a->batch, x.prec, x.nbins, need_w, true);
     unsigned char *ws = get_workspace(p, a, L.total, st);

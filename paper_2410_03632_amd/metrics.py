@@ -19,7 +19,42 @@ import math
 
 import numpy as np
 
+from .workloads import pair_list
+
 ARCMIN2_PER_SR = (180.0 * 60.0 / math.pi) ** 2
+
+
+def g16_err(C, Cref, n_g, n_s, types=("gg", "gs", "ss")):
+    """Per-element relative error |C - Cref| / max(|Cref|, 1e-3 sqrt(|Cref_ii Cref_jj|)) of
+    spectra [pair][ell]: cross spectra of separated bins pass through zero, so their error is
+    measured against the geometric mean of the two auto spectra below a thousandth of it."""
+    C = np.asarray(C, dtype=np.float64)
+    Cref = np.asarray(Cref, dtype=np.float64)
+    pairs = pair_list(n_g, n_s, types)
+    auto = {i: p for p, (t, i, j) in enumerate(pairs) if i == j}
+    out = np.empty_like(C)
+    for p, (t, i, j) in enumerate(pairs):
+        den = np.abs(Cref[p])
+        if i in auto and j in auto:
+            den = np.maximum(den, 1e-3 * np.sqrt(np.abs(Cref[auto[i]] * Cref[auto[j]])))
+        den = np.where(den > 0, den, 1.0)
+        out[p] = np.abs(C[p] - Cref[p]) / den
+    return out
+
+
+def error_by_pair(C, Cref, n_g, n_s, ell, worst=3):
+    """Error summary of one set of spectra against a reference (the g16_err metric): the largest
+    error of each pair type, and the `worst` pairs with the multipole where each peaks."""
+    e = g16_err(C, Cref, n_g, n_s)
+    pairs = pair_list(n_g, n_s)
+    by_type = {}
+    for p, (t, i, j) in enumerate(pairs):
+        by_type[t] = max(by_type.get(t, 0.0), float(e[p].max()))
+    peak = e.max(axis=1)
+    order = np.argsort(-peak)[:worst]
+    rows = [{"pair": "%s %d-%d" % (pairs[p][0], pairs[p][1], pairs[p][2]), "max": float(peak[p]),
+             "ell": float(np.asarray(ell)[int(np.argmax(e[p]))])} for p in order]
+    return {"max": float(e.max()), "by_type": by_type, "worst_pairs": rows}
 
 
 def spectra_matrix(C_pairs, n_g, n_s, pairs):

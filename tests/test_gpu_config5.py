@@ -11,9 +11,11 @@ f_sky = 0.4 (the error model of the paper's model-error appendix), held fixed;
 C_tgt comes from a second seeded cosmology and shifted bins.
 
 * At the full 3x2pt shapes (10 + 5 bins, 96 ell, 256 x 96 points, 128 nodes) the FP32
-  gradient is checked against central finite differences of the FP64 path with a
-  relative step of 1e-5: 20 random coefficients, 3 random coefficient directions and
-  every centre and width.
+  gradient is checked along 20 random coefficients and 3 random coefficient directions
+  against <G, C(d)> on the FP64 path (exact for a chi2 quadratic in C and a C linear in
+  c, and equal to the central differences, which are checked too), and against central
+  finite differences of the FP64 path with a relative step of 1e-5 for every centre and
+  width.
 * At small shapes the FP64 gradient is checked against the oracle's: its C from its own
   k-integrals and chi-R sums, differentiated by central differences in the bin
   parameters (C is bilinear in the kernels, so only the kernel builder's curvature
@@ -127,11 +129,27 @@ def test_full_shapes_fp32_gradient_vs_finite_differences(full):
         dirs.append(STEP * v)
     fd = _fd_coefficients(plan, cfg, K1d, K2d, c, Ct, s2, dirs).cpu().numpy()
     an = np.array([float((g_c * d).sum()) for d in dirs])
-    scale = np.abs(fd[20:]).max()
-    err = np.abs(an - fd) / np.maximum(np.abs(fd), 1e-3 * scale)
-    print("coefficient FD check, rel err per coordinate/direction:", np.array2string(err, precision=2), flush=True)
-    assert err[20:].max() < 1e-3
-    assert err[:20].max() < 1e-2
+    # chi2 is quadratic in C and C is linear in c, so the central difference has no truncation
+    # error: (chi2(c + d) - chi2(c - d)) / 2 = <G, C(d)> exactly, with G = 2 (C(c) - C_tgt) / sigma^2.
+    # The right side, with C(d) from the FP64 path on the direction alone, carries no cancellation
+    # of two large chi2 values (for one coefficient the difference is ~1e-9 of chi2, where the FP64
+    # rounding of chi2 leaves only a few digits), so each coordinate is checked against it at the
+    # directions' bar; the differences themselves must agree with it to their own rounding.
+    n = len(dirs)
+    Cd = plan.forward(torch.stack(dirs).contiguous(), K1d.expand(n, -1, -1).contiguous(),
+                      K2d.expand(n, -1, -1, -1).contiguous(), cfg.n_g, cfg.n_s, coef=True)
+    C0 = plan.forward(c[None].contiguous(), K1d[None].contiguous(), K2d[None].contiguous(), cfg.n_g, cfg.n_s,
+                      coef=True)[0]
+    G = 2.0 * (C0 - Ct) / s2
+    ref = (Cd * G).sum(dim=(-1, -2)).cpu().numpy()
+    scale = np.abs(ref[20:]).max()
+    err = np.abs(an - ref) / np.maximum(np.abs(ref), 1e-3 * scale)
+    err_fd = np.abs(fd - ref) / np.maximum(np.abs(ref), 1e-3 * scale)
+    print("coefficient check vs <G, C(d)>, rel err per coordinate/direction:", np.array2string(err, precision=2),
+          flush=True)
+    print("central differences vs <G, C(d)>:", np.array2string(err_fd, precision=2), flush=True)
+    assert err.max() < 1e-3
+    assert err_fd[20:].max() < 1e-6
 
     # every centre and width
     ths = []

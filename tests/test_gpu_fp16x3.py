@@ -2,7 +2,7 @@
 (about 22 significant bits each) with a power-of-two scale per basis row and per coefficient row,
 hi*hi + hi*lo + lo*hi on FP16 MFMA, FP32 accumulate; fused with the R-quadrature at every batch.
 
-The bar is the mixed paths' 1e-3 (relative error of ``_util.g16_err``) against the FP64 oracle,
+The bar is the mixed paths' 1e-3 (relative error of ``metrics.g16_err``) against the FP64 oracle,
 at small grids and at the two named shapes (stored oracle goldens).  The row scales are checked
 by exact scaling: P -> 2^k P must give C -> 2^k C bit for bit, because every scale is a power of
 two.  Requests outside the fused path are refused."""

@@ -2,8 +2,9 @@
 
 Every test calls the library through its C ABI (``paper_2410_03632_amd.blast``) and
 the oracle through ``oracle`` on identical P grids and kernels.  The bar is the
-relative error of ``_util.g16_err`` (|dC| / max(|C|, 1e-3 sqrt(C_ii C_jj))):
-<= 1e-6 for the FP64 path and <= 1e-3 for the mixed paths.
+relative error of ``metrics.g16_err`` (|dC| / max(|C|, 1e-3 sqrt(C_ii C_jj))):
+<= 1e-6 for the FP64 path, <= 1e-3 for FP32 and FP16X3, and the bounds blast_hip.h states
+for BF16X3 and plain BF16.
 """
 import json
 import os
@@ -198,16 +199,19 @@ def test_named_config_matches_oracle_golden(config):
     Cor = np.array(g["C"])
     assert g["oracle_rel_change"] < 1e-9
     res = {}
-    # at the full 3x2pt shapes BF16x3 misses the 1e-3 bar (in the gg cross spectra of separated
-    # bins at high ell, where the spectra are a small remainder of the integrand): reported only
-    x3_tol = 1e-3 if config == 1 else None
+    # bars of the library's stated accuracy (blast_hip.h): error ~ u * kappa, with kappa the
+    # cancellation of the problem, largest for the gg cross spectra of separated bins at high ell.
+    # BF16X3 (u ~ 2^-15) meets 1e-3 on the small grid only and stays within 2e-2 at the full
+    # 3x2pt shapes (9.2e-3 measured, so kappa ~ 300 there); plain BF16 (u ~ 2^-7) is not an
+    # accurate path: its stated bounds, 0.5 and 20, are u * kappa with that kappa and a factor
+    # of 2-3 to spare (0.26 and 6.2 measured), and catch a regression or a non-finite result.
+    x3_tol, b16_tol = (1e-3, 0.5) if config == 1 else (2e-2, 20.0)
     for prec, tol, p32 in (("fp64", 1e-6, False), ("fp32", 1e-3, True), ("bf16x3", x3_tol, True),
-                           ("bf16", None, True)):
+                           ("bf16", b16_tol, True)):
         C = _run(plan, inp, prec, p32=p32)
         e = g16_err(C, Cor, cfg.n_g, cfg.n_s)
         res[prec] = float(e.max())
-        if tol is not None:
-            assert e.max() <= tol, (prec, e.max())
+        assert np.isfinite(C).all() and e.max() <= tol, (prec, e.max())
     print("config", config, "max errors", res, flush=True)
     plan.close()
 
