@@ -226,6 +226,21 @@ blast_status blast_cl_workspace_bytes(const blast_plan *plan, int32_t batch, int
  * resident), OOM (plan scratch), HIP. */
 blast_status blast_cl_forward(blast_plan *plan, const blast_cl_args *args, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the computation of blast_cl_forward, with the call's
+ * scratch in a fixed device array of 64 MiB that the library holds on every GPU it has made a
+ * plan on, from then until the process ends, instead of plan-owned or caller memory.  The
+ * caller passes inputs and outputs as for blast_cl_forward; args->workspace must be NULL.  The
+ * call allocates nothing (no hipMalloc, no allocating library routine) and records no stage
+ * timing.  A call whose scratch would exceed 64 MiB is refused with BLAST_E_UNSUPPORTED before
+ * any work (the full 3x2pt grid fits one cosmology on the FP32 and FP16X3 paths, none on FP64).
+ * All calls on one GPU share that GPU's array, which keeps the last call's contents: calls that
+ * overlap in time on one GPU (other streams, other threads) race and must be serialised by the
+ * caller.  Every byte of scratch a call reads it has written first, so nothing is cleared.
+ * Errors: as blast_cl_forward; INVALID if args->workspace is set; HIP if the array's address on
+ * this GPU could not be found when the plan was made. */
+blast_status blast_cl_forward_noalloc(blast_plan *plan, const blast_cl_args *args, void *stream);
+
 /* Adjoint of blast_cl_forward (reverse mode; not in the paper, whose conclusion lists
  * differentiability as future work).  With the same `args` (precision FP64 or FP32)
  * and dC = dL/dC (device, FP64, shaped like args->C) it enqueues on `stream`:

@@ -81,7 +81,8 @@ class ServerStats(C.Structure):
 EXPORTS = [
     "blast_last_error", "blast_version", "blast_grid_chi_simpson", "blast_grid_R_fejer", "blast_grid_k_cheb",
     "blast_plan_create", "blast_plan_destroy", "blast_plan_info", "blast_plan_k_nodes", "blast_plan_basis_point",
-    "blast_cl_workspace_bytes", "blast_cl_forward", "blast_cl_backward", "blast_plan_profile",
+    "blast_cl_workspace_bytes", "blast_cl_forward", "blast_cl_forward_noalloc", "blast_cl_backward",
+    "blast_plan_profile",
     "blast_plan_profile_read", "blast_plan_save", "blast_plan_load", "blast_plan_eval_points",
     "blast_plan_grids", "blast_plan_limber_k", "blast_cl_limber",
     "blast_server_create", "blast_server_submit", "blast_server_wait",
@@ -114,6 +115,7 @@ def lib():
         L.blast_cl_workspace_bytes.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                                C.POINTER(C.c_size_t)]
         L.blast_cl_forward.argtypes = [C.c_void_p, C.POINTER(ClArgs), C.c_void_p]
+        L.blast_cl_forward_noalloc.argtypes = [C.c_void_p, C.POINTER(ClArgs), C.c_void_p]
         L.blast_cl_backward.argtypes = [C.c_void_p, C.POINTER(ClArgs), C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p]
         L.blast_server_create.argtypes = [C.c_void_p, C.POINTER(ServerDesc), C.POINTER(C.c_void_p)]
@@ -437,6 +439,21 @@ class Plan:
         if stream is None:
             stream = torch.cuda.current_stream(P.device).cuda_stream
         _check(lib().blast_cl_forward(self._h, C.byref(args), C.c_void_p(stream)))
+        return out
+
+    def forward_noalloc(self, P, K_chi, K_chi2, n_g, n_s, out, *, precision="fp64", types=None, ell_idx=None,
+                        stream=None, coef=False):
+        """forward() through blast_cl_forward_noalloc: the library allocates nothing (its scratch
+        is a fixed 64 MiB device array per GPU) and `out` must be given."""
+        import torch
+        args, keep, shape, prec = self._prepare(P, K_chi, K_chi2, n_g, n_s, precision, types, ell_idx, coef)
+        P = keep[0]
+        if tuple(out.shape) != shape or out.dtype != torch.float64 or not out.is_contiguous() or not out.is_cuda:
+            raise ValueError("out must be a contiguous float64 device tensor of shape %s" % (shape,))
+        args.C = out.data_ptr()
+        if stream is None:
+            stream = torch.cuda.current_stream(P.device).cuda_stream
+        _check(lib().blast_cl_forward_noalloc(self._h, C.byref(args), C.c_void_p(stream)))
         return out
 
     def backward(self, P, K_chi, K_chi2, n_g, n_s, dC, *, precision="fp64", types=None, ell_idx=None,

@@ -267,6 +267,7 @@ static blast_status plan_create_impl(const blast_plan_desc *d, int32_t device, B
     p->precisions = d->precisions | 1u;
 
     DeviceGuard guard(device);
+    blast::noalloc_init(device);  // once per device: the fixed scratch of blast_cl_forward_noalloc
     hipStream_t s = nullptr;
     auto fail = [&](blast_status e) {
         if (s) (void)hipStreamDestroy(s);
@@ -617,6 +618,13 @@ extern "C" blast_status blast_cl_forward(blast_plan *p, const blast_cl_args *a, 
     if (!p || !a) return blast::set_error("NULL argument"), BLAST_E_INVALID;
     DeviceGuard guard(p->device);
     return blast::forward(p, a, (hipStream_t)stream);
+}
+
+extern "C" blast_status blast_cl_forward_noalloc(blast_plan *p, const blast_cl_args *a, void *stream) {
+    blast::clear_error();
+    if (!p || !a) return blast::set_error("NULL argument"), BLAST_E_INVALID;
+    DeviceGuard guard(p->device);
+    return blast::forward_noalloc(p, a, (hipStream_t)stream);
 }
 
 extern "C" blast_status blast_cl_backward(blast_plan *p, const blast_cl_args *a, const double *dC, void *dP,

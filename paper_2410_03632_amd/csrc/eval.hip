@@ -2900,8 +2900,15 @@ void stage_quad_c(blast_plan *p, const blast_cl_args *a, const Ctx &x, const voi
 #undef BLAST_QC
 }
 
+// Device memory a call uses in place of plan-owned or caller scratch (the no-alloc entry point)
+struct FixedScratch {
+    unsigned char *ptr;
+    size_t bytes;
+};
+
 template <typename Mark>
-blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, Mark &mark) {
+blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, Mark &mark,
+                          const FixedScratch *fixed = nullptr) {
     Ctx x;
     blast_status st = check_args(p, a, x);
     if (st != BLAST_OK) return st;
@@ -2914,8 +2921,17 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     BLAST_HIP_TRY(allow_large_lds());
     const bool need_w = a->w_save == nullptr;
     const Layout L = layout_of(p, a->batch, x.prec, x.nbins, need_w, false);
-    unsigned char *ws = get_workspace(p, a, L.total, st);
-    if (!ws) return st;
+    unsigned char *ws = nullptr;
+    if (fixed) {
+        if (L.total > fixed->bytes)
+            return set_error("this call needs %zu bytes of scratch; the fixed scratch holds %zu", L.total,
+                             fixed->bytes),
+                   BLAST_E_UNSUPPORTED;
+        ws = fixed->ptr;
+    } else {
+        ws = get_workspace(p, a, L.total, st);
+        if (!ws) return st;
+    }
     void *c = ws + L.c;
     uint16_t *clo = x.prec == BLAST_BF16X3 || x.prec == BLAST_FP16X3 ? (uint16_t *)(ws + L.clo) : nullptr;
     float *cs = x.prec == BLAST_FP16X3 ? (float *)(ws + L.cs) : nullptr;
@@ -2947,7 +2963,52 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     return BLAST_OK;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Scratch of the forward that allocates nothing: a file-scope device array.  Each GPU the library
+// runs on holds its own copy, at its own address, from the time the library's code is loaded there
+// until the process ends.  In host code `scratch` names a host-side stand-in, not device memory:
+// kernels get the address hipGetSymbolAddress returns for the current device, taken once per
+// device when a plan is made there and kept in noalloc_ptr.
+// ---------------------------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex noalloc_mu;
+unsigned char *noalloc_ptr[kMaxDevices];
+hipError_t noalloc_err[kMaxDevices];
+
+struct NoMark {
+    void operator()(int) const {}
+};
+
 }  // namespace
+
+void noalloc_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(noalloc_mu);
+    if (noalloc_ptr[device]) return;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    noalloc_err[device] = e;
+    if (e == hipSuccess) noalloc_ptr[device] = (unsigned char *)ptr;
+}
+
+blast_status forward_noalloc(blast_plan *p, const blast_cl_args *a, hipStream_t s) {
+    if (a->workspace) return set_error("the no-alloc forward takes no workspace (its scratch is fixed)"), BLAST_E_INVALID;
+    FixedScratch fx{nullptr, kNoAllocScratchBytes};
+    {
+        std::lock_guard<std::mutex> lk(noalloc_mu);
+        if (p->device >= 0 && p->device < kMaxDevices) fx.ptr = noalloc_ptr[p->device];
+        if (!fx.ptr)
+            return set_error("no fixed scratch on device %d: %s", p->device,
+                             p->device >= 0 && p->device < kMaxDevices ? hipGetErrorString(noalloc_err[p->device])
+                                                                       : "device index out of range"),
+                   BLAST_E_HIP;
+    }
+    NoMark mark;
+    return forward_impl(p, a, s, mark, &fx);
+}
 
 size_t workspace_bytes(const blast_plan *p, int batch, int prec, int n_bins) {
     return workspace_bytes_impl(p, batch, prec, n_bins);
