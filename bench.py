@@ -132,9 +132,60 @@ def roofline(work, ms_per_launch, prec):
             "traffic": None, "algorithmic_flops": flops, "algorithmic_bytes": nbytes}
 
 
-def cpu_baseline(cfg, plan, inp, n_sample=144, seed=11):
-    """The FP64 oracle on a stratified sample of (chi_a, R_b) points of the same workload,
-    with the same two k-panel levels its doubling test runs, scaled to one full set."""
+def cpu_model():
+    """The host CPU's model name (first 'model name' line of /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_small_config(runs=3, st_chi=8):
+    """The FP64 oracle on one whole set of the small named configuration (20 ell, 2 + 2 bins,
+    chi 64 x R 32, 64 Chebyshev nodes) at its first k-panel level, `runs` times on all host
+    cores (mean and standard deviation, the protocol of the paper's timing table), and once on
+    one thread over `st_chi` of the 64 chi nodes (every R node of each), scaled by points."""
+    import oracle as O
+    from paper_2410_03632_amd import workloads as W
+    cfg = W.CONFIGS[1]
+    chi, wchi = O.grid_chi(cfg.n_chi, cfg.chi_min, cfg.chi_max)
+    R, wR = O.grid_R(cfg.n_R, cfg.R_min)
+    _, x = O.grid_k(cfg.n_cheb, cfg.k_min, cfg.k_max)
+    k = np.exp(np.log(cfg.k_min) + 0.5 * (x + 1.0) * np.log(cfg.k_max / cfg.k_min))
+    inp = W.make_inputs(cfg, W.seed_for(1, 0), k, chi, R)
+    cores = O.max_threads()
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        O.cl_grid(cfg.ells(), ("gg", "gs", "ss"), cfg.k_min, cfg.k_max, cfg.n_cheb, chi, wchi, R, wR, inp.P,
+                  cfg.n_g, cfg.n_s, inp.Kchi, inp.Kchi2, maxlev=1, nthreads=cores)
+        ts.append(time.perf_counter() - t0)
+    a = (np.arange(st_chi) * cfg.n_chi) // st_chi
+    c1 = np.repeat(chi[a], cfg.n_R)
+    c2 = (chi[a][:, None] * R[None, :]).ravel()
+    t0 = time.perf_counter()
+    O.w_points(cfg.ells(), ("gg", "gs", "ss"), cfg.k_min, cfg.k_max, c1, c2, nc=cfg.n_cheb,
+               P=inp.P[a].reshape(-1, cfg.n_cheb), M=max(64, 2 * cfg.n_cheb), Phi=10.0, nthreads=1)
+    t1 = (time.perf_counter() - t0) * cfg.n_chi / st_chi
+    # the oracle keeps the last thread count it was given: back to all cores
+    O.w_points(cfg.ells()[:1], ("gg",), cfg.k_min, cfg.k_max, c1[:1], c2[:1], nc=cfg.n_cheb,
+               P=inp.P[a[0], 0], shared=True, nthreads=cores)
+    return {"workload": "small named configuration: one whole set (20 ell, 10 pairs, chi 64 x R 32, 64 nodes), "
+                        "the oracle's first k-panel level",
+            "all_cores_s_per_set_mean": float(np.mean(ts)), "all_cores_s_per_set_std": float(np.std(ts)),
+            "runs": runs, "cores": cores,
+            "one_thread_s_per_set": t1,
+            "one_thread_sample": "%d of 64 chi nodes (all 32 R nodes each), scaled by points" % st_chi}
+
+
+def cpu_baseline(cfg, plan, inp, config, n_sample=144, seed=11):
+    """The FP64 oracle on a stratified sample of (chi_a, R_b) points of the benchmark workload,
+    with the same two k-panel levels its doubling test runs, scaled by points to one full set
+    (an estimate: a whole set takes the oracle about two hours), next to a measured whole set of
+    the small named configuration."""
     import oracle as O
     rng = np.random.default_rng(seed)
     a_idx = (np.arange(n_sample) * cfg.n_chi) // n_sample
@@ -148,10 +199,19 @@ def cpu_baseline(cfg, plan, inp, n_sample=144, seed=11):
         O.w_points(cfg.ells(), ("gg", "gs", "ss"), cfg.k_min, cfg.k_max, c1, c2, nc=cfg.n_cheb, P=P, M=M, Phi=Phi)
     t = time.time() - t0
     s_per_set = t * (cfg.n_chi * cfg.n_R) / n_sample
-    return {"value": 1.0 / s_per_set, "unit": "sets/s", "cores": O.max_threads(), "kind": "oracle",
-            "sample": "%d of %d (chi_a, R_b) points (stratified in chi), k-integrals at the oracle's first two "
-                      "refinement levels, %.1f s wall, scaled by points" % (n_sample, cfg.n_chi * cfg.n_R, t),
-            "s_per_set": s_per_set, "cpu": platform.processor() or platform.machine()}
+    out = {"value": 1.0 / s_per_set, "unit": "sets/s", "cores": O.max_threads(), "kind": "oracle",
+           "sample": "%d of %d (chi_a, R_b) points (stratified in chi), k-integrals at the oracle's first two "
+                     "refinement levels, %.1f s wall, scaled by points to one set (estimate)"
+                     % (n_sample, cfg.n_chi * cfg.n_R, t),
+           "s_per_set": s_per_set, "cpu": cpu_model()}
+    gpath = os.path.join(ROOT, "tests", "golden", "c%d_oracle.json" % config)
+    if os.path.exists(gpath):
+        g = json.load(open(gpath))
+        out["golden_whole_set"] = {"s": g.get("wall_s"), "threads": g.get("threads"),
+                                   "what": "the oracle's whole set of this workload when the stored values were "
+                                           "written (another host)"}
+    out["small_config_measured"] = cpu_small_config()
+    return out
 
 
 def serving_run(seconds, rate_hz=200.0, batch=16, precision="fp32", pool=32):
@@ -216,13 +276,18 @@ def serving_run(seconds, rate_hz=200.0, batch=16, precision="fp32", pool=32):
             time.sleep(dt)
         K1, K2 = kern(r.n_g, r.n_s)
         tickets.append(srv.submit(Ps[i % len(Ps)], K1, K2, r.n_g, r.n_s, r.ell_idx))
+        if (i + 1) % 2000 == 0:
+            log("serving: %d of %d requests submitted" % (i + 1, n))
     th.join()
     st = srv.stats()
     srv.close()
     plan.close()
-    return {"rate_hz": rate_hz, "requests": n, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+    return {"rate_hz": rate_hz, "requests": n, "seconds_of_arrivals": seconds, "p50_ms": st["p50_ms"],
+            "p99_ms": st["p99_ms"],
             "throughput_req_s": st["completed"] / (st["span_ms"] * 1e-3) if st["span_ms"] else None,
             "mean_fill": st["mean_fill"], "launches": st["launches"], "batch_slots": batch,
+            "max_sets_in_flight": st["max_sets_in_flight"], "set_bytes": st["set_bytes"],
+            "completed": st["completed"], "rejected": st["rejected"],
             "precision": precision, "plan_build_s": build_s,
             "workload": "200 master ell on [2,1000], chi 256, R 96, 128 Chebyshev nodes; per request 3-15 "
                         "clustering + 1-5 shear bins and 20-200 ell, Poisson arrivals; cosmologies cycle "
@@ -335,7 +400,7 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64-path and batch-1 timings")
-    ap.add_argument("--serving-seconds", type=float, default=5.0, help="seconds of Poisson arrivals (0: skip)")
+    ap.add_argument("--serving-seconds", type=float, default=60.0, help="seconds of Poisson arrivals (0: skip)")
     ap.add_argument("--sweep", action="store_true", help="only run the grid sweeps (one JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
@@ -366,7 +431,7 @@ def main():
     prec = args.precision
     log("building plan for config", args.config, cfg.name)
     t0 = time.time()
-    precs = ("fp64", "fp32", "bf16x3", "fp16x3") if prec != "bf16" else ("fp64", "bf16")
+    precs = ("fp64", "fp32", "bf16x3", "bf16", "fp16x3")
     plan = B.plan_for_config(cfg, precisions=precs)
     build_s = time.time() - t0
     log("plan built in %.1f s (%d k-nodes, basis %s bytes)" % (build_s, plan.kq_nodes, plan.basis_bytes))
@@ -429,15 +494,21 @@ def main():
         v.pop("algorithmic_flops", None)
         v.pop("algorithmic_bytes", None)
 
-    # accuracy of the timed path: cosmology 0 against the oracle's golden values
+    # accuracy of the timed path: cosmology 0 (the stored oracle values' cosmology) against them
     res = out[0].cpu().numpy()
     err = {}
+    gold = None
     gpath = os.path.join(ROOT, "tests", "golden", "c%d_oracle.json" % args.config)
     if os.path.exists(gpath):
         g = json.load(open(gpath))
         if g["seed"] == W.seed_for(args.config, 0):
-            e = g16_err(res, np.array(g["C"]), cfg.n_g, cfg.n_s)
-            err["max_rel_err_vs_oracle"] = float(e.max())
+            gold = np.array(g["C"])
+            err["max_rel_err_vs_oracle"] = float(g16_err(res, gold, cfg.n_g, cfg.n_s).max())
+    # per bin pair error of every precision against the oracle (the largest per pair type and the
+    # worst pairs), each from a call over the timed batch whose cosmology 0 is the stored one
+    perr = {}
+    if gold is not None:
+        perr[prec] = error_by_pair(res, gold, cfg.n_g, cfg.n_s, plan.ell)
     extras = {}
     if not args.no_extras:
         # FP64 path on the same batch (the mixed-vs-FP64 speedup compares equal work), and
@@ -450,15 +521,26 @@ def main():
             err["max_rel_err_vs_fp64_path"] = float(e.max())
         nb64 = Bn
         P64b = P[:nb64].double().contiguous()
+        P64b[0] = P64[0]  # cosmology 0 with its FP64 P, the oracle's input
+        out64 = torch.empty((nb64,) + tuple(out.shape[1:]), dtype=torch.float64, device=dev)
         for _ in range(2):
-            plan.forward(P64b, K1[:nb64].contiguous(), K2[:nb64].contiguous(), cfg.n_g, cfg.n_s, precision="fp64")
+            plan.forward(P64b, K1[:nb64].contiguous(), K2[:nb64].contiguous(), cfg.n_g, cfg.n_s, precision="fp64",
+                         out=out64)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(5):
-            plan.forward(P64b, K1[:nb64].contiguous(), K2[:nb64].contiguous(), cfg.n_g, cfg.n_s, precision="fp64")
+            plan.forward(P64b, K1[:nb64].contiguous(), K2[:nb64].contiguous(), cfg.n_g, cfg.n_s, precision="fp64",
+                         out=out64)
         torch.cuda.synchronize()
         ms64 = (time.perf_counter() - t0) * 1e3 / 5
-        extras["fp64_path"] = {"batch": nb64, "ms_per_step": ms64, "sets_per_s": nb64 / (ms64 * 1e-3)}
+        extras["fp64_path"] = {"batch": nb64, "ms_per_step": ms64, "sets_per_s": nb64 / (ms64 * 1e-3),
+                               "kernel": "contract_quad_f64_kernel" if fused_path("fp64", cfg.n_g + cfg.n_s, nb64)
+                               else "contract_kernel"}
+        if gold is not None:
+            r0 = out64[0].cpu().numpy()
+            extras["fp64_path"]["max_rel_err_vs_oracle"] = float(g16_err(r0, gold, cfg.n_g, cfg.n_s).max())
+            perr["fp64"] = error_by_pair(r0, gold, cfg.n_g, cfg.n_s, plan.ell)
+        del out64, P64b
         extras["mixed_vs_fp64_speedup"] = value / extras["fp64_path"]["sets_per_s"]
         if prec != "fp32":
             # the FP32 path on the same batch: throughput, its fused kernel's roofline, its error
@@ -483,15 +565,19 @@ def main():
             r32["traffic"] = counter_traffic("contract_quad_kernel", cfg.name, Bn, "fp32")
             f32 = {"batch": Bn, "ms_per_step": ms32, "sets_per_s": Bn / (ms32 * 1e-3), "stage_ms_per_launch": pl32,
                    "fused_kernel_roofline": r32}
-            gpath = os.path.join(ROOT, "tests", "golden", "c%d_oracle.json" % args.config)
-            if os.path.exists(gpath):
-                g = json.load(open(gpath))
-                if g["seed"] == W.seed_for(args.config, 0):
-                    f32["max_rel_err_vs_oracle"] = float(g16_err(out[0].cpu().numpy(), np.array(g["C"]), cfg.n_g,
-                                                                 cfg.n_s).max())
+            if gold is not None:
+                r0 = out[0].cpu().numpy()
+                f32["max_rel_err_vs_oracle"] = float(g16_err(r0, gold, cfg.n_g, cfg.n_s).max())
+                perr["fp32"] = error_by_pair(r0, gold, cfg.n_g, cfg.n_s, plan.ell)
             extras["fp32_path"] = f32
-            step()  # out holds the timed path's result again
-            torch.cuda.synchronize()
+        if gold is not None:
+            P32 = P if P.dtype == torch.float32 else P.float()
+            for pr in ("fp16x3", "bf16x3", "bf16"):
+                if pr not in perr:
+                    plan.forward(P32, K1, K2, cfg.n_g, cfg.n_s, precision=pr, out=out)
+                    perr[pr] = error_by_pair(out[0].cpu().numpy(), gold, cfg.n_g, cfg.n_s, plan.ell)
+        step()  # out holds the timed path's result again
+        torch.cuda.synchronize()
         # differentiation at the same batch (FP32): a forward that keeps w, then the adjoint from
         # dC = dL/dC to the gradients with respect to P at the nodes, K_chi and K_chi2
         P32 = P if P.dtype == torch.float32 else P.float()
@@ -588,7 +674,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
-        cpu = cpu_baseline(cfg, plan, inps[0])
+        cpu = cpu_baseline(cfg, plan, inps[0], args.config)
 
     line = {
         "metric": METRIC,
@@ -616,6 +702,12 @@ def main():
                           "hardware": "2x AMD EPYC 7532, 32 threads (CPU)", "grid": "N5K fiducial, not config 2"},
     }
     line.update(err)
+    if perr:
+        line["error_by_precision"] = {
+            "what": "cosmology 0 of the timed batch against the oracle's stored values: element-wise relative "
+                    "error (cross spectra floored at 1e-3 of the geometric mean of the two auto spectra), the "
+                    "largest per pair type and the three worst pairs with the multipole of their peak",
+            "batch": Bn, **perr}
     line.update(extras)
     if serving:
         line["p50_ms"] = serving["p50_ms"]

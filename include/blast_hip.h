@@ -260,27 +260,38 @@ blast_status blast_cl_backward(blast_plan *plan, const blast_cl_args *args, cons
  * chains in parallel is the way to use a whole machine (Sec. "Discussion").  The
  * server turns independent requests (one cosmology each, with their own bins and
  * multipoles) into batched forward calls:
- *  - it allocates `n_sets` slot-sets of `batch` slots each (device inputs, outputs and
- *    workspace) within `hbm_budget`; each set has its own stream, so a batch that is
- *    formed while others run overlaps with them on the device;
- *  - a scheduler thread admits queued requests into free slots as soon as a set is
- *    free, launches a set when it is full, when its oldest request has waited
- *    `max_wait_ms`, or when no other set is running, and completes requests as their
- *    set's event fires;
- *  - every set replays one hipGraph captured at creation (fixed shapes: bins padded to
- *    max_g + max_s, every plan multipole), so a launch is one graph launch;
- *  - each request's result depends only on its own inputs (per-cosmology arithmetic
- *    never mixes batch entries), so it is the same alone and in any mix.          */
+ *  - its device memory (hbm_budget) is split into `n_sets` slot-sets, each one arena with
+ *    a stream of its own, so that a batch formed while others run overlaps with them;
+ *  - a request's bins fall in a bucket: its clustering bins rounded up to a multiple of 4
+ *    (at most max_g; 0 when it has none) and max_s shear bins.  A launch takes the bucket
+ *    of its largest request; at creation a hipGraph is captured for every bucket and every
+ *    batch size 1, 2, 4, ... up to `batch` whose inputs, outputs and forward scratch fit the
+ *    arena (in the arena's layout for that shape), and a launch replays the smallest that
+ *    holds its requests;
+ *  - admission is by memory: a scheduler thread moves queued requests, in arrival order,
+ *    into the forming set while the launch they would make still fits its arena, and
+ *    launches the set when the next request does not fit, when its oldest request has
+ *    waited max_wait_ms, or when no other set is running; requests complete as their set's
+ *    event fires;
+ *  - every launch computes all plan multipoles: the contraction streams basis rows in
+ *    16-row tiles, and a request's multipoles are a subset spread over the plan's list, so
+ *    it touches nearly every tile whatever its count; the requested ones are picked out;
+ *  - each request's result depends only on its own inputs (per-cosmology arithmetic never
+ *    mixes batch entries and a bucket only adds bins whose kernels are zero), so it is the
+ *    same alone and in any mix.  The plan's memory (the basis) is fixed by its grids; the
+ *    budget is the server's. */
 
 typedef struct blast_server blast_server;
 
 typedef struct {
     int32_t precision;    /* blast_precision resident in the plan                        */
     int32_t p_dtype;      /* dtype of request P: 0 FP64, 1 FP32                           */
-    int32_t batch;        /* slots per set (cosmologies per launch), >= 1                */
-    int32_t n_sets;       /* sets (concurrent batches); 0 = as many as hbm_budget allows, max 4 */
+    int32_t batch;        /* most requests per launch, >= 1                               */
+    int32_t n_sets;       /* sets (concurrent batches), <= 4; 0 = as many as hbm_budget holds */
     int32_t max_g, max_s; /* largest clustering / shear bin counts a request may carry    */
-    size_t hbm_budget;    /* device bytes the server may allocate; 0 = 8 GiB              */
+    size_t hbm_budget;    /* device bytes the server may allocate; 0 = 8 GiB.  Each set gets
+                             min(the bytes of `batch` requests of the largest bucket,
+                             hbm_budget / n_sets)                                          */
     int32_t max_queue;    /* queued requests before submit returns BUSY; 0 = 4096         */
     double max_wait_ms;   /* launch a partly filled set after this wait                    */
     int32_t use_graphs;   /* 1: replay captured hipGraphs, 0: plain forward calls          */
@@ -301,15 +312,33 @@ typedef struct {
     double mean_fill;       /* mean requests per launch                                     */
     double p50_ms, p99_ms;  /* submit -> completion latency of completed requests           */
     double span_ms;         /* first submit -> last completion                              */
+    int64_t cancelled;      /* requests cancelled before they ran                           */
+    int64_t max_sets_in_flight; /* most sets running at once                                */
+    int64_t n_sets;         /* sets created                                                 */
+    int64_t set_bytes;      /* device bytes of one set's arena                              */
 } blast_server_stats;
 
-/* Errors: INVALID, OOM (budget below one set), HIP. */
+/* Errors: INVALID, OOM (the budget's share per set holds no request), UNSUPPORTED, HIP. */
 blast_status blast_server_create(blast_plan *plan, const blast_server_desc *desc, blast_server **out);
-/* Queues a request.  BUSY when the queue is full, INVALID for a malformed request. */
+/* Bytes of the arena a launch of `count` requests whose largest bins are (n_g, n_s) takes,
+ * and (set_bytes, nullable) the bytes of one set's arena.  Errors: INVALID. */
+blast_status blast_server_footprint(const blast_server *srv, int32_t n_g, int32_t n_s, int32_t count, size_t *bytes,
+                                    size_t *set_bytes);
+/* Queues a request.  BUSY when the queue is full, INVALID for a malformed request, OOM when a
+ * launch of this request alone does not fit a set's arena. */
 blast_status blast_server_submit(blast_server *srv, const blast_request *req, uint64_t *ticket);
+/* Cancels a request that has not started: it completes at once with status BLAST_E_CANCELLED
+ * (as wait or poll report).  BUSY if it is running (it will complete normally), INVALID if
+ * the ticket is not pending. */
+blast_status blast_server_cancel(blast_server *srv, uint64_t ticket);
 /* Waits up to timeout_ms (< 0: forever) for a ticket.  Returns BUSY on timeout; on
- * completion writes the request's status and latency (either may be NULL). */
+ * completion writes the request's status and latency (either may be NULL) and forgets the
+ * ticket. */
 blast_status blast_server_wait(blast_server *srv, uint64_t ticket, int32_t timeout_ms, blast_status *req_status,
+                               double *latency_ms);
+/* Non-blocking wait: *done = 1 and the status and latency as wait writes them if the ticket
+ * has completed (the ticket is then forgotten), else *done = 0. */
+blast_status blast_server_poll(blast_server *srv, uint64_t ticket, int32_t *done, blast_status *req_status,
                                double *latency_ms);
 blast_status blast_server_stats_get(blast_server *srv, blast_server_stats *stats);
 /* Drains pending work, stops the scheduler and frees the server. */

@@ -75,7 +75,8 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
                 ("launches", C.c_int64), ("queued", C.c_int64), ("in_flight", C.c_int64),
                 ("mean_fill", C.c_double), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
-                ("span_ms", C.c_double)]
+                ("span_ms", C.c_double), ("cancelled", C.c_int64), ("max_sets_in_flight", C.c_int64),
+                ("n_sets", C.c_int64), ("set_bytes", C.c_int64)]
 
 
 EXPORTS = [
@@ -85,8 +86,8 @@ EXPORTS = [
     "blast_plan_profile",
     "blast_plan_profile_read", "blast_plan_save", "blast_plan_load", "blast_plan_eval_points",
     "blast_plan_grids", "blast_plan_limber_k", "blast_cl_limber",
-    "blast_server_create", "blast_server_submit", "blast_server_wait",
-    "blast_server_stats_get", "blast_server_destroy",
+    "blast_server_create", "blast_server_footprint", "blast_server_submit", "blast_server_cancel",
+    "blast_server_wait", "blast_server_poll", "blast_server_stats_get", "blast_server_destroy",
 ]
 STAGES = ("projection", "contraction", "quad_R", "quad_chi")
 
@@ -122,6 +123,11 @@ def lib():
         L.blast_server_submit.argtypes = [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]
         L.blast_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(C.c_int),
                                         C.POINTER(C.c_double)]
+        L.blast_server_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_int),
+                                        C.POINTER(C.c_double)]
+        L.blast_server_cancel.argtypes = [C.c_void_p, C.c_uint64]
+        L.blast_server_footprint.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t),
+                                             C.POINTER(C.c_size_t)]
         L.blast_server_stats_get.argtypes = [C.c_void_p, C.POINTER(ServerStats)]
         L.blast_server_destroy.argtypes = [C.c_void_p]
         L.blast_plan_profile.argtypes = [C.c_void_p, C.c_int32]
@@ -591,12 +597,37 @@ class Server:
         return t.value
 
     def wait(self, ticket, timeout_ms=-1):
+        """(C [pairs, ell], latency in ms) of a ticket; raises BlastError with the request's status
+        if it failed or was cancelled."""
         st, lat = C.c_int(), C.c_double()
         _check(lib().blast_server_wait(self._h, ticket, timeout_ms, C.byref(st), C.byref(lat)))
         keep = self._live.pop(ticket)
         if st.value != OK:
-            raise BlastError(st.value, "request %d failed" % ticket)
+            raise BlastError(st.value, "request %d did not complete" % ticket)
         return keep[4], lat.value
+
+    def poll(self, ticket):
+        """None while the ticket is pending, else what wait() returns (or raises)."""
+        done, st, lat = C.c_int32(), C.c_int(), C.c_double()
+        _check(lib().blast_server_poll(self._h, ticket, C.byref(done), C.byref(st), C.byref(lat)))
+        if not done.value:
+            return None
+        keep = self._live.pop(ticket)
+        if st.value != OK:
+            raise BlastError(st.value, "request %d did not complete" % ticket)
+        return keep[4], lat.value
+
+    def cancel(self, ticket):
+        """Cancel a request that has not started (blast_server_cancel); wait() then raises
+        BlastError with status E_CANCELLED."""
+        _check(lib().blast_server_cancel(self._h, ticket))
+
+    def footprint(self, n_g, n_s, count=1):
+        """(arena bytes of a launch of `count` requests whose largest bins are (n_g, n_s), bytes of
+        one set's arena)."""
+        b, sb = C.c_size_t(), C.c_size_t()
+        _check(lib().blast_server_footprint(self._h, n_g, n_s, count, C.byref(b), C.byref(sb)))
+        return b.value, sb.value
 
     def stats(self):
         s = ServerStats()

@@ -3014,6 +3014,10 @@ size_t workspace_bytes(const blast_plan *p, int batch, int prec, int n_bins) {
     return workspace_bytes_impl(p, batch, prec, n_bins);
 }
 
+size_t forward_workspace_bytes(const blast_plan *p, int batch, int prec, int n_bins) {
+    return layout_of(p, batch, prec, n_bins, true, false).total;
+}
+
 blast_status forward(blast_plan *p, const blast_cl_args *a, hipStream_t s) {
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     bool prof = false;

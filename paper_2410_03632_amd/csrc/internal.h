@@ -107,6 +107,8 @@ blast_status forward(blast_plan *p, const blast_cl_args *a, hipStream_t s);
 blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, void *dP, double *dK_chi,
                       double *dK_chi2, hipStream_t s);
 size_t workspace_bytes(const blast_plan *p, int batch, int prec, int n_bins);
+// scratch of a forward call alone (no w_save), the part the server reserves per launch
+size_t forward_workspace_bytes(const blast_plan *p, int batch, int prec, int n_bins);
 // the forward that allocates nothing: its scratch is a fixed device array, whose address on a
 // device noalloc_init (called with that device current, when a plan is made there) looks up once
 void noalloc_init(int device);
