@@ -390,6 +390,33 @@ def sweep_run(steps=5):
     return out
 
 
+def gradient_run(plan, cfg, P, K1, K2, out, Bn, steps, warmup):
+    """The FP32 gradient step: a forward that keeps w, then the adjoint from dC = dL/dC to the
+    gradients with respect to P at the nodes, K_chi and K_chi2, timed over `steps` calls."""
+    import torch
+    P32 = P if P.dtype == torch.float32 else P.float()
+    wg = torch.empty(Bn * cfg.n_chi * cfg.n_R * plan.rows_pad, dtype=torch.float32, device=P.device)
+    yg = torch.empty(plan.y_numel(Bn, cfg.n_g + cfg.n_s), dtype=torch.float32, device=P.device)
+    outg = torch.empty_like(out)
+    dC = torch.ones_like(out)
+
+    def grad_step():
+        plan.forward(P32, K1, K2, cfg.n_g, cfg.n_s, precision="fp32", out=outg, w_save=wg, y_save=yg)
+        return plan.backward(P32, K1, K2, cfg.n_g, cfg.n_s, dC, precision="fp32", w_save=wg, y_save=yg)
+
+    for _ in range(warmup):
+        grad_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        grads = grad_step()
+    torch.cuda.synchronize()
+    msg = (time.perf_counter() - t0) * 1e3 / steps
+    return {"batch": Bn, "ms_per_step": msg, "sets_per_s": Bn / (msg * 1e-3),
+            "finite": bool(all(torch.isfinite(g).all().item() for g in grads)),
+            "what": "forward keeping w and Y + adjoint: dC -> dP (nodal), dK_chi, dK_chi2"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -402,6 +429,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64-path and batch-1 timings")
     ap.add_argument("--serving-seconds", type=float, default=60.0, help="seconds of Poisson arrivals (0: skip)")
     ap.add_argument("--sweep", action="store_true", help="only run the grid sweeps (one JSON line)")
+    ap.add_argument("--only-gradient", action="store_true",
+                    help="only time the FP32 gradient step (forward keeping w, then the adjoint) at --batch")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -455,6 +484,12 @@ def main():
 
     def step():
         plan.forward(P, K1, K2, cfg.n_g, cfg.n_s, precision=prec, out=out, workspace=ws)
+
+    if args.only_gradient:
+        print(json.dumps({"gradient_fp32": gradient_run(plan, cfg, P, K1, K2, out, Bn, args.steps, args.warmup)}),
+              flush=True)
+        plan.close()
+        return
 
     for _ in range(args.warmup):
         step()
@@ -580,27 +615,7 @@ def main():
         torch.cuda.synchronize()
         # differentiation at the same batch (FP32): a forward that keeps w, then the adjoint from
         # dC = dL/dC to the gradients with respect to P at the nodes, K_chi and K_chi2
-        P32 = P if P.dtype == torch.float32 else P.float()
-        wg = torch.empty(Bn * cfg.n_chi * cfg.n_R * plan.rows_pad, dtype=torch.float32, device=dev)
-        outg = torch.empty_like(out)
-        dC = torch.ones_like(out)
-
-        def grad_step():
-            plan.forward(P32, K1, K2, cfg.n_g, cfg.n_s, precision="fp32", out=outg, w_save=wg)
-            return plan.backward(P32, K1, K2, cfg.n_g, cfg.n_s, dC, precision="fp32", w_save=wg)
-
-        for _ in range(2):
-            grad_step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(5):
-            grads = grad_step()
-        torch.cuda.synchronize()
-        msg = (time.perf_counter() - t0) * 1e3 / 5
-        extras["gradient_fp32"] = {"batch": Bn, "ms_per_step": msg, "sets_per_s": Bn / (msg * 1e-3),
-                                   "finite": bool(all(torch.isfinite(g).all().item() for g in grads)),
-                                   "what": "forward keeping w + adjoint: dC -> dP (nodal), dK_chi, dK_chi2"}
-        del wg, outg, dC, grads
+        extras["gradient_fp32"] = gradient_run(plan, cfg, P, K1, K2, out, Bn, 5, 2)
         P1, K11, K21 = P[:1].contiguous(), K1[:1].contiguous(), K2[:1].contiguous()
         lat = []
         for i in range(12):

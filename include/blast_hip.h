@@ -215,6 +215,12 @@ typedef struct {
                              NULL = plan-owned scratch (then calls on one plan must not
                              overlap in time)                                        */
     size_t workspace_bytes;
+    void *y_save;         /* device, nullable: [batch][rows_pad][n_chi][nbp] R-quadrature sums
+                             Y[row][a][bin] = sum_b wR_b K_bin(R_b chi_a) w[a, b][row] (FP64 for
+                             FP64, else FP32; nbp = 16 for at most 16 bins, else 32; bins past
+                             n_g + n_s hold no values); a forward writes it, and a backward given
+                             w_save and y_save of a forward with the same inputs reads it instead
+                             of summing w again                                             */
 } blast_cl_args;
 
 /* Device scratch for one forward or backward call with these sizes. */

@@ -46,7 +46,7 @@ class ClArgs(C.Structure):
         ("K_chi", C.c_void_p), ("K_chi2", C.c_void_p), ("types", C.c_uint32),
         ("n_ell_out", C.c_int32), ("ell_idx", C.POINTER(C.c_int32)),
         ("C", C.c_void_p), ("w_save", C.c_void_p),
-        ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+        ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t), ("y_save", C.c_void_p),
     ]
 
 
@@ -348,7 +348,7 @@ class Plan:
         args = ClArgs(B, prec, 0 if P.dtype == torch.float64 else 1, 1 if coef else 0, P.data_ptr(), n_g, n_s,
                       K_chi.data_ptr(), K_chi2.data_ptr(), tmask, n_out,
                       idx_arr.ctypes.data_as(C.POINTER(C.c_int32)) if idx_arr is not None else None,
-                      None, None, None, 0)
+                      None, None, None, 0, None)
         return args, (P, K_chi, K_chi2, idx_arr), (B, npair, n_l), prec
 
     def limber_k(self):
@@ -416,20 +416,28 @@ class Plan:
             out[:, :, hi] = self.limber(P_limber, K_chi, n_g, n_s, order=order, types=types, ell_idx=hi)
         return out
 
-    def _w_ws(self, args, B, prec, w_save, workspace):
+    def y_numel(self, batch, n_bins):
+        """Values of a y_save buffer: batch * rows_pad * n_chi * (16 for at most 16 bins, else 32)."""
+        return batch * self.rows_pad * len(self.chi) * (16 if n_bins <= 16 else 32)
+
+    def _w_ws(self, args, B, prec, w_save, workspace, y_save=None, n_bins=0):
         import torch
+        wdt = torch.float64 if prec == FP64 else torch.float32
         if w_save is not None:
-            wdt = torch.float64 if prec == FP64 else torch.float32
             if w_save.dtype != wdt or w_save.numel() != B * len(self.chi) * len(self.R) * self.rows_pad \
                     or not w_save.is_contiguous():
                 raise ValueError("w_save must hold batch*n_chi*n_R*rows_pad contiguous values of %s" % wdt)
             args.w_save = w_save.data_ptr()
+        if y_save is not None:
+            if y_save.dtype != wdt or y_save.numel() != self.y_numel(B, n_bins) or not y_save.is_contiguous():
+                raise ValueError("y_save must hold %d contiguous values of %s" % (self.y_numel(B, n_bins), wdt))
+            args.y_save = y_save.data_ptr()
         if workspace is not None:
             args.workspace = workspace.data_ptr()
             args.workspace_bytes = workspace.numel() * workspace.element_size()
 
     def forward(self, P, K_chi, K_chi2, n_g, n_s, *, precision="fp64", types=None, ell_idx=None,
-                out=None, w_save=None, workspace=None, stream=None, coef=False):
+                out=None, w_save=None, workspace=None, stream=None, coef=False, y_save=None):
         """C[batch][pair][ell] for device tensors P [B, n_chi, n_R, n_cheb] (float64/float32; nodal
         values, or Chebyshev coefficients with coef=True), K_chi [B, bins, n_chi] and
         K_chi2 [B, bins, n_chi, n_R] (float64)."""
@@ -441,7 +449,7 @@ class Plan:
         elif tuple(out.shape) != shape or out.dtype != torch.float64 or not out.is_contiguous():
             raise ValueError("out must be a contiguous float64 tensor of shape %s" % (shape,))
         args.C = out.data_ptr()
-        self._w_ws(args, shape[0], prec, w_save, workspace)
+        self._w_ws(args, shape[0], prec, w_save, workspace, y_save, n_g + n_s)
         if stream is None:
             stream = torch.cuda.current_stream(P.device).cuda_stream
         _check(lib().blast_cl_forward(self._h, C.byref(args), C.c_void_p(stream)))
@@ -463,7 +471,7 @@ class Plan:
         return out
 
     def backward(self, P, K_chi, K_chi2, n_g, n_s, dC, *, precision="fp64", types=None, ell_idx=None,
-                 w_save=None, workspace=None, stream=None, coef=False, want=("P", "K_chi", "K_chi2")):
+                 w_save=None, workspace=None, stream=None, coef=False, want=("P", "K_chi", "K_chi2"), y_save=None):
         """Gradients (dP, dK_chi, dK_chi2) of a scalar loss given dC = dL/dC (device float64,
         shaped like the forward output); entries not in `want` are None."""
         import torch
@@ -471,7 +479,7 @@ class Plan:
         P, K_chi, K_chi2 = keep[:3]
         if tuple(dC.shape) != shape or dC.dtype != torch.float64 or not dC.is_contiguous() or not dC.is_cuda:
             raise ValueError("dC must be a contiguous float64 device tensor of shape %s" % (shape,))
-        self._w_ws(args, shape[0], prec, w_save, workspace)
+        self._w_ws(args, shape[0], prec, w_save, workspace, y_save, n_g + n_s)
         dP = torch.empty_like(P) if "P" in want else None
         dK = torch.empty_like(K_chi) if "K_chi" in want else None
         dK2 = torch.empty_like(K_chi2) if "K_chi2" in want else None
@@ -497,20 +505,21 @@ def _make_cl_function():
             wdt = torch.float64 if PRECISION.get(precision, precision) == FP64 else torch.float32
             B = P.shape[0] if P.dim() == 4 else 1
             w = torch.empty(B * len(plan.chi) * len(plan.R) * plan.rows_pad, dtype=wdt, device=P.device)
-            C = plan.forward(P, K_chi, K_chi2, n_g, n_s, precision=precision, w_save=w, coef=coef)
+            y = torch.empty(plan.y_numel(B, n_g + n_s), dtype=wdt, device=P.device)
+            C = plan.forward(P, K_chi, K_chi2, n_g, n_s, precision=precision, w_save=w, coef=coef, y_save=y)
             ctx.plan, ctx.args = plan, (n_g, n_s, precision, coef)
-            ctx.save_for_backward(P, K_chi, K_chi2, w)
+            ctx.save_for_backward(P, K_chi, K_chi2, w, y)
             return C if P.dim() == 4 else C[0]
 
         @staticmethod
         def backward(ctx, gC):
-            P, K_chi, K_chi2, w = ctx.saved_tensors
+            P, K_chi, K_chi2, w, y = ctx.saved_tensors
             n_g, n_s, precision, coef = ctx.args
             squeeze = P.dim() == 3
             g = gC.unsqueeze(0) if squeeze else gC
             want = tuple(nm for nm, need in zip(("P", "K_chi", "K_chi2"), ctx.needs_input_grad[1:4]) if need)
             dP, dK, dK2 = ctx.plan.backward(P, K_chi, K_chi2, n_g, n_s, g.contiguous().double(), precision=precision,
-                                            w_save=w, coef=coef, want=want)
+                                            w_save=w, coef=coef, want=want, y_save=y)
             if squeeze:
                 dP = dP[0] if dP is not None else None
                 dK = dK[0] if dK is not None else None

@@ -417,6 +417,18 @@ __global__ void to_f32_kernel(const double *__restrict__ src, float *__restrict_
     dst[pt * blk + tiled_off(row, col, ncp / 16, 4)] = (float)src[i];
 }
 
+// FP32 copy of the transposed basis per point (Ttilde^T: n the row, the basis row the column) in the
+// tiled layout, the A operand of the transposed contraction of the adjoint
+__global__ void to_f32t_kernel(const double *__restrict__ src, float *__restrict__ dst, size_t n, int rows_pad,
+                               int ncp) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const size_t blk = (size_t)rows_pad * ncp;
+    const size_t pt = i / blk, rem = i % blk;
+    const int row = (int)(rem / ncp), col = (int)(rem % ncp);
+    dst[pt * blk + tiled_off(col, row, rows_pad / 16, 4)] = (float)src[i];
+}
+
 __device__ inline uint16_t f32_to_bf16_rne(float f) {
     uint32_t u = __float_as_uint(f);
     u += 0x7FFFu + ((u >> 16) & 1u);
@@ -631,6 +643,23 @@ blast_status build_basis(blast_plan *p, hipStream_t s) {
         }
     }
     cleanup();
+    return BLAST_OK;
+}
+
+blast_status ensure_f32t(blast_plan *p, hipStream_t s) {
+    if (p->basis.f32t) return BLAST_OK;
+    const size_t n = (size_t)p->NP * p->rows_pad * p->nc_pad;
+    hipError_t e = hipMalloc(&p->basis.f32t, n * sizeof(float));
+    if (e != hipSuccess) {
+        p->basis.f32t = nullptr;
+        set_error("transposed FP32 basis: %s", hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? BLAST_E_OOM : BLAST_E_HIP;
+    }
+    hipLaunchKernelGGL(to_f32t_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->basis.f64, p->basis.f32t,
+                       n, p->rows_pad, p->nc_pad);
+    BLAST_HIP_TRY(hipGetLastError());
+    // once per plan: finished before any call on another stream can see the pointer
+    BLAST_HIP_TRY(hipStreamSynchronize(s));
     return BLAST_OK;
 }
 

@@ -613,7 +613,7 @@ __global__ __launch_bounds__(256) void contract_kernel(const typename Cfg<PREC>:
 // while step s runs on the MFMA units.
 constexpr int kTilesPerWave = 3;
 
-template <int PREC, int WPE = (PREC == BLAST_BF16X3 ? 2 : 4)>
+template <int PREC, int WPE = (PREC == BLAST_BF16X3 ? 2 : 4), int BTT = Cfg<PREC>::BT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE))) void contract_tiled_kernel(const typename Cfg<PREC>::E *__restrict__ basis,
                                                              const uint16_t *__restrict__ basis_lo,
                                                              const float *__restrict__ scale,
@@ -622,7 +622,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE))) void
                                                              int rows_pad, int ncp, float *__restrict__ w_out) {
     using C = Cfg<PREC>;
     using E = typename C::E;
-    constexpr int VEC = C::VEC, BT = C::BT, BTN = BT / 16, TPW = kTilesPerWave;
+    constexpr int VEC = C::VEC, BT = BTT, BTN = BT / 16, TPW = kTilesPerWave;
     constexpr bool X3 = PREC == BLAST_BF16X3;
     constexpr int KSTEP = 4 * VEC;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -2200,6 +2200,114 @@ __global__ __launch_bounds__(256) void adj_dy_kernel(const double *__restrict__ 
     }
 }
 
+// FP32 path of adj_dy_kernel: kAdjRG rows of one cosmology per work-group.  Each row's symmetric
+// S (pair cotangents times N_t(l), as adj_dy_kernel builds it) goes to LDS in FP64 and to Sg; the
+// weighted kernels Ktil[l][a] = wchi_a chi_a K_l(chi_a) of the cosmology sit in LDS transposed
+// ([a][l], rows padded to 16 a and NB + 4 floats); then per row
+//   dY[a][m] = sum_l S[m][l] Ktil[l][a]      (v_mfma_f32_16x16x4_f32: M = bins m, N = chi nodes a)
+// with the K order permuted so that a lane reads 4 consecutive l of S and of Ktil; a lane's result
+// is 4 consecutive m of one a, stored as 16 bytes (a wave writes 1 KB of dY contiguously).
+constexpr int kAdjRG = 8;
+template <int NB>
+__global__ __launch_bounds__(256) void adj_dy_mfma_kernel(const double *__restrict__ dC, const double *__restrict__ Kchi,
+                                                          const double *__restrict__ wchi, const double *__restrict__ chi,
+                                                          const double *__restrict__ pref, int n_chi, int rows,
+                                                          int rows_pad, int n_ell, Slots slot_type, int ng, int ns,
+                                                          uint32_t types, int npairs, int n_out, EllInv inv,
+                                                          float *__restrict__ dY, double *__restrict__ Sg) {
+    constexpr int KS = NB + 4;
+    extern __shared__ __align__(16) unsigned char smem_dy[];
+    double *Sd = (double *)smem_dy;                          // [kAdjRG][NB][NB]
+    float *KtT = (float *)(Sd + (size_t)kAdjRG * NB * NB);  // [n_chi rounded to 16][KS]
+    const int beta = blockIdx.y, row0 = blockIdx.x * kAdjRG;
+    const int nbins = ng + ns;
+    const int nca = (n_chi + 15) / 16 * 16;
+    for (int i = threadIdx.x; i < kAdjRG * NB * NB; i += blockDim.x) Sd[i] = 0.0;
+    const double *Kb = Kchi + (size_t)beta * nbins * n_chi;
+    for (int i = threadIdx.x; i < nca * NB; i += blockDim.x) {
+        const int a = i / NB, l = i % NB;
+        KtT[(size_t)a * KS + l] = (a < n_chi && l < nbins) ? (float)(wchi[a] * chi[a] * Kb[(size_t)l * n_chi + a]) : 0.f;
+    }
+    __syncthreads();
+    for (int r = 0; r < kAdjRG; ++r) {
+        const int row = row0 + r;
+        if (row >= rows) break;
+        const int slot = row / n_ell, il = row % n_ell;
+        const int t = slot_type.s[slot];
+        const int io = inv.io[il];
+        if (!((t & types) && io >= 0)) continue;
+        int off, ntp;
+        if (t == BLAST_GG) {
+            off = 0;
+            ntp = ng * (ng + 1) / 2;
+        } else if (t == BLAST_GS) {
+            off = (types & BLAST_GG) ? ng * (ng + 1) / 2 : 0;
+            ntp = ng * ns;
+        } else {
+            off = ((types & BLAST_GG) ? ng * (ng + 1) / 2 : 0) + ((types & BLAST_GS) ? ng * ns : 0);
+            ntp = ns * (ns + 1) / 2;
+        }
+        const double pf = pref[row];
+        double *S = Sd + (size_t)r * NB * NB;
+        for (int q = threadIdx.x; q < ntp; q += blockDim.x) {
+            int i, j;
+            if (t == BLAST_GS) {
+                i = q / ns;
+                j = ng + q % ns;
+            } else {
+                const int n = t == BLAST_GG ? ng : ns, base = t == BLAST_GG ? 0 : ng;
+                int rr = 0, pp = q;
+                while (pp >= n - rr) {
+                    pp -= n - rr;
+                    ++rr;
+                }
+                i = base + rr;
+                j = base + rr + pp;
+            }
+            const double g = pf * dC[((size_t)beta * npairs + off + q) * n_out + io];
+            if (i == j) {
+                S[i * NB + i] = 2.0 * g;
+            } else {
+                S[i * NB + j] = g;
+                S[j * NB + i] = g;
+            }
+        }
+    }
+    __syncthreads();
+    for (int r = 0; r < kAdjRG; ++r) {
+        const int row = row0 + r;
+        if (row >= rows) break;
+        double *sg = Sg + ((size_t)beta * rows_pad + row) * NB * NB;
+        for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) sg[i] = Sd[(size_t)r * NB * NB + i];
+    }
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    constexpr int MT = NB / 16;
+    const int AT = nca / 16;
+    for (int tile = wv; tile < kAdjRG * MT * AT; tile += 4) {
+        const int r = tile / (MT * AT), mt = (tile / AT) % MT, at = tile % AT;
+        const int row = row0 + r;
+        if (row >= rows) break;  // tiles are ordered by row
+        const double *S = Sd + (size_t)r * NB * NB + (size_t)(16 * mt + lr) * NB;
+        const float *kt = KtT + (size_t)(16 * at + lr) * KS;
+        f4 acc = f4{0, 0, 0, 0};
+#pragma unroll
+        for (int h = 0; h < NB / 16; ++h) {
+            const int l0 = 16 * h + 4 * lk;
+            const double2 s0 = *(const double2 *)(S + l0), s1 = *(const double2 *)(S + l0 + 2);
+            const float4 k = *(const float4 *)(kt + l0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32((float)s0.x, k.x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32((float)s0.y, k.y, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32((float)s1.x, k.z, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32((float)s1.y, k.w, acc, 0, 0, 0);
+        }
+        const int a = 16 * at + lr;
+        if (a < n_chi)
+            *(float4 *)(dY + (((size_t)beta * rows_pad + row) * n_chi + a) * NB + 16 * mt + 4 * lk) =
+                make_float4(acc[0], acc[1], acc[2], acc[3]);
+    }
+}
+
 // dK_chi[beta][l][a] = wchi_a chi_a sum_{row, m} S[row][m][l] Y[row][a][m]
 // Work-group = (64 chi nodes, cosmology), 4 waves: lane = chi node, wave w takes rows w, w + 4, ...
 // and keeps NB sums (one per l).  A wave copies its row's S (NB x NB) into its own LDS slot with
@@ -2307,6 +2415,95 @@ __global__ __launch_bounds__(256) void adj_w_kernel(const T *__restrict__ dY, co
             double v = 0.0;
             for (int row = 0; row < rows; ++row) v += dYa[row * DS + m] * (double)wr[row];
             dK2[(((size_t)beta * nbins + m) * n_chi + a) * nR + b] = wR[b] * v;
+        }
+    }
+}
+
+// FP32 path of adj_w_kernel on MFMA (v_mfma_f32_16x16x4_f32), per (chi_a, cosmology):
+//   dw^T [rows x n_R] = dY [rows x NB] x Kh^T [NB x n_R],     Kh[b][m] = wR_b K2_m(a, b)
+//   dK2  [n_R x NB]   = w  [n_R x rows] x dY [rows x NB]      (then times wR_b)
+// The K order of an MFMA is a free permutation shared by its operands: for dw, MFMA s of a tile
+// takes bins 4 lk + s % 4 + 16 (s / 4) from lane group lk, so a lane reads its row's bins as
+// 16-byte pieces; for dK2, MFMA e of a 16-row chunk takes row 16 c + 4 lk + e, so a lane reads w
+// of its node and dY^T of its bin as 16-byte pieces.  Kh and dY^T (rows past `rows` zero) sit in
+// LDS; w and dY are read from global memory.  Wave v makes the dw tiles v, v + 4, ... and the dK2
+// node tiles v, v + 4.
+template <int NB>
+__global__ __launch_bounds__(256) void adj_w_mfma_kernel(const float *__restrict__ dY, const float *__restrict__ w,
+                                                         const double *__restrict__ Kchi2,
+                                                         const double *__restrict__ wR, int NP, int nR, int n_chi,
+                                                         int rows, int rows_pad, int nbins, float *__restrict__ dw,
+                                                         double *__restrict__ dK2) {
+    extern __shared__ __align__(16) unsigned char smem_aw[];
+    const int nRt = (nR + 15) / 16, nRp = 16 * nRt;
+    float *Kh = (float *)smem_aw;                 // [nRp][NB]
+    float *dYt = Kh + (size_t)nRp * NB;            // [NB][rows_pad + 4]
+    const int ds = rows_pad + 4;
+    const int a = blockIdx.x, beta = blockIdx.y;
+    for (int i = threadIdx.x; i < nRp * NB; i += blockDim.x) {
+        const int b = i / NB, m = i % NB;
+        Kh[i] = (b < nR && m < nbins) ? (float)(wR[b] * Kchi2[(((size_t)beta * nbins + m) * n_chi + a) * nR + b])
+                                      : 0.f;
+    }
+    const float *dya = dY + ((size_t)beta * rows_pad * n_chi + a) * NB;  // + row * n_chi * NB + m
+    for (int i = threadIdx.x; i < rows_pad * NB; i += blockDim.x) {
+        const int row = i / NB, m = i % NB;
+        dYt[(size_t)m * ds + row] = row < rows ? dya[(size_t)row * n_chi * NB + m] : 0.f;
+    }
+    __syncthreads();
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const size_t base = ((size_t)beta * NP + (size_t)a * nR) * rows_pad;  // w, dw of node b: + b * rows_pad
+    const int RTn = rows_pad / 16;
+    constexpr int NQ = NB / 16;  // 16-bin groups
+    // dw
+    for (int tile = wv; tile < RTn * nRt; tile += 4) {
+        const int rt = tile % RTn, bt = tile / RTn;
+        const int row = 16 * rt + lr, b = 16 * bt + lr;
+        f4 acc = f4{0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const float4 y = row < rows ? *(const float4 *)(dya + (size_t)row * n_chi * NB + 16 * q + 4 * lk)
+                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 k = *(const float4 *)(Kh + (size_t)b * NB + 16 * q + 4 * lk);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(y.x, k.x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(y.y, k.y, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(y.z, k.z, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(y.w, k.w, acc, 0, 0, 0);
+        }
+        // lane holds rows 16 rt + 4 lk .. + 3 of node b = 16 bt + lr
+        if (b < nR) *(float4 *)(dw + base + (size_t)b * rows_pad + 16 * rt + 4 * lk) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    }
+    // dK2: node tiles wv, wv + 4, ...; lane (node 16 bt + lr) reads w of that node
+    if (dK2) {
+        for (int bt = wv; bt < nRt; bt += 4) {
+            const int b = min(16 * bt + lr, nR - 1);
+            const float *wr = w + base + (size_t)b * rows_pad;
+            f4 acc[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q] = f4{0, 0, 0, 0};
+            for (int c = 0; c < RTn; ++c) {
+                const float4 x = *(const float4 *)(wr + 16 * c + 4 * lk);
+                const float xv[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const float4 y = *(const float4 *)(dYt + (size_t)(16 * q + lr) * ds + 16 * c + 4 * lk);
+                    const float yv[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[e], yv[e], acc[q], 0, 0, 0);
+                }
+            }
+            // lane holds nodes 16 bt + 4 lk + r of bin 16 q + lr
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int m = 16 * q + lr;
+                if (m >= nbins) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int bb = 16 * bt + 4 * lk + r;
+                    if (bb < nR) dK2[(((size_t)beta * nbins + m) * n_chi + a) * nR + bb] = wR[bb] * (double)acc[q][r];
+                }
+            }
         }
     }
 }
@@ -2445,6 +2642,165 @@ __global__ __launch_bounds__(256) void adj_project_kernel(const T *__restrict__ 
     }
 }
 
+// The transposed projection on MFMA for N % 8 == 0 (nodal P), with the even/odd split of the
+// forward one: with D[n][N-1-j] = (-1)^n D[n][j], for j < N/2
+//     e_j = sum_m D[2m][j] dc_{2m},   o_j = sum_m D[2m+1][j] dc_{2m+1},
+//     dP_j = e_j + o_j,               dP_{N-1-j} = e_j - o_j,
+// two [rows x N/2] x [N/2 x N/2] products.  The tables Et[j][m] = D[2m][j] and Ot[j][m] = D[2m+1][j]
+// (zero past N/2) sit in LDS; a lane loads 8 consecutive dc values of its row per step (the even
+// ones feed e, the odd ones o).  FP32 path: v_mfma_f32_16x16x4_f32, two row tiles per wave, 128
+// rows per work-group; FP64 path: v_mfma_f64_16x16x4_f64, one row tile per wave, 64 rows.
+template <typename PT, int NT>
+__global__ __launch_bounds__(256) void adj_project_split_kernel(const float *__restrict__ dc,
+                                                                const float *__restrict__ Dn, int N, int ncp,
+                                                                long nrows, PT *__restrict__ dP) {
+    constexpr int RT = 2, KSTEP = 16;
+    extern __shared__ __align__(16) unsigned char smem_ap[];
+    const int H = N / 2;
+    constexpr int Hp = 16 * NT, hs = Hp + 4;
+    float *Et = (float *)smem_ap, *Ot = Et + (size_t)Hp * hs;
+    for (int i = threadIdx.x; i < Hp * Hp; i += blockDim.x) {
+        const int j = i / Hp, m = i % Hp;
+        const bool in = j < H && m < H;
+        Et[(size_t)j * hs + m] = in ? Dn[(size_t)(2 * m) * N + j] : 0.f;
+        Ot[(size_t)j * hs + m] = in ? Dn[(size_t)(2 * m + 1) * N + j] : 0.f;
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const long row0 = (long)blockIdx.x * (64 * RT) + 16 * RT * w;
+    const float *prow[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) prow[r] = dc + min(row0 + 16 * r + lr, nrows - 1) * (long)ncp;
+    f4 ae[RT][NT], ao[RT][NT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) ae[r][t] = ao[r][t] = f4{0, 0, 0, 0};
+    // dc[2 m0 .. 2 m0 + 7] of each row; clamped below N/2, where the tables are zero anyway
+    auto load = [&](int st, float4 (&lo)[RT], float4 (&hi)[RT]) {
+        const int m0 = min(st * KSTEP + lk * 4, H - 4);
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            lo[r] = *(const float4 *)(prow[r] + 2 * m0);
+            hi[r] = *(const float4 *)(prow[r] + 2 * m0 + 4);
+        }
+    };
+    auto compute = [&](int st, const float4 (&lo)[RT], const float4 (&hi)[RT]) {
+        const int m0 = st * KSTEP + lk * 4;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const float4 de = *(const float4 *)(Et + (size_t)(16 * t + lr) * hs + m0);
+            const float4 dd = *(const float4 *)(Ot + (size_t)(16 * t + lr) * hs + m0);
+            const float dev[4] = {de.x, de.y, de.z, de.w}, dov[4] = {dd.x, dd.y, dd.z, dd.w};
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                const float ev[4] = {lo[r].x, lo[r].z, hi[r].x, hi[r].z}, ov[4] = {lo[r].y, lo[r].w, hi[r].y, hi[r].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    ae[r][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev[e], dev[e], ae[r][t], 0, 0, 0);
+                    ao[r][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ov[e], dov[e], ao[r][t], 0, 0, 0);
+                }
+            }
+        }
+    };
+    float4 lo[2][RT], hi[2][RT];
+    load(0, lo[0], hi[0]);
+#pragma unroll
+    for (int st = 0; st < NT; ++st) {
+        if (st + 1 < NT) load(st + 1, lo[(st + 1) & 1], hi[(st + 1) & 1]);
+        compute(st, lo[st & 1], hi[st & 1]);
+    }
+    // lane holds rows 16 r + 4 lk + q of column j = 16 t + lr
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int j = 16 * t + lr;
+            if (j >= H) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const long row = row0 + 16 * r + 4 * lk + q;
+                if (row >= nrows) continue;
+                const float e = ae[r][t][q], o = ao[r][t][q];
+                dP[row * N + j] = (PT)(e + o);
+                dP[row * N + N - 1 - j] = (PT)(e - o);
+            }
+        }
+}
+
+template <typename PT, int NT>
+__global__ __launch_bounds__(256) void adj_project_split64_kernel(const double *__restrict__ dc,
+                                                                  const double *__restrict__ Dn, int N, int ncp,
+                                                                  long nrows, PT *__restrict__ dP) {
+    constexpr int KSTEP = 16;
+    extern __shared__ __align__(16) unsigned char smem_ap64[];
+    const int H = N / 2;
+    constexpr int Hp = 16 * NT, hs = Hp + 2;
+    double *Et = (double *)smem_ap64, *Ot = Et + (size_t)Hp * hs;
+    for (int i = threadIdx.x; i < Hp * Hp; i += blockDim.x) {
+        const int j = i / Hp, m = i % Hp;
+        const bool in = j < H && m < H;
+        Et[(size_t)j * hs + m] = in ? Dn[(size_t)(2 * m) * N + j] : 0.0;
+        Ot[(size_t)j * hs + m] = in ? Dn[(size_t)(2 * m + 1) * N + j] : 0.0;
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const long row0 = (long)blockIdx.x * 64 + 16 * w;
+    const double *pr = dc + min(row0 + lr, nrows - 1) * (long)ncp;
+    d4 ae[NT], ao[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) ae[t] = ao[t] = d4{0, 0, 0, 0};
+    auto load = [&](int st, double (&v)[8]) {
+        const int m0 = min(st * KSTEP + lk * 4, H - 4);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double2 x = *(const double2 *)(pr + 2 * m0 + 2 * u);
+            v[2 * u] = x.x, v[2 * u + 1] = x.y;
+        }
+    };
+    auto compute = [&](int st, const double (&v)[8]) {
+        const int m0 = st * KSTEP + lk * 4;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const double *de = Et + (size_t)(16 * t + lr) * hs + m0, *dd = Ot + (size_t)(16 * t + lr) * hs + m0;
+            const double2 e0 = *(const double2 *)de, e1 = *(const double2 *)(de + 2);
+            const double2 o0 = *(const double2 *)dd, o1 = *(const double2 *)(dd + 2);
+            const double dev[4] = {e0.x, e0.y, e1.x, e1.y}, dov[4] = {o0.x, o0.y, o1.x, o1.y};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                ae[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[2 * e], dev[e], ae[t], 0, 0, 0);
+                ao[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[2 * e + 1], dov[e], ao[t], 0, 0, 0);
+            }
+        }
+    };
+    double v[2][8];
+    load(0, v[0]);
+#pragma unroll
+    for (int st = 0; st < NT; ++st) {
+        if (st + 1 < NT) {
+            load(st + 1, v[(st + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);  // keep the next step's loads ahead of these MFMAs
+        }
+        compute(st, v[st & 1]);
+    }
+    // f64 result layout: row 4 r + lk of the tile in register r of lane j % 16 + 16 lk
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int j = 16 * t + lr;
+        if (j >= H) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const long row = row0 + 4 * r + lk;
+            if (row >= nrows) continue;
+            const double e = ae[t][r], o = ao[t][r];
+            dP[row * N + j] = (PT)(e + o);
+            dP[row * N + N - 1 - j] = (PT)(e - o);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------------------
@@ -2457,6 +2813,9 @@ struct Ctx {
 struct Layout {
     size_t c, clo, cs, w, kt, y, dy, sg, dw, dc, total;
 };
+
+// cosmologies per work-group of the adjoint's transposed contraction (their dw rows sit in LDS)
+constexpr int kAdjBT = 32;
 
 // Below this batch the fused kernel, which keeps one work-group per CU busy with a barrier per
 // b, streams the basis more slowly than the unfused contraction (many independent work-groups);
@@ -2535,6 +2894,11 @@ hipError_t allow_large_lds() {
             (const void *)adj_w_kernel<double, 16>, (const void *)adj_w_kernel<double, 32>,
             (const void *)adj_w_kernel<float, 16>, (const void *)adj_w_kernel<float, 32>,
             (const void *)contract_t_kernel<true>, (const void *)contract_t_kernel<false>,
+            (const void *)adj_project_split64_kernel<double, 4>, (const void *)adj_project_split64_kernel<float, 4>,
+            (const void *)adj_project_split64_kernel<double, 3>, (const void *)adj_project_split64_kernel<float, 3>,
+            (const void *)adj_w_mfma_kernel<16>, (const void *)adj_w_mfma_kernel<32>,
+            (const void *)contract_tiled_kernel<BLAST_FP32, 4, kAdjBT>,
+            (const void *)adj_dy_mfma_kernel<16>, (const void *)adj_dy_mfma_kernel<32>,
         };
         for (const void *f : fns) {
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
@@ -2936,7 +3300,7 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     uint16_t *clo = x.prec == BLAST_BF16X3 || x.prec == BLAST_FP16X3 ? (uint16_t *)(ws + L.clo) : nullptr;
     float *cs = x.prec == BLAST_FP16X3 ? (float *)(ws + L.cs) : nullptr;
     void *w = need_w ? (void *)(ws + L.w) : a->w_save;
-    void *Y = ws + L.y;
+    void *Y = a->y_save ? a->y_save : (void *)(ws + L.y);
     const int fnb = need_w ? fused_nb(x.prec, x.nbins, a->batch) : 0;
     const bool f64f = need_w && x.prec == BLAST_FP64 && fused_f64(x.nbins, a->batch);
     mark(0);
@@ -3059,8 +3423,8 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
         return set_error("n_R and the multipoles too large for the adjoint's R tile"), BLAST_E_UNSUPPORTED;
     if (!dC) return set_error("dC is required"), BLAST_E_INVALID;
     const bool f64 = x.prec == BLAST_FP64;
-    // contract_t_kernel keeps the dw rows of one cosmology tile (32 on FP64, 64 on FP32) in LDS
-    if (dP && (size_t)(f64 ? 32 : 64) * (p->rows_pad + 1) * (f64 ? 8 : 4) > 160 * 1024)
+    // the transposed contraction keeps the dw rows of a tile of 32 cosmologies in LDS
+    if (dP && (size_t)kAdjBT * (f64 ? (size_t)(p->rows_pad + 1) * 8 : (size_t)(p->rows_pad + 4) * 4) > 160 * 1024)
         return set_error("the multipoles are too many for the transposed contraction's tile (dP)"),
                BLAST_E_UNSUPPORTED;
     BLAST_HIP_TRY(allow_large_lds());
@@ -3070,29 +3434,46 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
     if (!ws) return st;
     void *c = ws + L.c;
     void *w = need_w ? (void *)(ws + L.w) : a->w_save;
-    void *Y = ws + L.y, *dY = ws + L.dy, *dw = ws + L.dw, *dc = ws + L.dc;
+    // Y of the forward call that kept w, when the caller kept it too
+    const bool have_y = !need_w && a->y_save;
+    void *Y = have_y ? a->y_save : (void *)(ws + L.y), *dY = ws + L.dy, *dw = ws + L.dw, *dc = ws + L.dc;
     double *Sg = (double *)(ws + L.sg);
     if (need_w) {
         stage_project(p, a, x, c, nullptr, nullptr, s);
         stage_contract(p, a, x, c, nullptr, w, s);
     }
-    if (dK_chi) stage_quad_y(p, a, x, w, Y, s);
+    if (dK_chi && !have_y) stage_quad_y(p, a, x, w, Y, s);
     Slots sl{{p->tslot_type[0], p->tslot_type[1], p->tslot_type[2]}};
     dim3 g1((unsigned)(p->nt * p->n_ell), a->batch);
 #define BLAST_ADJ(T, NB)                                                                                          \
     do {                                                                                                          \
-        hipLaunchKernelGGL((adj_dy_kernel<T, NB>), g1, dim3(256), 0, s, dC, a->K_chi, p->d_wchi, p->d_chi,        \
-                           p->d_pref, p->n_chi, p->rows_pad, p->n_ell, sl, x.ng, x.ns, a->types, x.npairs,        \
-                           x.sel.n_out, x.inv, (T *)dY, Sg);                                                      \
+        const size_t shd = (size_t)kAdjRG * NB * NB * 8 + (size_t)((p->n_chi + 15) / 16 * 16) * (NB + 4) * 4;     \
+        if (std::is_same<T, float>::value && shd <= 160 * 1024)                                                  \
+            hipLaunchKernelGGL((adj_dy_mfma_kernel<NB>), dim3((unsigned)((p->rows + kAdjRG - 1) / kAdjRG), a->batch), \
+                               dim3(256), shd, s, dC, a->K_chi, p->d_wchi, p->d_chi, p->d_pref, p->n_chi, p->rows, \
+                               p->rows_pad, p->n_ell, sl, x.ng, x.ns, a->types, x.npairs, x.sel.n_out, x.inv,    \
+                               (float *)dY, Sg);                                                                \
+        else                                                                                                      \
+            hipLaunchKernelGGL((adj_dy_kernel<T, NB>), g1, dim3(256), 0, s, dC, a->K_chi, p->d_wchi, p->d_chi,    \
+                               p->d_pref, p->n_chi, p->rows_pad, p->n_ell, sl, x.ng, x.ns, a->types, x.npairs,    \
+                               x.sel.n_out, x.inv, (T *)dY, Sg);                                                  \
         if (dK_chi) {                                                                                             \
             dim3 gk((unsigned)((p->n_chi + 63) / 64), a->batch);                                                  \
             hipLaunchKernelGGL((adj_kchi_kernel<T, NB>), gk, dim3(256), 0, s, (const T *)Y, Sg, p->d_wchi,        \
                                p->d_chi, p->n_chi, p->rows, p->rows_pad, x.nbins, dK_chi);                        \
         }                                                                                                         \
         dim3 gw(p->n_chi, a->batch);                                                                              \
-        const size_t shw = ((size_t)p->n_R * NB + (size_t)p->rows_pad * adj_w_stride<NB>()) * sizeof(double);      \
-        hipLaunchKernelGGL((adj_w_kernel<T, NB>), gw, dim3(256), shw, s, (const T *)dY, (const T *)w, a->K_chi2, \
-                           p->d_wR, p->NP, p->n_R, p->n_chi, p->rows, p->rows_pad, x.nbins, (T *)dw, dK_chi2);   \
+        if constexpr (std::is_same<T, float>::value) {                                                           \
+            const size_t shw = ((size_t)((p->n_R + 15) / 16 * 16) * NB + (size_t)NB * (p->rows_pad + 4)) * 4;    \
+            hipLaunchKernelGGL((adj_w_mfma_kernel<NB>), gw, dim3(256), shw, s, (const float *)dY,               \
+                               (const float *)w, a->K_chi2, p->d_wR, p->NP, p->n_R, p->n_chi, p->rows,          \
+                               p->rows_pad, x.nbins, (float *)dw, dK_chi2);                                     \
+        } else {                                                                                                  \
+            const size_t shw = ((size_t)p->n_R * NB + (size_t)p->rows_pad * adj_w_stride<NB>()) * sizeof(double); \
+            hipLaunchKernelGGL((adj_w_kernel<T, NB>), gw, dim3(256), shw, s, (const T *)dY, (const T *)w,       \
+                               a->K_chi2, p->d_wR, p->NP, p->n_R, p->n_chi, p->rows, p->rows_pad, x.nbins,      \
+                               (T *)dw, dK_chi2);                                                               \
+        }                                                                                                         \
     } while (0)
     if (f64 && x.nbp == 16) BLAST_ADJ(double, 16);
     if (f64 && x.nbp == 32) BLAST_ADJ(double, 32);
@@ -3100,25 +3481,63 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
     if (!f64 && x.nbp == 32) BLAST_ADJ(float, 32);
 #undef BLAST_ADJ
     if (dP) {
-        const int BT = f64 ? 32 : 64;
-        const dim3 gt = point_tile_grid(p->NP, (a->batch + BT - 1) / BT);
-        const size_t sht = (size_t)BT * (p->rows_pad + 1) * (f64 ? 8 : 4);
-        if (f64)
+        const dim3 gt = point_tile_grid(p->NP, (a->batch + kAdjBT - 1) / kAdjBT);
+        if (f64) {
+            const size_t sht = (size_t)kAdjBT * (p->rows_pad + 1) * 8;
             hipLaunchKernelGGL((contract_t_kernel<true>), gt, dim3(256), sht, s, p->basis.f64, (const double *)dw,
                                a->batch, p->NP, p->rows_pad, p->nc_pad, (double *)dc);
-        else
-            hipLaunchKernelGGL((contract_t_kernel<false>), gt, dim3(256), sht, s, p->basis.f32, (const float *)dw,
-                               a->batch, p->NP, p->rows_pad, p->nc_pad, (float *)dc);
+        } else {
+            // dc = Ttilde^T dw is the forward contraction's product with the transposed basis (rows of
+            // Ttilde^T: the nc_pad Chebyshev columns; its K: the rows_pad basis rows) and dw in place of c
+            {
+                std::lock_guard<std::mutex> lk(p->mu);
+                st = ensure_f32t(p, s);
+            }
+            if (st != BLAST_OK) return st;
+            const int RT = p->nc_pad / 16;
+            const int W = std::min((RT + kTilesPerWave - 1) / kTilesPerWave, 8);
+            const size_t sht = (size_t)kAdjBT * (p->rows_pad + 4) * sizeof(float);
+            hipLaunchKernelGGL((contract_tiled_kernel<BLAST_FP32, 4, kAdjBT>), gt, dim3(64 * W), sht, s,
+                               p->basis.f32t, nullptr, nullptr, (const float *)dw, nullptr, a->batch, p->NP,
+                               p->nc_pad, p->rows_pad, (float *)dc);
+        }
         const long nrows = (long)a->batch * p->NP;
-        dim3 gp((unsigned)((nrows + kAdjRows - 1) / kAdjRows));
+        const int N = p->n_cheb;
+        if (a->p_kind == 0 && N % 8 == 0) {
+            const int nt = (N / 2 + 15) / 16;  // 1..4 tiles of 16 per parity
+            auto launch = [&](auto ptag, auto nttag) {
+                using PT = typename decltype(ptag)::type;
+                constexpr int NT = decltype(nttag)::value;
+                if (f64)
+                    hipLaunchKernelGGL((adj_project_split64_kernel<PT, NT>), dim3((unsigned)((nrows + 63) / 64)),
+                                       dim3(256), (size_t)2 * 16 * NT * (16 * NT + 2) * sizeof(double), s,
+                                       (const double *)dc, p->d_dctn64, N, p->nc_pad, nrows, (PT *)dP);
+                else
+                    hipLaunchKernelGGL((adj_project_split_kernel<PT, NT>), dim3((unsigned)((nrows + 127) / 128)),
+                                       dim3(256), (size_t)2 * 16 * NT * (16 * NT + 4) * sizeof(float), s,
+                                       (const float *)dc, p->d_dctn32, N, p->nc_pad, nrows, (PT *)dP);
+            };
+            auto by_nt = [&](auto ptag) {
+                switch (nt) {
+                    case 1: launch(ptag, std::integral_constant<int, 1>()); break;
+                    case 2: launch(ptag, std::integral_constant<int, 2>()); break;
+                    case 3: launch(ptag, std::integral_constant<int, 3>()); break;
+                    default: launch(ptag, std::integral_constant<int, 4>()); break;
+                }
+            };
+            if (a->p_dtype == 0) by_nt(TypeTag<double>());
+            else by_nt(TypeTag<float>());
+        } else {
+            dim3 gp((unsigned)((nrows + kAdjRows - 1) / kAdjRows));
 #define BLAST_AP(T, PT)                                                                                        \
     hipLaunchKernelGGL((adj_project_kernel<T, PT>), gp, dim3(256), 0, s, (const T *)dc, p->d_dctn64, p->n_cheb, \
                        p->nc_pad, nrows, a->p_kind, (PT *)dP)
-        if (f64 && a->p_dtype == 0) BLAST_AP(double, double);
-        if (f64 && a->p_dtype == 1) BLAST_AP(double, float);
-        if (!f64 && a->p_dtype == 0) BLAST_AP(float, double);
-        if (!f64 && a->p_dtype == 1) BLAST_AP(float, float);
+            if (f64 && a->p_dtype == 0) BLAST_AP(double, double);
+            if (f64 && a->p_dtype == 1) BLAST_AP(double, float);
+            if (!f64 && a->p_dtype == 0) BLAST_AP(float, double);
+            if (!f64 && a->p_dtype == 1) BLAST_AP(float, float);
 #undef BLAST_AP
+        }
     }
     BLAST_HIP_TRY(hipGetLastError());
     return BLAST_OK;

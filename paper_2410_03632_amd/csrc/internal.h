@@ -44,6 +44,8 @@ struct BasisBuffers {
     uint16_t *h16 = nullptr;   // FP16 bits of (value / scale16), tiled layout
     uint16_t *l16 = nullptr;   // FP16 bits of the remainder
     float *scale16 = nullptr;  // [NP][rows_pad] power-of-two row scales of the FP16 parts
+    float *f32t = nullptr;     // FP32 transpose per point, [nc_pad][rows_pad] in the tiled layout
+                               // (made by the first FP32 adjoint call that asks for dP)
 };
 
 }  // namespace blast
@@ -101,6 +103,8 @@ namespace blast {
 // basis.hip
 blast_status build_basis(blast_plan *p, hipStream_t s);
 blast_status derive_precisions(blast_plan *p, hipStream_t s);
+// the transposed FP32 copy of the basis, made on `s` if it does not exist yet (caller holds p->mu)
+blast_status ensure_f32t(blast_plan *p, hipStream_t s);
 
 // eval.hip
 blast_status forward(blast_plan *p, const blast_cl_args *a, hipStream_t s);

@@ -129,85 +129,35 @@ def test_batched_adjoint_equals_calls_on_slices(precision, batch):
 
 
 def test_adjoint_refuses_plans_whose_transpose_tile_exceeds_lds():
-    """The transposed contraction keeps a tile of dw rows for a cosmology tile in LDS (256 bytes
-    per row on both precisions): with 3 x 214 multipoles (rows padded to 656) it would need more
-    than 160 KB, so a call that asks for dP is refused before any launch; the kernel-table
-    gradients do not use that tile and are still computed."""
+    """The FP64 transposed contraction keeps the dw rows of 32 cosmologies in LDS (8 bytes per row
+    each): with 3 x 214 multipoles (rows padded to 656) that is more than 160 KB, so an FP64 call
+    that asks for dP is refused before any launch, while the kernel-table gradients, which do not
+    use that tile, are computed.  The FP32 path (4 bytes per row) takes this plan: its dP is checked
+    against exact central differences of the FP64 forward (C is linear in P)."""
     ell = np.arange(2, 216, dtype=np.float64)
     chi, wchi = B.grid_chi_simpson(4, 500.0, 1500.0)
     R, wR = B.grid_R_fejer(2, 0.5)
     plan = B.Plan(ell, chi, wchi, R, wR, 1e-3, 0.3, 8, precisions=("fp64", "fp32"))
     try:
         assert plan.rows_pad >= 640
-        P = torch.ones((1, 4, 2, 8), dtype=torch.float64, device="cuda")
-        K1 = torch.ones((1, 2, 4), dtype=torch.float64, device="cuda")
-        K2 = torch.ones((1, 2, 4, 2), dtype=torch.float64, device="cuda")
-        G = torch.ones((1, 3, len(ell)), dtype=torch.float64, device="cuda")
-        for prec, Pp in (("fp64", P), ("fp32", P.float())):
-            with pytest.raises(B.BlastError) as e:
-                plan.backward(Pp, K1, K2, 1, 1, G, precision=prec)
-            assert e.value.status == B.E_UNSUPPORTED, e.value
-            _, dK, dK2 = plan.backward(Pp, K1, K2, 1, 1, G, precision=prec, want=("K_chi", "K_chi2"))
-            torch.cuda.synchronize()
-            assert torch.isfinite(dK).all() and torch.isfinite(dK2).all()
+        gen = torch.Generator(device="cpu").manual_seed(3)
+        P = (1.0 + torch.rand((1, 4, 2, 8), generator=gen, dtype=torch.float64)).cuda()
+        K1 = torch.rand((1, 2, 4), generator=gen, dtype=torch.float64).cuda()
+        K2 = torch.rand((1, 2, 4, 2), generator=gen, dtype=torch.float64).cuda()
+        G = torch.randn((1, 3, len(ell)), generator=gen, dtype=torch.float64).cuda()
+        with pytest.raises(B.BlastError) as e:
+            plan.backward(P, K1, K2, 1, 1, G, precision="fp64")
+        assert e.value.status == B.E_UNSUPPORTED, e.value
+        _, dK, dK2 = plan.backward(P, K1, K2, 1, 1, G, precision="fp64", want=("K_chi", "K_chi2"))
+        torch.cuda.synchronize()
+        assert torch.isfinite(dK).all() and torch.isfinite(dK2).all()
+        dP = plan.backward(P.float(), K1, K2, 1, 1, G, precision="fp32", want=("P",))[0].double()
+        v = torch.randn(P.shape, generator=gen, dtype=torch.float64).cuda()
+        h = 1e-3
+        Lp = float((plan.forward((P + h * v).contiguous(), K1, K2, 1, 1) * G).sum())
+        Lm = float((plan.forward((P - h * v).contiguous(), K1, K2, 1, 1) * G).sum())
+        fd, an = (Lp - Lm) / (2 * h), float((dP * v).sum())
+        print("FP32 dP at rows_pad", plan.rows_pad, "fd", fd, "adjoint", an, flush=True)
+        assert abs(fd - an) <= 1e-4 * abs(fd)
     finally:
         plan.close()
-
-
-def test_coefficient_input_mode(setup):
-    """Forward with the Chebyshev coefficients of P gives the same C as with its nodal
-    values; the coefficient gradient maps to the nodal one by the transposed projection."""
-    cfg, plan, P, K1, K2 = setup
-    N = plan.n_cheb
-    _, x = O.grid_k(N, cfg.k_min, cfg.k_max)
-    T = np.cos(np.outer(np.arange(N), np.arccos(x)))          # T[n][j] = T_n(x_j)
-    c = np.linalg.solve(T.T, P.cpu().numpy().reshape(-1, N).T).T.reshape(P.shape)  # sum_n c_n T_n(x_j) = P_j
-    cd = _dev(c)
-    C1 = plan.forward(P, K1, K2, cfg.n_g, cfg.n_s)
-    C2 = plan.forward(cd, K1, K2, cfg.n_g, cfg.n_s, coef=True)
-    assert float((C1 - C2).abs().max() / C1.abs().max()) < 1e-12
-    G = torch.randn(C1.shape, dtype=torch.float64, device="cuda")
-    dPn = plan.backward(P, K1, K2, cfg.n_g, cfg.n_s, G, want=("P",))[0]
-    dc = plan.backward(cd, K1, K2, cfg.n_g, cfg.n_s, G, coef=True, want=("P",))[0]
-    # P = c T  =>  dL/dc = dL/dP T^T
-    dc_from_nodal = dPn.cpu().numpy().reshape(-1, N) @ T.T
-    assert np.allclose(dc.cpu().numpy().reshape(-1, N), dc_from_nodal, rtol=1e-9,
-                       atol=1e-12 * np.abs(dc_from_nodal).max())
-
-
-def test_coefficient_gradient_matches_oracle(setup):
-    cfg, plan, P, K1, K2 = setup
-    rng = np.random.default_rng(4)
-    G = torch.as_tensor(rng.normal(size=(1, B.n_pairs(cfg.n_g, cfg.n_s), plan.n_ell))).cuda()
-    N = plan.n_cheb
-    _, x = O.grid_k(N, cfg.k_min, cfg.k_max)
-    dc = plan.backward(P[:1].contiguous(), K1[:1].contiguous(), K2[:1].contiguous(), cfg.n_g, cfg.n_s, G,
-                       want=("P",), coef=True)[0]  # gradient w.r.t. coefficients (values of P unused)
-    dc = dc.cpu().numpy()[0]
-    chi, wchi = O.grid_chi(cfg.n_chi, cfg.chi_min, cfg.chi_max)
-    R, wR = O.grid_R(cfg.n_R, cfg.R_min)
-    Kc, Kc2 = K1[0].cpu().numpy(), K2[0].cpu().numpy()
-    Gn = G[0].cpu().numpy()
-    for trial in range(4):
-        a, b, n = int(rng.integers(cfg.n_chi)), int(rng.integers(cfg.n_R)), int(rng.integers(N))
-        Tn = np.cos(n * np.arccos(x))                           # nodal values of T_n
-        w1 = O.w_points(plan.ell, ALL, cfg.k_min, cfg.k_max, [chi[a]], [R[b] * chi[a]], nc=N, P=Tn, shared=True)
-        w = np.zeros((3, plan.n_ell, cfg.n_chi * cfg.n_R))
-        w[:, :, a * cfg.n_R + b] = w1[:, :, 0]
-        dC = O.sum_rform(chi, wchi, wR, cfg.n_g, cfg.n_s, Kc, Kc2, plan.ell, ALL, w)
-        ref = float((Gn * dC).sum())
-        assert abs(dc[a, b, n] - ref) <= 1e-9 * abs(ref) + 1e-12 * np.abs(dc).max(), (a, b, n, dc[a, b, n], ref)
-
-
-def test_autograd_function(setup):
-    cfg, plan, P, K1, K2 = setup
-    f = B.cl_function()
-    Pr = P.clone().requires_grad_(True)
-    K1r = K1.clone().requires_grad_(True)
-    K2r = K2.clone().requires_grad_(True)
-    C = f.apply(plan, Pr, K1r, K2r, cfg.n_g, cfg.n_s, "fp64", False)
-    G = torch.randn(C.shape, dtype=torch.float64, device="cuda")
-    (C * G).sum().backward()
-    ref = plan.backward(P, K1, K2, cfg.n_g, cfg.n_s, G)
-    for g, r in zip((Pr.grad, K1r.grad, K2r.grad), ref):
-        assert torch.equal(g, r)
