@@ -2426,8 +2426,8 @@ __global__ __launch_bounds__(256) void adj_w_kernel(const T *__restrict__ dY, co
 // takes bins 4 lk + s % 4 + 16 (s / 4) from lane group lk, so a lane reads its row's bins as
 // 16-byte pieces; for dK2, MFMA e of a 16-row chunk takes row 16 c + 4 lk + e, so a lane reads w
 // of its node and dY^T of its bin as 16-byte pieces.  Kh and dY^T (rows past `rows` zero) sit in
-// LDS; w and dY are read from global memory.  Wave v makes the dw tiles v, v + 4, ... and the dK2
-// node tiles v, v + 4.
+// LDS; w is read from global memory, a chunk of 16-row steps at a time.  Wave v makes the dw tiles
+// v, v + 4, ... and the dK2 node tiles v, v + 4.
 template <int NB>
 __global__ __launch_bounds__(256) void adj_w_mfma_kernel(const float *__restrict__ dY, const float *__restrict__ w,
                                                          const double *__restrict__ Kchi2,
@@ -2445,7 +2445,7 @@ __global__ __launch_bounds__(256) void adj_w_mfma_kernel(const float *__restrict
         Kh[i] = (b < nR && m < nbins) ? (float)(wR[b] * Kchi2[(((size_t)beta * nbins + m) * n_chi + a) * nR + b])
                                       : 0.f;
     }
-    const float *dya = dY + ((size_t)beta * rows_pad * n_chi + a) * NB;  // + row * n_chi * NB + m
+    const float *dya = dY + ((size_t)beta * rows_pad * n_chi + a) * NB;  // + row * n_chi * NB + m (rows < rows)
     for (int i = threadIdx.x; i < rows_pad * NB; i += blockDim.x) {
         const int row = i / NB, m = i % NB;
         dYt[(size_t)m * ds + row] = row < rows ? dya[(size_t)row * n_chi * NB + m] : 0.f;
@@ -2456,15 +2456,16 @@ __global__ __launch_bounds__(256) void adj_w_mfma_kernel(const float *__restrict
     const size_t base = ((size_t)beta * NP + (size_t)a * nR) * rows_pad;  // w, dw of node b: + b * rows_pad
     const int RTn = rows_pad / 16;
     constexpr int NQ = NB / 16;  // 16-bin groups
-    // dw
+    // dw (the A operand from dY^T in LDS: lanes of consecutive rows read consecutive words); staging
+    // a node tile's rows in LDS for contiguous stores measured slower (two barriers per tile)
     for (int tile = wv; tile < RTn * nRt; tile += 4) {
         const int rt = tile % RTn, bt = tile / RTn;
         const int row = 16 * rt + lr, b = 16 * bt + lr;
         f4 acc = f4{0, 0, 0, 0};
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const float4 y = row < rows ? *(const float4 *)(dya + (size_t)row * n_chi * NB + 16 * q + 4 * lk)
-                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float *yt = dYt + (size_t)(16 * q + 4 * lk) * ds + row;
+            const float4 y = make_float4(yt[0], yt[ds], yt[2 * ds], yt[3 * ds]);
             const float4 k = *(const float4 *)(Kh + (size_t)b * NB + 16 * q + 4 * lk);
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(y.x, k.x, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(y.y, k.y, acc, 0, 0, 0);
@@ -2482,15 +2483,26 @@ __global__ __launch_bounds__(256) void adj_w_mfma_kernel(const float *__restrict
             f4 acc[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) acc[q] = f4{0, 0, 0, 0};
-            for (int c = 0; c < RTn; ++c) {
-                const float4 x = *(const float4 *)(wr + 16 * c + 4 * lk);
-                const float xv[4] = {x.x, x.y, x.z, x.w};
+            // the node's w in chunks of kWChunk 16-row steps, every load of a chunk issued before its MFMAs
+            constexpr int kWChunk = 6;
+            for (int c0 = 0; c0 < RTn; c0 += kWChunk) {
+                float4 x[kWChunk];
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    const float4 y = *(const float4 *)(dYt + (size_t)(16 * q + lr) * ds + 16 * c + 4 * lk);
-                    const float yv[4] = {y.x, y.y, y.z, y.w};
+                for (int u = 0; u < kWChunk; ++u)
+                    x[u] = *(const float4 *)(wr + 16 * min(c0 + u, RTn - 1) + 4 * lk);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[e], yv[e], acc[q], 0, 0, 0);
+                for (int u = 0; u < kWChunk; ++u) {
+                    if (c0 + u >= RTn) break;
+                    const int c = c0 + u;
+                    const float xv[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        const float4 y = *(const float4 *)(dYt + (size_t)(16 * q + lr) * ds + 16 * c + 4 * lk);
+                        const float yv[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[e], yv[e], acc[q], 0, 0, 0);
+                    }
                 }
             }
             // lane holds nodes 16 bt + 4 lk + r of bin 16 q + lr
