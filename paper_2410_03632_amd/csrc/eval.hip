@@ -1081,7 +1081,7 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     const typename Cfg<PREC>::E *__restrict__ basis, const uint16_t *__restrict__ basis_lo,
     const float *__restrict__ scale, const typename Cfg<PREC>::E *__restrict__ c, const uint16_t *__restrict__ c_lo,
     const float *__restrict__ Kt, int batch, int n_chi, int n_R, int rows_pad, int nBT, int units, int n_ell,
-    int nslots, int granges, float *__restrict__ Y) {
+    int nslots, int granges, float *__restrict__ Y, float *__restrict__ w_out) {
     using S = FusedShape<PREC, NS>;
     using E = typename S::E;
     constexpr int TR = kFusedTR, VEC = S::VEC, KSTEP = S::KSTEP, ncp = S::ncp, NPART = S::NPART;
@@ -1276,6 +1276,10 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
                 kt[16] = v[0], kt[17] = v[1], kt[18] = v[2], kt[19] = v[3];
             }
             wv = c0 + c1;
+            // a call that keeps w (FP32, for the adjoint) also stores the tile: 4 rows of one cosmology
+            if (w_out && beta < batch && ti < ntile)
+                *(float4 *)(w_out + ((size_t)beta * NP + (size_t)a * n_R + b) * rows_pad + 16 * (rt0 + ti) + 4 * lk) =
+                    make_float4(wv[0], wv[1], wv[2], wv[3]);
         } else if constexpr (X3 && NS >= 2 && NB <= 16) {  // (20 bins: registers run out, steps below)
             constexpr int ALO = TR * NS * 1024;          // lo parts of the basis tiles
             constexpr int CLO = (int)(S::C_BUF / NPART);  // lo parts of the c rows
@@ -2840,6 +2844,9 @@ int fused_nb(int prec, int nbins, int batch) {
     return (nbins + 3) / 4 * 4;
 }
 
+// FP32 calls that keep w take the fused path too (its kernel stores the w tiles as it goes)
+bool fused_keeps_w(int prec, int nbins, int batch) { return prec == BLAST_FP32 && fused_nb(prec, nbins, batch); }
+
 Layout layout_of(const blast_plan *p, int batch, int prec, int nbins, bool need_w, bool adjoint) {
     Layout L{};
     const size_t nc = (size_t)batch * p->NP * p->nc_pad;
@@ -2860,6 +2867,8 @@ Layout layout_of(const blast_plan *p, int batch, int prec, int nbins, bool need_
         const int fnb = adjoint ? 0 : fused_nb(prec, nbins, batch);
         // the fused path keeps Kt where the unfused one keeps w
         off += align256(std::max((size_t)batch * p->NP * p->rows_pad * te, (size_t)batch * p->NP * fnb * 4));
+    } else if (!adjoint && fused_keeps_w(prec, nbins, batch)) {
+        off += align256((size_t)batch * p->NP * fused_nb(prec, nbins, batch) * 4);
     }
     L.y = off;
     off += align256(ny * te);
@@ -3155,7 +3164,7 @@ void stage_r_weights(blast_plan *p, const blast_cl_args *a, const Ctx &x, int nb
 }
 
 void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, int nb, const void *c,
-                         const uint16_t *clo, const float *Kt, float *Y, hipStream_t s) {
+                         const uint16_t *clo, const float *Kt, float *Y, float *w_out, hipStream_t s) {
     const int RT = p->rows_pad / 16, nBT = (a->batch + 63) / 64;
     const int groups = (RT + kFusedTR - 1) / kFusedTR;
     const int units = p->n_chi * nBT * groups;
@@ -3188,7 +3197,8 @@ void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, in
         // all LDS of the fused kernel is static (FusedShape::LDS bytes)
         hipLaunchKernelGGL((contract_quad_kernel<PR, NB, NBP, NS>), dim3(grid), dim3(256 * kFusedTR), 0, s, bas,
                            H ? p->basis.l16 : p->basis.lo, H ? p->basis.scale16 : p->basis.scale, (const E *)c, clo,
-                           Kt, a->batch, p->n_chi, p->n_R, p->rows_pad, nBT, units, p->n_ell, p->nt, granges, Y);
+                           Kt, a->batch, p->n_chi, p->n_R, p->rows_pad, nBT, units, p->n_ell, p->nt, granges, Y,
+                           w_out);
     };
     // nc_pad is a multiple of 32 up to 128: 1..4 blocks of 32 columns
     auto by_ns = [&](auto ptag, auto nbtag, auto nbptag) {
@@ -3313,7 +3323,8 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     float *cs = x.prec == BLAST_FP16X3 ? (float *)(ws + L.cs) : nullptr;
     void *w = need_w ? (void *)(ws + L.w) : a->w_save;
     void *Y = a->y_save ? a->y_save : (void *)(ws + L.y);
-    const int fnb = need_w ? fused_nb(x.prec, x.nbins, a->batch) : 0;
+    const bool keep_fused = !need_w && fused_keeps_w(x.prec, x.nbins, a->batch);
+    const int fnb = need_w || keep_fused ? fused_nb(x.prec, x.nbins, a->batch) : 0;
     const bool f64f = need_w && x.prec == BLAST_FP64 && fused_f64(x.nbins, a->batch);
     mark(0);
     stage_project(p, a, x, c, clo, cs, s);
@@ -3322,7 +3333,8 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
         // fused path: interval 1 = the R-weights table, interval 2 = contraction + R-quadrature
         stage_r_weights(p, a, x, fnb, cs, (float *)(ws + L.kt), s);
         mark(2);
-        stage_contract_quad(p, a, x, fnb, c, clo, (float *)(ws + L.kt), (float *)Y, s);
+        stage_contract_quad(p, a, x, fnb, c, clo, (float *)(ws + L.kt), (float *)Y,
+                            keep_fused ? (float *)a->w_save : nullptr, s);
     } else if (f64f) {
         stage_r_weights64(p, a, x, (double *)(ws + L.kt), s);
         mark(2);

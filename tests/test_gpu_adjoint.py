@@ -161,3 +161,45 @@ def test_adjoint_refuses_plans_whose_transpose_tile_exceeds_lds():
         assert abs(fd - an) <= 1e-4 * abs(fd)
     finally:
         plan.close()
+
+
+def test_fp32_forward_keeping_w_on_the_fused_path():
+    """From 32 cosmologies on, an FP32 forward that keeps w (and Y) for the adjoint runs the fused
+    contraction + R-quadrature, whose kernel stores the w tiles as it makes them: its spectra equal
+    those of the same call without w_save bit for bit, its w matches the FP64 path's w to FP32
+    rounding (relative to each row's largest value), and the adjoint from the kept w and Y matches
+    the adjoint that recomputes them (unfused, another summation order) to FP32 rounding."""
+    cfg = W.tiny_config(n_ell=9, ell_max=60, n_chi=8, n_R=7, n_cheb=32, k_max=0.8, n_g=3, n_s=2)
+    plan = B.plan_for_config(cfg, precisions=("fp64", "fp32"))
+    try:
+        nb = 40
+        inps = [W.make_inputs(cfg, W.seed_for(34, i), plan.k_nodes, plan.chi, plan.R, vary=True) for i in range(nb)]
+        P = _dev(np.stack([x.P for x in inps]))
+        K1 = _dev(np.stack([x.Kchi for x in inps]))
+        K2 = _dev(np.stack([x.Kchi2 for x in inps]))
+        P32 = P.float()
+        nw = nb * len(plan.chi) * len(plan.R) * plan.rows_pad
+        w32 = torch.full((nw,), float("nan"), dtype=torch.float32, device="cuda")
+        y32 = torch.empty(plan.y_numel(nb, 5), dtype=torch.float32, device="cuda")
+        C_keep = plan.forward(P32, K1, K2, 3, 2, precision="fp32", w_save=w32, y_save=y32)
+        C_plain = plan.forward(P32, K1, K2, 3, 2, precision="fp32")
+        torch.cuda.synchronize()
+        assert torch.equal(C_keep, C_plain)
+        w64 = torch.zeros(nw, dtype=torch.float64, device="cuda")
+        plan.forward(P, K1, K2, 3, 2, precision="fp64", w_save=w64)
+        a = w64.cpu().numpy().reshape(-1, plan.rows_pad)[:, :plan.rows]
+        b = w32.double().cpu().numpy().reshape(-1, plan.rows_pad)[:, :plan.rows]
+        scale = np.abs(a).max(axis=1, keepdims=True)
+        ew = float((np.abs(a - b) / scale).max())
+        print("fused FP32 w vs FP64 w, max error per row scale", ew, flush=True)
+        assert np.isfinite(b).all() and ew < 1e-5
+        G = torch.randn(C_keep.shape, generator=torch.Generator(device="cpu").manual_seed(9), dtype=torch.float64).cuda()
+        g_keep = plan.backward(P32, K1, K2, 3, 2, G, precision="fp32", w_save=w32, y_save=y32)
+        g_new = plan.backward(P32, K1, K2, 3, 2, G, precision="fp32")
+        for name, x, y in zip(("P", "K_chi", "K_chi2"), g_keep, g_new):
+            x, y = x.double().cpu().numpy(), y.double().cpu().numpy()
+            e = float((np.abs(x - y) / np.maximum(np.abs(y), 1e-3 * np.abs(y).max())).max())
+            print("adjoint from kept w, Y vs recomputed:", name, e, flush=True)
+            assert e < 1e-4, (name, e)
+    finally:
+        plan.close()
