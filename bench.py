@@ -390,6 +390,38 @@ def sweep_run(steps=5):
     return out
 
 
+def adjoint_work(plan, cfg, batch):
+    """Algorithmic flops and HBM bytes per launch of the kernels of the FP32 gradient step (a
+    forward that keeps w and Y on the fused path, then the adjoint to dP, dK_chi and dK_chi2).
+
+    contract_quad_kernel : the fused forward (as stage_work's contraction) plus the w it keeps
+    adj_dy_mfma_kernel   : dY = S Ktil per row: dC, K_chi read; dY (FP32), S (FP64) written
+    adj_kchi_kernel      : dK_chi = S^T Y: Y and S read, dK_chi written
+    adj_w_mfma_kernel    : dw = Khat dY and dK_chi2 = dY^T w: w, dY, K_chi2 read; dw, dK_chi2 written
+    contract_tiled_kernel: dc = Ttilde^T dw: transposed basis once, dw read, dc written
+    adj_project_split_kernel: dP = D^T dc (even/odd split, N^2 flops per row): dc read, dP written"""
+    NP = cfg.n_chi * cfg.n_R
+    N, ncp, R, Rp = cfg.n_cheb, plan.nc_pad, plan.rows, plan.rows_pad
+    nb = cfg.n_g + cfg.n_s
+    NB = 16 if nb <= 16 else 32
+    fwd = stage_work(plan, cfg, "fp32", batch)["contraction"]
+    w_bytes = 4.0 * NP * Rp * batch
+    dy_bytes = 4.0 * R * cfg.n_chi * NB * batch
+    return {
+        "contract_quad_kernel": dict(flops=fwd["flops"], bytes=fwd["bytes"] + w_bytes),
+        "adj_dy_mfma_kernel": dict(flops=2.0 * NB * NB * cfg.n_chi * R * batch,
+                                   bytes=8.0 * batch * (B_pairs(cfg) * plan.n_ell + nb * cfg.n_chi) + dy_bytes
+                                   + 8.0 * R * NB * NB * batch),
+        "adj_kchi_kernel": dict(flops=2.0 * NB * NB * cfg.n_chi * R * batch,
+                                bytes=dy_bytes + 8.0 * R * NB * NB * batch + 8.0 * nb * cfg.n_chi * batch),
+        "adj_w_mfma_kernel": dict(flops=4.0 * NB * R * NP * batch,
+                                  bytes=2 * w_bytes + dy_bytes + 16.0 * nb * NP * batch),
+        "contract_tiled_kernel": dict(flops=2.0 * R * N * NP * batch,
+                                      bytes=4.0 * NP * R * N + w_bytes + 4.0 * NP * ncp * batch),
+        "adj_project_split_kernel": dict(flops=1.0 * N * N * NP * batch, bytes=4.0 * NP * (ncp + N) * batch),
+    }
+
+
 def gradient_run(plan, cfg, P, K1, K2, out, Bn, steps, warmup):
     """The FP32 gradient step: a forward that keeps w, then the adjoint from dC = dL/dC to the
     gradients with respect to P at the nodes, K_chi and K_chi2, timed over `steps` calls."""
@@ -413,6 +445,7 @@ def gradient_run(plan, cfg, P, K1, K2, out, Bn, steps, warmup):
     torch.cuda.synchronize()
     msg = (time.perf_counter() - t0) * 1e3 / steps
     return {"batch": Bn, "ms_per_step": msg, "sets_per_s": Bn / (msg * 1e-3),
+            "kernel_work": adjoint_work(plan, cfg, Bn),
             "finite": bool(all(torch.isfinite(g).all().item() for g in grads)),
             "what": "forward keeping w and Y + adjoint: dC -> dP (nodal), dK_chi, dK_chi2"}
 
