@@ -100,6 +100,7 @@ __global__ __launch_bounds__(256) void project_kernel(const PT *__restrict__ P, 
 // per SIMD: 1.71 ms against 1.48 ms at full 3x2pt, batch 256), the others two.
 template <int OUT>
 constexpr int split_rt() { return OUT == 3 ? 1 : 2; }
+constexpr long kProjPG = 8;
 
 // NT = Hp / 16 output tiles per parity (1..4) and as many K steps: with both known at compile time
 // the step loop unrolls and every load is unconditional (rows past the end read the last row and
@@ -108,10 +109,17 @@ constexpr int split_rt() { return OUT == 3 ? 1 : 2; }
 // OUT: 1 -> float c, 2 -> BF16 hi (+ lo when c_lo != nullptr), 3 -> FP16 hi and lo of c / s with a
 // power-of-two s per row that keeps every |c_n / s| below 2^15 (from the row's largest |P_j|);
 // cs[row] = s.
+// Outputs 1 and 2 keep P's row order (row = beta * NP + point), 64 RT consecutive rows per
+// work-group.  Output 3 is written point-major, c[(point * batch + beta) * ncp + n], so that the fused
+// contraction reads the rows of 64 cosmologies at one point as one contiguous block (cs stays in P's
+// order): a work-group takes 16 points of 4 cosmologies (one per wave), so that each wave reads 16
+// consecutive P rows and each point's 4 rows land side by side.  (Cosmology-major c takes 1.48 ms
+// here at full 3x2pt, batch 256, and point-major 1.66; the fused kernel reading it saves 0.5 ms.)
 template <typename PT, int OUT, int NT>
 __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict__ P, const float *__restrict__ Dn,
                                                             int N, int ncp, long nrows, void *__restrict__ c_out,
-                                                            uint16_t *__restrict__ c_lo, float *__restrict__ cs) {
+                                                            uint16_t *__restrict__ c_lo, float *__restrict__ cs,
+                                                            long NP, int batch) {
     constexpr int RT = split_rt<OUT>(), VEC = 4, KSTEP = 16;
     extern __shared__ __align__(16) unsigned char smem_s[];
     const int H = N / 2;
@@ -131,9 +139,23 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
     const long row0 = (long)blockIdx.x * (64 * RT) + 16 * RT * w;
+    // output 3: blocks of 16 points (pbk) x 4 cosmologies (bbk), the cosmology blocks of kProjPG
+    // consecutive point blocks next to each other in the launch order (measured: 2.5 % faster than
+    // the point blocks of one cosmology block next to each other)
+    long pbk = 0, bbk = 0;
+    if (OUT == 3) {
+        const long NPB = (NP + 15) / 16, NBB = (batch + 3) / 4, L = blockIdx.x;
+        const long grp = L / (kProjPG * NBB), rem = L % (kProjPG * NBB);
+        pbk = grp * kProjPG + rem % kProjPG, bbk = rem / kProjPG;
+        if (pbk >= NPB) return;  // uniform over the work-group (no barrier follows)
+    }
+    const long pt0 = 16L * pbk;           // output 3: the work-group's first point
+    const int beta = 4 * (int)bbk + w;    // output 3: the wave's cosmology
     const PT *prow[RT];
 #pragma unroll
-    for (int r = 0; r < RT; ++r) prow[r] = P + min(row0 + 16 * r + lr, nrows - 1) * (long)N;
+    for (int r = 0; r < RT; ++r)
+        prow[r] = OUT == 3 ? P + ((long)min(beta, batch - 1) * NP + min(pt0 + lr, NP - 1)) * N
+                           : P + min(row0 + 16 * r + lr, nrows - 1) * (long)N;
     f4 ae[RT][NT], ao[RT][NT];
 #pragma unroll
     for (int r = 0; r < RT; ++r)
@@ -220,8 +242,8 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
                 // e kept where 2^(13 - e) is a finite float; rows of zeros get s = 1
                 const int e = mx > 0.f ? min(max(ilogbf(mx), -100), 127) : 13;
                 mul[r][q] = ldexpf(1.f, 13 - e);
-                const long row = row0 + 16 * r + 4 * lk + q;
-                if (lr == 0 && row < nrows) cs[row] = ldexpf(1.f, e - 13);
+                const long pt = pt0 + 4 * lk + q;
+                if (lr == 0 && pt < NP && beta < batch) cs[(long)beta * NP + pt] = ldexpf(1.f, e - 13);
             }
         }
     }
@@ -232,9 +254,9 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
             const int n = 2 * (16 * t + lr);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const long row = row0 + 16 * r + 4 * lk + q;
-                if (row >= nrows) continue;
-                const size_t o = (size_t)row * ncp + n;
+                const long row = row0 + 16 * r + 4 * lk + q, pt = pt0 + 4 * lk + q;
+                if (OUT == 3 ? pt >= NP || beta >= batch : row >= nrows) continue;
+                const size_t o = (OUT == 3 ? (size_t)pt * batch + beta : (size_t)row) * ncp + n;
                 const float ce = ae[r][t][q], co = ao[r][t][q];
                 if (OUT == 1) {
                     *(float2 *)((float *)c_out + o) = make_float2(ce, co);
@@ -1179,6 +1201,9 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
         const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
         lds_dma16(srcX + ab * strideX, buf + S::C_BUF + (size_t)chX * 1024);
     };
+    // FP16X3 coefficients are point-major ([point][beta][n]), the others cosmology-major
+    constexpr bool PM = PREC == BLAST_FP16X3;
+    const size_t cstride = PM ? (size_t)batch * ncp : (size_t)ncp;  // per point
     const void *srcC[S::C_PW];
 #pragma unroll
     for (int k = 0; k < S::C_PW; ++k) {
@@ -1189,13 +1214,13 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
         const int row = pos / S::ROWB, gp = (pos % S::ROWB) / 16;
         const int v = gp ^ (row & SWZ);          // granule stored at position gp
         const int bb = bt * 64 + (row < nb ? row : 0);
-        srcC[k] = (part ? (const E *)c_lo : c) + (size_t)bb * NP * ncp + v * VEC;
+        srcC[k] = (part ? (const E *)c_lo : c) + (size_t)bb * (PM ? ncp : NP * ncp) + v * VEC;
     }
     auto dma_C = [&](int b, unsigned char *__restrict__ buf) {
         const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
 #pragma unroll
         for (int k = 0; k < S::C_PW; ++k)
-            lds_dma16((const E *)srcC[k] + ab * ncp, buf + (size_t)min(w + k * S::NW, S::C_CH - 1) * 1024);
+            lds_dma16((const E *)srcC[k] + ab * cstride, buf + (size_t)min(w + k * S::NW, S::C_CH - 1) * 1024);
     };
 
     float y[4][NB];
@@ -1413,12 +1438,15 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     }
 }
 
-// Split 16-bit fused kernel with wider wave tiles (FP16X3 and BF16X3, NB <= 16).  The 12-wave kernel
-// above is bound by the bytes it moves from L2 into LDS per (row, cosmology) pair; here a work-group
-// is (chi_a, 64 cosmologies, 4 row tiles) with 8 waves, and wave (i, k) makes two 16 x 16 tiles per b
-// (row tile i, cosmologies 32k..32k+15 and 32k+16..32k+31), keeping Y for 4 rows x NB bins of both
-// (two waves per SIMD).  Per b it moves 32 KB of basis and 32 KB of c rows for 4096 pairs, against
-// 24 + 32 KB for 3072.  Basis and c one b ahead (two LDS buffers each, 138 KB); one barrier per b.
+// FP16X3 fused kernel with wider wave tiles (NB <= 16).  The 12-wave kernel above is bound by the
+// bytes it moves from L2 into LDS per (row, cosmology) pair; here a work-group is (chi_a, 64
+// cosmologies, 4 row tiles) with 8 waves, and wave (i, k) makes two 16 x 16 tiles per b (row tile i,
+// cosmologies 32k..32k+15 and 32k+16..32k+31), keeping Y for 4 rows x NB bins of both (two waves per
+// SIMD).  Per b it moves 32 KB of basis and 32 KB of c rows for 4096 pairs, against 24 + 32 KB for
+// 3072.  Basis and c one b ahead (two LDS buffers each, 138 KB); one barrier per b.  The time is
+// that of the data movement (a copy without the MFMAs and R-sum takes as long), so the coefficients
+// are point-major: the 64 rows of one point are one 16 KB block per part, where cosmology-major rows
+// were 64 separate 256-byte pieces, 6 MB apart, and took 3.95 ms against 3.45 at full 3x2pt.
 // Steps are not software-pipelined (the registers hold both tiles' accumulators and Y).
 constexpr int kWideTR = 4;
 
@@ -1446,7 +1474,7 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
     constexpr int GPR = S::ROWB / 16;
     constexpr int SWZ = GPR % 16 == 0 ? 15 : (GPR % 8 == 0 ? 7 : (GPR % 4 == 0 ? 3 : (GPR % 2 == 0 ? 1 : 0)));
     constexpr bool KROT = NB == 16;
-    static_assert(NB <= 16 && S::LDS <= 160 * 1024, "LDS of the wide fused kernel");
+    static_assert(PREC == BLAST_FP16X3 && NB <= 16 && S::LDS <= 160 * 1024, "LDS of the wide fused kernel");
     __shared__ __align__(1024) unsigned char A0[S::A_BUF], A1[S::A_BUF];
     __shared__ __align__(1024) unsigned char C0[S::C_BUF + S::X_BUF], C1[S::C_BUF + S::X_BUF];
 
@@ -1526,13 +1554,15 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
         const int row = pos / S::ROWB, gp = (pos % S::ROWB) / 16;
         const int v = gp ^ (row & SWZ);
         const int bb = bt * 64 + (row < nb ? row : 0);
-        srcC[k] = (part ? c_lo : c) + (size_t)bb * NP * ncp + v * VEC;
+        srcC[k] = (part ? c_lo : c) + (size_t)bb * ncp + v * VEC;
     }
+    // point-major coefficients: the 64 rows of one point are one block of 64 ncp elements per part
+    const size_t cstride = (size_t)batch * ncp;
     auto dma_C = [&](int b, unsigned char *__restrict__ buf) {
         const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
 #pragma unroll
         for (int k = 0; k < S::C_PW; ++k)
-            lds_dma16(srcC[k] + ab * ncp, buf + (size_t)min(w + k * S::NW, S::C_CH - 1) * 1024);
+            lds_dma16(srcC[k] + ab * cstride, buf + (size_t)min(w + k * S::NW, S::C_CH - 1) * 1024);
     };
 
     float y[2][4][NB];
@@ -2094,11 +2124,12 @@ __global__ __launch_bounds__(256) void coef_in_kernel(const PT *__restrict__ cin
 }
 
 // FP16 hi and lo parts of coefficients given as input, one wave per row: the same power-of-two
-// row scale as the projection's FP16 output (largest |c_n| in [2^14, 2^15), cs[row] = scale)
+// row scale as the projection's FP16 output (largest |c_n| in [2^14, 2^15), cs[row] = scale), and
+// written point-major like it (row = beta * NP + point goes to point * batch + beta)
 template <typename PT>
 __global__ __launch_bounds__(256) void coef_in16_kernel(const PT *__restrict__ cin, int N, int ncp, long nrows,
                                                         uint16_t *__restrict__ c_hi, uint16_t *__restrict__ c_lo,
-                                                        float *__restrict__ cs) {
+                                                        float *__restrict__ cs, long NP, int batch) {
     const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= nrows) return;  // uniform over the wave
@@ -2114,14 +2145,15 @@ __global__ __launch_bounds__(256) void coef_in16_kernel(const PT *__restrict__ c
     const int e = mx > 0.f ? min(max(ilogbf(mx), -100), 127) : 14;
     const float mul = ldexpf(1.f, 14 - e);
     if (lane == 0) cs[row] = ldexpf(1.f, e - 14);
+    const size_t orow = (size_t)(row % NP) * batch + row / NP;
 #pragma unroll
     for (int i = 0; i < kMaxCheb / 64; ++i) {
         const int n = lane + 64 * i;
         if (n >= ncp) break;
         const float x = v[i] * mul;
         const _Float16 h = (_Float16)x;
-        c_hi[row * ncp + n] = __builtin_bit_cast(uint16_t, h);
-        c_lo[row * ncp + n] = __builtin_bit_cast(uint16_t, (_Float16)(x - (float)h));
+        c_hi[orow * ncp + n] = __builtin_bit_cast(uint16_t, h);
+        c_lo[orow * ncp + n] = __builtin_bit_cast(uint16_t, (_Float16)(x - (float)h));
     }
 }
 
@@ -3028,10 +3060,10 @@ void stage_project(blast_plan *p, const blast_cl_args *a, const Ctx &x, void *c,
         dim3 grid((unsigned)((nrows + 3) / 4));
         if (p64)
             hipLaunchKernelGGL((coef_in16_kernel<double>), grid, dim3(256), 0, s, (const double *)a->P, N, ncp, nrows,
-                               (uint16_t *)c, clo, cs);
+                               (uint16_t *)c, clo, cs, (long)p->NP, a->batch);
         else
             hipLaunchKernelGGL((coef_in16_kernel<float>), grid, dim3(256), 0, s, (const float *)a->P, N, ncp, nrows,
-                               (uint16_t *)c, clo, cs);
+                               (uint16_t *)c, clo, cs, (long)p->NP, a->batch);
         return;
     }
     if (a->p_kind == 1) {
@@ -3072,9 +3104,12 @@ void stage_project(blast_plan *p, const blast_cl_args *a, const Ctx &x, void *c,
             using PT = typename decltype(ptag)::type;
             constexpr int O = decltype(otag)::value, NT = decltype(nttag)::value;
             constexpr int rows_wg = 64 * split_rt<O>();
-            dim3 grid((unsigned)((nrows + rows_wg - 1) / rows_wg));
+            // output 3: 16 points x 4 cosmologies per work-group, in groups of kProjPG point blocks
+            const long NPB = (p->NP + 15) / 16, NBB = (a->batch + 3) / 4;
+            const dim3 grid = O == 3 ? dim3((unsigned)((NPB + kProjPG - 1) / kProjPG * kProjPG * NBB))
+                                     : dim3((unsigned)((nrows + rows_wg - 1) / rows_wg));
             hipLaunchKernelGGL((project_split_kernel<PT, O, NT>), grid, dim3(256), shp, s, (const PT *)a->P,
-                               p->d_dctn32, N, ncp, nrows, c, clo, cs);
+                               p->d_dctn32, N, ncp, nrows, c, clo, cs, (long)p->NP, a->batch);
         };
         auto by_nt = [&](auto ptag, auto otag) {
             switch (ncp / 32) {  // Hp / 16 = ncp / 32, ncp a multiple of 32 up to 128
