@@ -65,7 +65,9 @@ typedef enum {
  * (one cosmology, one point) carries its own power-of-two scale that keeps its
  * magnitudes below 2^15, inside FP16's range (basis rows and coefficients given
  * as input: largest magnitude in [2^14, 2^15); coefficients projected from nodal
- * P: from the row's largest |P_j|, which bounds |c_n| / 2).  FP16X3 runs the
+ * P: from the row's largest |P_j|, which bounds |c_n| / 2), and the projection
+ * of nodal P runs the same three products on P and the DCT matrix split into
+ * FP16 hi + lo parts.  FP16X3 runs the
  * fused contraction + R-quadrature only: it needs nodal P with n_cheb % 8 == 0
  * (or P given as coefficients), n_g + n_s <= 20 and no w_save, and is not
  * available to the adjoint; other requests are refused with BLAST_E_UNSUPPORTED.
@@ -80,8 +82,8 @@ typedef enum {
  * (FP16X3), 2^-15 (BF16X3: the hi*lo sum leaves 16 bits per operand) and 2^-7 (BF16: 8 bits
  * per operand).  Measured against the FP64 oracle (element-wise, cross spectra floored at
  * 1e-3 of the geometric mean of the two auto spectra): at 20 multipoles on [2, 200] with 64
- * Chebyshev nodes FP64 8e-12, FP32 3e-5, FP16X3 1e-5, BF16X3 9e-4, BF16 0.26; at 96
- * multipoles on [2, 1000] with 128 nodes FP64 4e-11, FP32 6e-4, FP16X3 2e-4, BF16X3 9e-3,
+ * Chebyshev nodes FP64 8e-12, FP32 3e-5, FP16X3 1.4e-5, BF16X3 9e-4, BF16 0.26; at 96
+ * multipoles on [2, 1000] with 128 nodes FP64 4e-11, FP32 6e-4, FP16X3 3e-4, BF16X3 9e-3,
  * BF16 6.2.  FP64 is the path for a 1e-6 bar and FP16X3 or FP32 for 1e-3; BF16X3 meets 1e-3
  * only on grids like the first and stays within 2e-2 on grids like the second; plain BF16
  * is not an accurate evaluation of C at either (errors of order 1 at the second) and is

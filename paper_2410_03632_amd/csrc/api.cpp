@@ -140,6 +140,7 @@ static void free_plan(blast_plan *p) {
     f(p->d_dct32);
     f(p->d_dctn64);
     f(p->d_dctn32);
+    f(p->d_dct16);
     f(p->d_chi);
     f(p->d_wchi);
     f(p->d_wR);

@@ -486,6 +486,22 @@ __global__ __launch_bounds__(256) void to_fp16_kernel(const double *__restrict__
     }
 }
 
+// the FP16X3 projection's operand table (layout: dct16_off), one thread per 8-half entry
+__global__ __launch_bounds__(256) void to_dct16_kernel(const double *__restrict__ dctn, int N, int NT, int NK, int g,
+                                                       uint16_t *__restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= 2 * NT * NK * 2 * 64) return;
+    const int lane = i % 64, hl = (i / 64) % 2, k = (i / 128) % NK, t = (i / (128 * NK)) % NT, par = i / (128 * NK * NT);
+    const int n = 2 * (16 * t + lane % 16) + par;
+    for (int e = 0; e < 8; ++e) {
+        const int j = 32 * k + 8 * (lane / 16) + e;
+        const double v = (n < N && j < N / 2) ? ldexp(dctn[(size_t)n * N + j], g) : 0.0;
+        const _Float16 h = (_Float16)(float)v;
+        const _Float16 x = hl ? (_Float16)(float)(v - (double)(float)h) : h;
+        out[dct16_off(par, t, k, hl, lane, NT, NK) + e] = __builtin_bit_cast(uint16_t, x);
+    }
+}
+
 void gauss_legendre16(double *x, double *w) {
     const int n = 16;
     for (int i = 0; i < n; ++i) {
@@ -699,6 +715,11 @@ blast_status derive_precisions(blast_plan *p, hipStream_t s) {
         if (e != hipSuccess) return p->basis.scale16 = nullptr, fail(e, "FP16 basis scales");
         hipLaunchKernelGGL(to_fp16_kernel, dim3((unsigned)((nrows + 3) / 4)), dim3(256), 0, s, p->basis.f64, nrows,
                            p->rows_pad, p->nc_pad, p->basis.h16, p->basis.l16, p->basis.scale16);
+        const int NT = p->nc_pad / 32, NK = (NT + 1) / 2, nent = 2 * NT * NK * 2 * 64;
+        e = hipMalloc(&p->d_dct16, (size_t)nent * 8 * sizeof(uint16_t));
+        if (e != hipSuccess) return p->d_dct16 = nullptr, fail(e, "FP16 projection table");
+        hipLaunchKernelGGL(to_dct16_kernel, dim3((unsigned)((nent + 255) / 256)), dim3(256), 0, s, p->d_dctn64,
+                           p->n_cheb, NT, NK, dct16_exp(p->n_cheb), p->d_dct16);
     }
     BLAST_HIP_TRY(hipGetLastError());
     return BLAST_OK;

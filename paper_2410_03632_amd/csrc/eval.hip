@@ -94,33 +94,26 @@ __global__ __launch_bounds__(256) void project_kernel(const PT *__restrict__ P, 
 //     c_{2m} = sum_{j<N/2} D[2m][j] u_j,      c_{2m+1} = sum_{j<N/2} D[2m+1][j] v_j,
 // two [rows x N/2] x [N/2 x N/2] products: half the MFMA work of the plain product.  N/2 is padded
 // to Hp (a multiple of 16) with zero weights, so the nc_pad = 2 Hp outputs of a row come out with
-// exact zeros past N.  Each wave owns split_rt<OUT>() row tiles and every even and odd output tile; the
+// exact zeros past N.  Each wave owns split_rt() row tiles and every even and odd output tile; the
 // P values of step s+1 are loaded while step s runs.  A lane stores (c_{2m}, c_{2m+1}) as one
-// 8-byte pair.  The FP16 output takes one row tile per wave (two need 169 registers, two waves
-// per SIMD: 1.71 ms against 1.48 ms at full 3x2pt, batch 256), the others two.
-template <int OUT>
-constexpr int split_rt() { return OUT == 3 ? 1 : 2; }
+// 8-byte pair.
+constexpr int split_rt() { return 2; }
+// the FP16X3 projection's launch order: the cosmology blocks of kProjPG consecutive 16-point blocks
+// next to each other (measured 2.5 % faster than the point blocks of one cosmology block)
 constexpr long kProjPG = 8;
+constexpr int kProjPasses = 8;  // passes of 4 cosmologies per work-group of the FP16X3 projection
 
 // NT = Hp / 16 output tiles per parity (1..4) and as many K steps: with both known at compile time
 // the step loop unrolls and every load is unconditional (rows past the end read the last row and
 // are never stored), so the compiler can wait for exactly the loads a step needs and the next
 // step's loads stay in flight under the current step's MFMAs.
-// OUT: 1 -> float c, 2 -> BF16 hi (+ lo when c_lo != nullptr), 3 -> FP16 hi and lo of c / s with a
-// power-of-two s per row that keeps every |c_n / s| below 2^15 (from the row's largest |P_j|);
-// cs[row] = s.
-// Outputs 1 and 2 keep P's row order (row = beta * NP + point), 64 RT consecutive rows per
-// work-group.  Output 3 is written point-major, c[(point * batch + beta) * ncp + n], so that the fused
-// contraction reads the rows of 64 cosmologies at one point as one contiguous block (cs stays in P's
-// order): a work-group takes 16 points of 4 cosmologies (one per wave), so that each wave reads 16
-// consecutive P rows and each point's 4 rows land side by side.  (Cosmology-major c takes 1.48 ms
-// here at full 3x2pt, batch 256, and point-major 1.66; the fused kernel reading it saves 0.5 ms.)
+// OUT: 1 -> float c, 2 -> BF16 hi (+ lo when c_lo != nullptr); the FP16X3 output has a kernel of its
+// own (project_h16_kernel).
 template <typename PT, int OUT, int NT>
 __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict__ P, const float *__restrict__ Dn,
                                                             int N, int ncp, long nrows, void *__restrict__ c_out,
-                                                            uint16_t *__restrict__ c_lo, float *__restrict__ cs,
-                                                            long NP, int batch) {
-    constexpr int RT = split_rt<OUT>(), VEC = 4, KSTEP = 16;
+                                                            uint16_t *__restrict__ c_lo) {
+    constexpr int RT = split_rt(), VEC = 4, KSTEP = 16;
     extern __shared__ __align__(16) unsigned char smem_s[];
     const int H = N / 2;
     constexpr int Hp = 16 * NT, hs = Hp + 4;  // LDS row stride: 16 bytes of padding
@@ -139,23 +132,9 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
     const long row0 = (long)blockIdx.x * (64 * RT) + 16 * RT * w;
-    // output 3: blocks of 16 points (pbk) x 4 cosmologies (bbk), the cosmology blocks of kProjPG
-    // consecutive point blocks next to each other in the launch order (measured: 2.5 % faster than
-    // the point blocks of one cosmology block next to each other)
-    long pbk = 0, bbk = 0;
-    if (OUT == 3) {
-        const long NPB = (NP + 15) / 16, NBB = (batch + 3) / 4, L = blockIdx.x;
-        const long grp = L / (kProjPG * NBB), rem = L % (kProjPG * NBB);
-        pbk = grp * kProjPG + rem % kProjPG, bbk = rem / kProjPG;
-        if (pbk >= NPB) return;  // uniform over the work-group (no barrier follows)
-    }
-    const long pt0 = 16L * pbk;           // output 3: the work-group's first point
-    const int beta = 4 * (int)bbk + w;    // output 3: the wave's cosmology
     const PT *prow[RT];
 #pragma unroll
-    for (int r = 0; r < RT; ++r)
-        prow[r] = OUT == 3 ? P + ((long)min(beta, batch - 1) * NP + min(pt0 + lr, NP - 1)) * N
-                           : P + min(row0 + 16 * r + lr, nrows - 1) * (long)N;
+    for (int r = 0; r < RT; ++r) prow[r] = P + min(row0 + 16 * r + lr, nrows - 1) * (long)N;
     f4 ae[RT][NT], ao[RT][NT];
 #pragma unroll
     for (int r = 0; r < RT; ++r)
@@ -181,20 +160,8 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
             }
         }
     };
-    // FP16 output: the largest |P_j| of the lane's rows (loads past N/2 repeat values of the row)
-    float pm[RT];
-#pragma unroll
-    for (int r = 0; r < RT; ++r) pm[r] = 0.f;
     auto compute = [&](int st, const float4 (&front)[RT], const float4 (&back)[RT]) {
         const int j0 = st * KSTEP + lk * VEC;
-        if constexpr (OUT == 3) {
-#pragma unroll
-            for (int r = 0; r < RT; ++r)
-                pm[r] = fmaxf(pm[r], fmaxf(fmaxf(fmaxf(fabsf(front[r].x), fabsf(front[r].y)),
-                                                 fmaxf(fabsf(front[r].z), fabsf(front[r].w))),
-                                           fmaxf(fmaxf(fabsf(back[r].x), fabsf(back[r].y)),
-                                                 fmaxf(fabsf(back[r].z), fabsf(back[r].w)))));
-        }
         float u[RT][VEC], v[RT][VEC];
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
@@ -226,27 +193,6 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
         compute(st, fr[st & 1], bk[st & 1]);
     }
     // lane holds rows 16r + 4lk + q of output m = 16t + lr, i.e. n = 2m and 2m + 1
-    // FP16 output: the row scale from the largest |P_j| of the row (over its 4 lanes lk).  Each half
-    // row of D has absolute sum <= 1 and |u_j|, |v_j| <= 2 max|P|, so |c_n| <= 2 max|P| < 2^(e + 2)
-    // with e = floor(log2 max|P|), and c / s with s = 2^(e - 13) stays below 2^15 (FP16's normal
-    // range reaches 65504); the hi + lo split keeps its 22 bits at any magnitude in that range.
-    float mul[RT][4];
-    if constexpr (OUT == 3) {
-#pragma unroll
-        for (int r = 0; r < RT; ++r) {
-            pm[r] = fmaxf(pm[r], __shfl_xor(pm[r], 16));
-            pm[r] = fmaxf(pm[r], __shfl_xor(pm[r], 32));
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float mx = __shfl(pm[r], 4 * lk + q);  // the max of row 16 r + 4 lk + q
-                // e kept where 2^(13 - e) is a finite float; rows of zeros get s = 1
-                const int e = mx > 0.f ? min(max(ilogbf(mx), -100), 127) : 13;
-                mul[r][q] = ldexpf(1.f, 13 - e);
-                const long pt = pt0 + 4 * lk + q;
-                if (lr == 0 && pt < NP && beta < batch) cs[(long)beta * NP + pt] = ldexpf(1.f, e - 13);
-            }
-        }
-    }
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
@@ -254,20 +200,12 @@ __global__ __launch_bounds__(256) void project_split_kernel(const PT *__restrict
             const int n = 2 * (16 * t + lr);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const long row = row0 + 16 * r + 4 * lk + q, pt = pt0 + 4 * lk + q;
-                if (OUT == 3 ? pt >= NP || beta >= batch : row >= nrows) continue;
-                const size_t o = (OUT == 3 ? (size_t)pt * batch + beta : (size_t)row) * ncp + n;
+                const long row = row0 + 16 * r + 4 * lk + q;
+                if (row >= nrows) continue;
+                const size_t o = (size_t)row * ncp + n;
                 const float ce = ae[r][t][q], co = ao[r][t][q];
                 if (OUT == 1) {
                     *(float2 *)((float *)c_out + o) = make_float2(ce, co);
-                } else if (OUT == 3) {
-                    const float ve = ce * mul[r][q], vo = co * mul[r][q];  // exact: powers of two
-                    const _Float16 he = (_Float16)ve, ho = (_Float16)vo;
-                    const _Float16 le = (_Float16)(ve - (float)he), lo = (_Float16)(vo - (float)ho);
-                    *(uint32_t *)((uint16_t *)c_out + o) = (uint32_t)__builtin_bit_cast(uint16_t, he) |
-                                                           ((uint32_t)__builtin_bit_cast(uint16_t, ho) << 16);
-                    *(uint32_t *)(c_lo + o) = (uint32_t)__builtin_bit_cast(uint16_t, le) |
-                                              ((uint32_t)__builtin_bit_cast(uint16_t, lo) << 16);
                 } else {
                     const uint16_t he = bf16_rne(ce), ho = bf16_rne(co);
                     *(uint32_t *)((uint16_t *)c_out + o) = (uint32_t)he | ((uint32_t)ho << 16);
@@ -443,6 +381,139 @@ __device__ inline f4 mfma16(U4 a, U4 b, f4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0,
                                                        0);
 }
+
+// FP16X3 projection on FP16 MFMA.  The even/odd split of project_split_kernel (c_2m from
+// u_j = P_j + P_{N-1-j}, c_2m+1 from v_j = P_j - P_{N-1-j}, j < N/2), with u, v and the matrix
+// halves as FP16 hi + lo pairs and the three products hi*hi + hi*lo + lo*hi of each 32-column step
+// on v_mfma_f32_16x16x32_f16 (FP32 accumulate): a fifth of the MFMA cycles of the FP32 products,
+// which the FP32 form could not hide under its HBM traffic.  Each row is scaled by s = 2^(13 - e),
+// e = floor(log2 max|P_j|), before the split, so |u s|, |v s| < 2^15 stay in FP16's normal range;
+// then c s (the scaled output, cs = 1 / s) comes straight out of the products, whose matrix factor
+// 2^g (dct16_exp) is taken off exactly.  u and v carry 22 significant bits through the split, the
+// matrix 22, and the dropped lo*lo term is 2^-22 of a product.
+// A work-group takes 16 points x 4 npass cosmologies, in npass passes of 4 (one per wave), and
+// writes c point-major, c[(point * batch + beta) * ncp + n], each point's 4 rows of a pass side by
+// side; the operand table (32 KB at 128 nodes) is copied to LDS once per work-group (measured at
+// full 3x2pt, batch 256: 1.48 ms with one pass, 1.31 with 4, 1.29 with 8).
+template <typename PT, int NT>
+__global__ __launch_bounds__(256) void project_h16_kernel(const PT *__restrict__ P, const uint16_t *__restrict__ Dh,
+                                                          int N, int ncp, int g, long NP, int batch,
+                                                          uint16_t *__restrict__ c_hi, uint16_t *__restrict__ c_lo,
+                                                          float *__restrict__ cs, int npass) {
+    constexpr int NK = (NT + 1) / 2, TAB = 2 * NT * NK * 2 * 64;
+    __shared__ U4 tab[TAB];
+    for (int i = threadIdx.x; i < TAB; i += 256) tab[i] = ((const U4 *)Dh)[i];
+    __syncthreads();
+    const long NPB = (NP + 15) / 16, NBB = (batch + 4 * npass - 1) / (4 * npass), L = blockIdx.x;
+    const long grp = L / (kProjPG * NBB), rem = L % (kProjPG * NBB);
+    const long pbk = grp * kProjPG + rem % kProjPG, bbk = rem / kProjPG;
+    if (pbk >= NPB) return;  // uniform over the work-group (no barrier follows)
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const long pt0 = 16L * pbk;
+    for (int it = 0; it < npass; ++it) {
+        if (4 * npass * bbk + 4 * it >= batch) break;  // uniform over the work-group
+        const int beta = 4 * npass * (int)bbk + 4 * it + w;
+        const int H = N / 2;
+        const PT *prow = P + ((long)min(beta, batch - 1) * NP + min(pt0 + lr, NP - 1)) * N;
+        // the lane's columns of each step: j0 = 32 k + 8 lk + 4 h (h = 0, 1) and the mirrored ones;
+        // chunks past N/2 (zero weights) read the row's last chunk below N/2 instead (H % 4 == 0)
+        float4 fr[NK][2], bk[NK][2];
+#pragma unroll
+        for (int k = 0; k < NK; ++k)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                int j0 = 32 * k + 8 * lk + 4 * h;
+                j0 = j0 < H ? j0 : H - 4;
+                if constexpr (sizeof(PT) == 4) {
+                    fr[k][h] = *(const float4 *)(prow + j0);
+                    bk[k][h] = *(const float4 *)(prow + N - 4 - j0);
+                } else {
+                    const double2 f0 = *(const double2 *)(prow + j0), f1 = *(const double2 *)(prow + j0 + 2);
+                    const double2 b0 = *(const double2 *)(prow + N - 4 - j0), b1 = *(const double2 *)(prow + N - 2 - j0);
+                    fr[k][h] = make_float4((float)f0.x, (float)f0.y, (float)f1.x, (float)f1.y);
+                    bk[k][h] = make_float4((float)b0.x, (float)b0.y, (float)b1.x, (float)b1.y);
+                }
+            }
+        // the row's largest |P_j| (its four lanes together load every P_j of the row)
+        float pm = 0.f;
+#pragma unroll
+        for (int k = 0; k < NK; ++k)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                pm = fmaxf(pm, fmaxf(fmaxf(fmaxf(fabsf(fr[k][h].x), fabsf(fr[k][h].y)),
+                                           fmaxf(fabsf(fr[k][h].z), fabsf(fr[k][h].w))),
+                                     fmaxf(fmaxf(fabsf(bk[k][h].x), fabsf(bk[k][h].y)),
+                                           fmaxf(fabsf(bk[k][h].z), fabsf(bk[k][h].w)))));
+        pm = fmaxf(pm, __shfl_xor(pm, 16));
+        pm = fmaxf(pm, __shfl_xor(pm, 32));
+        // e kept where 2^(13 - e) is a finite float; rows of zeros get s = 1
+        const int e = pm > 0.f ? min(max(ilogbf(pm), -100), 127) : 13;
+        const float mul = ldexpf(1.f, 13 - e);
+        // A operands: lane (row lr, lk) holds columns 32 k + 8 lk .. + 7 of u s and v s, hi and lo
+        U4 uh[NK], ul[NK], vh[NK], vl[NK];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            h8 a, b, c, d;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                // the mirror of column j0 + q is N - 1 - j0 - q = (N - 4 - j0) + (3 - q)
+                const float f[4] = {fr[k][h].x, fr[k][h].y, fr[k][h].z, fr[k][h].w};
+                const float r[4] = {bk[k][h].w, bk[k][h].z, bk[k][h].y, bk[k][h].x};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float u = (f[q] + r[q]) * mul, v = (f[q] - r[q]) * mul;  // exact scaling
+                    const _Float16 uhi = (_Float16)u, vhi = (_Float16)v;
+                    a[4 * h + q] = uhi;
+                    b[4 * h + q] = (_Float16)(u - (float)uhi);
+                    c[4 * h + q] = vhi;
+                    d[4 * h + q] = (_Float16)(v - (float)vhi);
+                }
+            }
+            uh[k] = __builtin_bit_cast(U4, a), ul[k] = __builtin_bit_cast(U4, b);
+            vh[k] = __builtin_bit_cast(U4, c), vl[k] = __builtin_bit_cast(U4, d);
+        }
+        f4 ae[NT], ao[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            ae[t] = ao[t] = f4{0, 0, 0, 0};
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                const U4 *te = tab + dct16_off(0, t, k, 0, lane, NT, NK) / 8;
+                const U4 *to = tab + dct16_off(1, t, k, 0, lane, NT, NK) / 8;
+                const U4 eh = te[0], el = te[64], oh = to[0], ol = to[64];
+                ae[t] = mfma16<BLAST_FP16X3>(uh[k], eh, ae[t]);
+                ao[t] = mfma16<BLAST_FP16X3>(vh[k], oh, ao[t]);
+                ae[t] = mfma16<BLAST_FP16X3>(uh[k], el, ae[t]);
+                ao[t] = mfma16<BLAST_FP16X3>(vh[k], ol, ao[t]);
+                ae[t] = mfma16<BLAST_FP16X3>(ul[k], eh, ae[t]);
+                ao[t] = mfma16<BLAST_FP16X3>(vl[k], oh, ao[t]);
+            }
+        }
+        // lane holds rows 4 lk + q (points pt0 + 4 lk + q) of output m = 16 t + lr, i.e. n = 2m, 2m + 1
+        const float og = ldexpf(1.f, -g);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const long pt = pt0 + 4 * lk + q;
+            const int eq = __shfl(e, 4 * lk + q);  // the scale exponent of that row
+            if (pt >= NP || beta >= batch) continue;
+            if (lr == 0) cs[(long)beta * NP + pt] = ldexpf(1.f, eq - 13);
+            const size_t o = ((size_t)pt * batch + beta) * ncp;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int n = 2 * (16 * t + lr);
+                const float ve = ae[t][q] * og, vo = ao[t][q] * og;  // exact: powers of two
+                const _Float16 he = (_Float16)ve, ho = (_Float16)vo;
+                const _Float16 le = (_Float16)(ve - (float)he), lo = (_Float16)(vo - (float)ho);
+                *(uint32_t *)(c_hi + o + n) = (uint32_t)__builtin_bit_cast(uint16_t, he) |
+                                              ((uint32_t)__builtin_bit_cast(uint16_t, ho) << 16);
+                *(uint32_t *)(c_lo + o + n) = (uint32_t)__builtin_bit_cast(uint16_t, le) |
+                                              ((uint32_t)__builtin_bit_cast(uint16_t, lo) << 16);
+            }
+        }
+    }
+}
+
 
 template <int PREC>
 __global__ __launch_bounds__(256) void contract_kernel(const typename Cfg<PREC>::E *__restrict__ basis,
@@ -3103,13 +3174,10 @@ void stage_project(blast_plan *p, const blast_cl_args *a, const Ctx &x, void *c,
         auto launch = [&](auto ptag, auto otag, auto nttag) {
             using PT = typename decltype(ptag)::type;
             constexpr int O = decltype(otag)::value, NT = decltype(nttag)::value;
-            constexpr int rows_wg = 64 * split_rt<O>();
-            // output 3: 16 points x 4 cosmologies per work-group, in groups of kProjPG point blocks
-            const long NPB = (p->NP + 15) / 16, NBB = (a->batch + 3) / 4;
-            const dim3 grid = O == 3 ? dim3((unsigned)((NPB + kProjPG - 1) / kProjPG * kProjPG * NBB))
-                                     : dim3((unsigned)((nrows + rows_wg - 1) / rows_wg));
+            constexpr int rows_wg = 64 * split_rt();
+            dim3 grid((unsigned)((nrows + rows_wg - 1) / rows_wg));
             hipLaunchKernelGGL((project_split_kernel<PT, O, NT>), grid, dim3(256), shp, s, (const PT *)a->P,
-                               p->d_dctn32, N, ncp, nrows, c, clo, cs, (long)p->NP, a->batch);
+                               p->d_dctn32, N, ncp, nrows, c, clo);
         };
         auto by_nt = [&](auto ptag, auto otag) {
             switch (ncp / 32) {  // Hp / 16 = ncp / 32, ncp a multiple of 32 up to 128
@@ -3121,13 +3189,34 @@ void stage_project(blast_plan *p, const blast_cl_args *a, const Ctx &x, void *c,
         };
         using I1 = std::integral_constant<int, 1>;
         using I2 = std::integral_constant<int, 2>;
-        using I3 = std::integral_constant<int, 3>;
         if (p64 && out == 1) by_nt(TypeTag<double>(), I1());
         if (p64 && out == 2) by_nt(TypeTag<double>(), I2());
-        if (p64 && out == 3) by_nt(TypeTag<double>(), I3());
         if (!p64 && out == 1) by_nt(TypeTag<float>(), I1());
         if (!p64 && out == 2) by_nt(TypeTag<float>(), I2());
-        if (!p64 && out == 3) by_nt(TypeTag<float>(), I3());
+        if (out == 3) {
+            // FP16 MFMA form: 16 points x 4 npass cosmologies per work-group, the work-groups of
+            // kProjPG consecutive point blocks next to each other
+            const int npass = std::min(kProjPasses, (a->batch + 3) / 4);
+            const long NPB = (p->NP + 15) / 16, NBB = (a->batch + 4 * npass - 1) / (4 * npass);
+            const dim3 grid((unsigned)((NPB + kProjPG - 1) / kProjPG * kProjPG * NBB));
+            const int g = dct16_exp(N);
+            auto launch16 = [&](auto ptag, auto nttag) {
+                using PT = typename decltype(ptag)::type;
+                constexpr int NT = decltype(nttag)::value;
+                hipLaunchKernelGGL((project_h16_kernel<PT, NT>), grid, dim3(256), 0, s, (const PT *)a->P,
+                                   p->d_dct16, N, ncp, g, (long)p->NP, a->batch, (uint16_t *)c, clo, cs, npass);
+            };
+            auto by_nt16 = [&](auto ptag) {
+                switch (ncp / 32) {
+                    case 1: launch16(ptag, std::integral_constant<int, 1>()); break;
+                    case 2: launch16(ptag, std::integral_constant<int, 2>()); break;
+                    case 3: launch16(ptag, std::integral_constant<int, 3>()); break;
+                    default: launch16(ptag, std::integral_constant<int, 4>()); break;
+                }
+            };
+            if (p64) by_nt16(TypeTag<double>());
+            else by_nt16(TypeTag<float>());
+        }
     } else {
         dim3 grid((unsigned)((nrows + kProjRows - 1) / kProjRows));
 #define BLAST_PROJ(PT, AT, O, D) \

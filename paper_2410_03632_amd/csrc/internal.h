@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <mutex>
 #include <string>
@@ -33,6 +34,18 @@ __host__ __device__ inline size_t tiled_off(int row, int n, int nsteps, int VEC)
     const int lane = (row & 15) + 16 * ((n % KSTEP) / VEC);
     return (((size_t)(row >> 4) * nsteps + n / KSTEP) * 64 + lane) * VEC + n % VEC;
 }
+
+// FP16 hi + lo copy of the projection matrix used by the FP16X3 projection, in the register order
+// of the B operand of v_mfma_f32_16x16x32_f16.  With NT = nc_pad / 32 output tiles of 16 per parity
+// and NK = (NT + 1) / 2 steps of 32 columns, entry (parity p, tile t, step k, part hl, lane L) is
+// 8 halves: element e is 2^g D[2 (16 t + L % 16) + p][32 k + 8 (L / 16) + e], zero for columns
+// j >= n_cheb / 2 and rows n >= n_cheb (D[n][j] = the DCT-II matrix entry of c_n and P_j, whose
+// rows have the parity symmetry D[n][N-1-j] = (-1)^n D[n][j]), hi = fp16(x) and lo = fp16(x - hi).
+// g = dct16_exp(n_cheb) puts the largest |2^g D| in [2^14, 2^15).  Returns the offset in halves.
+__host__ __device__ inline size_t dct16_off(int p, int t, int k, int hl, int lane, int NT, int NK) {
+    return (((((size_t)p * NT + t) * NK + k) * 2 + hl) * 64 + lane) * 8;
+}
+inline int dct16_exp(int N) { return 14 - std::ilogb(2.0 / N); }
 
 // Power-of-two scale and the BF16 bit pattern helpers shared by host conversions.
 struct BasisBuffers {
@@ -79,6 +92,7 @@ struct blast_plan {
     float *d_dct32 = nullptr;
     double *d_dctn64 = nullptr; // projection matrix [nc_pad n][n_cheb j] (MFMA path)
     float *d_dctn32 = nullptr;
+    uint16_t *d_dct16 = nullptr;  // FP16 hi + lo operand table of the FP16X3 projection (dct16_off)
     double *d_chi = nullptr, *d_wchi = nullptr, *d_wR = nullptr;
     double *d_pref = nullptr;   // [rows] N_t(l)
     double *d_ell = nullptr;    // [n_ell] multipoles
