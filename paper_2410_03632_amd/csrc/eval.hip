@@ -1979,11 +1979,11 @@ __global__ __launch_bounds__(256) void kt_kernel(const double *__restrict__ Kchi
         __syncthreads();
     }
     // a thread always handles point ab0 + threadIdx.x % KP (blockDim is a multiple of KP), so its R
-    // weight is loaded once; eight K_chi2 loads in flight per thread (clamped addresses, values masked)
+    // weight is loaded once; sixteen K_chi2 loads in flight per thread (clamped addresses, values masked)
     static_assert(256 % KP == 0, "point of a thread");
     const int pt = threadIdx.x % KP, ab = min(ab0 + pt, NP - 1);
     const double wv = wR[ab % n_R];
-    constexpr int U = 8;
+    constexpr int U = 16;
     const int total = KB * NB * KP;
     for (int i0 = threadIdx.x; i0 < total; i0 += U * blockDim.x) {
         double kv[U];
