@@ -549,18 +549,21 @@ def main():
     work = stage_work(plan, cfg, prec, Bn)
     dom = max(per_launch, key=per_launch.get)
     roof = roofline(work[dom], per_launch[dom], prec)
-    split = "project_split64_kernel" if prec == "fp64" else "project_split_kernel"
-    roof["kernel"] = {"projection": split if cfg.n_cheb % 8 == 0 else "project_kernel",
-                      "contraction": (("contract_quad_f64_kernel" if prec == "fp64" else
-                                       "contract_quad_wide_kernel" if prec == "fp16x3" and cfg.n_g + cfg.n_s <= 16
-                                       else "contract_quad_kernel") if fused else "contract_kernel"),
-                      "quad_R": "quad_y_kernel", "quad_chi": "quad_c_mfma_kernel", "r_weights": "kt_kernel"}[dom]
+    split = {"fp64": "project_split64_kernel", "fp16x3": "project_h16_kernel"}.get(prec, "project_split_kernel")
+    kernel_of = {"projection": split if cfg.n_cheb % 8 == 0 else "project_kernel",
+                 "contraction": (("contract_quad_f64_kernel" if prec == "fp64" else
+                                  "contract_quad_wide_kernel" if prec == "fp16x3" and cfg.n_g + cfg.n_s <= 16
+                                  else "contract_quad_kernel") if fused else "contract_kernel"),
+                 "quad_R": "quad_y_kernel", "quad_chi": "quad_c_mfma_kernel", "r_weights": "kt_kernel"}
+    roof["kernel"] = kernel_of[dom]
     roof["traffic"] = counter_traffic(roof["kernel"], cfg.name, Bn, prec)
     roof["stage_ms_per_launch"] = per_launch
     roof["stage_roofline"] = {k: roofline(work[k], per_launch[k], prec) for k in per_launch if k in work}
-    for v in roof["stage_roofline"].values():
+    for k, v in roof["stage_roofline"].items():
         v.pop("algorithmic_flops", None)
         v.pop("algorithmic_bytes", None)
+        v["kernel"] = kernel_of[k]
+        v["traffic"] = counter_traffic(kernel_of[k], cfg.name, Bn, prec)
 
     # accuracy of the timed path: cosmology 0 (the stored oracle values' cosmology) against them
     res = out[0].cpu().numpy()
