@@ -706,7 +706,7 @@ __global__ __launch_bounds__(256) void contract_kernel(const typename Cfg<PREC>:
 // while step s runs on the MFMA units.
 constexpr int kTilesPerWave = 3;
 
-template <int PREC, int WPE = (PREC == BLAST_BF16X3 ? 2 : 4), int BTT = Cfg<PREC>::BT>
+template <int PREC, int WPE = (PREC == BLAST_BF16X3 ? 2 : 4), int BTT = Cfg<PREC>::BT, int TPWT = kTilesPerWave>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE))) void contract_tiled_kernel(const typename Cfg<PREC>::E *__restrict__ basis,
                                                              const uint16_t *__restrict__ basis_lo,
                                                              const float *__restrict__ scale,
@@ -715,7 +715,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE))) void
                                                              int rows_pad, int ncp, float *__restrict__ w_out) {
     using C = Cfg<PREC>;
     using E = typename C::E;
-    constexpr int VEC = C::VEC, BT = BTT, BTN = BT / 16, TPW = kTilesPerWave;
+    constexpr int VEC = C::VEC, BT = BTT, BTN = BT / 16, TPW = TPWT;
     constexpr bool X3 = PREC == BLAST_BF16X3;
     constexpr int KSTEP = 4 * VEC;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -822,16 +822,25 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE))) void
                 }
             }
         };
-        U4 a0[TPW], a0l[TPW], a1[TPW], a1l[TPW];
-        loadA(0, a0, a0l);
-        for (int st = 0; st < nsteps; st += 2) {
-            if (st + 1 < nsteps) loadA(st + 1, a1, a1l);
-            compute(st, a0, a0l);
-            if (st + 1 < nsteps) {
-                if (st + 2 < nsteps) loadA(st + 2, a0, a0l);
-                compute(st + 1, a1, a1l);
+        // basis steps PD - 1 ahead of the MFMAs (a ring of PD register sets; deeper with one row
+        // tile per wave, whose step has the fewest MFMAs to cover a load)
+        // Loads past the last step repeat it (unconditional, so that the compiler waits for exactly
+        // the loads a step needs); the last nsteps % PD steps run after the loop.
+        constexpr int PD = TPW == 1 ? 4 : 2;
+        U4 ar[PD][TPW], arl[PD][TPW];
+#pragma unroll
+        for (int u = 0; u < PD - 1; ++u) loadA(min(u, nsteps - 1), ar[u], arl[u]);
+        int st = 0;
+        for (; st + PD <= nsteps; st += PD) {
+#pragma unroll
+            for (int u = 0; u < PD; ++u) {
+                loadA(min(st + u + PD - 1, nsteps - 1), ar[(u + PD - 1) % PD], arl[(u + PD - 1) % PD]);
+                compute(st + u, ar[u], arl[u]);
             }
         }
+#pragma unroll
+        for (int u = 0; u < PD - 1; ++u)
+            if (st + u < nsteps) compute(st + u, ar[u], arl[u]);
         // lane holds rows 16*rt + 4*lk + r for cosmology 16*j + lr
 #pragma unroll
         for (int i = 0; i < TPW; ++i) {
@@ -3022,6 +3031,7 @@ hipError_t allow_large_lds() {
             (const void *)adj_project_split64_kernel<double, 3>, (const void *)adj_project_split64_kernel<float, 3>,
             (const void *)adj_w_mfma_kernel<16>, (const void *)adj_w_mfma_kernel<32>,
             (const void *)contract_tiled_kernel<BLAST_FP32, 4, kAdjBT>,
+            (const void *)contract_tiled_kernel<BLAST_FP32, 4, 2 * kAdjBT, 1>,
             (const void *)adj_dy_mfma_kernel<16>, (const void *)adj_dy_mfma_kernel<32>,
         };
         for (const void *f : fns) {
@@ -3643,11 +3653,21 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
             }
             if (st != BLAST_OK) return st;
             const int RT = p->nc_pad / 16;
-            const int W = std::min((RT + kTilesPerWave - 1) / kTilesPerWave, 8);
-            const size_t sht = (size_t)kAdjBT * (p->rows_pad + 4) * sizeof(float);
-            hipLaunchKernelGGL((contract_tiled_kernel<BLAST_FP32, 4, kAdjBT>), gt, dim3(64 * W), sht, s,
-                               p->basis.f32t, nullptr, nullptr, (const float *)dw, nullptr, a->batch, p->NP,
-                               p->nc_pad, p->rows_pad, (float *)dc);
+            const size_t sh64 = (size_t)2 * kAdjBT * (p->rows_pad + 4) * sizeof(float);
+            if (sh64 <= 160 * 1024) {
+                // 64 cosmologies per work-group and one row tile per wave: each basis tile read from
+                // L2 feeds twice the MFMAs of the 32-cosmology tile
+                const dim3 g64 = point_tile_grid(p->NP, (a->batch + 2 * kAdjBT - 1) / (2 * kAdjBT));
+                hipLaunchKernelGGL((contract_tiled_kernel<BLAST_FP32, 4, 2 * kAdjBT, 1>), g64, dim3(64 * RT), sh64,
+                                   s, p->basis.f32t, nullptr, nullptr, (const float *)dw, nullptr, a->batch, p->NP,
+                                   p->nc_pad, p->rows_pad, (float *)dc);
+            } else {
+                const int W = std::min((RT + kTilesPerWave - 1) / kTilesPerWave, 8);
+                const size_t sht = (size_t)kAdjBT * (p->rows_pad + 4) * sizeof(float);
+                hipLaunchKernelGGL((contract_tiled_kernel<BLAST_FP32, 4, kAdjBT>), gt, dim3(64 * W), sht, s,
+                                   p->basis.f32t, nullptr, nullptr, (const float *)dw, nullptr, a->batch, p->NP,
+                                   p->nc_pad, p->rows_pad, (float *)dc);
+            }
         }
         const long nrows = (long)a->batch * p->NP;
         const int N = p->n_cheb;
