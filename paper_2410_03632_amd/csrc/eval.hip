@@ -1186,7 +1186,7 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     int nslots, int granges, float *__restrict__ Y, float *__restrict__ w_out) {
     using S = FusedShape<PREC, NS>;
     using E = typename S::E;
-    constexpr int TR = kFusedTR, VEC = S::VEC, KSTEP = S::KSTEP, ncp = S::ncp, NPART = S::NPART;
+    constexpr int TR = kFusedTR, VEC = S::VEC, ncp = S::ncp, NPART = S::NPART;
     constexpr bool X3 = PREC == BLAST_BF16X3 || PREC == BLAST_FP16X3;
     constexpr int GPR = S::ROWB / 16;            // granules per c row
     // granule permutation mask: XOR by up to SWZ stays inside the row when SWZ + 1 divides GPR;
@@ -1570,7 +1570,6 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
     const int lr = lane & 15, lk = lane >> 4;
     const int ti = w >> 1, tk = w & 1;  // row tile, 32-cosmology half
     const int nb = min(64, batch - bt * 64);
-    const size_t NP = (size_t)n_chi * n_R;
     const size_t pt_u4 = (size_t)RT * NS * 64;
     const bool busy = ti < ntile && bt * 64 + 32 * tk < batch;
     int gq0 = NB / 4, gq1 = 0;
