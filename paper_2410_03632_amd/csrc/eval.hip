@@ -1206,7 +1206,9 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     const int unit = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (unit >= units) return;  // uniform over the work-group
     const int RT = rows_pad / 16;
-    const int g = unit % groups, bt = (unit / groups) % nBT, a = unit / (groups * nBT);
+    // the cosmology tiles of a row group next to each other (they read the same basis tiles): the
+    // same time as row groups next to each other, with fewer HBM reads
+    const int bt = unit % nBT, g = (unit / nBT) % groups, a = unit / (groups * nBT);
     const int rt0 = g * TR;
     const int ntile = min(TR, RT - rt0);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -1563,7 +1565,9 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
     const int unit = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (unit >= units) return;  // uniform over the work-group
     const int RT = rows_pad / 16;
-    const int g = unit % groups, bt = (unit / groups) % nBT, a = unit / (groups * nBT);
+    // the cosmology tiles of a row group next to each other (they read the same basis tiles): the
+    // same time as row groups next to each other, 17.0 GB of HBM reads per launch against 20.6
+    const int bt = unit % nBT, g = (unit / nBT) % groups, a = unit / (groups * nBT);
     const int rt0 = g * TR;
     const int ntile = min(TR, RT - rt0);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -1824,7 +1828,9 @@ __global__ __launch_bounds__(512) void contract_quad_f64_kernel(const double *__
     const int per = (units + 7) / 8;
     const int unit = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (unit >= units) return;  // uniform over the work-group
-    const int g = unit % groups, bt = (unit / groups) % nBT, a = unit / (groups * nBT);
+    // the cosmology tiles of a row group next to each other (they read the same basis tiles): the
+    // same time as row groups next to each other, with fewer HBM reads
+    const int bt = unit % nBT, g = (unit / nBT) % groups, a = unit / (groups * nBT);
     const int rt0 = g * TR;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
