@@ -138,12 +138,15 @@ def test_fp16x3_power_of_two_scaling_is_exact():
         plan.close()
 
 
-def test_fp16x3_coefficient_input():
-    """P given as Chebyshev coefficients (FP64) gives the nodal path's C to FP16X3 accuracy."""
+@pytest.mark.parametrize("nb", [4, 70])
+def test_fp16x3_coefficient_input(nb):
+    """P given as Chebyshev coefficients (FP64) gives the nodal path's C to FP16X3 accuracy; 70
+    cosmologies span two cosmology tiles of the fused kernel (one ragged) in the point-major
+    coefficient layout that the coefficient input writes."""
     cfg = W.tiny_config(n_ell=6, ell_max=40, n_chi=8, n_R=6, n_cheb=40, k_max=0.4)
     plan = B.plan_for_config(cfg, precisions=("fp64", "fp16x3"))
     try:
-        inps = [W.make_inputs(cfg, W.seed_for(23, i), plan.k_nodes, plan.chi, plan.R, vary=True) for i in range(4)]
+        inps = [W.make_inputs(cfg, W.seed_for(23, i), plan.k_nodes, plan.chi, plan.R, vary=True) for i in range(nb)]
         Pn = np.stack([x.P for x in inps])
         N = plan.n_cheb
         _, xk = O.grid_k(N, cfg.k_min, cfg.k_max)
@@ -153,7 +156,7 @@ def test_fp16x3_coefficient_input():
         K2 = _dev(np.stack([x.Kchi2 for x in inps]))
         C64 = plan.forward(_dev(Pn), K1, K2, cfg.n_g, cfg.n_s, precision="fp64").cpu().numpy()
         Cc = plan.forward(_dev(c), K1, K2, cfg.n_g, cfg.n_s, precision="fp16x3", coef=True).cpu().numpy()
-        e = max(g16_err(Cc[i], C64[i], cfg.n_g, cfg.n_s).max() for i in range(4))
+        e = max(g16_err(Cc[i], C64[i], cfg.n_g, cfg.n_s).max() for i in range(nb))
         print("fp16x3 coefficient input vs FP64 nodal", e, flush=True)
         assert e <= 1e-3
     finally:
