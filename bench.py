@@ -436,18 +436,30 @@ def gradient_run(plan, cfg, P, K1, K2, out, Bn, steps, warmup):
         plan.forward(P32, K1, K2, cfg.n_g, cfg.n_s, precision="fp32", out=outg, w_save=wg, y_save=yg)
         return plan.backward(P32, K1, K2, cfg.n_g, cfg.n_s, dC, precision="fp32", w_save=wg, y_save=yg)
 
-    for _ in range(warmup):
-        grad_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        grads = grad_step()
-    torch.cuda.synchronize()
-    msg = (time.perf_counter() - t0) * 1e3 / steps
+    def grad_step_p():
+        # dL/dP alone: the adjoint reads neither w nor Y, so the forward keeps nothing
+        plan.forward(P32, K1, K2, cfg.n_g, cfg.n_s, precision="fp32", out=outg)
+        return plan.backward(P32, K1, K2, cfg.n_g, cfg.n_s, dC, precision="fp32", want=("P",))
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps, r
+
+    msg, grads = timed(grad_step)
+    msp, gp = timed(grad_step_p)
     return {"batch": Bn, "ms_per_step": msg, "sets_per_s": Bn / (msg * 1e-3),
             "kernel_work": adjoint_work(plan, cfg, Bn),
-            "finite": bool(all(torch.isfinite(g).all().item() for g in grads)),
-            "what": "forward keeping w and Y + adjoint: dC -> dP (nodal), dK_chi, dK_chi2"}
+            "finite": bool(all(torch.isfinite(g).all().item() for g in grads if g is not None)),
+            "what": "forward keeping w and Y + adjoint: dC -> dP (nodal), dK_chi, dK_chi2",
+            "dP_only": {"ms_per_step": msp, "sets_per_s": Bn / (msp * 1e-3),
+                        "finite": bool(torch.isfinite(gp[0]).all().item()),
+                        "what": "forward keeping nothing + adjoint to dP alone"}}
 
 
 def main():

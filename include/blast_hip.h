@@ -221,8 +221,8 @@ typedef struct {
                              Y[row][a][bin] = sum_b wR_b K_bin(R_b chi_a) w[a, b][row] (FP64 for
                              FP64, else FP32; nbp = 16 for at most 16 bins, else 32; bins past
                              n_g + n_s hold no values); a forward writes it, and a backward given
-                             w_save and y_save of a forward with the same inputs reads it instead
-                             of summing w again                                             */
+                             y_save of a forward with the same inputs reads it instead of summing
+                             w again                                                        */
 } blast_cl_args;
 
 /* Device scratch for one forward or backward call with these sizes. */
@@ -256,8 +256,11 @@ blast_status blast_cl_forward_noalloc(blast_plan *plan, const blast_cl_args *arg
  *           per args->p_kind) -- the transposed contraction streams the basis again;
  *   dK_chi  device, nullable, FP64 [batch][bins][n_chi]: dL/dK_chi;
  *   dK_chi2 device, nullable, FP64 [batch][bins][n_chi][n_R]: dL/dK_chi2.
- * args->C is not read.  args->w_save, if given, must hold w of a forward call with the
- * same inputs (saves recomputing it).  Errors: INVALID, UNSUPPORTED (BF16 paths), OOM, HIP. */
+ * args->C is not read.  args->w_save and args->y_save, if given, must hold w and Y of a
+ * forward call with the same inputs.  w is read only for dK_chi2, and for dK_chi when
+ * y_save is not given; without w_save a call that needs it recomputes w (projection and
+ * contraction), and one that asks only for dP (or for dP and dK_chi with y_save) needs
+ * neither.  Errors: INVALID, UNSUPPORTED (BF16 paths), OOM, HIP. */
 blast_status blast_cl_backward(blast_plan *plan, const blast_cl_args *args, const double *dC, void *dP,
                                double *dK_chi, double *dK_chi2, void *stream);
 

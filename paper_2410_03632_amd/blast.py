@@ -504,8 +504,11 @@ def _make_cl_function():
             P, K_chi, K_chi2 = P.contiguous(), K_chi.contiguous(), K_chi2.contiguous()
             wdt = torch.float64 if PRECISION.get(precision, precision) == FP64 else torch.float32
             B = P.shape[0] if P.dim() == 4 else 1
-            w = torch.empty(B * len(plan.chi) * len(plan.R) * plan.rows_pad, dtype=wdt, device=P.device)
-            y = torch.empty(plan.y_numel(B, n_g + n_s), dtype=wdt, device=P.device)
+            # the adjoint reads w only for dK_chi2 and Y only for dK_chi: keep what it will read
+            keep_w, keep_y = ctx.needs_input_grad[3], ctx.needs_input_grad[2]
+            w = torch.empty(B * len(plan.chi) * len(plan.R) * plan.rows_pad, dtype=wdt,
+                            device=P.device) if keep_w else None
+            y = torch.empty(plan.y_numel(B, n_g + n_s), dtype=wdt, device=P.device) if keep_y else None
             C = plan.forward(P, K_chi, K_chi2, n_g, n_s, precision=precision, w_save=w, coef=coef, y_save=y)
             ctx.plan, ctx.args = plan, (n_g, n_s, precision, coef)
             ctx.save_for_backward(P, K_chi, K_chi2, w, y)

@@ -3591,17 +3591,20 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
         return set_error("the multipoles are too many for the transposed contraction's tile (dP)"),
                BLAST_E_UNSUPPORTED;
     BLAST_HIP_TRY(allow_large_lds());
-    const bool need_w = a->w_save == nullptr;
-    const Layout L = layout_of(p, a->batch, x.prec, x.nbins, need_w, true);
+    // Y of a forward call with the same inputs, when the caller kept it
+    const bool have_y = a->y_save != nullptr;
+    // w is read only for dK_chi2, and for dK_chi when Y has to be summed again: a backward that
+    // asks for neither (dP alone, or dK_chi with Y kept) never recomputes it
+    const bool use_w = dK_chi2 != nullptr || (dK_chi != nullptr && !have_y);
+    const bool make_w = a->w_save == nullptr && use_w;
+    const Layout L = layout_of(p, a->batch, x.prec, x.nbins, make_w, true);
     unsigned char *ws = get_workspace(p, a, L.total, st);
     if (!ws) return st;
     void *c = ws + L.c;
-    void *w = need_w ? (void *)(ws + L.w) : a->w_save;
-    // Y of the forward call that kept w, when the caller kept it too
-    const bool have_y = !need_w && a->y_save;
+    void *w = a->w_save ? a->w_save : (make_w ? (void *)(ws + L.w) : nullptr);
     void *Y = have_y ? a->y_save : (void *)(ws + L.y), *dY = ws + L.dy, *dw = ws + L.dw, *dc = ws + L.dc;
     double *Sg = (double *)(ws + L.sg);
-    if (need_w) {
+    if (make_w) {
         stage_project(p, a, x, c, nullptr, nullptr, s);
         stage_contract(p, a, x, c, nullptr, w, s);
     }

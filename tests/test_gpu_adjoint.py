@@ -203,3 +203,42 @@ def test_fp32_forward_keeping_w_on_the_fused_path():
             assert e < 1e-4, (name, e)
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_backward_reads_w_and_y_only_when_needed(setup, precision):
+    """dP alone needs neither w nor Y, and dK_chi with Y kept needs no w: such calls skip the
+    recomputation of w and must give the same gradients, bit for bit, as the full call with w
+    and Y kept (the same kernels on the same dY).  The autograd function keeps only what the
+    adjoint will read and gives the library's gradients."""
+    cfg, plan, P, K1, K2 = setup
+    if precision == "fp32":
+        P = P.float()
+    wdt = torch.float64 if precision == "fp64" else torch.float32
+    B_ = P.shape[0]
+    w = torch.empty(B_ * len(plan.chi) * len(plan.R) * plan.rows_pad, dtype=wdt, device="cuda")
+    y = torch.empty(plan.y_numel(B_, cfg.n_g + cfg.n_s), dtype=wdt, device="cuda")
+    C = plan.forward(P, K1, K2, cfg.n_g, cfg.n_s, precision=precision, w_save=w, y_save=y)
+    G = torch.randn(C.shape, generator=torch.Generator(device="cpu").manual_seed(7), dtype=torch.float64).cuda()
+    dP, dK, dK2 = plan.backward(P, K1, K2, cfg.n_g, cfg.n_s, G, precision=precision, w_save=w, y_save=y)
+    dPa = plan.backward(P, K1, K2, cfg.n_g, cfg.n_s, G, precision=precision, want=("P",))[0]
+    dPb, dKb = plan.backward(P, K1, K2, cfg.n_g, cfg.n_s, G, precision=precision, want=("P", "K_chi"),
+                             y_save=y)[:2]
+    torch.cuda.synchronize()
+    assert torch.equal(dPa, dP) and torch.equal(dPb, dP) and torch.equal(dKb, dK)
+    # autograd with only P differentiable: no w or Y kept, the same dP
+    fn = B.cl_function()
+    Pg = P.clone().requires_grad_(True)
+    L = (fn.apply(plan, Pg, K1, K2, cfg.n_g, cfg.n_s, precision) * G).sum()
+    L.backward()
+    assert torch.equal(Pg.grad, dP)
+    # only K_chi differentiable: Y kept, no w
+    K1g = K1.clone().requires_grad_(True)
+    L = (fn.apply(plan, P, K1g, K2, cfg.n_g, cfg.n_s, precision) * G).sum()
+    L.backward()
+    assert torch.equal(K1g.grad, dK)
+    # only K_chi2 differentiable: w kept
+    K2g = K2.clone().requires_grad_(True)
+    L = (fn.apply(plan, P, K1, K2g, cfg.n_g, cfg.n_s, precision) * G).sum()
+    L.backward()
+    assert torch.equal(K2g.grad, dK2)
