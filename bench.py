@@ -33,11 +33,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def nodal_path(prec, cfg):
+    """Whether the library contracts the nodal basis (the DCT applied to the basis when the plan
+    is made) with FP32 nodal P itself, with no projection per call: FP16X3 with n_cheb % 8 == 0
+    and at most 16 bins, FP32 with n_cheb % 32 == 0."""
+    if prec == "fp16x3":
+        return cfg.n_cheb % 8 == 0 and cfg.n_g + cfg.n_s <= 16
+    return prec == "fp32" and cfg.n_cheb % 32 == 0
+
+
 def stage_work(plan, cfg, prec, batch):
     """Algorithmic flops and HBM bytes of each stage for one launch over `batch` sets.
 
     projection : c = D P as the even/odd split DCT (two [N/2 x N/2] products per point): N^2
-                 flops per (point, set); P read, c written once.
+                 flops per (point, set); P read, c written once.  Absent on the nodal path,
+                 whose contraction reads P in place of c.
     contraction: fused with the R-quadrature (w stays in registers; mixed paths, and the FP64
                  path at batches of 32 or more with at most 16 bins): basis and c read, weighted
                  kernels Kt written and read (from K_chi2; FP32 with the bins rounded up to a
@@ -54,7 +64,8 @@ def stage_work(plan, cfg, prec, batch):
     nbp = 16 if nb <= 16 else 32
     eb = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4, "fp16x3": 4}[prec]  # basis bytes per element (hi+lo)
     ec = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4, "fp16x3": 4}[prec]  # coefficient bytes
-    es = 4 if prec == "fp16x3" else 0  # coefficient row scale, written by the projection, read for Kt
+    nodal = nodal_path(prec, cfg)
+    es = 4 if prec == "fp16x3" and not nodal else 0  # coefficient row scale (projection -> Kt)
     ew = 8 if prec == "fp64" else 4                                    # w and Y bytes
     ep = 8 if prec == "fp64" else 4                                    # P bytes
     rows_bins = plan.n_ell * (cfg.n_g + nb + cfg.n_s)                 # (row, bin) products in the R-sum
@@ -76,7 +87,7 @@ def stage_work(plan, cfg, prec, batch):
     ek = 4  # weights table bytes per element
     if prec == "fp64":
         nbf, ek = 16, 8
-    return {
+    out = {
         "projection": proj,
         "r_weights": dict(flops=float(nb * NP * batch),
                           bytes=float(nb * NP * 8 * batch + NP * nbf * ek * batch + NP * es * batch)),
@@ -84,6 +95,9 @@ def stage_work(plan, cfg, prec, batch):
                             bytes=float(NP * rows * N * eb + NP * N * ec * batch + NP * nbf * ek * batch) + y_bytes),
         "quad_chi": quad_chi,
     }
+    if nodal:
+        del out["projection"]
+    return out
 
 
 def fused_path(prec, nbins, batch):
@@ -560,6 +574,8 @@ def main():
         # intervals of the fused path: R-quadrature weights, then contraction + R-quadrature
         per_launch = {"projection": per_launch["projection"], "r_weights": per_launch["contraction"],
                       "contraction": per_launch["quad_R"], "quad_chi": per_launch["quad_chi"]}
+    if nodal_path(prec, cfg):
+        del per_launch["projection"]  # nothing runs there
     log("ms/step %.3f  sets/s %.1f  stages(ms/launch) %s" % (ms_per_step, value, per_launch))
     work = stage_work(plan, cfg, prec, Bn)
     dom = max(per_launch, key=per_launch.get)
@@ -646,6 +662,8 @@ def main():
             pl32 = {k: v / max(n32, 1) for k, v in st32.items()}
             pl32 = {"projection": pl32["projection"], "r_weights": pl32["contraction"],
                     "contraction": pl32["quad_R"], "quad_chi": pl32["quad_chi"]}
+            if nodal_path("fp32", cfg):
+                del pl32["projection"]
             r32 = roofline(stage_work(plan, cfg, "fp32", Bn)["contraction"], pl32["contraction"], "fp32")
             r32.pop("algorithmic_bytes", None)
             r32["traffic"] = counter_traffic("contract_quad_kernel", cfg.name, Bn, "fp32")

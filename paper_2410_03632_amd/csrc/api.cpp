@@ -135,6 +135,10 @@ static void free_plan(blast_plan *p) {
     f(p->basis.h16);
     f(p->basis.l16);
     f(p->basis.scale16);
+    f(p->basis.n16);
+    f(p->basis.nl16);
+    f(p->basis.nscale16);
+    f(p->basis.nf32);
     f(p->basis.f32t);
     f(p->d_dct64);
     f(p->d_dct32);

@@ -486,6 +486,65 @@ __global__ __launch_bounds__(256) void to_fp16_kernel(const double *__restrict__
     }
 }
 
+__device__ inline double readlane_f64(double v, int l) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// The nodal basis: B[row][j] = sum_n Ttilde[row][n] D[n][j] with D the DCT-II matrix of Eq. dft
+// (c_n = sum_j D[n][j] P_j), so that sum_j B[row][j] P_j = sum_n Ttilde[row][n] c_n (Eq. pmd): the
+// projection applied once to the basis instead of to every P.  FP64 sums in n order, then
+// (H16) the FP16 hi + lo split of to_fp16_kernel (row scale, tiled layout) or (!H16) the FP32
+// copy of to_f32_kernel; column j = k node j, zero past n_cheb.  D sits in LDS; one wave per basis
+// row (grid-stride over all rows of all points), lane L making columns L and L + 64, the row's
+// Ttilde values broadcast one per step from the lane that loaded them.
+template <bool H16>
+__global__ __launch_bounds__(256) void to_nodal_kernel(const double *__restrict__ src, const double *__restrict__ dctn,
+                                                       size_t nrows, int rows_pad, int ncp, int N,
+                                                       uint16_t *__restrict__ hi, uint16_t *__restrict__ lo,
+                                                       float *__restrict__ scale, float *__restrict__ f32) {
+    __shared__ double Dl[kMaxCheb * kMaxCheb];  // [n][j], ncp x ncp
+    for (int i = threadIdx.x; i < ncp * ncp; i += blockDim.x) {
+        const int n = i / ncp, j = i % ncp;
+        Dl[i] = (n < N && j < N) ? dctn[(size_t)n * N + j] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const bool c0 = lane < ncp, c1 = lane + 64 < ncp;
+    for (size_t row = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < nrows; row += (size_t)gridDim.x * 4) {
+        const double *r = src + row * ncp;
+        const double t0 = c0 ? r[lane] : 0.0, t1 = c1 ? r[lane + 64] : 0.0;
+        double a0 = 0.0, a1 = 0.0;
+        for (int n = 0; n < ncp; ++n) {
+            const double tn = readlane_f64(n < 64 ? t0 : t1, n & 63);
+            if (c0) a0 = fma(tn, Dl[n * ncp + lane], a0);
+            if (c1) a1 = fma(tn, Dl[n * ncp + lane + 64], a1);
+        }
+        const size_t base = (row / rows_pad) * (size_t)rows_pad * ncp;
+        const int rr = (int)(row % rows_pad);
+        if constexpr (!H16) {
+            if (c0) f32[base + tiled_off(rr, lane, ncp / 16, 4)] = (float)a0;
+            if (c1) f32[base + tiled_off(rr, lane + 64, ncp / 16, 4)] = (float)a1;
+            continue;
+        }
+        double mx = fmax(fabs(a0), fabs(a1));
+        for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+        const double sc = mx > 0.0 ? ldexp(1.0, ilogb(mx) - 14) : 1.0;
+        if (lane == 0) scale[row] = (float)sc;
+        for (int h = 0; h < 2; ++h) {
+            const int j = lane + 64 * h;
+            if (j >= ncp) continue;
+            const double v = (h ? a1 : a0) / sc;
+            const _Float16 x = (_Float16)(float)v;
+            const size_t o = base + tiled_off(rr, j, ncp / 32, 8);
+            hi[o] = __builtin_bit_cast(uint16_t, x);
+            lo[o] = __builtin_bit_cast(uint16_t, (_Float16)(float)(v - (double)(float)x));
+        }
+    }
+}
+
 // the FP16X3 projection's operand table (layout: dct16_off), one thread per 8-half entry
 __global__ __launch_bounds__(256) void to_dct16_kernel(const double *__restrict__ dctn, int N, int NT, int NK, int g,
                                                        uint16_t *__restrict__ out) {
@@ -691,6 +750,13 @@ blast_status derive_precisions(blast_plan *p, hipStream_t s) {
         if (e != hipSuccess) return p->basis.f32 = nullptr, fail(e, "FP32 basis");
         hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->basis.f64,
                            p->basis.f32, n, p->rows_pad, p->nc_pad);
+        if (p->n_cheb == p->nc_pad) {  // P rows in the coefficient rows' layout: the nodal FP32 path
+            e = hipMalloc(&p->basis.nf32, n * sizeof(float));
+            if (e != hipSuccess) return p->basis.nf32 = nullptr, fail(e, "FP32 nodal basis");
+            const unsigned g = (unsigned)std::min<size_t>((nrows + 3) / 4, 2048);
+            hipLaunchKernelGGL(to_nodal_kernel<false>, dim3(g), dim3(256), 0, s, p->basis.f64, p->d_dctn64, nrows,
+                               p->rows_pad, p->nc_pad, p->n_cheb, nullptr, nullptr, nullptr, p->basis.nf32);
+        }
     }
     const bool want_hi = p->precisions & ((1u << BLAST_BF16) | (1u << BLAST_BF16X3));
     const bool want_lo = p->precisions & (1u << BLAST_BF16X3);
@@ -720,6 +786,18 @@ blast_status derive_precisions(blast_plan *p, hipStream_t s) {
         if (e != hipSuccess) return p->d_dct16 = nullptr, fail(e, "FP16 projection table");
         hipLaunchKernelGGL(to_dct16_kernel, dim3((unsigned)((nent + 255) / 256)), dim3(256), 0, s, p->d_dctn64,
                            p->n_cheb, NT, NK, dct16_exp(p->n_cheb), p->d_dct16);
+        if (p->n_cheb % 8 == 0) {  // P rows of whole 32-byte granules: the nodal path's DMA unit
+            e = hipMalloc(&p->basis.n16, n * sizeof(uint16_t));
+            if (e != hipSuccess) return p->basis.n16 = nullptr, fail(e, "FP16 nodal basis");
+            e = hipMalloc(&p->basis.nl16, n * sizeof(uint16_t));
+            if (e != hipSuccess) return p->basis.nl16 = nullptr, fail(e, "FP16 lo nodal basis");
+            e = hipMalloc(&p->basis.nscale16, nrows * sizeof(float));
+            if (e != hipSuccess) return p->basis.nscale16 = nullptr, fail(e, "FP16 nodal basis scales");
+            const unsigned g = (unsigned)std::min<size_t>((nrows + 3) / 4, 2048);
+            hipLaunchKernelGGL(to_nodal_kernel<true>, dim3(g), dim3(256), 0, s, p->basis.f64, p->d_dctn64, nrows,
+                               p->rows_pad, p->nc_pad, p->n_cheb, p->basis.n16, p->basis.nl16, p->basis.nscale16,
+                               nullptr);
+        }
     }
     BLAST_HIP_TRY(hipGetLastError());
     return BLAST_OK;

@@ -1530,33 +1530,88 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
 // are point-major: the 64 rows of one point are one 16 KB block per part, where cosmology-major rows
 // were 64 separate 256-byte pieces, 6 MB apart, and took 3.95 ms against 3.45 at full 3x2pt.
 // Steps are not software-pipelined (the registers hold both tiles' accumulators and Y).
+//
+// Nodal variant (NOD): the basis operand is the nodal basis B = Ttilde D (the projection of
+// Eq. dft applied to the basis when the plan is made), contracted with the FP32 nodal values P
+// themselves, so no coefficients are made or stored per call.  Each wave moves 8 of the 64 P rows
+// of a node (ncp floats each, k nodes past n_cheb repeating node n_cheb - 1, whose basis columns
+// are zero) into its own part of the node's c buffer, and once they have landed splits them there
+// in place: per row a power-of-two scale puts the largest |P| in [2^14, 2^15), hi = fp16(v) and
+// lo = fp16(v - hi), laid out as the coefficient rows (hi then lo part of each row, granules
+// permuted by row), the row's inverse scale beside the weights.  The split of node b + 1 runs
+// after node b's MFMAs and R-sum, under the basis DMAs of node b + 1, so one barrier per b still
+// orders everything.  The inverse scale multiplies w with the basis row scale (both powers of two).
 constexpr int kWideTR = 4;
 
-template <int PREC, int NS>
+template <int PREC, int NS, bool NOD = false>
 struct WideShape {
     using E = uint16_t;
     static constexpr int VEC = 8, KSTEP = 32, ncp = NS * KSTEP, NPART = 2;
-    static constexpr int ROWB = ncp * 2;
+    static constexpr int ROWB = ncp * 2;                 // bytes of one row's part (hi or lo)
+    static constexpr int CROW = NOD ? 2 * ROWB : ROWB;   // LDS stride of the c rows
     static constexpr int A_CH = kWideTR * NS * NPART, C_CH = 64 * ROWB * NPART / 1024;
     static constexpr int NW = 8;
     static constexpr int A_PW = (A_CH + NW - 1) / NW, C_PW = (C_CH + NW - 1) / NW;
     static constexpr size_t A_BUF = (size_t)A_CH * 1024, C_BUF = (size_t)C_CH * 1024;
-    static constexpr size_t X_BUF = 5 * 1024;  // weights (NB <= 16: <= 4 KB) and the row scales
+    // weights (NB <= 16: <= 4 KB) and the basis row scales; nodal: the 64 P row scales after them
+    static constexpr size_t X_BUF = (NOD ? 6 : 5) * 1024;
     static constexpr size_t LDS = 2 * A_BUF + 2 * (C_BUF + X_BUF);
 };
 
-template <int PREC, int NB, int NBP, int NS>
+// one 16-byte LDS read at base + offset, waited for
+template <int O0>
+__device__ inline void lds_read1(uint32_t b0, U4 &r0) {
+    asm volatile("ds_read_b128 %0, %1 offset:%2\n\ts_waitcnt lgkmcnt(0)" : "=&v"(r0) : "v"(b0), "i"(O0) : "memory");
+}
+// two 4-byte LDS reads at base + offsets, waited for
+template <int O0, int O1>
+__device__ inline void lds_read_f2(uint32_t b0, float &r0, float &r1) {
+    asm volatile("ds_read_b32 %0, %2 offset:%3\n\tds_read_b32 %1, %2 offset:%4\n\ts_waitcnt lgkmcnt(0)"
+                 : "=&v"(r0), "=&v"(r1)
+                 : "v"(b0), "i"(O0), "i"(O1)
+                 : "memory");
+}
+__device__ inline void lds_write8(uint32_t a, uint64_t v) {
+    asm volatile("ds_write_b64 %0, %1" : : "v"(a), "v"(v) : "memory");
+}
+__device__ inline void lds_write4(uint32_t a, float v) {
+    asm volatile("ds_write_b32 %0, %1" : : "v"(a), "v"(v) : "memory");
+}
+// vmcnt(n) for a wave-uniform n in [0, 6]
+__device__ inline void wait_vmcnt_n(int n) {
+    switch (n) {
+        case 0: wait_vmcnt<0>(); break;
+        case 1: wait_vmcnt<1>(); break;
+        case 2: wait_vmcnt<2>(); break;
+        case 3: wait_vmcnt<3>(); break;
+        case 4: wait_vmcnt<4>(); break;
+        case 5: wait_vmcnt<5>(); break;
+        default: wait_vmcnt<6>(); break;
+    }
+}
+// maximum over the 8 lanes of an aligned group (DPP: swap neighbours, swap pairs, mirror halves)
+__device__ inline float max8(float m) {
+    m = fmaxf(m, __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, m), 0xB1, 0xF, 0xF, false)));
+    m = fmaxf(m, __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, m), 0x4E, 0xF, 0xF, false)));
+    m = fmaxf(m, __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, m), 0x141, 0xF, 0xF, false)));
+    return m;
+}
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+
+template <int PREC, int NB, int NBP, int NS, bool NOD>
 __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
     const uint16_t *__restrict__ basis, const uint16_t *__restrict__ basis_lo, const float *__restrict__ scale,
-    const uint16_t *__restrict__ c, const uint16_t *__restrict__ c_lo, const float *__restrict__ Kt, int batch,
-    int n_chi, int n_R, int rows_pad, int nBT, int units, int n_ell, int nslots, int granges, float *__restrict__ Y) {
-    using S = WideShape<PREC, NS>;
+    const void *__restrict__ cv, const uint16_t *__restrict__ c_lo, const float *__restrict__ Kt, int batch,
+    int n_chi, int n_R, int rows_pad, int nBT, int units, int n_ell, int nslots, int granges, int n_cheb,
+    float *__restrict__ Y) {
+    using S = WideShape<PREC, NS, NOD>;
     using E = typename S::E;
     constexpr int TR = kWideTR, VEC = S::VEC, ncp = S::ncp, NPART = S::NPART;
     constexpr int GPR = S::ROWB / 16;
     constexpr int SWZ = GPR % 16 == 0 ? 15 : (GPR % 8 == 0 ? 7 : (GPR % 4 == 0 ? 3 : (GPR % 2 == 0 ? 1 : 0)));
     constexpr bool KROT = NB == 16;
     static_assert(PREC == BLAST_FP16X3 && NB <= 16 && S::LDS <= 160 * 1024, "LDS of the wide fused kernel");
+    static_assert(!NOD || S::C_PW * 1024 == 8 * S::CROW, "nodal: a wave's P DMAs are its 8 rows");
     __shared__ __align__(1024) unsigned char A0[S::A_BUF], A1[S::A_BUF];
     __shared__ __align__(1024) unsigned char C0[S::C_BUF + S::X_BUF], C1[S::C_BUF + S::X_BUF];
 
@@ -1592,6 +1647,7 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
     // end of the last group are skipped (each b waits for all DMAs, so the counts may differ)
     const U4 *srcA[S::A_PW];
     bool useA[S::A_PW];
+    int nA = 0;  // basis DMAs this wave issues per b
 #pragma unroll
     for (int k = 0; k < S::A_PW; ++k) {
         const int ch = min(w + k * S::NW, S::A_CH - 1);
@@ -1599,6 +1655,7 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
         const int rt = min(rt0 + tl, RT - 1);
         srcA[k] = (const U4 *)(part ? basis_lo : basis) + ((size_t)rt * NS + st) * 64 + lane;
         useA[k] = tl < ntile;  // uniform over the wave
+        nA += useA[k] ? 1 : 0;
     }
     auto dma_A = [&](int b, unsigned char *__restrict__ buf) {
         const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
@@ -1609,7 +1666,9 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
     // weights Kt[ab][64 cosmologies][NB] and the row scales of the group: waves 0..KCH-1 move weight
     // chunks, wave KCH the scales, the others nothing
     constexpr int KCH = 64 * NB * 4 / 1024;
-    static_assert(KCH + 1 <= S::NW && TR * 16 * 4 <= 1024 && KCH * 1024 + 1024 <= (int)S::X_BUF, "extra region");
+    static_assert(KCH + 1 <= S::NW && TR * 16 * 4 <= 1024 && KCH * 1024 + 1024 + (NOD ? 256 : 0) <= (int)S::X_BUF,
+                  "extra region");
+    constexpr int PSC = (int)S::C_BUF + (KCH + 1) * 1024;  // nodal: inverse P row scales [64]
     const int chX = min(w, KCH);
     const float *srcX;
     {
@@ -1628,24 +1687,92 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
         const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
         lds_dma16(srcX + ab * strideX, buf + S::C_BUF + (size_t)chX * 1024);
     };
-    const E *srcC[S::C_PW];
+    // DMAs issued after a wave's c (or P) DMAs of one b: its weight or scale chunk and its basis
+    const int nXA = (w <= KCH ? 1 : 0) + nA;
+    const char *srcC[S::C_PW];
+    size_t cstride;
+    if constexpr (NOD) {
+        // wave w: chunks C_PW w .. C_PW w + C_PW - 1 = rows 8w .. 8w + 7 of P[beta][a, b][n]
+        const float *P = (const float *)cv;
+        const size_t NPN = (size_t)n_chi * n_R * n_cheb;
+        const int gmax = n_cheb / 4 - 1;
 #pragma unroll
-    for (int k = 0; k < S::C_PW; ++k) {
-        const int ch = min(w + k * S::NW, S::C_CH - 1);
-        const int part = ch / (S::C_CH / NPART), chp = ch % (S::C_CH / NPART);
-        const int pos = chp * 1024 + lane * 16;
-        const int row = pos / S::ROWB, gp = (pos % S::ROWB) / 16;
-        const int v = gp ^ (row & SWZ);
-        const int bb = bt * 64 + (row < nb ? row : 0);
-        srcC[k] = (part ? c_lo : c) + (size_t)bb * ncp + v * VEC;
+        for (int k = 0; k < S::C_PW; ++k) {
+            const int pos = (w * S::C_PW + k) * 1024 + lane * 16;
+            const int row = pos / S::CROW, gp = (pos % S::CROW) / 16;
+            const int bb = bt * 64 + (row < nb ? row : 0);
+            srcC[k] = (const char *)(P + (size_t)bb * NPN + 4 * min(gp, gmax));
+        }
+        cstride = (size_t)n_cheb * 4;
+    } else {
+        const uint16_t *c = (const uint16_t *)cv;
+#pragma unroll
+        for (int k = 0; k < S::C_PW; ++k) {
+            const int ch = min(w + k * S::NW, S::C_CH - 1);
+            const int part = ch / (S::C_CH / NPART), chp = ch % (S::C_CH / NPART);
+            const int pos = chp * 1024 + lane * 16;
+            const int row = pos / S::ROWB, gp = (pos % S::ROWB) / 16;
+            const int v = gp ^ (row & SWZ);
+            const int bb = bt * 64 + (row < nb ? row : 0);
+            srcC[k] = (const char *)((part ? c_lo : c) + (size_t)bb * ncp + v * VEC);
+        }
+        // point-major coefficients: the 64 rows of one point are one block of 64 ncp elements per part
+        cstride = (size_t)batch * ncp * sizeof(E);
     }
-    // point-major coefficients: the 64 rows of one point are one block of 64 ncp elements per part
-    const size_t cstride = (size_t)batch * ncp;
     auto dma_C = [&](int b, unsigned char *__restrict__ buf) {
         const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
 #pragma unroll
         for (int k = 0; k < S::C_PW; ++k)
-            lds_dma16(srcC[k] + ab * cstride, buf + (size_t)min(w + k * S::NW, S::C_CH - 1) * 1024);
+            lds_dma16(srcC[k] + ab * cstride,
+                      buf + (size_t)(NOD ? w * S::C_PW + k : min(w + k * S::NW, S::C_CH - 1)) * 1024);
+    };
+    // nodal: split this wave's 8 P rows of a landed buffer in place (lane: row 8w + lane / 8,
+    // 16-byte granules lane % 8 + 8 (q ^ o) of it, o = r mod NS for NS = 2 and 4: the two rows of a
+    // 16-lane read phase read different 128-byte halves of the 64 banks, and the four rows of a
+    // 32-lane write phase write four different 64-byte quarters of a part)
+    auto split_rows = [&](unsigned char *__restrict__ buf) {
+        if constexpr (NOD) {
+            const int r = 8 * w + (lane >> 3), sub = lane & 7;
+            const int o = NS == 4 ? (r & 3) : (NS == 2 ? (r & 1) : 0);
+            const uint32_t rb = lds_addr(buf) + (uint32_t)(r * S::CROW);
+            int gq[NS];
+#pragma unroll
+            for (int q = 0; q < NS; ++q) gq[q] = sub + 8 * (q ^ o);
+            U4 raw[NS];
+            if constexpr (NS == 4) {
+                lds_read4<0, 0, 0, 0>(rb + 16 * gq[0], rb + 16 * gq[1], rb + 16 * gq[2], rb + 16 * gq[3], raw[0],
+                                      raw[1], raw[2], raw[3]);
+            } else if constexpr (NS == 2) {
+                lds_read2<0, 0>(rb + 16 * gq[0], rb + 16 * gq[1], raw[0], raw[1]);
+            } else if constexpr (NS == 3) {
+                lds_read2<0, 128>(rb + 16 * sub, rb + 16 * sub, raw[0], raw[1]);
+                lds_read1<256>(rb + 16 * sub, raw[2]);
+            } else {
+                lds_read1<0>(rb + 16 * sub, raw[0]);
+            }
+            float m = 0.f;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const f4v v = __builtin_bit_cast(f4v, raw[q]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) m = fmaxf(m, fabsf(v[e]));
+            }
+            m = max8(m);
+            const int ex = __builtin_amdgcn_frexp_expf(m) - 1;  // floor(log2 m); -1 for m = 0
+            const float sc = __builtin_amdgcn_ldexpf(1.f, 14 - ex);
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const f4v x = __builtin_bit_cast(f4v, raw[q]) * sc;
+                const h4v h = __builtin_convertvector(x, h4v);
+                const h4v l = __builtin_convertvector(x - __builtin_convertvector(h, f4v), h4v);
+                const int gr = gq[q], G = gr >> 1;
+                const uint32_t o = rb + (uint32_t)(((G ^ (r & SWZ)) << 4) | ((gr & 1) << 3));
+                lds_write8(o, __builtin_bit_cast(uint64_t, h));
+                lds_write8(o + S::ROWB, __builtin_bit_cast(uint64_t, l));
+            }
+            if (sub == 0) lds_write4(lds_addr(buf) + PSC + 4 * r, __builtin_amdgcn_ldexpf(1.f, ex - 14));
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        }
     };
 
     float y[2][4][NB];
@@ -1667,82 +1794,99 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
         dma_X(b + 1, Cnext);
         dma_A(b + 1, Anext);
         __builtin_amdgcn_sched_barrier(0);
-        if (!busy) return;
-        constexpr int NQ = NB / 4;
-        constexpr int ALO = TR * NS * 1024, CLO = (int)(S::C_BUF / NPART);
-        // the second half's rows are 16 rows further on with the same granule permutation and the
-        // same weight rotation (16 is a multiple of SWZ + 1 and of 16): fixed offsets
-        constexpr int C16 = 16 * S::ROWB, K16 = 16 * NB * 4;
-        const uint32_t As = lds_addr(Ab) + (uint32_t)arow * 16;
-        const int crow = 32 * tk + lr;
-        uint32_t Cq[4], kq[4];
-        {
-            const uint32_t Cr = lds_addr(Cb) + (uint32_t)crow * S::ROWB;
-            const int m = crow & SWZ, mh = m >> 2, ml = lk ^ (m & 3);
+        if (busy) {
+            constexpr int NQ = NB / 4;
+            constexpr int ALO = TR * NS * 1024, CLO = NOD ? S::ROWB : (int)(S::C_BUF / NPART);
+            // the second half's rows are 16 rows further on with the same granule permutation and
+            // the same weight rotation (16 is a multiple of SWZ + 1 and of 16): fixed offsets
+            constexpr int C16 = 16 * S::CROW, K16 = 16 * NB * 4;
+            const uint32_t As = lds_addr(Ab) + (uint32_t)arow * 16;
+            const int crow = 32 * tk + lr;
+            uint32_t Cq[4], kq[4];
+            {
+                const uint32_t Cr = lds_addr(Cb) + (uint32_t)crow * S::CROW;
+                const int m = crow & SWZ, mh = m >> 2, ml = lk ^ (m & 3);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) Cq[k] = Cr + 16 * (4 * (k ^ mh) + ml);
-            const uint32_t kb = lds_addr(Cb + S::C_BUF) + (uint32_t)crow * (NB * 4);
-            const int rr = (crow >> 2) & 3;
+                for (int k = 0; k < 4; ++k) Cq[k] = Cr + 16 * (4 * (k ^ mh) + ml);
+                const uint32_t kb = lds_addr(Cb + S::C_BUF) + (uint32_t)crow * (NB * 4);
+                const int rr = (crow >> 2) & 3;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) kq[q] = KROT ? kb + 16 * ((q + rr) & 3) : kb + 16 * (q < NQ ? q : NQ - 1);
-        }
-        const uint32_t sa = lds_addr(Cb + S::C_BUF + (size_t)KCH * 1024) + (uint32_t)(16 * min(ti, TR - 1) + 4 * lk) * 4;
-        f4 acc[2][3];
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int u = 0; u < 3; ++u) acc[j][u] = f4{0, 0, 0, 0};
-        auto step_k = [&](auto stc) {
-            constexpr int st = decltype(stc)::value;
-            constexpr int coff = 256 * (st >> 2);
-            U4 ua, ual, ub0, ub0l, ub1, ub1l;
-            const uint32_t cq = Cq[st & 3];
-            lds_read6<st * 1024, st * 1024 + ALO, coff, coff + CLO, coff + C16, coff + C16 + CLO>(As, cq, ua, ual, ub0,
-                                                                                                ub0l, ub1, ub1l);
-            acc[0][0] = mfma16<PREC>(ua, ub0, acc[0][0]);
-            acc[1][0] = mfma16<PREC>(ua, ub1, acc[1][0]);
-            acc[0][1] = mfma16<PREC>(ua, ub0l, acc[0][1]);
-            acc[1][1] = mfma16<PREC>(ua, ub1l, acc[1][1]);
-            acc[0][2] = mfma16<PREC>(ual, ub0, acc[0][2]);
-            acc[1][2] = mfma16<PREC>(ual, ub1, acc[1][2]);
-        };
-        static_for<0, NS>(step_k);
-        float4 sc;
-        {
-            U4 qs, qd;
-            lds_read2<0, 0>(sa, sa, qs, qd);
-            const f4v v = __builtin_bit_cast(f4v, qs);
-            sc = make_float4(v[0], v[1], v[2], v[3]);
-        }
-        // R-sum, one half at a time (its weights read just before)
-        auto rsum = [&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            U4 q[4];
-            lds_read4<j * K16, j * K16, j * K16, j * K16>(kq[0], kq[1], kq[2], kq[3], q[0], q[1], q[2], q[3]);
-            float kt[NB];
-#pragma unroll
-            for (int g4 = 0; g4 < NQ; ++g4) {
-                const f4v v = __builtin_bit_cast(f4v, q[g4]);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) kt[4 * g4 + e] = v[e];
+                for (int q = 0; q < 4; ++q) kq[q] = KROT ? kb + 16 * ((q + rr) & 3) : kb + 16 * (q < NQ ? q : NQ - 1);
             }
-            f4 wv = acc[j][0] + (acc[j][1] + acc[j][2]);
-            wv[0] *= sc.x, wv[1] *= sc.y, wv[2] *= sc.z, wv[3] *= sc.w;
+            const uint32_t sa =
+                lds_addr(Cb + S::C_BUF + (size_t)KCH * 1024) + (uint32_t)(16 * min(ti, TR - 1) + 4 * lk) * 4;
+            f4 acc[2][3];
 #pragma unroll
-            for (int gq = 0; gq < NB / 4; ++gq)
-                if ((gmask >> gq) & 1)  // uniform over the wave
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
+                for (int u = 0; u < 3; ++u) acc[j][u] = f4{0, 0, 0, 0};
+            auto step_k = [&](auto stc) {
+                constexpr int st = decltype(stc)::value;
+                constexpr int coff = 256 * (st >> 2);
+                U4 ua, ual, ub0, ub0l, ub1, ub1l;
+                const uint32_t cq = Cq[st & 3];
+                lds_read6<st * 1024, st * 1024 + ALO, coff, coff + CLO, coff + C16, coff + C16 + CLO>(
+                    As, cq, ua, ual, ub0, ub0l, ub1, ub1l);
+                acc[0][0] = mfma16<PREC>(ua, ub0, acc[0][0]);
+                acc[1][0] = mfma16<PREC>(ua, ub1, acc[1][0]);
+                acc[0][1] = mfma16<PREC>(ua, ub0l, acc[0][1]);
+                acc[1][1] = mfma16<PREC>(ua, ub1l, acc[1][1]);
+                acc[0][2] = mfma16<PREC>(ual, ub0, acc[0][2]);
+                acc[1][2] = mfma16<PREC>(ual, ub1, acc[1][2]);
+            };
+            static_for<0, NS>(step_k);
+            float4 sc;
+            {
+                U4 qs, qd;
+                lds_read2<0, 0>(sa, sa, qs, qd);
+                const f4v v = __builtin_bit_cast(f4v, qs);
+                sc = make_float4(v[0], v[1], v[2], v[3]);
+            }
+            float ps[2] = {1.f, 1.f};  // nodal: inverse P row scales of the lane's two cosmologies
+            if constexpr (NOD) lds_read_f2<0, 64>(lds_addr(Cb) + PSC + 4 * crow, ps[0], ps[1]);
+            // R-sum, one half at a time (its weights read just before)
+            auto rsum = [&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                U4 q[4];
+                lds_read4<j * K16, j * K16, j * K16, j * K16>(kq[0], kq[1], kq[2], kq[3], q[0], q[1], q[2], q[3]);
+                float kt[NB];
 #pragma unroll
-                        for (int qq = 4 * gq; qq < 4 * gq + 4; ++qq) y[j][r][qq] += wv[r] * kt[qq];
-        };
-        static_for<0, 2>(rsum);
+                for (int g4 = 0; g4 < NQ; ++g4) {
+                    const f4v v = __builtin_bit_cast(f4v, q[g4]);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) kt[4 * g4 + e] = v[e];
+                }
+                f4 wv = acc[j][0] + (acc[j][1] + acc[j][2]);
+                if constexpr (NOD) {
+                    wv[0] *= sc.x * ps[j], wv[1] *= sc.y * ps[j], wv[2] *= sc.z * ps[j], wv[3] *= sc.w * ps[j];
+                } else {
+                    wv[0] *= sc.x, wv[1] *= sc.y, wv[2] *= sc.z, wv[3] *= sc.w;
+                }
+#pragma unroll
+                for (int gq = 0; gq < NB / 4; ++gq)
+                    if ((gmask >> gq) & 1)  // uniform over the wave
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int qq = 4 * gq; qq < 4 * gq + 4; ++qq) y[j][r][qq] += wv[r] * kt[qq];
+            };
+            static_for<0, 2>(rsum);
+        }
+        if constexpr (NOD) {
+            // this wave's P rows of b + 1 (issued first) have landed; its weight and basis DMAs may not
+            wait_vmcnt_n(nXA);
+            split_rows(Cnext);
+        }
     };
 
-    // issue order: A(0), c(0) + weights(0); then per b, after its barrier: c(b+1) + weights(b+1), A(b+1)
+    // issue order: c(0) + weights(0), A(0); then per b, after its barrier: c(b+1) + weights(b+1), A(b+1)
     dma_C(0, C0);
     dma_X(0, C0);
     dma_A(0, A0);
+    if constexpr (NOD) {
+        wait_vmcnt_n(nXA);
+        split_rows(C0);
+    }
     for (int b = 0; b < n_R; b += 2) {
         step(b, A0, C0, C1, A1);
         if (b + 1 < n_R) step(b + 1, A1, C1, C0, A0);
@@ -2939,6 +3083,8 @@ __global__ __launch_bounds__(256) void adj_project_split64_kernel(const double *
 // ---------------------------------------------------------------------------------------------
 struct Ctx {
     int prec, ng, ns, nbins, npairs, nbp;
+    // the call contracts the nodal basis with its FP32 nodal P (no projection; P read as c)
+    bool nodal = false;
     EllSel sel;
     EllInv inv;
 };
@@ -2964,9 +3110,10 @@ int fused_nb(int prec, int nbins, int batch) {
 // FP32 calls that keep w take the fused path too (its kernel stores the w tiles as it goes)
 bool fused_keeps_w(int prec, int nbins, int batch) { return prec == BLAST_FP32 && fused_nb(prec, nbins, batch); }
 
-Layout layout_of(const blast_plan *p, int batch, int prec, int nbins, bool need_w, bool adjoint) {
+Layout layout_of(const blast_plan *p, int batch, int prec, int nbins, bool need_w, bool adjoint,
+                 bool nodal = false) {
     Layout L{};
-    const size_t nc = (size_t)batch * p->NP * p->nc_pad;
+    const size_t nc = nodal ? 0 : (size_t)batch * p->NP * p->nc_pad;
     const size_t ce = prec == BLAST_FP64 ? 8 : (prec == BLAST_FP32 ? 4 : 2);
     const size_t te = prec == BLAST_FP64 ? 8 : 4;
     const int nbp = nbins <= 16 ? 16 : 32;
@@ -2977,7 +3124,7 @@ Layout layout_of(const blast_plan *p, int batch, int prec, int nbins, bool need_
     L.clo = off;
     if (prec == BLAST_BF16X3 || prec == BLAST_FP16X3) off += align256(nc * 2);
     L.cs = off;
-    if (prec == BLAST_FP16X3) off += align256((size_t)batch * p->NP * 4);
+    if (prec == BLAST_FP16X3 && !nodal) off += align256((size_t)batch * p->NP * 4);
     L.w = off;
     L.kt = off;
     if (need_w) {
@@ -3257,8 +3404,10 @@ void stage_contract(blast_plan *p, const blast_cl_args *a, const Ctx &x, const v
         const size_t cst = ncp + 16 / sizeof(E);
         const size_t sh = (size_t)BT * cst * sizeof(E) + (PR == BLAST_BF16X3 ? (size_t)BT * cst * 2 : 0);
         const dim3 grid = point_tile_grid(p->NP, (a->batch + BT - 1) / BT);
-        const E *bas = PR == BLAST_FP64 ? (const E *)p->basis.f64
-                                        : (PR == BLAST_FP32 ? (const E *)p->basis.f32 : (const E *)p->basis.hi);
+        const E *bas = PR == BLAST_FP64
+                           ? (const E *)p->basis.f64
+                           : (PR == BLAST_FP32 ? (const E *)(x.nodal ? p->basis.nf32 : p->basis.f32)
+                                               : (const E *)p->basis.hi);
         if constexpr (PR == BLAST_FP64) {
             hipLaunchKernelGGL((contract_kernel<PR>), grid, dim3(256), sh, s, bas, p->basis.lo, p->basis.scale,
                                (const E *)c, clo, a->batch, p->NP, p->rows_pad, ncp, w);
@@ -3302,8 +3451,10 @@ void stage_r_weights(blast_plan *p, const blast_cl_args *a, const Ctx &x, int nb
                        p->n_R, Kt);
 }
 
+// x.nodal: c is the caller's FP32 P and the basis operand the nodal basis
 void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, int nb, const void *c,
                          const uint16_t *clo, const float *Kt, float *Y, float *w_out, hipStream_t s) {
+    const bool nodal = x.nodal;
     const int RT = p->rows_pad / 16, nBT = (a->batch + 63) / 64;
     const int groups = (RT + kFusedTR - 1) / kFusedTR;
     const int units = p->n_chi * nBT * groups;
@@ -3326,13 +3477,21 @@ void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, in
             // wide wave tiles (8 waves, 4 row tiles, 64 cosmologies per work-group)
             const int wgroups = (RT + kWideTR - 1) / kWideTR;
             const int wunits = p->n_chi * nBT * wgroups;
-            hipLaunchKernelGGL((contract_quad_wide_kernel<PR, NB, NBP, NS>), dim3((unsigned)((wunits + 7) / 8 * 8)),
-                               dim3(512), 0, s, (const uint16_t *)p->basis.h16, p->basis.l16, p->basis.scale16,
-                               (const uint16_t *)c, clo, Kt, a->batch, p->n_chi, p->n_R, p->rows_pad, nBT, wunits,
-                               p->n_ell, p->nt, granges, Y);
+            const dim3 wg((unsigned)((wunits + 7) / 8 * 8));
+            if (nodal)
+                hipLaunchKernelGGL((contract_quad_wide_kernel<PR, NB, NBP, NS, true>), wg, dim3(512), 0, s,
+                                   (const uint16_t *)p->basis.n16, p->basis.nl16, p->basis.nscale16, c, nullptr, Kt,
+                                   a->batch, p->n_chi, p->n_R, p->rows_pad, nBT, wunits, p->n_ell, p->nt, granges,
+                                   p->n_cheb, Y);
+            else
+                hipLaunchKernelGGL((contract_quad_wide_kernel<PR, NB, NBP, NS, false>), wg, dim3(512), 0, s,
+                                   (const uint16_t *)p->basis.h16, p->basis.l16, p->basis.scale16, c, clo, Kt,
+                                   a->batch, p->n_chi, p->n_R, p->rows_pad, nBT, wunits, p->n_ell, p->nt, granges,
+                                   p->n_cheb, Y);
             return;
         }
-        const E *bas = PR == BLAST_FP32 ? (const E *)p->basis.f32 : (const E *)(H ? p->basis.h16 : p->basis.hi);
+        const E *bas = PR == BLAST_FP32 ? (const E *)(nodal ? p->basis.nf32 : p->basis.f32)
+                                        : (const E *)(H ? p->basis.h16 : p->basis.hi);
         // all LDS of the fused kernel is static (FusedShape::LDS bytes)
         hipLaunchKernelGGL((contract_quad_kernel<PR, NB, NBP, NS>), dim3(grid), dim3(256 * kFusedTR), 0, s, bas,
                            H ? p->basis.l16 : p->basis.lo, H ? p->basis.scale16 : p->basis.scale, (const E *)c, clo,
@@ -3445,7 +3604,13 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     }
     BLAST_HIP_TRY(allow_large_lds());
     const bool need_w = a->w_save == nullptr;
-    const Layout L = layout_of(p, a->batch, x.prec, x.nbins, need_w, false);
+    // FP32 nodal values: the nodal basis contracted with P itself, FP16X3 (at most 16 bins; P
+    // split in the kernel) or FP32 (P rows in the coefficient rows' layout: n_cheb == nc_pad)
+    const bool fp32p = a->p_kind == 0 && a->p_dtype == 1;
+    x.nodal = fp32p && ((x.prec == BLAST_FP16X3 && p->basis.n16 && fused_nb(x.prec, x.nbins, a->batch) <= 16) ||
+                        (x.prec == BLAST_FP32 && p->basis.nf32));
+    const bool nodal = x.nodal;
+    const Layout L = layout_of(p, a->batch, x.prec, x.nbins, need_w, false, nodal);
     unsigned char *ws = nullptr;
     if (fixed) {
         if (L.total > fixed->bytes)
@@ -3457,16 +3622,16 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
         ws = get_workspace(p, a, L.total, st);
         if (!ws) return st;
     }
-    void *c = ws + L.c;
-    uint16_t *clo = x.prec == BLAST_BF16X3 || x.prec == BLAST_FP16X3 ? (uint16_t *)(ws + L.clo) : nullptr;
-    float *cs = x.prec == BLAST_FP16X3 ? (float *)(ws + L.cs) : nullptr;
+    const void *c = nodal ? a->P : (const void *)(ws + L.c);
+    uint16_t *clo = !nodal && (x.prec == BLAST_BF16X3 || x.prec == BLAST_FP16X3) ? (uint16_t *)(ws + L.clo) : nullptr;
+    float *cs = !nodal && x.prec == BLAST_FP16X3 ? (float *)(ws + L.cs) : nullptr;
     void *w = need_w ? (void *)(ws + L.w) : a->w_save;
     void *Y = a->y_save ? a->y_save : (void *)(ws + L.y);
     const bool keep_fused = !need_w && fused_keeps_w(x.prec, x.nbins, a->batch);
     const int fnb = need_w || keep_fused ? fused_nb(x.prec, x.nbins, a->batch) : 0;
     const bool f64f = need_w && x.prec == BLAST_FP64 && fused_f64(x.nbins, a->batch);
     mark(0);
-    stage_project(p, a, x, c, clo, cs, s);
+    if (!nodal) stage_project(p, a, x, (void *)c, clo, cs, s);
     mark(1);
     if (fnb) {
         // fused path: interval 1 = the R-weights table, interval 2 = contraction + R-quadrature

@@ -57,6 +57,12 @@ struct BasisBuffers {
     uint16_t *h16 = nullptr;   // FP16 bits of (value / scale16), tiled layout
     uint16_t *l16 = nullptr;   // FP16 bits of the remainder
     float *scale16 = nullptr;  // [NP][rows_pad] power-of-two row scales of the FP16 parts
+    // the nodal basis B = Ttilde D (D: the DCT-II matrix taking nodal P to Chebyshev coefficients),
+    // split the same way: sum_j B[row][j] P_j = sum_n Ttilde[row][n] c_n, contracted with P itself
+    uint16_t *n16 = nullptr;   // FP16 bits of (B / nscale16), tiled layout (column = k node)
+    uint16_t *nl16 = nullptr;  // FP16 bits of the remainder
+    float *nscale16 = nullptr; // [NP][rows_pad]
+    float *nf32 = nullptr;     // FP32 nodal basis, layout of f32 (plans with n_cheb == nc_pad)
     float *f32t = nullptr;     // FP32 transpose per point, [nc_pad][rows_pad] in the tiled layout
                                // (made by the first FP32 adjoint call that asks for dP)
 };

@@ -50,12 +50,19 @@ def test_stage_work_of_the_precisions():
     w16 = bench.stage_work(plan, cfg, "fp16x3", B)
     w64 = bench.stage_work(plan, cfg, "fp64", B)
     NP, N = 256 * 96, 128
-    # FP16 hi + lo move the bytes of FP32 (4 per element); FP16X3 also writes and reads a scale per
-    # coefficient row
+    # FP16 hi + lo move the bytes of FP32 (4 per element); with 128 nodes and 15 bins both paths
+    # contract the nodal basis with P itself: no projection stage, no coefficient row scales
+    assert bench.nodal_path("fp32", cfg) and bench.nodal_path("fp16x3", cfg)
+    assert "projection" not in w16 and "projection" not in w32 and "projection" in w64
     assert w16["contraction"]["bytes"] == w32["contraction"]["bytes"]
     assert w16["contraction"]["flops"] == w32["contraction"]["flops"]
-    assert w16["projection"]["bytes"] - w32["projection"]["bytes"] == NP * 4 * B
-    assert w16["r_weights"]["bytes"] - w32["r_weights"]["bytes"] == NP * 4 * B
+    assert w16["r_weights"]["bytes"] == w32["r_weights"]["bytes"]
+    # 20 bins: FP16X3 projects into split coefficients with a scale per coefficient row
+    cfg20 = types.SimpleNamespace(n_chi=256, n_R=96, n_cheb=128, n_g=15, n_s=5)
+    assert not bench.nodal_path("fp16x3", cfg20)
+    v16, v32 = bench.stage_work(plan, cfg20, "fp16x3", B), bench.stage_work(plan, cfg20, "fp32", B)
+    assert v16["projection"]["bytes"] == NP * (N * (4 + 4) + 4) * B and "projection" not in v32
+    assert v16["r_weights"]["bytes"] - v32["r_weights"]["bytes"] == NP * 4 * B
     # contraction: 2 flops per (row, Chebyshev node, point, set), plus the R-sum's where it is
     # fused; basis read once per launch
     rows_bins = 96 * (10 + 15 + 5)
@@ -72,7 +79,7 @@ def test_stage_work_of_the_precisions():
     assert bench.fused_path("fp16x3", 20, 1) and not bench.fused_path("fp32", 20, 31)
     # the even/odd split halves the projection's products when N % 8 == 0
     plan, cfg7 = _shapes(n_cheb=100)
-    assert bench.stage_work(plan, cfg, "fp32", B)["projection"]["flops"] * 2 == pytest.approx(
+    assert bench.stage_work(plan, cfg, "fp64", B)["projection"]["flops"] * 2 == pytest.approx(
         bench.stage_work(plan, cfg7, "fp32", B)["projection"]["flops"] * (128 / 100) ** 2)
 
 

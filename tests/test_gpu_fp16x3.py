@@ -163,6 +163,34 @@ def test_fp16x3_coefficient_input(nb):
         plan.close()
 
 
+@pytest.mark.parametrize("n_cheb", [32, 64, 96, 128])
+def test_fp16x3_nodal_basis_and_projection_agree(n_cheb):
+    """FP32 nodal P runs the nodal basis (the DCT applied to the basis when the plan is made, P
+    split in the kernel); FP64 nodal P takes the per-call projection into split coefficients.  Both
+    against the oracle at the mixed paths' bar, at the first and last cosmology and at the one
+    where the two paths differ most (they differ only by the rounding of their FP16 splits)."""
+    cfg = W.tiny_config(n_ell=7, ell_max=60, n_chi=9, n_R=7, n_cheb=n_cheb, k_max=0.6, n_g=6, n_s=4)
+    plan = B.plan_for_config(cfg, precisions=("fp16x3",))
+    try:
+        inps = [W.make_inputs(cfg, W.seed_for(26, i), plan.k_nodes, plan.chi, plan.R, vary=True) for i in range(67)]
+        P64 = _dev(np.stack([x.P for x in inps]))
+        K1 = _dev(np.stack([x.Kchi for x in inps]))
+        K2 = _dev(np.stack([x.Kchi2 for x in inps]))
+        Cn = plan.forward(P64.float().contiguous(), K1, K2, cfg.n_g, cfg.n_s, precision="fp16x3").cpu().numpy()
+        Cp = plan.forward(P64, K1, K2, cfg.n_g, cfg.n_s, precision="fp16x3").cpu().numpy()
+        d = [g16_err(Cn[i], Cp[i], cfg.n_g, cfg.n_s).max() for i in range(len(inps))]
+        far = int(np.argmax(d))
+        en, ep = 0.0, 0.0
+        for i in sorted({0, len(inps) - 1, far}):
+            Cor = _oracle(plan, cfg, inps[i])
+            en = max(en, g16_err(Cn[i], Cor, cfg.n_g, cfg.n_s).max())
+            ep = max(ep, g16_err(Cp[i], Cor, cfg.n_g, cfg.n_s).max())
+        print("fp16x3 vs oracle: nodal", en, "projected", ep, "; largest difference", d[far], "at", far, flush=True)
+        assert en <= 1e-3 and ep <= 1e-3, (en, ep)
+    finally:
+        plan.close()
+
+
 def test_fp16x3_refuses_requests_outside_the_fused_path():
     cfg = W.tiny_config(n_ell=4, ell_max=30, n_chi=6, n_R=5, n_cheb=20, k_max=0.4, n_g=12, n_s=9)
     plan = B.plan_for_config(cfg, precisions=("fp16x3",))

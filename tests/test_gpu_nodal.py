@@ -1,0 +1,73 @@
+"""GPU parity of the nodal basis: B = Ttilde D, the DCT of Eq. dft applied to the basis when the
+plan is made, so that sum_j B[row][j] P_j = sum_n Ttilde[row][n] c_n (Eq. pmd) is contracted with
+the nodal values P themselves and no coefficients are made per call.  The library takes it for
+FP32 nodal P: on the FP32 path when n_cheb is a multiple of 32 (P rows then have the coefficient
+rows' layout), on the FP16X3 path (tested with that path) when n_cheb % 8 == 0 and there are at
+most 16 bins.  FP64 nodal P, coefficient input and other shapes take the per-call projection.
+
+Both routes are checked against the FP64 oracle at the FP32 bar (1e-3 of ``metrics.g16_err``),
+on the unfused (batch 1, w kept) and the fused (batch 40) contraction, and w itself against the
+projected route's w element by element."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2410_03632_amd import blast as B
+from paper_2410_03632_amd import workloads as W
+from _util import g16_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ALL = ("gg", "gs", "ss")
+
+
+def _dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).cuda()
+
+
+def _oracle(plan, cfg, inp):
+    C, err, _, _ = O.cl_grid(plan.ell, ALL, cfg.k_min, cfg.k_max, cfg.n_cheb, plan.chi, plan.w_chi, plan.R,
+                             plan.w_R, inp.P, inp.n_g, inp.n_s, inp.Kchi, inp.Kchi2)
+    assert err < 1e-9
+    return C
+
+
+@pytest.mark.parametrize("n_cheb", [32, 40, 64, 128])
+def test_fp32_nodal_basis_and_projection_agree(n_cheb):
+    """n_cheb = 32, 64, 128: FP32 P runs the nodal basis, FP64 P the projection; n_cheb = 40 (not a
+    multiple of 32): both project.  Batch 1 takes the unfused contraction with w kept, batch 40
+    the fused one (w kept by the fused kernel as it goes)."""
+    cfg = W.tiny_config(n_ell=7, ell_max=60, n_chi=9, n_R=7, n_cheb=n_cheb, k_max=0.6, n_g=4, n_s=3)
+    plan = B.plan_for_config(cfg, precisions=("fp32",))
+    try:
+        inps = [W.make_inputs(cfg, W.seed_for(27, i), plan.k_nodes, plan.chi, plan.R, vary=True) for i in range(40)]
+        P64 = _dev(np.stack([x.P for x in inps]))
+        P32 = P64.float().contiguous()
+        K1 = _dev(np.stack([x.Kchi for x in inps]))
+        K2 = _dev(np.stack([x.Kchi2 for x in inps]))
+        nw = len(plan.chi) * len(plan.R) * plan.rows_pad
+        Cor = [_oracle(plan, cfg, inps[i]) for i in (0, 39)]
+        worst = {}
+        for nb in (1, 40):
+            res = {}
+            for name, P in (("nodal", P32), ("projected", P64)):
+                w = torch.zeros(nb * nw, dtype=torch.float32, device="cuda")
+                C = plan.forward(P[:nb].contiguous(), K1[:nb].contiguous(), K2[:nb].contiguous(), cfg.n_g, cfg.n_s,
+                                 precision="fp32", w_save=w).cpu().numpy()
+                res[name] = (C, w.cpu().numpy().reshape(nb, -1, plan.rows_pad)[:, :, :plan.rows])
+                for k, i in enumerate((0, 39)):
+                    if i < nb:
+                        e = g16_err(C[i], Cor[k], cfg.n_g, cfg.n_s).max()
+                        worst[(name, nb)] = max(worst.get((name, nb), 0.0), e)
+            # w of the two routes: same sum, FP32 operands either way (relative to each row's largest |w|)
+            wn, wp = res["nodal"][1], res["projected"][1]
+            scale = np.abs(wp).max(axis=1, keepdims=True) + 1e-300
+            dw = (np.abs(wn - wp) / scale).max()
+            worst[("w", nb)] = dw
+        print("fp32 nodal / projected", {str(k): float(v) for k, v in worst.items()}, flush=True)
+        for k, v in worst.items():
+            assert v <= (1e-5 if k[0] == "w" else 1e-3), (k, v)
+    finally:
+        plan.close()
+
