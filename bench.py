@@ -35,11 +35,12 @@ def log(*a):
 
 def nodal_path(prec, cfg):
     """Whether the library contracts the nodal basis (the DCT applied to the basis when the plan
-    is made) with FP32 nodal P itself, with no projection per call: FP16X3 with n_cheb % 8 == 0
-    and at most 16 bins, FP32 with n_cheb % 32 == 0."""
+    is made) with nodal P itself, with no projection per call: FP16X3 on FP32 P with
+    n_cheb % 8 == 0 and at most 16 bins; FP32 on FP32 P and FP64 on FP64 P (the bench's P types)
+    with n_cheb % 32 == 0."""
     if prec == "fp16x3":
         return cfg.n_cheb % 8 == 0 and cfg.n_g + cfg.n_s <= 16
-    return prec == "fp32" and cfg.n_cheb % 32 == 0
+    return prec in ("fp32", "fp64") and cfg.n_cheb % 32 == 0
 
 
 def stage_work(plan, cfg, prec, batch):
@@ -75,7 +76,7 @@ def stage_work(plan, cfg, prec, batch):
                     bytes=float(cfg.n_chi * rows_pad * nbp * ew * batch))
     y_bytes = float(cfg.n_chi * rows_pad * nbp * ew * batch)
     if prec == "fp64" and not fused_path(prec, nb, batch):
-        return {
+        out = {
             "projection": proj,
             "contraction": dict(flops=2.0 * rows * N * NP * batch,
                                 bytes=float(NP * rows * N * eb + NP * N * ec * batch + NP * rows_pad * ew * batch)),
@@ -83,6 +84,9 @@ def stage_work(plan, cfg, prec, batch):
                            bytes=float(NP * rows_pad * ew * batch + nb * NP * 8 * batch) + y_bytes),
             "quad_chi": quad_chi,
         }
+        if nodal:
+            del out["projection"]
+        return out
     nbf = (nb + 3) // 4 * 4
     ek = 4  # weights table bytes per element
     if prec == "fp64":

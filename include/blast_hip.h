@@ -241,7 +241,7 @@ blast_status blast_cl_forward(blast_plan *plan, const blast_cl_args *args, void 
  * caller passes inputs and outputs as for blast_cl_forward; args->workspace must be NULL.  The
  * call allocates nothing (no hipMalloc, no allocating library routine) and records no stage
  * timing.  A call whose scratch would exceed 64 MiB is refused with BLAST_E_UNSUPPORTED before
- * any work (the full 3x2pt grid fits one cosmology on the FP32 and FP16X3 paths, none on FP64).
+ * any work (the full 3x2pt grid with nodal P on 128 nodes fits one cosmology on every path).
  * All calls on one GPU share that GPU's array, which keeps the last call's contents: calls that
  * overlap in time on one GPU (other streams, other threads) race and must be serialised by the
  * caller.  Every byte of scratch a call reads it has written first, so nothing is cleared.

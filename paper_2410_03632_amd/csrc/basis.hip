@@ -496,15 +496,17 @@ __device__ inline double readlane_f64(double v, int l) {
 // The nodal basis: B[row][j] = sum_n Ttilde[row][n] D[n][j] with D the DCT-II matrix of Eq. dft
 // (c_n = sum_j D[n][j] P_j), so that sum_j B[row][j] P_j = sum_n Ttilde[row][n] c_n (Eq. pmd): the
 // projection applied once to the basis instead of to every P.  FP64 sums in n order, then
-// (H16) the FP16 hi + lo split of to_fp16_kernel (row scale, tiled layout) or (!H16) the FP32
-// copy of to_f32_kernel; column j = k node j, zero past n_cheb.  D sits in LDS; one wave per basis
-// row (grid-stride over all rows of all points), lane L making columns L and L + 64, the row's
-// Ttilde values broadcast one per step from the lane that loaded them.
-template <bool H16>
+// (OUT 16) the FP16 hi + lo split of to_fp16_kernel (row scale, tiled layout), (OUT 32) the FP32
+// copy of to_f32_kernel or (OUT 64) FP64 in the FP64 basis' row-major layout; column j = k node j,
+// zero past n_cheb.  D sits in LDS; one wave per basis row (grid-stride over all rows of all
+// points), lane L making columns L and L + 64, the row's Ttilde values broadcast one per step
+// from the lane that loaded them.
+template <int OUT>
 __global__ __launch_bounds__(256) void to_nodal_kernel(const double *__restrict__ src, const double *__restrict__ dctn,
                                                        size_t nrows, int rows_pad, int ncp, int N,
                                                        uint16_t *__restrict__ hi, uint16_t *__restrict__ lo,
-                                                       float *__restrict__ scale, float *__restrict__ f32) {
+                                                       float *__restrict__ scale, float *__restrict__ f32,
+                                                       double *__restrict__ f64) {
     __shared__ double Dl[kMaxCheb * kMaxCheb];  // [n][j], ncp x ncp
     for (int i = threadIdx.x; i < ncp * ncp; i += blockDim.x) {
         const int n = i / ncp, j = i % ncp;
@@ -524,9 +526,14 @@ __global__ __launch_bounds__(256) void to_nodal_kernel(const double *__restrict_
         }
         const size_t base = (row / rows_pad) * (size_t)rows_pad * ncp;
         const int rr = (int)(row % rows_pad);
-        if constexpr (!H16) {
+        if constexpr (OUT == 32) {
             if (c0) f32[base + tiled_off(rr, lane, ncp / 16, 4)] = (float)a0;
             if (c1) f32[base + tiled_off(rr, lane + 64, ncp / 16, 4)] = (float)a1;
+            continue;
+        }
+        if constexpr (OUT == 64) {
+            if (c0) f64[row * ncp + lane] = a0;
+            if (c1) f64[row * ncp + lane + 64] = a1;
             continue;
         }
         double mx = fmax(fabs(a0), fabs(a1));
@@ -754,9 +761,16 @@ blast_status derive_precisions(blast_plan *p, hipStream_t s) {
             e = hipMalloc(&p->basis.nf32, n * sizeof(float));
             if (e != hipSuccess) return p->basis.nf32 = nullptr, fail(e, "FP32 nodal basis");
             const unsigned g = (unsigned)std::min<size_t>((nrows + 3) / 4, 2048);
-            hipLaunchKernelGGL(to_nodal_kernel<false>, dim3(g), dim3(256), 0, s, p->basis.f64, p->d_dctn64, nrows,
-                               p->rows_pad, p->nc_pad, p->n_cheb, nullptr, nullptr, nullptr, p->basis.nf32);
+            hipLaunchKernelGGL(to_nodal_kernel<32>, dim3(g), dim3(256), 0, s, p->basis.f64, p->d_dctn64, nrows,
+                               p->rows_pad, p->nc_pad, p->n_cheb, nullptr, nullptr, nullptr, p->basis.nf32, nullptr);
         }
+    }
+    if ((p->precisions & (1u << BLAST_FP64)) && p->n_cheb == p->nc_pad) {  // FP64 nodal P read as c
+        hipError_t e = hipMalloc(&p->basis.nf64, n * sizeof(double));
+        if (e != hipSuccess) return p->basis.nf64 = nullptr, fail(e, "FP64 nodal basis");
+        const unsigned g = (unsigned)std::min<size_t>((nrows + 3) / 4, 2048);
+        hipLaunchKernelGGL(to_nodal_kernel<64>, dim3(g), dim3(256), 0, s, p->basis.f64, p->d_dctn64, nrows,
+                           p->rows_pad, p->nc_pad, p->n_cheb, nullptr, nullptr, nullptr, nullptr, p->basis.nf64);
     }
     const bool want_hi = p->precisions & ((1u << BLAST_BF16) | (1u << BLAST_BF16X3));
     const bool want_lo = p->precisions & (1u << BLAST_BF16X3);
@@ -794,9 +808,9 @@ blast_status derive_precisions(blast_plan *p, hipStream_t s) {
             e = hipMalloc(&p->basis.nscale16, nrows * sizeof(float));
             if (e != hipSuccess) return p->basis.nscale16 = nullptr, fail(e, "FP16 nodal basis scales");
             const unsigned g = (unsigned)std::min<size_t>((nrows + 3) / 4, 2048);
-            hipLaunchKernelGGL(to_nodal_kernel<true>, dim3(g), dim3(256), 0, s, p->basis.f64, p->d_dctn64, nrows,
+            hipLaunchKernelGGL(to_nodal_kernel<16>, dim3(g), dim3(256), 0, s, p->basis.f64, p->d_dctn64, nrows,
                                p->rows_pad, p->nc_pad, p->n_cheb, p->basis.n16, p->basis.nl16, p->basis.nscale16,
-                               nullptr);
+                               nullptr, nullptr);
         }
     }
     BLAST_HIP_TRY(hipGetLastError());

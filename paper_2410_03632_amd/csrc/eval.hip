@@ -3405,7 +3405,7 @@ void stage_contract(blast_plan *p, const blast_cl_args *a, const Ctx &x, const v
         const size_t sh = (size_t)BT * cst * sizeof(E) + (PR == BLAST_BF16X3 ? (size_t)BT * cst * 2 : 0);
         const dim3 grid = point_tile_grid(p->NP, (a->batch + BT - 1) / BT);
         const E *bas = PR == BLAST_FP64
-                           ? (const E *)p->basis.f64
+                           ? (const E *)(x.nodal ? p->basis.nf64 : p->basis.f64)
                            : (PR == BLAST_FP32 ? (const E *)(x.nodal ? p->basis.nf32 : p->basis.f32)
                                                : (const E *)p->basis.hi);
         if constexpr (PR == BLAST_FP64) {
@@ -3542,7 +3542,8 @@ void stage_contract_quad_f64(blast_plan *p, const blast_cl_args *a, const Ctx &x
     const unsigned grid = (unsigned)((units + 7) / 8 * 8);
     auto launch = [&](auto nbtag, auto kstag, auto nstag) {
         constexpr int NB = decltype(nbtag)::value, KS = decltype(kstag)::value, NSTG = decltype(nstag)::value;
-        hipLaunchKernelGGL((contract_quad_f64_kernel<NB, KS, NSTG>), dim3(grid), dim3(512), 0, s, p->basis.f64,
+        hipLaunchKernelGGL((contract_quad_f64_kernel<NB, KS, NSTG>), dim3(grid), dim3(512), 0, s,
+                           x.nodal ? p->basis.nf64 : p->basis.f64,
                            (const double *)c, Kt, a->batch, p->n_chi, p->n_R, p->rows_pad, nBT, units, Y);
     };
     using I32 = std::integral_constant<int, 32>;
@@ -3604,11 +3605,13 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     }
     BLAST_HIP_TRY(allow_large_lds());
     const bool need_w = a->w_save == nullptr;
-    // FP32 nodal values: the nodal basis contracted with P itself, FP16X3 (at most 16 bins; P
-    // split in the kernel) or FP32 (P rows in the coefficient rows' layout: n_cheb == nc_pad)
-    const bool fp32p = a->p_kind == 0 && a->p_dtype == 1;
-    x.nodal = fp32p && ((x.prec == BLAST_FP16X3 && p->basis.n16 && fused_nb(x.prec, x.nbins, a->batch) <= 16) ||
-                        (x.prec == BLAST_FP32 && p->basis.nf32));
+    // nodal values: the nodal basis contracted with P itself, FP16X3 on FP32 P (at most 16 bins; P
+    // split in the kernel), FP32 on FP32 P and FP64 on FP64 P (P rows in the coefficient rows'
+    // layout: n_cheb == nc_pad)
+    const bool fp32p = a->p_kind == 0 && a->p_dtype == 1, fp64p = a->p_kind == 0 && a->p_dtype == 0;
+    x.nodal = (fp32p && ((x.prec == BLAST_FP16X3 && p->basis.n16 && fused_nb(x.prec, x.nbins, a->batch) <= 16) ||
+                         (x.prec == BLAST_FP32 && p->basis.nf32))) ||
+              (fp64p && x.prec == BLAST_FP64 && p->basis.nf64);
     const bool nodal = x.nodal;
     const Layout L = layout_of(p, a->batch, x.prec, x.nbins, need_w, false, nodal);
     unsigned char *ws = nullptr;

@@ -63,6 +63,7 @@ struct BasisBuffers {
     uint16_t *nl16 = nullptr;  // FP16 bits of the remainder
     float *nscale16 = nullptr; // [NP][rows_pad]
     float *nf32 = nullptr;     // FP32 nodal basis, layout of f32 (plans with n_cheb == nc_pad)
+    double *nf64 = nullptr;    // FP64 nodal basis, layout of f64 (plans with n_cheb == nc_pad)
     float *f32t = nullptr;     // FP32 transpose per point, [nc_pad][rows_pad] in the tiled layout
                                // (made by the first FP32 adjoint call that asks for dP)
 };

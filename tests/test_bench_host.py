@@ -52,8 +52,8 @@ def test_stage_work_of_the_precisions():
     NP, N = 256 * 96, 128
     # FP16 hi + lo move the bytes of FP32 (4 per element); with 128 nodes and 15 bins both paths
     # contract the nodal basis with P itself: no projection stage, no coefficient row scales
-    assert bench.nodal_path("fp32", cfg) and bench.nodal_path("fp16x3", cfg)
-    assert "projection" not in w16 and "projection" not in w32 and "projection" in w64
+    assert bench.nodal_path("fp32", cfg) and bench.nodal_path("fp16x3", cfg) and bench.nodal_path("fp64", cfg)
+    assert "projection" not in w16 and "projection" not in w32 and "projection" not in w64
     assert w16["contraction"]["bytes"] == w32["contraction"]["bytes"]
     assert w16["contraction"]["flops"] == w32["contraction"]["flops"]
     assert w16["r_weights"]["bytes"] == w32["r_weights"]["bytes"]
@@ -79,8 +79,10 @@ def test_stage_work_of_the_precisions():
     assert bench.fused_path("fp16x3", 20, 1) and not bench.fused_path("fp32", 20, 31)
     # the even/odd split halves the projection's products when N % 8 == 0
     plan, cfg7 = _shapes(n_cheb=100)
-    assert bench.stage_work(plan, cfg, "fp64", B)["projection"]["flops"] * 2 == pytest.approx(
-        bench.stage_work(plan, cfg7, "fp32", B)["projection"]["flops"] * (128 / 100) ** 2)
+    cfg96 = types.SimpleNamespace(n_chi=256, n_R=96, n_cheb=120, n_g=10, n_s=5)
+    assert not bench.nodal_path("fp32", cfg96)
+    assert bench.stage_work(plan, cfg96, "fp32", B)["projection"]["flops"] * 2 == pytest.approx(
+        bench.stage_work(plan, cfg7, "fp32", B)["projection"]["flops"] * (120 / 100) ** 2)
 
 
 def test_counter_traffic_only_for_the_measured_source(tmp_path, monkeypatch):

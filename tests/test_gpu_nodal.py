@@ -71,3 +71,30 @@ def test_fp32_nodal_basis_and_projection_agree(n_cheb):
     finally:
         plan.close()
 
+
+
+@pytest.mark.parametrize("nb", [1, 40])
+def test_fp64_nodal_basis_against_coefficient_input(nb):
+    """FP64 nodal P (n_cheb = 64, a multiple of 32) runs the nodal basis B = Ttilde D; the same P
+    given as its Chebyshev coefficients (solved on the host) runs Ttilde itself.  The two FP64
+    routes agree to 1e-10 (G16 metric) and both meet the FP64 bar against the oracle, on the
+    unfused (batch 1) and fused (batch 40) contraction."""
+    cfg = W.tiny_config(n_ell=6, ell_max=50, n_chi=8, n_R=6, n_cheb=64, k_max=0.5, n_g=3, n_s=2)
+    plan = B.plan_for_config(cfg, precisions=("fp64",))
+    try:
+        inps = [W.make_inputs(cfg, W.seed_for(29, i), plan.k_nodes, plan.chi, plan.R, vary=True) for i in range(nb)]
+        Pn = np.stack([x.P for x in inps])
+        N = plan.n_cheb
+        _, xk = O.grid_k(N, cfg.k_min, cfg.k_max)
+        T = np.cos(np.outer(np.arange(N), np.arccos(xk)))  # sum_n c_n T_n(x_j) = P_j
+        c = np.linalg.solve(T.T, Pn.reshape(-1, N).T).T.reshape(Pn.shape)
+        K1 = _dev(np.stack([x.Kchi for x in inps]))
+        K2 = _dev(np.stack([x.Kchi2 for x in inps]))
+        Cn = plan.forward(_dev(Pn), K1, K2, cfg.n_g, cfg.n_s, precision="fp64").cpu().numpy()
+        Cc = plan.forward(_dev(c), K1, K2, cfg.n_g, cfg.n_s, precision="fp64", coef=True).cpu().numpy()
+        d = max(g16_err(Cn[i], Cc[i], cfg.n_g, cfg.n_s).max() for i in range(nb))
+        eo = g16_err(Cn[0], _oracle(plan, cfg, inps[0]), cfg.n_g, cfg.n_s).max()
+        print("fp64 nodal vs coefficient input", d, "nodal vs oracle", eo, flush=True)
+        assert d <= 1e-10 and eo <= 1e-6, (d, eo)
+    finally:
+        plan.close()

@@ -75,10 +75,10 @@ def test_noalloc_equals_forward_twice_second_smaller(precision, big):
 
 
 def test_noalloc_full_3x2pt_fits_one_cosmology_and_refuses_more():
-    """At the full 3x2pt shapes one cosmology fits the 64 MiB scratch on the FP32 and FP16X3 paths
-    (bitwise equal to blast_cl_forward); the FP64 path's scratch for one cosmology, and a batch of
-    8 on FP32, exceed it and are refused with BLAST_E_UNSUPPORTED before any launch; a workspace
-    argument is refused with BLAST_E_INVALID."""
+    """At the full 3x2pt shapes one cosmology fits the 64 MiB scratch on the FP32, FP16X3 and FP64
+    paths (nodal P with 128 nodes keeps no coefficients; bitwise equal to blast_cl_forward); two
+    cosmologies on FP64 and a batch of 8 on FP32 exceed it and are refused with
+    BLAST_E_UNSUPPORTED before any launch; a workspace argument is refused with BLAST_E_INVALID."""
     cfg = W.CONFIGS[2]
     plan = B.plan_for_config(cfg, precisions=("fp64", "fp32", "fp16x3"))
     try:
@@ -91,8 +91,14 @@ def test_noalloc_full_3x2pt_fits_one_cosmology_and_refuses_more():
             ref = plan.forward(P, K1, K2, cfg.n_g, cfg.n_s, precision=precision)
             torch.cuda.synchronize()
             assert torch.equal(got, ref), precision
-        P64 = _dev(inp.P[None])
-        st, got, _ = _call_abi(plan, P64, _dev(inp.Kchi[None]), _dev(inp.Kchi2[None]), cfg.n_g, cfg.n_s, "fp64")
+        P64, K1, K2 = _dev(inp.P[None]), _dev(inp.Kchi[None]), _dev(inp.Kchi2[None])
+        st, got, _ = _call_abi(plan, P64, K1, K2, cfg.n_g, cfg.n_s, "fp64")
+        assert st == B.OK, B.lib().blast_last_error()
+        ref = plan.forward(P64, K1, K2, cfg.n_g, cfg.n_s, precision="fp64")
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref)
+        st, got, _ = _call_abi(plan, P64.expand(2, -1, -1, -1).contiguous(), K1.expand(2, -1, -1).contiguous(),
+                               K2.expand(2, -1, -1, -1).contiguous(), cfg.n_g, cfg.n_s, "fp64")
         assert st == B.E_UNSUPPORTED and torch.isnan(got).all()
         P8 = _dev(inp.P[None], torch.float32).expand(8, -1, -1, -1).contiguous()
         K18 = _dev(inp.Kchi[None]).expand(8, -1, -1).contiguous()
