@@ -416,8 +416,11 @@ def adjoint_work(plan, cfg, batch):
     adj_dy_mfma_kernel   : dY = S Ktil per row: dC, K_chi read; dY (FP32), S (FP64) written
     adj_kchi_kernel      : dK_chi = S^T Y: Y and S read, dK_chi written
     adj_w_mfma_kernel    : dw = Khat dY and dK_chi2 = dY^T w: w, dY, K_chi2 read; dw, dK_chi2 written
-    contract_tiled_kernel: dc = Ttilde^T dw: transposed basis once, dw read, dc written
-    adj_project_split_kernel: dP = D^T dc (even/odd split, N^2 flops per row): dc read, dP written"""
+    contract_tiled_kernel: dc = Ttilde^T dw: transposed basis once, dw read, dc written; on the
+                           nodal path (n_cheb % 32 == 0) dP = B^T dw with the transposed nodal
+                           basis, written straight into dP
+    adj_project_split_kernel: dP = D^T dc (even/odd split, N^2 flops per row): dc read, dP written
+                           (not on the nodal path)"""
     NP = cfg.n_chi * cfg.n_R
     N, ncp, R, Rp = cfg.n_cheb, plan.nc_pad, plan.rows, plan.rows_pad
     nb = cfg.n_g + cfg.n_s
@@ -425,7 +428,7 @@ def adjoint_work(plan, cfg, batch):
     fwd = stage_work(plan, cfg, "fp32", batch)["contraction"]
     w_bytes = 4.0 * NP * Rp * batch
     dy_bytes = 4.0 * R * cfg.n_chi * NB * batch
-    return {
+    out = {
         "contract_quad_kernel": dict(flops=fwd["flops"], bytes=fwd["bytes"] + w_bytes),
         "adj_dy_mfma_kernel": dict(flops=2.0 * NB * NB * cfg.n_chi * R * batch,
                                    bytes=8.0 * batch * (B_pairs(cfg) * plan.n_ell + nb * cfg.n_chi) + dy_bytes
@@ -438,6 +441,9 @@ def adjoint_work(plan, cfg, batch):
                                       bytes=4.0 * NP * R * N + w_bytes + 4.0 * NP * ncp * batch),
         "adj_project_split_kernel": dict(flops=1.0 * N * N * NP * batch, bytes=4.0 * NP * (ncp + N) * batch),
     }
+    if nodal_path("fp32", cfg):
+        del out["adj_project_split_kernel"]
+    return out
 
 
 def gradient_run(plan, cfg, P, K1, K2, out, Bn, steps, warmup, dp_only=True):

@@ -140,6 +140,7 @@ static void free_plan(blast_plan *p) {
     f(p->basis.nscale16);
     f(p->basis.nf32);
     f(p->basis.nf64);
+    f(p->basis.nf32t);
     f(p->basis.f32t);
     f(p->d_dct64);
     f(p->d_dct32);

@@ -497,8 +497,8 @@ __device__ inline double readlane_f64(double v, int l) {
 // (c_n = sum_j D[n][j] P_j), so that sum_j B[row][j] P_j = sum_n Ttilde[row][n] c_n (Eq. pmd): the
 // projection applied once to the basis instead of to every P.  FP64 sums in n order, then
 // (OUT 16) the FP16 hi + lo split of to_fp16_kernel (row scale, tiled layout), (OUT 32) the FP32
-// copy of to_f32_kernel or (OUT 64) FP64 in the FP64 basis' row-major layout; column j = k node j,
-// zero past n_cheb.  D sits in LDS; one wave per basis row (grid-stride over all rows of all
+// copy of to_f32_kernel, (OUT 33) the FP32 transpose of to_f32t_kernel (B^T, for the adjoint) or
+// (OUT 64) FP64 in the FP64 basis' row-major layout; column j = k node j, zero past n_cheb.  D sits in LDS; one wave per basis row (grid-stride over all rows of all
 // points), lane L making columns L and L + 64, the row's Ttilde values broadcast one per step
 // from the lane that loaded them.
 template <int OUT>
@@ -529,6 +529,11 @@ __global__ __launch_bounds__(256) void to_nodal_kernel(const double *__restrict_
         if constexpr (OUT == 32) {
             if (c0) f32[base + tiled_off(rr, lane, ncp / 16, 4)] = (float)a0;
             if (c1) f32[base + tiled_off(rr, lane + 64, ncp / 16, 4)] = (float)a1;
+            continue;
+        }
+        if constexpr (OUT == 33) {
+            if (c0) f32[base + tiled_off(lane, rr, rows_pad / 16, 4)] = (float)a0;
+            if (c1) f32[base + tiled_off(lane + 64, rr, rows_pad / 16, 4)] = (float)a1;
             continue;
         }
         if constexpr (OUT == 64) {
@@ -739,6 +744,24 @@ blast_status ensure_f32t(blast_plan *p, hipStream_t s) {
     }
     hipLaunchKernelGGL(to_f32t_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->basis.f64, p->basis.f32t,
                        n, p->rows_pad, p->nc_pad);
+    BLAST_HIP_TRY(hipGetLastError());
+    // once per plan: finished before any call on another stream can see the pointer
+    BLAST_HIP_TRY(hipStreamSynchronize(s));
+    return BLAST_OK;
+}
+
+blast_status ensure_nf32t(blast_plan *p, hipStream_t s) {
+    if (p->basis.nf32t) return BLAST_OK;
+    const size_t n = (size_t)p->NP * p->rows_pad * p->nc_pad, nrows = (size_t)p->NP * p->rows_pad;
+    hipError_t e = hipMalloc(&p->basis.nf32t, n * sizeof(float));
+    if (e != hipSuccess) {
+        p->basis.nf32t = nullptr;
+        set_error("transposed FP32 nodal basis: %s", hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? BLAST_E_OOM : BLAST_E_HIP;
+    }
+    const unsigned g = (unsigned)std::min<size_t>((nrows + 3) / 4, 2048);
+    hipLaunchKernelGGL(to_nodal_kernel<33>, dim3(g), dim3(256), 0, s, p->basis.f64, p->d_dctn64, nrows, p->rows_pad,
+                       p->nc_pad, p->n_cheb, nullptr, nullptr, nullptr, p->basis.nf32t, nullptr);
     BLAST_HIP_TRY(hipGetLastError());
     // once per plan: finished before any call on another stream can see the pointer
     BLAST_HIP_TRY(hipStreamSynchronize(s));

@@ -3816,18 +3816,24 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
 #undef BLAST_ADJ
     if (dP) {
         const dim3 gt = point_tile_grid(p->NP, (a->batch + kAdjBT - 1) / kAdjBT);
+        // nodal P of the path's own type with n_cheb == nc_pad: dP = B^T dw with the nodal basis
+        // B = Ttilde D (the adjoint of the projection folded in), written straight into dP
+        const bool ndp = a->p_kind == 0 && p->n_cheb == p->nc_pad &&
+                         (f64 ? a->p_dtype == 0 && p->basis.nf64 : a->p_dtype == 1 && p->basis.nf32);
+        void *dcn = ndp ? dP : dc;
         if (f64) {
             const size_t sht = (size_t)kAdjBT * (p->rows_pad + 1) * 8;
-            hipLaunchKernelGGL((contract_t_kernel<true>), gt, dim3(256), sht, s, p->basis.f64, (const double *)dw,
-                               a->batch, p->NP, p->rows_pad, p->nc_pad, (double *)dc);
+            hipLaunchKernelGGL((contract_t_kernel<true>), gt, dim3(256), sht, s, ndp ? p->basis.nf64 : p->basis.f64,
+                               (const double *)dw, a->batch, p->NP, p->rows_pad, p->nc_pad, (double *)dcn);
         } else {
             // dc = Ttilde^T dw is the forward contraction's product with the transposed basis (rows of
             // Ttilde^T: the nc_pad Chebyshev columns; its K: the rows_pad basis rows) and dw in place of c
             {
                 std::lock_guard<std::mutex> lk(p->mu);
-                st = ensure_f32t(p, s);
+                st = ndp ? ensure_nf32t(p, s) : ensure_f32t(p, s);
             }
             if (st != BLAST_OK) return st;
+            const float *bt = ndp ? p->basis.nf32t : p->basis.f32t;
             const int RT = p->nc_pad / 16;
             const size_t sh64 = (size_t)2 * kAdjBT * (p->rows_pad + 4) * sizeof(float);
             if (sh64 <= 160 * 1024) {
@@ -3835,15 +3841,19 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
                 // L2 feeds twice the MFMAs of the 32-cosmology tile
                 const dim3 g64 = point_tile_grid(p->NP, (a->batch + 2 * kAdjBT - 1) / (2 * kAdjBT));
                 hipLaunchKernelGGL((contract_tiled_kernel<BLAST_FP32, 4, 2 * kAdjBT, 1>), g64, dim3(64 * RT), sh64,
-                                   s, p->basis.f32t, nullptr, nullptr, (const float *)dw, nullptr, a->batch, p->NP,
-                                   p->nc_pad, p->rows_pad, (float *)dc);
+                                   s, bt, nullptr, nullptr, (const float *)dw, nullptr, a->batch, p->NP, p->nc_pad,
+                                   p->rows_pad, (float *)dcn);
             } else {
                 const int W = std::min((RT + kTilesPerWave - 1) / kTilesPerWave, 8);
                 const size_t sht = (size_t)kAdjBT * (p->rows_pad + 4) * sizeof(float);
-                hipLaunchKernelGGL((contract_tiled_kernel<BLAST_FP32, 4, kAdjBT>), gt, dim3(64 * W), sht, s,
-                                   p->basis.f32t, nullptr, nullptr, (const float *)dw, nullptr, a->batch, p->NP,
-                                   p->nc_pad, p->rows_pad, (float *)dc);
+                hipLaunchKernelGGL((contract_tiled_kernel<BLAST_FP32, 4, kAdjBT>), gt, dim3(64 * W), sht, s, bt,
+                                   nullptr, nullptr, (const float *)dw, nullptr, a->batch, p->NP, p->nc_pad,
+                                   p->rows_pad, (float *)dcn);
             }
+        }
+        if (ndp) {
+            BLAST_HIP_TRY(hipGetLastError());
+            return BLAST_OK;
         }
         const long nrows = (long)a->batch * p->NP;
         const int N = p->n_cheb;

@@ -64,6 +64,8 @@ struct BasisBuffers {
     float *nscale16 = nullptr; // [NP][rows_pad]
     float *nf32 = nullptr;     // FP32 nodal basis, layout of f32 (plans with n_cheb == nc_pad)
     double *nf64 = nullptr;    // FP64 nodal basis, layout of f64 (plans with n_cheb == nc_pad)
+    float *nf32t = nullptr;    // FP32 nodal basis transposed, layout of f32t (made by the first FP32
+                               // adjoint on nodal FP32 P that asks for dP)
     float *f32t = nullptr;     // FP32 transpose per point, [nc_pad][rows_pad] in the tiled layout
                                // (made by the first FP32 adjoint call that asks for dP)
 };
@@ -126,6 +128,8 @@ blast_status build_basis(blast_plan *p, hipStream_t s);
 blast_status derive_precisions(blast_plan *p, hipStream_t s);
 // the transposed FP32 copy of the basis, made on `s` if it does not exist yet (caller holds p->mu)
 blast_status ensure_f32t(blast_plan *p, hipStream_t s);
+// the transposed FP32 nodal basis, likewise (plans with n_cheb == nc_pad)
+blast_status ensure_nf32t(blast_plan *p, hipStream_t s);
 
 // eval.hip
 blast_status forward(blast_plan *p, const blast_cl_args *a, hipStream_t s);
