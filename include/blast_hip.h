@@ -61,33 +61,45 @@ typedef enum {
  * coefficients (per-row power-of-two scales), FP32 accumulate.  BF16X3: basis and
  * coefficients split into BF16 hi + lo parts, hi*hi + hi*lo + lo*hi, FP32
  * accumulate.  FP16X3: the same three products with FP16 hi + lo parts (about 22
- * significant bits per operand); every basis row and every coefficient row
+ * significant bits per operand); every basis row and every row of the other operand
  * (one cosmology, one point) carries its own power-of-two scale that keeps its
- * magnitudes below 2^15, inside FP16's range (basis rows and coefficients given
- * as input: largest magnitude in [2^14, 2^15); coefficients projected from nodal
- * P: from the row's largest |P_j|, which bounds |c_n| / 2), and the projection
- * of nodal P runs the same three products on P and the DCT matrix split into
- * FP16 hi + lo parts.  FP16X3 runs the
- * fused contraction + R-quadrature only: it needs nodal P with n_cheb % 8 == 0
- * (or P given as coefficients), n_g + n_s <= 20 and no w_save, and is not
- * available to the adjoint; other requests are refused with BLAST_E_UNSUPPORTED.
+ * magnitudes below 2^15, inside FP16's range (largest magnitude in [2^14, 2^15);
+ * coefficients projected from nodal P: from the row's largest |P_j|, which bounds
+ * |c_n| / 2, the projection running the same three products on P and the DCT matrix
+ * split into FP16 hi + lo parts).  FP16X3 runs the fused contraction + R-quadrature
+ * only: it needs nodal P with n_cheb % 8 == 0 (or P given as coefficients),
+ * n_g + n_s <= 20 and no w_save, and is not available to the adjoint; other requests
+ * are refused with BLAST_E_UNSUPPORTED.
+ *
+ * Nodal basis.  Since c = D P (Eq. dft, D the DCT-II matrix), the contraction
+ * sum_n Ttilde_n c_n equals sum_j B_j P_j with B = Ttilde D; the plan keeps B next to
+ * Ttilde and the forward contracts it with the nodal P values themselves, making and
+ * storing no coefficients, when: FP16X3 on FP32 P with n_cheb % 8 == 0 and at most 16
+ * bins (P rows split into FP16 hi + lo inside the contraction kernel); FP32 on FP32 P
+ * and FP64 on FP64 P with n_cheb a multiple of 32 (P rows are then laid out as the
+ * coefficient rows).  The backward on such calls computes dP = B^T dw likewise.  The
+ * result is that of the projection route up to rounding; on the ridge R ~ 1 the terms
+ * B_j P_j are quadrature weights of one sign, so the sum cancels far less than the
+ * Chebyshev terms do and the error of the mixed paths drops (figures below).  Other
+ * calls (FP64 P on FP32 or FP16X3, coefficient input, BF16 paths) project per call.
  * The basis precompute is always FP64; the quadrature always accumulates in FP64.
  *
  * Accuracy.  The relative error of C against exact arithmetic on the same grids is about
  * u * kappa, where u is the relative error of one product of the contraction's operands and
  * kappa >= 1 is the cancellation of the problem: the ratio of the sum of the magnitudes of
- * the terms (Chebyshev terms of Eq. pmd, then the chi-R sum of Eq. final_cls) to |C|.  kappa
- * grows with the multipole and the Chebyshev order, and is largest for cross spectra of
- * well separated bins at high multipoles.  u is about 2^-52 (FP64), 2^-23 (FP32), 2^-21
- * (FP16X3), 2^-15 (BF16X3: the hi*lo sum leaves 16 bits per operand) and 2^-7 (BF16: 8 bits
- * per operand).  Measured against the FP64 oracle (element-wise, cross spectra floored at
- * 1e-3 of the geometric mean of the two auto spectra): at 20 multipoles on [2, 200] with 64
- * Chebyshev nodes FP64 8e-12, FP32 3e-5, FP16X3 1.4e-5, BF16X3 9e-4, BF16 0.26; at 96
- * multipoles on [2, 1000] with 128 nodes FP64 4e-11, FP32 6e-4, FP16X3 3e-4, BF16X3 9e-3,
- * BF16 6.2.  FP64 is the path for a 1e-6 bar and FP16X3 or FP32 for 1e-3; BF16X3 meets 1e-3
- * only on grids like the first and stays within 2e-2 on grids like the second; plain BF16
- * is not an accurate evaluation of C at either (errors of order 1 at the second) and is
- * kept to measure what the compensated split buys. */
+ * the terms (Chebyshev or nodal terms of Eq. pmd, then the chi-R sum of Eq. final_cls) to
+ * |C|.  kappa grows with the multipole and the Chebyshev order, and is largest for cross
+ * spectra of well separated bins at high multipoles.  u is about 2^-52 (FP64), 2^-23 (FP32),
+ * 2^-21 (FP16X3), 2^-15 (BF16X3: the hi*lo sum leaves 16 bits per operand) and 2^-7 (BF16: 8
+ * bits per operand).  Measured against the FP64 oracle (element-wise, cross spectra floored at
+ * 1e-3 of the geometric mean of the two auto spectra), nodal basis where it applies: at 20
+ * multipoles on [2, 200] with 64 Chebyshev nodes FP64 8e-12, FP32 3.4e-6, FP16X3 1.5e-6,
+ * BF16X3 9e-4, BF16 0.26; at 96 multipoles on [2, 1000] with 128 nodes FP64 4e-11, FP32
+ * 4.4e-5, FP16X3 1.5e-5, BF16X3 9e-3, BF16 6.2 (through the per-call projection FP32 6e-4 and
+ * FP16X3 3e-4 there).  FP64 is the path for a 1e-6 bar and FP16X3 or FP32 for 1e-3; BF16X3
+ * meets 1e-3 only on grids like the first and stays within 2e-2 on grids like the second;
+ * plain BF16 is not an accurate evaluation of C at either (errors of order 1 at the second)
+ * and is kept to measure what the compensated split buys. */
 typedef enum {
     BLAST_FP64 = 0,
     BLAST_FP32 = 1,
@@ -230,7 +242,8 @@ blast_status blast_cl_workspace_bytes(const blast_plan *plan, int32_t batch, int
                                       size_t *bytes);
 
 /* Enqueues projection (Eq. dft) -> contraction (Eq. pmd) -> quadrature
- * (Eq. final_cls) on `stream`.  Errors: INVALID (shapes, types, precision not
+ * (Eq. final_cls) on `stream`; calls that take the nodal basis (see the precisions
+ * above) run no projection.  Errors: INVALID (shapes, types, precision not
  * resident), OOM (plan scratch), HIP. */
 blast_status blast_cl_forward(blast_plan *plan, const blast_cl_args *args, void *stream);
 
@@ -253,7 +266,11 @@ blast_status blast_cl_forward_noalloc(blast_plan *plan, const blast_cl_args *arg
  * differentiability as future work).  With the same `args` (precision FP64 or FP32)
  * and dC = dL/dC (device, FP64, shaped like args->C) it enqueues on `stream`:
  *   dP      device, nullable, P's dtype and shape: dL/dP (nodal values or coefficients
- *           per args->p_kind) -- the transposed contraction streams the basis again;
+ *           per args->p_kind) -- the transposed contraction streams the basis again (on
+ *           nodal P of the path's own type with n_cheb a multiple of 32 the nodal basis,
+ *           whose product B^T dw is dP itself: FP64 reads the FP64 nodal basis, FP32 a
+ *           transposed FP32 copy of it made at the first such call; otherwise Ttilde^T dw
+ *           followed by the projection's adjoint);
  *   dK_chi  device, nullable, FP64 [batch][bins][n_chi]: dL/dK_chi;
  *   dK_chi2 device, nullable, FP64 [batch][bins][n_chi][n_R]: dL/dK_chi2.
  * args->C is not read.  args->w_save and args->y_save, if given, must hold w and Y of a
