@@ -75,13 +75,16 @@ typedef enum {
  * sum_n Ttilde_n c_n equals sum_j B_j P_j with B = Ttilde D; the plan keeps B next to
  * Ttilde and the forward contracts it with the nodal P values themselves, making and
  * storing no coefficients, when: FP16X3 on FP32 P with n_cheb % 8 == 0 and at most 16
- * bins (P rows split into FP16 hi + lo inside the contraction kernel); FP32 on FP32 P
- * and FP64 on FP64 P with n_cheb a multiple of 32 (P rows are then laid out as the
+ * bins (P rows split into FP16 hi + lo inside the contraction kernel; with 17-20 bins P is
+ * split by the coefficient-input conversion instead of projected); FP32 on FP32 P and
+ * FP64 on FP64 P with n_cheb a multiple of 32 (P rows are then laid out as the
  * coefficient rows).  The backward on such calls computes dP = B^T dw likewise.  The
  * result is that of the projection route up to rounding; on the ridge R ~ 1 the terms
  * B_j P_j are quadrature weights of one sign, so the sum cancels far less than the
- * Chebyshev terms do and the error of the mixed paths drops (figures below).  Other
- * calls (FP64 P on FP32 or FP16X3, coefficient input, BF16 paths) project per call.
+ * Chebyshev terms do and the error of the mixed paths drops on the named workloads
+ * (figures below; on small grids with k up to 0.6/Mpc the two routes trade places, both
+ * within 1e-4).  Other calls (FP64 P on FP32 or FP16X3, coefficient input, BF16 paths)
+ * project per call.
  * The basis precompute is always FP64; the quadrature always accumulates in FP64.
  *
  * Accuracy.  The relative error of C against exact arithmetic on the same grids is about

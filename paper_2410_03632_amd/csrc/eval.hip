@@ -3083,8 +3083,10 @@ __global__ __launch_bounds__(256) void adj_project_split64_kernel(const double *
 // ---------------------------------------------------------------------------------------------
 struct Ctx {
     int prec, ng, ns, nbins, npairs, nbp;
-    // the call contracts the nodal basis with its FP32 nodal P (no projection; P read as c)
+    // the call contracts the nodal basis (B = Ttilde D) with its nodal P: P read in place of c, or
+    // converted into c's layout as coefficient input is (no projection either way)
     bool nodal = false;
+    bool direct = false;  // nodal, with P itself as the contraction's operand
     EllSel sel;
     EllInv inv;
 };
@@ -3478,7 +3480,7 @@ void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, in
             const int wgroups = (RT + kWideTR - 1) / kWideTR;
             const int wunits = p->n_chi * nBT * wgroups;
             const dim3 wg((unsigned)((wunits + 7) / 8 * 8));
-            if (nodal)
+            if (x.direct)
                 hipLaunchKernelGGL((contract_quad_wide_kernel<PR, NB, NBP, NS, true>), wg, dim3(512), 0, s,
                                    (const uint16_t *)p->basis.n16, p->basis.nl16, p->basis.nscale16, c, nullptr, Kt,
                                    a->batch, p->n_chi, p->n_R, p->rows_pad, nBT, wunits, p->n_ell, p->nt, granges,
@@ -3491,10 +3493,12 @@ void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, in
             return;
         }
         const E *bas = PR == BLAST_FP32 ? (const E *)(nodal ? p->basis.nf32 : p->basis.f32)
-                                        : (const E *)(H ? p->basis.h16 : p->basis.hi);
+                                        : (const E *)(H ? (nodal ? p->basis.n16 : p->basis.h16) : p->basis.hi);
+        const uint16_t *blo = H ? (nodal ? p->basis.nl16 : p->basis.l16) : p->basis.lo;
+        const float *bsc = H ? (nodal ? p->basis.nscale16 : p->basis.scale16) : p->basis.scale;
         // all LDS of the fused kernel is static (FusedShape::LDS bytes)
         hipLaunchKernelGGL((contract_quad_kernel<PR, NB, NBP, NS>), dim3(grid), dim3(256 * kFusedTR), 0, s, bas,
-                           H ? p->basis.l16 : p->basis.lo, H ? p->basis.scale16 : p->basis.scale, (const E *)c, clo,
+                           blo, bsc, (const E *)c, clo,
                            Kt, a->batch, p->n_chi, p->n_R, p->rows_pad, nBT, units, p->n_ell, p->nt, granges, Y,
                            w_out);
     };
@@ -3605,14 +3609,19 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     }
     BLAST_HIP_TRY(allow_large_lds());
     const bool need_w = a->w_save == nullptr;
-    // nodal values: the nodal basis contracted with P itself, FP16X3 on FP32 P (at most 16 bins; P
-    // split in the kernel), FP32 on FP32 P and FP64 on FP64 P (P rows in the coefficient rows'
-    // layout: n_cheb == nc_pad)
+    // nodal values: the nodal basis contracted with P itself (direct): FP16X3 on FP32 P (at most
+    // 16 bins; P split in the kernel), FP32 on FP32 P and FP64 on FP64 P (P rows in the coefficient
+    // rows' layout: n_cheb == nc_pad).  FP32 P on FP16X3 with more bins: the nodal basis, with P
+    // split as coefficient input is (conv).  The BF16 paths keep the projection: with 8 or 16 bits
+    // per operand and no row scale on P, the rounding of every P_j can cost more than the
+    // cancellation the nodal sum saves (BF16X3 measured both better and worse than through c)
     const bool fp32p = a->p_kind == 0 && a->p_dtype == 1, fp64p = a->p_kind == 0 && a->p_dtype == 0;
-    x.nodal = (fp32p && ((x.prec == BLAST_FP16X3 && p->basis.n16 && fused_nb(x.prec, x.nbins, a->batch) <= 16) ||
-                         (x.prec == BLAST_FP32 && p->basis.nf32))) ||
-              (fp64p && x.prec == BLAST_FP64 && p->basis.nf64);
-    const bool nodal = x.nodal;
+    const bool nodal = (fp32p && ((x.prec == BLAST_FP16X3 && p->basis.n16 && fused_nb(x.prec, x.nbins, a->batch) <= 16) ||
+                                  (x.prec == BLAST_FP32 && p->basis.nf32))) ||
+                       (fp64p && x.prec == BLAST_FP64 && p->basis.nf64);
+    const bool conv = !nodal && fp32p && x.prec == BLAST_FP16X3 && p->basis.n16;
+    x.nodal = nodal || conv;
+    x.direct = nodal;
     const Layout L = layout_of(p, a->batch, x.prec, x.nbins, need_w, false, nodal);
     unsigned char *ws = nullptr;
     if (fixed) {
@@ -3634,7 +3643,13 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     const int fnb = need_w || keep_fused ? fused_nb(x.prec, x.nbins, a->batch) : 0;
     const bool f64f = need_w && x.prec == BLAST_FP64 && fused_f64(x.nbins, a->batch);
     mark(0);
-    if (!nodal) stage_project(p, a, x, (void *)c, clo, cs, s);
+    if (conv) {
+        blast_cl_args ac = *a;
+        ac.p_kind = 1;  // P's nodal values are the nodal basis' coefficients
+        stage_project(p, &ac, x, (void *)c, clo, cs, s);
+    } else if (!nodal) {
+        stage_project(p, a, x, (void *)c, clo, cs, s);
+    }
     mark(1);
     if (fnb) {
         // fused path: interval 1 = the R-weights table, interval 2 = contraction + R-quadrature
