@@ -170,7 +170,8 @@ blast_status blast_plan_create(const blast_plan_desc *desc, int32_t device, blas
 blast_status blast_plan_destroy(blast_plan *plan);
 
 /* Sizes: number of basis rows (types x ell), padded Chebyshev length, bytes of
- * resident basis per precision (host [5], indexed by blast_precision), k-quadrature node count, basis build
+ * resident basis per precision (host [5], indexed by blast_precision; FP64, FP32 and FP16X3
+ * count their nodal basis too where the plan keeps one), k-quadrature node count, basis build
  * time in milliseconds.  Any output pointer may be NULL. */
 blast_status blast_plan_info(const blast_plan *plan, int32_t *rows, int32_t *n_cheb_pad, size_t *basis_bytes,
                              int64_t *kq_nodes, double *build_ms);

@@ -579,12 +579,12 @@ extern "C" blast_status blast_plan_info(const blast_plan *p, int32_t *rows, int3
     if (rows) *rows = p->rows;
     if (n_cheb_pad) *n_cheb_pad = p->nc_pad;
     if (basis_bytes) {
-        const size_t n = (size_t)p->NP * p->rows_pad * p->nc_pad;
-        basis_bytes[0] = p->basis.f64 ? n * 8 : 0;
-        basis_bytes[1] = p->basis.f32 ? n * 4 : 0;
-        basis_bytes[2] = p->basis.hi ? n * 2 + (size_t)p->NP * p->rows_pad * 4 : 0;
-        basis_bytes[3] = p->basis.lo ? n * 4 + (size_t)p->NP * p->rows_pad * 4 : 0;
-        basis_bytes[4] = p->basis.l16 ? n * 4 + (size_t)p->NP * p->rows_pad * 4 : 0;
+        const size_t n = (size_t)p->NP * p->rows_pad * p->nc_pad, sc = (size_t)p->NP * p->rows_pad * 4;
+        basis_bytes[0] = (p->basis.f64 ? n * 8 : 0) + (p->basis.nf64 ? n * 8 : 0);
+        basis_bytes[1] = (p->basis.f32 ? n * 4 : 0) + (p->basis.nf32 ? n * 4 : 0);
+        basis_bytes[2] = p->basis.hi ? n * 2 + sc : 0;
+        basis_bytes[3] = p->basis.lo ? n * 4 + sc : 0;
+        basis_bytes[4] = (p->basis.l16 ? n * 4 + sc : 0) + (p->basis.nl16 ? n * 4 + sc : 0);
     }
     if (kq_nodes) *kq_nodes = p->kq_nodes;
     if (build_ms) *build_ms = p->build_ms;
