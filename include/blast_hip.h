@@ -219,7 +219,8 @@ typedef struct {
     int32_t p_kind;       /* 0: P holds nodal values P(k_j, chi_a, R_b chi_a), k ascending
                              (blast_plan_k_nodes); 1: P holds the Chebyshev coefficients
                              c_n(chi_a, R_b chi_a) of Eq. cheb_pk (the projection is skipped) */
-    const void *P;        /* device [batch][n_chi][n_R][n_cheb]                      */
+    const void *P;        /* device [batch][n_chi][n_R][n_cheb], 16-byte aligned (as
+                             hipMalloc and torch allocations are): read in 16-byte pieces */
     int32_t n_g, n_s;     /* clustering / shear bins, n_g + n_s <= 32              */
     const double *K_chi;  /* device [batch][n_g+n_s][n_chi]: K at chi_a             */
     const double *K_chi2; /* device [batch][n_g+n_s][n_chi][n_R]: K at R_b chi_a    */

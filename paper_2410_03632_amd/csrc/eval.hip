@@ -3615,10 +3615,14 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     // split as coefficient input is (conv).  The BF16 paths keep the projection: with 8 or 16 bits
     // per operand and no row scale on P, the rounding of every P_j can cost more than the
     // cancellation the nodal sum saves (BF16X3 measured both better and worse than through c)
+    // P read in place of c is read in 16-byte pieces, as the library's own c buffers are: a caller's
+    // P that is not 16-byte aligned takes the conversion or projection route instead
+    const bool al16 = ((uintptr_t)a->P & 15) == 0;
     const bool fp32p = a->p_kind == 0 && a->p_dtype == 1, fp64p = a->p_kind == 0 && a->p_dtype == 0;
-    const bool nodal = (fp32p && ((x.prec == BLAST_FP16X3 && p->basis.n16 && fused_nb(x.prec, x.nbins, a->batch) <= 16) ||
-                                  (x.prec == BLAST_FP32 && p->basis.nf32))) ||
-                       (fp64p && x.prec == BLAST_FP64 && p->basis.nf64);
+    const bool nodal = al16 && ((fp32p && ((x.prec == BLAST_FP16X3 && p->basis.n16 &&
+                                             fused_nb(x.prec, x.nbins, a->batch) <= 16) ||
+                                            (x.prec == BLAST_FP32 && p->basis.nf32))) ||
+                                (fp64p && x.prec == BLAST_FP64 && p->basis.nf64));
     const bool conv = !nodal && fp32p && x.prec == BLAST_FP16X3 && p->basis.n16;
     x.nodal = nodal || conv;
     x.direct = nodal;
@@ -3833,7 +3837,7 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
         const dim3 gt = point_tile_grid(p->NP, (a->batch + kAdjBT - 1) / kAdjBT);
         // nodal P of the path's own type with n_cheb == nc_pad: dP = B^T dw with the nodal basis
         // B = Ttilde D (the adjoint of the projection folded in), written straight into dP
-        const bool ndp = a->p_kind == 0 && p->n_cheb == p->nc_pad &&
+        const bool ndp = a->p_kind == 0 && p->n_cheb == p->nc_pad && ((uintptr_t)dP & 15) == 0 &&
                          (f64 ? a->p_dtype == 0 && p->basis.nf64 : a->p_dtype == 1 && p->basis.nf32);
         void *dcn = ndp ? dP : dc;
         if (f64) {
