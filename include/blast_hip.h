@@ -99,10 +99,10 @@ typedef enum {
  * multipoles on [2, 200] with 64 Chebyshev nodes FP64 8e-12, FP32 3.4e-6, FP16X3 1.5e-6,
  * BF16X3 9e-4, BF16 0.26; at 96 multipoles on [2, 1000] with 128 nodes FP64 4e-11, FP32
  * 4.4e-5, FP16X3 1.5e-5, BF16X3 9e-3, BF16 6.2 (through the per-call projection, on FP64 P:
- * FP32 3.1e-6 and 2.4e-4, FP16X3 1.4e-5 and 2.7e-4).  FP64 is the path for a 1e-6 bar and FP16X3 or FP32 for 1e-3; BF16X3
- * meets 1e-3 only on grids like the first and stays within 2e-2 on grids like the second;
- * plain BF16 is not an accurate evaluation of C at either (errors of order 1 at the second)
- * and is kept to measure what the compensated split buys. */
+ * FP32 3.1e-6 and 2.4e-4, FP16X3 1.4e-5 and 2.7e-4).  FP64 is the path for a 1e-6 bar and
+ * FP16X3 or FP32 for 1e-3; BF16X3 meets 1e-3 only on grids like the first and stays within
+ * 2e-2 on grids like the second; plain BF16 is not an accurate evaluation of C at either
+ * (errors of order 1 at the second) and is kept to measure what the compensated split buys. */
 typedef enum {
     BLAST_FP64 = 0,
     BLAST_FP32 = 1,
