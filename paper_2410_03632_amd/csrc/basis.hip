@@ -780,7 +780,7 @@ blast_status derive_precisions(blast_plan *p, hipStream_t s) {
         if (e != hipSuccess) return p->basis.f32 = nullptr, fail(e, "FP32 basis");
         hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->basis.f64,
                            p->basis.f32, n, p->rows_pad, p->nc_pad);
-        if (p->n_cheb == p->nc_pad) {  // P rows in the coefficient rows' layout: the nodal FP32 path
+        if (p->n_cheb % 4 == 0) {  // P rows of whole 16-byte granules, read in place of c rows
             e = hipMalloc(&p->basis.nf32, n * sizeof(float));
             if (e != hipSuccess) return p->basis.nf32 = nullptr, fail(e, "FP32 nodal basis");
             const unsigned g = (unsigned)std::min<size_t>((nrows + 3) / 4, 2048);

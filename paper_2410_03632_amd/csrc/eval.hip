@@ -712,7 +712,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE))) void
                                                              const float *__restrict__ scale,
                                                              const typename Cfg<PREC>::E *__restrict__ c,
                                                              const uint16_t *__restrict__ c_lo, int batch, int NP,
-                                                             int rows_pad, int ncp, float *__restrict__ w_out) {
+                                                             int rows_pad, int ncp, float *__restrict__ w_out,
+                                                             int cld) {
     using C = Cfg<PREC>;
     using E = typename C::E;
     constexpr int VEC = C::VEC, BT = BTT, BTN = BT / 16, TPW = TPWT;
@@ -732,7 +733,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE))) void
         const int bb = i / vec_per_row, v = i % vec_per_row;
         U4 val = {0u, 0u, 0u, 0u}, vlo = {0u, 0u, 0u, 0u};
         if (bb < nb) {
-            const size_t off = ((size_t)(beta0 + bb) * NP + ab) * ncp + (size_t)v * VEC;
+            // c rows of cld elements (ncp for the library's own c; n_cheb for a caller's nodal P,
+            // whose granules past its end repeat the last one: their basis columns are zero)
+            const size_t off = ((size_t)(beta0 + bb) * NP + ab) * cld + (size_t)min(v, cld / VEC - 1) * VEC;
             val = *(const U4 *)(c + off);
             if (X3) vlo = *(const U4 *)(c_lo + off);
         }
@@ -1183,7 +1186,7 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
     const typename Cfg<PREC>::E *__restrict__ basis, const uint16_t *__restrict__ basis_lo,
     const float *__restrict__ scale, const typename Cfg<PREC>::E *__restrict__ c, const uint16_t *__restrict__ c_lo,
     const float *__restrict__ Kt, int batch, int n_chi, int n_R, int rows_pad, int nBT, int units, int n_ell,
-    int nslots, int granges, float *__restrict__ Y, float *__restrict__ w_out) {
+    int nslots, int granges, float *__restrict__ Y, float *__restrict__ w_out, int cld) {
     using S = FusedShape<PREC, NS>;
     using E = typename S::E;
     constexpr int TR = kFusedTR, VEC = S::VEC, ncp = S::ncp, NPART = S::NPART;
@@ -1283,9 +1286,11 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
         const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
         lds_dma16(srcX + ab * strideX, buf + S::C_BUF + (size_t)chX * 1024);
     };
-    // FP16X3 coefficients are point-major ([point][beta][n]), the others cosmology-major
+    // FP16X3 coefficients are point-major ([point][beta][n]), the others cosmology-major with rows
+    // of cld elements (ncp, or n_cheb for a caller's nodal P: granules past its end repeat the last
+    // one, whose basis columns are zero)
     constexpr bool PM = PREC == BLAST_FP16X3;
-    const size_t cstride = PM ? (size_t)batch * ncp : (size_t)ncp;  // per point
+    const size_t cstride = PM ? (size_t)batch * ncp : (size_t)cld;  // per point
     const void *srcC[S::C_PW];
 #pragma unroll
     for (int k = 0; k < S::C_PW; ++k) {
@@ -1296,7 +1301,8 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
         const int row = pos / S::ROWB, gp = (pos % S::ROWB) / 16;
         const int v = gp ^ (row & SWZ);          // granule stored at position gp
         const int bb = bt * 64 + (row < nb ? row : 0);
-        srcC[k] = (part ? (const E *)c_lo : c) + (size_t)bb * (PM ? ncp : NP * ncp) + v * VEC;
+        srcC[k] = (part ? (const E *)c_lo : c) + (size_t)bb * (PM ? (size_t)ncp : (size_t)NP * cld) +
+                  (PM ? v : min(v, cld / VEC - 1)) * VEC;
     }
     auto dma_C = [&](int b, unsigned char *__restrict__ buf) {
         const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
@@ -3417,7 +3423,8 @@ void stage_contract(blast_plan *p, const blast_cl_args *a, const Ctx &x, const v
             const int RT = p->rows_pad / 16;
             const int W = std::min((RT + kTilesPerWave - 1) / kTilesPerWave, 8);
             hipLaunchKernelGGL((contract_tiled_kernel<PR>), grid, dim3(64 * W), sh, s, bas, p->basis.lo,
-                               p->basis.scale, (const E *)c, clo, a->batch, p->NP, p->rows_pad, ncp, (float *)w);
+                               p->basis.scale, (const E *)c, clo, a->batch, p->NP, p->rows_pad, ncp, (float *)w,
+                               x.direct ? p->n_cheb : ncp);
         }
     };
     if (x.prec == BLAST_FP64) launch(std::integral_constant<int, BLAST_FP64>());
@@ -3500,7 +3507,7 @@ void stage_contract_quad(blast_plan *p, const blast_cl_args *a, const Ctx &x, in
         hipLaunchKernelGGL((contract_quad_kernel<PR, NB, NBP, NS>), dim3(grid), dim3(256 * kFusedTR), 0, s, bas,
                            blo, bsc, (const E *)c, clo,
                            Kt, a->batch, p->n_chi, p->n_R, p->rows_pad, nBT, units, p->n_ell, p->nt, granges, Y,
-                           w_out);
+                           w_out, x.direct ? p->n_cheb : p->nc_pad);
     };
     // nc_pad is a multiple of 32 up to 128: 1..4 blocks of 32 columns
     auto by_ns = [&](auto ptag, auto nbtag, auto nbptag) {
@@ -3610,8 +3617,9 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     BLAST_HIP_TRY(allow_large_lds());
     const bool need_w = a->w_save == nullptr;
     // nodal values: the nodal basis contracted with P itself (direct): FP16X3 on FP32 P (at most
-    // 16 bins; P split in the kernel), FP32 on FP32 P and FP64 on FP64 P (P rows in the coefficient
-    // rows' layout: n_cheb == nc_pad).  FP32 P on FP16X3 with more bins: the nodal basis, with P
+    // 16 bins; P split in the kernel), FP32 on FP32 P (P rows of n_cheb % 4 == 0 elements read in
+    // place of c rows) and FP64 on FP64 P (P rows in the coefficient rows' layout: n_cheb ==
+    // nc_pad).  FP32 P on FP16X3 with more bins: the nodal basis, with P
     // split as coefficient input is (conv).  The BF16 paths keep the projection: with 8 or 16 bits
     // per operand and no row scale on P, the rounding of every P_j can cost more than the
     // cancellation the nodal sum saves (BF16X3 measured both better and worse than through c)
@@ -3621,7 +3629,7 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     const bool fp32p = a->p_kind == 0 && a->p_dtype == 1, fp64p = a->p_kind == 0 && a->p_dtype == 0;
     const bool nodal = al16 && ((fp32p && ((x.prec == BLAST_FP16X3 && p->basis.n16 &&
                                              fused_nb(x.prec, x.nbins, a->batch) <= 16) ||
-                                            (x.prec == BLAST_FP32 && p->basis.nf32))) ||
+                                            (x.prec == BLAST_FP32 && p->basis.nf32 && p->n_cheb % 4 == 0))) ||
                                 (fp64p && x.prec == BLAST_FP64 && p->basis.nf64));
     const bool conv = !nodal && fp32p && x.prec == BLAST_FP16X3 && p->basis.n16;
     x.nodal = nodal || conv;
@@ -3861,13 +3869,13 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
                 const dim3 g64 = point_tile_grid(p->NP, (a->batch + 2 * kAdjBT - 1) / (2 * kAdjBT));
                 hipLaunchKernelGGL((contract_tiled_kernel<BLAST_FP32, 4, 2 * kAdjBT, 1>), g64, dim3(64 * RT), sh64,
                                    s, bt, nullptr, nullptr, (const float *)dw, nullptr, a->batch, p->NP, p->nc_pad,
-                                   p->rows_pad, (float *)dcn);
+                                   p->rows_pad, (float *)dcn, p->rows_pad);
             } else {
                 const int W = std::min((RT + kTilesPerWave - 1) / kTilesPerWave, 8);
                 const size_t sht = (size_t)kAdjBT * (p->rows_pad + 4) * sizeof(float);
                 hipLaunchKernelGGL((contract_tiled_kernel<BLAST_FP32, 4, kAdjBT>), gt, dim3(64 * W), sht, s, bt,
                                    nullptr, nullptr, (const float *)dw, nullptr, a->batch, p->NP, p->nc_pad,
-                                   p->rows_pad, (float *)dcn);
+                                   p->rows_pad, (float *)dcn, p->rows_pad);
             }
         }
         if (ndp) {

@@ -62,7 +62,7 @@ struct BasisBuffers {
     uint16_t *n16 = nullptr;   // FP16 bits of (B / nscale16), tiled layout (column = k node)
     uint16_t *nl16 = nullptr;  // FP16 bits of the remainder
     float *nscale16 = nullptr; // [NP][rows_pad]
-    float *nf32 = nullptr;     // FP32 nodal basis, layout of f32 (plans with n_cheb == nc_pad)
+    float *nf32 = nullptr;     // FP32 nodal basis, layout of f32 (plans with n_cheb % 4 == 0)
     double *nf64 = nullptr;    // FP64 nodal basis, layout of f64 (plans with n_cheb == nc_pad)
     float *nf32t = nullptr;    // FP32 nodal basis transposed, layout of f32t (made by the first FP32
                                // adjoint on nodal FP32 P that asks for dP)

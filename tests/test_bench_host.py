@@ -80,9 +80,11 @@ def test_stage_work_of_the_precisions():
     # the even/odd split halves the projection's products when N % 8 == 0
     plan, cfg7 = _shapes(n_cheb=100)
     cfg96 = types.SimpleNamespace(n_chi=256, n_R=96, n_cheb=120, n_g=10, n_s=5)
-    assert not bench.nodal_path("fp32", cfg96)
-    assert bench.stage_work(plan, cfg96, "fp32", B)["projection"]["flops"] * 2 == pytest.approx(
-        bench.stage_work(plan, cfg7, "fp32", B)["projection"]["flops"] * (120 / 100) ** 2)
+    assert bench.nodal_path("fp32", cfg96) and not bench.nodal_path("fp64", cfg96)
+    cfg7b = types.SimpleNamespace(n_chi=256, n_R=96, n_cheb=102, n_g=10, n_s=5)
+    assert not bench.nodal_path("fp32", cfg7b)
+    assert bench.stage_work(plan, cfg96, "fp64", B)["projection"]["flops"] * 2 == pytest.approx(
+        bench.stage_work(plan, cfg7b, "fp32", B)["projection"]["flops"] * (120 / 102) ** 2)
 
 
 def test_counter_traffic_only_for_the_measured_source(tmp_path, monkeypatch):

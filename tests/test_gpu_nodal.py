@@ -1,9 +1,9 @@
 """GPU parity of the nodal basis: B = Ttilde D, the DCT of Eq. dft applied to the basis when the
 plan is made, so that sum_j B[row][j] P_j = sum_n Ttilde[row][n] c_n (Eq. pmd) is contracted with
 the nodal values P themselves and no coefficients are made per call.  The library takes it for
-FP32 nodal P: on the FP32 path when n_cheb is a multiple of 32 (P rows then have the coefficient
-rows' layout), on the FP16X3 path (tested with that path) when n_cheb % 8 == 0 and there are at
-most 16 bins.  FP64 nodal P, coefficient input and other shapes take the per-call projection.
+FP32 nodal P on the FP32 path when n_cheb % 4 == 0 (P rows read in place of coefficient rows),
+on the FP16X3 path (tested with that path) when n_cheb % 8 == 0, and for FP64 nodal P on the
+FP64 path when n_cheb is a multiple of 32.  Other inputs take the per-call projection.
 
 Both routes are checked against the FP64 oracle at the FP32 bar (1e-3 of ``metrics.g16_err``),
 on the unfused (batch 1, w kept) and the fused (batch 40) contraction, and w itself against the
@@ -33,11 +33,13 @@ def _oracle(plan, cfg, inp):
     return C
 
 
-@pytest.mark.parametrize("n_cheb", [32, 40, 64, 128])
+@pytest.mark.parametrize("n_cheb", [32, 40, 42, 64, 128])
 def test_fp32_nodal_basis_and_projection_agree(n_cheb):
-    """n_cheb = 32, 64, 128: FP32 P runs the nodal basis, FP64 P the projection; n_cheb = 40 (not a
-    multiple of 32): both project.  Batch 1 takes the unfused contraction with w kept, batch 40
-    the fused one (w kept by the fused kernel as it goes)."""
+    """FP32 P runs the nodal basis when n_cheb % 4 == 0 (32, 64, 128: P rows are the coefficient
+    rows' length; 40: rows of 40 read in place of 64-element rows, the granules past the end
+    repeating the last one), FP64 P the projection; n_cheb = 42: both project.  Batch 1 takes the
+    unfused contraction with w kept, batch 40 the fused one (w kept by the fused kernel as it
+    goes)."""
     cfg = W.tiny_config(n_ell=7, ell_max=60, n_chi=9, n_R=7, n_cheb=n_cheb, k_max=0.6, n_g=4, n_s=3)
     plan = B.plan_for_config(cfg, precisions=("fp32",))
     try:
