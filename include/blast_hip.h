@@ -76,9 +76,9 @@ typedef enum {
  * Ttilde and the forward contracts it with the nodal P values themselves, making and
  * storing no coefficients, when: FP16X3 on FP32 P with n_cheb % 8 == 0 and at most 16
  * bins (P rows split into FP16 hi + lo inside the contraction kernel; with 17-20 bins P is
- * split by the coefficient-input conversion instead of projected); FP32 on FP32 P and
- * FP64 on FP64 P with n_cheb a multiple of 32 (P rows are then laid out as the
- * coefficient rows).  The backward on such calls computes dP = B^T dw likewise.  The
+ * split by the coefficient-input conversion instead of projected); FP32 on FP32 P with
+ * n_cheb % 4 == 0 (P rows read in place of the padded coefficient rows); FP64 on FP64 P
+ * with n_cheb a multiple of 32 (P rows are then laid out as the coefficient rows).  The backward on such calls computes dP = B^T dw likewise.  The
  * result is that of the projection route up to rounding; on the ridge R ~ 1 the terms
  * B_j P_j are quadrature weights of one sign, so the sum cancels far less than the
  * Chebyshev terms do and the error of the mixed paths drops on the named workloads
