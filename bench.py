@@ -607,6 +607,11 @@ def main():
         v.pop("algorithmic_bytes", None)
         v["kernel"] = kernel_of[k]
         v["traffic"] = counter_traffic(kernel_of[k], cfg.name, Bn, prec)
+    # the whole step against HBM: every stage's algorithmic bytes (including the R-weights table
+    # and Y, which one stage writes and the next reads) over the step's wall time
+    step_bytes = float(sum(work[k]["bytes"] for k in per_launch if k in work))
+    roof["step"] = {"algorithmic_bytes": step_bytes, "achieved": step_bytes / (ms_per_step * 1e-3) / 1e9,
+                    "peak": 8000.0, "unit": "GB/s", "frac": step_bytes / (ms_per_step * 1e-3) / 8e12}
 
     # accuracy of the timed path: cosmology 0 (the stored oracle values' cosmology) against them
     res = out[0].cpu().numpy()

@@ -32,5 +32,8 @@ def test_bench_prints_one_json_line_with_the_contract_keys():
         assert k in roof, k
     assert roof["bound"] in ("hbm", "mfma") and 0 < roof["frac"] < 1
     assert roof["frac"] == pytest.approx(roof["achieved"] / roof["peak"], rel=1e-9)
+    step = roof["step"]  # the whole step against HBM: at least the dominant kernel's bytes, in more time
+    assert step["algorithmic_bytes"] >= roof["algorithmic_bytes"] and 0 < step["frac"] < 1
+    assert step["frac"] == pytest.approx(step["achieved"] / step["peak"], rel=1e-9)
     print("config 1 bench:", d["value"], "sets/s, error", d.get("max_rel_err_vs_oracle"), flush=True)
     assert d["max_rel_err_vs_oracle"] <= 1e-3
