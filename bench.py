@@ -36,10 +36,10 @@ def log(*a):
 def nodal_path(prec, cfg):
     """Whether the library contracts the nodal basis (the DCT applied to the basis when the plan
     is made) with nodal P itself, with no projection per call: FP16X3 on FP32 P with
-    n_cheb % 8 == 0 and at most 16 bins; FP32 on FP32 P with n_cheb % 4 == 0; FP64 on FP64 P with
+    n_cheb % 4 == 0 and at most 16 bins; FP32 on FP32 P with n_cheb % 4 == 0; FP64 on FP64 P with
     n_cheb % 32 == 0 (the bench's P types)."""
     if prec == "fp16x3":
-        return cfg.n_cheb % 8 == 0 and cfg.n_g + cfg.n_s <= 16
+        return cfg.n_cheb % 4 == 0 and cfg.n_g + cfg.n_s <= 16
     if prec == "fp32":
         return cfg.n_cheb % 4 == 0
     return prec == "fp64" and cfg.n_cheb % 32 == 0

@@ -67,14 +67,14 @@ typedef enum {
  * coefficients projected from nodal P: from the row's largest |P_j|, which bounds
  * |c_n| / 2, the projection running the same three products on P and the DCT matrix
  * split into FP16 hi + lo parts).  FP16X3 runs the fused contraction + R-quadrature
- * only: it needs nodal P with n_cheb % 8 == 0 (or P given as coefficients),
- * n_g + n_s <= 20 and no w_save, and is not available to the adjoint; other requests
+ * only: it needs nodal P with n_cheb % 4 == 0 in FP32 or n_cheb % 8 == 0 in FP64 (or P
+ * given as coefficients), n_g + n_s <= 20 and no w_save, and is not available to the adjoint; other requests
  * are refused with BLAST_E_UNSUPPORTED.
  *
  * Nodal basis.  Since c = D P (Eq. dft, D the DCT-II matrix), the contraction
  * sum_n Ttilde_n c_n equals sum_j B_j P_j with B = Ttilde D; the plan keeps B next to
  * Ttilde and the forward contracts it with the nodal P values themselves, making and
- * storing no coefficients, when: FP16X3 on FP32 P with n_cheb % 8 == 0 and at most 16
+ * storing no coefficients, when: FP16X3 on FP32 P with n_cheb % 4 == 0 and at most 16
  * bins (P rows split into FP16 hi + lo inside the contraction kernel; with 17-20 bins P is
  * split by the coefficient-input conversion instead of projected); FP32 on FP32 P with
  * n_cheb % 4 == 0 (P rows read in place of the padded coefficient rows); FP64 on FP64 P

@@ -3612,7 +3612,11 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     if (x.prec == BLAST_FP16X3) {
         if (a->w_save) return set_error("FP16X3 runs the fused path only and cannot keep w"), BLAST_E_UNSUPPORTED;
         if (x.nbins > 20) return set_error("FP16X3 takes at most 20 bins"), BLAST_E_UNSUPPORTED;
-        if (a->p_kind == 0 && p->n_cheb % 8) return set_error("FP16X3 needs n_cheb % 8 == 0"), BLAST_E_UNSUPPORTED;
+        // nodal P: the projection's even/odd split needs n_cheb % 8 == 0; FP32 P with the FP16 nodal
+        // basis (n_cheb % 4 == 0) needs no projection
+        if (a->p_kind == 0 && p->n_cheb % 8 && !(a->p_dtype == 1 && p->basis.n16))
+            return set_error("FP16X3 on nodal P needs n_cheb % 8 == 0, or FP32 P with n_cheb % 4 == 0"),
+                   BLAST_E_UNSUPPORTED;
     }
     BLAST_HIP_TRY(allow_large_lds());
     const bool need_w = a->w_save == nullptr;

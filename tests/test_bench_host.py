@@ -83,6 +83,9 @@ def test_stage_work_of_the_precisions():
     assert bench.nodal_path("fp32", cfg96) and not bench.nodal_path("fp64", cfg96)
     cfg7b = types.SimpleNamespace(n_chi=256, n_R=96, n_cheb=102, n_g=10, n_s=5)
     assert not bench.nodal_path("fp32", cfg7b)
+    # FP16X3 on FP32 P needs whole 16-byte granules per row, as FP32 does
+    cfg20n = types.SimpleNamespace(n_chi=256, n_R=96, n_cheb=20, n_g=10, n_s=5)
+    assert bench.nodal_path("fp16x3", cfg20n) and not bench.nodal_path("fp16x3", cfg7b)
     assert bench.stage_work(plan, cfg96, "fp64", B)["projection"]["flops"] * 2 == pytest.approx(
         bench.stage_work(plan, cfg7b, "fp32", B)["projection"]["flops"] * (120 / 102) ** 2)
 

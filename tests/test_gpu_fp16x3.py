@@ -6,6 +6,7 @@ The bar is the mixed paths' 1e-3 (relative error of ``metrics.g16_err``) against
 at small grids and at the two named shapes (stored oracle goldens).  The row scales are checked
 by exact scaling: P -> 2^k P must give C -> 2^k C bit for bit, because every scale is a power of
 two.  Requests outside the fused path are refused."""
+import dataclasses
 import json
 import os
 
@@ -191,8 +192,39 @@ def test_fp16x3_nodal_basis_and_projection_agree(n_cheb):
         plan.close()
 
 
+@pytest.mark.parametrize("n_cheb,n_g,n_s", [(20, 6, 4), (20, 12, 6), (36, 3, 5)])
+def test_fp16x3_fp32_nodal_p_with_n_cheb_a_multiple_of_four(n_cheb, n_g, n_s):
+    """FP32 nodal P needs whole 16-byte granules per row (n_cheb % 4 == 0), not the projection's
+    n_cheb % 8 == 0: the k nodes past n_cheb repeat the last granule against zero basis columns.
+    With up to 16 bins the fused kernel splits P itself, with 17 to 20 P is split into coefficient
+    rows first.  Against the oracle at the mixed paths' bar, batch 1 and a batch of 70."""
+    cfg = W.tiny_config(n_ell=6, ell_max=50, n_chi=8, n_R=6, n_cheb=n_cheb, k_max=0.5, n_g=n_g, n_s=n_s)
+    plan = B.plan_for_config(cfg, precisions=("fp16x3",))
+    try:
+        inps = [W.make_inputs(cfg, W.seed_for(27, i), plan.k_nodes, plan.chi, plan.R, vary=True) for i in range(70)]
+        P = _dev(np.stack([x.P for x in inps]), torch.float32)
+        K1 = _dev(np.stack([x.Kchi for x in inps]))
+        K2 = _dev(np.stack([x.Kchi2 for x in inps]))
+        print("fp16x3 fp32 nodal P", n_cheb, n_g, n_s, flush=True)
+        Cb = plan.forward(P, K1, K2, n_g, n_s, precision="fp16x3").cpu().numpy()
+        C1 = plan.forward(P[-1:].contiguous(), K1[-1:].contiguous(), K2[-1:].contiguous(), n_g, n_s,
+                          precision="fp16x3").cpu().numpy()
+        e = 0.0
+        for i in (0, 33, 69):
+            # the oracle on the FP32-rounded P the kernel reads
+            inp = dataclasses.replace(inps[i], P=inps[i].P.astype(np.float32).astype(np.float64))
+            Cor = _oracle(plan, cfg, inp)
+            e = max(e, g16_err(Cb[i], Cor, n_g, n_s).max())
+            if i == 69:
+                e = max(e, g16_err(C1[0], Cor, n_g, n_s).max())
+        print("fp16x3 fp32 nodal P vs oracle", e, flush=True)
+        assert e <= 1e-3
+    finally:
+        plan.close()
+
+
 def test_fp16x3_refuses_requests_outside_the_fused_path():
-    cfg = W.tiny_config(n_ell=4, ell_max=30, n_chi=6, n_R=5, n_cheb=20, k_max=0.4, n_g=12, n_s=9)
+    cfg = W.tiny_config(n_ell=4, ell_max=30, n_chi=6, n_R=5, n_cheb=22, k_max=0.4, n_g=12, n_s=9)
     plan = B.plan_for_config(cfg, precisions=("fp16x3",))
     try:
         inp = W.make_inputs(cfg, W.seed_for(24), plan.k_nodes, plan.chi, plan.R)
@@ -202,10 +234,12 @@ def test_fp16x3_refuses_requests_outside_the_fused_path():
         with pytest.raises(B.BlastError) as e:
             plan.forward(P, K1, K2, 12, 9, precision="fp16x3")
         assert e.value.status == B.E_UNSUPPORTED
-        # n_cheb = 20 is not a multiple of 8 (nodal P); 10 bins would otherwise be fine
-        with pytest.raises(B.BlastError) as e:
-            plan.forward(P, K1[:, :10].contiguous(), K2[:, :10].contiguous(), 6, 4, precision="fp16x3")
-        assert e.value.status == B.E_UNSUPPORTED
+        # n_cheb = 22 is neither a multiple of 8 (FP64 nodal P) nor of 4 (FP32 nodal P); 10 bins
+        # would otherwise be fine
+        for Pd in (P, _dev(inp.P[None])):
+            with pytest.raises(B.BlastError) as e:
+                plan.forward(Pd, K1[:, :10].contiguous(), K2[:, :10].contiguous(), 6, 4, precision="fp16x3")
+            assert e.value.status == B.E_UNSUPPORTED
         # w cannot be kept
         w = torch.empty(len(plan.chi) * len(plan.R) * plan.rows_pad, dtype=torch.float32, device="cuda")
         with pytest.raises(B.BlastError) as e:
