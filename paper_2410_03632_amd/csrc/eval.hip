@@ -1540,13 +1540,14 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
 // Nodal variant (NOD): the basis operand is the nodal basis B = Ttilde D (the projection of
 // Eq. dft applied to the basis when the plan is made), contracted with the FP32 nodal values P
 // themselves, so no coefficients are made or stored per call.  Each wave moves 8 of the 64 P rows
-// of a node (ncp floats each, k nodes past n_cheb repeating node n_cheb - 1, whose basis columns
-// are zero) into its own part of the node's c buffer, and once they have landed splits them there
-// in place: per row a power-of-two scale puts the largest |P| in [2^14, 2^15), hi = fp16(v) and
-// lo = fp16(v - hi), laid out as the coefficient rows (hi then lo part of each row, granules
-// permuted by row), the row's inverse scale beside the weights.  The split of node b + 1 runs
-// after node b's MFMAs and R-sum, under the basis DMAs of node b + 1, so one barrier per b still
-// orders everything.  The inverse scale multiplies w with the basis row scale (both powers of two).
+// of a node (ncp floats each; past a row's n_cheb values, n_cheb % 4 == 0, its last 16-byte
+// granule again, where the basis columns are zero) into its own part of the node's c buffer, and
+// once they have landed splits them there in place: per row a power-of-two scale puts the largest
+// |P| in [2^14, 2^15), hi = fp16(v) and lo = fp16(v - hi), laid out as the coefficient rows (hi
+// then lo part of each row, granules permuted by row), the row's inverse scale beside the weights.
+// The split of node b + 1 runs after node b's MFMAs and R-sum, under the basis DMAs of node b + 1,
+// so one barrier per b still orders everything.  The inverse scale multiplies w with the basis row
+// scale (both powers of two).
 constexpr int kWideTR = 4;
 
 template <int PREC, int NS, bool NOD = false>
