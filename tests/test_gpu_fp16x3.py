@@ -192,12 +192,13 @@ def test_fp16x3_nodal_basis_and_projection_agree(n_cheb):
         plan.close()
 
 
-@pytest.mark.parametrize("n_cheb,n_g,n_s", [(20, 6, 4), (20, 12, 6), (36, 3, 5)])
+@pytest.mark.parametrize("n_cheb,n_g,n_s", [(20, 6, 4), (20, 12, 6), (36, 3, 5), (68, 2, 2), (100, 10, 5)])
 def test_fp16x3_fp32_nodal_p_with_n_cheb_a_multiple_of_four(n_cheb, n_g, n_s):
     """FP32 nodal P needs whole 16-byte granules per row (n_cheb % 4 == 0), not the projection's
     n_cheb % 8 == 0: the k nodes past n_cheb repeat the last granule against zero basis columns.
     With up to 16 bins the fused kernel splits P itself, with 17 to 20 P is split into coefficient
-    rows first.  Against the oracle at the mixed paths' bar, batch 1 and a batch of 70."""
+    rows first.  One to four blocks of 32 columns (20, 36, 68, 100 nodes).  Against the oracle at
+    the mixed paths' bar, batch 1 and a batch of 70."""
     cfg = W.tiny_config(n_ell=6, ell_max=50, n_chi=8, n_R=6, n_cheb=n_cheb, k_max=0.5, n_g=n_g, n_s=n_s)
     plan = B.plan_for_config(cfg, precisions=("fp16x3",))
     try:
