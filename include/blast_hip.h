@@ -220,7 +220,8 @@ typedef struct {
                              (blast_plan_k_nodes); 1: P holds the Chebyshev coefficients
                              c_n(chi_a, R_b chi_a) of Eq. cheb_pk (the projection is skipped) */
     const void *P;        /* device [batch][n_chi][n_R][n_cheb], 16-byte aligned (as
-                             hipMalloc and torch allocations are): read in 16-byte pieces */
+                             hipMalloc and torch allocations are; INVALID otherwise): read
+                             in 16-byte pieces */
     int32_t n_g, n_s;     /* clustering / shear bins, n_g + n_s <= 32              */
     const double *K_chi;  /* device [batch][n_g+n_s][n_chi]: K at chi_a             */
     const double *K_chi2; /* device [batch][n_g+n_s][n_chi][n_R]: K at R_b chi_a    */
@@ -270,8 +271,8 @@ blast_status blast_cl_forward_noalloc(blast_plan *plan, const blast_cl_args *arg
 /* Adjoint of blast_cl_forward (reverse mode; not in the paper, whose conclusion lists
  * differentiability as future work).  With the same `args` (precision FP64 or FP32)
  * and dC = dL/dC (device, FP64, shaped like args->C) it enqueues on `stream`:
- *   dP      device, nullable, P's dtype and shape: dL/dP (nodal values or coefficients
- *           per args->p_kind) -- the transposed contraction streams the basis again (on
+ *   dP      device, nullable, P's dtype and shape, 16-byte aligned: dL/dP (nodal values or
+ *           coefficients per args->p_kind) -- the transposed contraction streams the basis again (on
  *           nodal P of the path's own type with n_cheb a multiple of 32 the nodal basis,
  *           whose product B^T dw is dP itself: FP64 reads the FP64 nodal basis, FP32 a
  *           transposed FP32 copy of it made at the first such call; otherwise Ttilde^T dw

@@ -3227,6 +3227,8 @@ blast_status check_args(const blast_plan *p, const blast_cl_args *a, Ctx &x) {
     if (a->p_dtype != 0 && a->p_dtype != 1) return set_error("p_dtype must be 0 (FP64) or 1 (FP32)"), BLAST_E_INVALID;
     if (a->p_kind != 0 && a->p_kind != 1) return set_error("p_kind must be 0 (nodal) or 1 (coefficients)"), BLAST_E_INVALID;
     if (!a->P || !a->K_chi || !a->K_chi2) return set_error("P, K_chi and K_chi2 are required"), BLAST_E_INVALID;
+    // every route reads P in 16-byte pieces (the projections' vector loads, the nodal DMAs)
+    if ((uintptr_t)a->P & 15) return set_error("P must be 16-byte aligned"), BLAST_E_INVALID;
     x.ng = a->n_g;
     x.ns = a->n_s;
     x.nbins = x.ng + x.ns;
@@ -3628,14 +3630,12 @@ blast_status forward_impl(blast_plan *p, const blast_cl_args *a, hipStream_t s, 
     // split as coefficient input is (conv).  The BF16 paths keep the projection: with 8 or 16 bits
     // per operand and no row scale on P, the rounding of every P_j can cost more than the
     // cancellation the nodal sum saves (BF16X3 measured both better and worse than through c)
-    // P read in place of c is read in 16-byte pieces, as the library's own c buffers are: a caller's
-    // P that is not 16-byte aligned takes the conversion or projection route instead
-    const bool al16 = ((uintptr_t)a->P & 15) == 0;
+    // P read in place of c is read in 16-byte pieces, as the library's own c buffers are (P is
+    // 16-byte aligned, checked with the arguments)
     const bool fp32p = a->p_kind == 0 && a->p_dtype == 1, fp64p = a->p_kind == 0 && a->p_dtype == 0;
-    const bool nodal = al16 && ((fp32p && ((x.prec == BLAST_FP16X3 && p->basis.n16 &&
-                                             fused_nb(x.prec, x.nbins, a->batch) <= 16) ||
-                                            (x.prec == BLAST_FP32 && p->basis.nf32 && p->n_cheb % 4 == 0))) ||
-                                (fp64p && x.prec == BLAST_FP64 && p->basis.nf64));
+    const bool h16 = x.prec == BLAST_FP16X3 && p->basis.n16 && fused_nb(x.prec, x.nbins, a->batch) <= 16;
+    const bool nodal = (fp32p && (h16 || (x.prec == BLAST_FP32 && p->basis.nf32 && p->n_cheb % 4 == 0))) ||
+                       (fp64p && x.prec == BLAST_FP64 && p->basis.nf64);
     const bool conv = !nodal && fp32p && x.prec == BLAST_FP16X3 && p->basis.n16;
     x.nodal = nodal || conv;
     x.direct = nodal;
@@ -3785,6 +3785,7 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
     if (((size_t)p->n_R * x.nbp + (size_t)p->rows_pad * (x.nbp + 1)) * sizeof(double) > 160 * 1024)
         return set_error("n_R and the multipoles too large for the adjoint's R tile"), BLAST_E_UNSUPPORTED;
     if (!dC) return set_error("dC is required"), BLAST_E_INVALID;
+    if ((uintptr_t)dP & 15) return set_error("dP must be 16-byte aligned"), BLAST_E_INVALID;
     const bool f64 = x.prec == BLAST_FP64;
     // the transposed contraction keeps the dw rows of a tile of 32 cosmologies in LDS
     if (dP && (size_t)kAdjBT * (f64 ? (size_t)(p->rows_pad + 1) * 8 : (size_t)(p->rows_pad + 4) * 4) > 160 * 1024)
@@ -3850,7 +3851,7 @@ blast_status backward(blast_plan *p, const blast_cl_args *a, const double *dC, v
         const dim3 gt = point_tile_grid(p->NP, (a->batch + kAdjBT - 1) / kAdjBT);
         // nodal P of the path's own type with n_cheb == nc_pad: dP = B^T dw with the nodal basis
         // B = Ttilde D (the adjoint of the projection folded in), written straight into dP
-        const bool ndp = a->p_kind == 0 && p->n_cheb == p->nc_pad && ((uintptr_t)dP & 15) == 0 &&
+        const bool ndp = a->p_kind == 0 && p->n_cheb == p->nc_pad &&
                          (f64 ? a->p_dtype == 0 && p->basis.nf64 : a->p_dtype == 1 && p->basis.nf32);
         void *dcn = ndp ? dP : dc;
         if (f64) {

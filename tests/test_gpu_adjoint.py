@@ -108,7 +108,7 @@ def test_batched_adjoint_equals_calls_on_slices(precision, batch):
             if hi <= lo:
                 continue
             sl = slice(lo, hi)
-            part = plan.backward(P[sl].contiguous(), K1[sl].contiguous(), K2[sl].contiguous(), cfg.n_g, cfg.n_s,
+            part = plan.backward(P[sl].clone(), K1[sl].contiguous(), K2[sl].contiguous(), cfg.n_g, cfg.n_s,
                                  G[sl].contiguous(), precision=precision)
             for name, f, q in zip(("P", "K_chi", "K_chi2"), full, part):
                 assert torch.equal(f[sl], q), (precision, name, lo, hi)

@@ -63,7 +63,7 @@ def test_fp16x3_matches_oracle_at_any_batch(n_g, n_s, n_cheb):
         worst = 0.0
         for lo, nb in ((0, 1), (0, 5), (64, 6)):
             sl = slice(lo, lo + nb)
-            Cs = plan.forward(P[sl].contiguous(), K1[sl].contiguous(), K2[sl].contiguous(), n_g, n_s,
+            Cs = plan.forward(P[sl].clone(), K1[sl].contiguous(), K2[sl].contiguous(), n_g, n_s,
                               precision="fp16x3").cpu().numpy()
             for i in range(nb):
                 worst = max(worst, g16_err(Cs[i], Cb[lo + i], n_g, n_s).max())

@@ -60,7 +60,7 @@ def test_fp64_fused_matches_unfused_and_oracle(n_g, n_s, n_cheb, n_ell):
             assert err < 1e-9
             eo = max(eo, g16_err(Cf[i], Cor, n_g, n_s).max())
         sl = slice(39, 70)
-        Cs = plan.forward(P[sl].contiguous(), K1[sl].contiguous(), K2[sl].contiguous(), n_g, n_s,
+        Cs = plan.forward(P[sl].clone(), K1[sl].contiguous(), K2[sl].contiguous(), n_g, n_s,
                           precision="fp64").cpu().numpy()
         es = max(g16_err(Cs[i], Cf[39 + i], n_g, n_s).max() for i in range(31))
         print("fused vs unfused", eu, "vs oracle", eo, "batch 31 vs 70", es, flush=True)

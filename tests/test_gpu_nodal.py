@@ -2,12 +2,14 @@
 plan is made, so that sum_j B[row][j] P_j = sum_n Ttilde[row][n] c_n (Eq. pmd) is contracted with
 the nodal values P themselves and no coefficients are made per call.  The library takes it for
 FP32 nodal P on the FP32 path when n_cheb % 4 == 0 (P rows read in place of coefficient rows),
-on the FP16X3 path (tested with that path) when n_cheb % 8 == 0, and for FP64 nodal P on the
+on the FP16X3 path (tested with that path) when n_cheb % 4 == 0, and for FP64 nodal P on the
 FP64 path when n_cheb is a multiple of 32.  Other inputs take the per-call projection.
 
 Both routes are checked against the FP64 oracle at the FP32 bar (1e-3 of ``metrics.g16_err``),
 on the unfused (batch 1, w kept) and the fused (batch 40) contraction, and w itself against the
 projected route's w element by element."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -125,5 +127,44 @@ def test_named_config_nodal_and_projected_routes(config):
         print("config", config, {"%s %s" % k: v for k, v in res.items()}, flush=True)
         for (prec, route), e in res.items():
             assert e <= (1e-4 if route == "nodal" else 1e-3), (prec, route, e)
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3"])
+def test_p_and_dp_must_be_16_byte_aligned(prec):
+    """Every route reads P in 16-byte pieces (the projections' vector loads, the nodal routes'
+    DMAs), so P one element into its buffer is refused with INVALID before anything runs, as is a
+    dP that is not 16-byte aligned; the same P copied to an aligned buffer goes through."""
+    import ctypes as C
+
+    cfg = W.tiny_config(n_ell=6, ell_max=50, n_chi=8, n_R=6, n_cheb=32, k_max=0.5, n_g=3, n_s=2)
+    plan = B.plan_for_config(cfg, precisions=(prec,))
+    try:
+        inp = W.make_inputs(cfg, W.seed_for(28), plan.k_nodes, plan.chi, plan.R)
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        Pa = _dev(inp.P[None], dt)
+        buf = torch.zeros(Pa.numel() + 1, dtype=dt, device="cuda")
+        Pu = buf[1:].view(Pa.shape)
+        Pu.copy_(Pa)
+        assert Pa.data_ptr() % 16 == 0 and Pu.data_ptr() % 16 != 0
+        K1, K2 = _dev(inp.Kchi[None]), _dev(inp.Kchi2[None])
+        with pytest.raises(B.BlastError) as e:
+            plan.forward(Pu, K1, K2, cfg.n_g, cfg.n_s, precision=prec)
+        assert e.value.status == B.E_INVALID and "aligned" in str(e.value)
+        Ca = plan.forward(Pa, K1, K2, cfg.n_g, cfg.n_s, precision=prec).cpu().numpy()
+        Cor = _oracle(plan, cfg, dataclasses.replace(inp, P=inp.P.astype(np.float32).astype(np.float64))
+                      if dt == torch.float32 else inp)
+        assert g16_err(Ca[0], Cor, cfg.n_g, cfg.n_s).max() <= (1e-6 if prec == "fp64" else 1e-3)
+        if prec == "fp16x3":
+            return  # no adjoint on this path
+        dC = torch.ones((1, B.n_pairs(cfg.n_g, cfg.n_s), cfg.n_ell), dtype=torch.float64, device="cuda")
+        args, keep, shape, _ = plan._prepare(Pa, K1, K2, cfg.n_g, cfg.n_s, prec, None, None, False)
+        dbuf = torch.zeros(Pa.numel() + 1, dtype=dt, device="cuda")
+        st = B.lib().blast_cl_backward(plan._h, C.byref(args), C.c_void_p(dC.data_ptr()),
+                                       C.c_void_p(dbuf[1:].data_ptr()), None, None,
+                                       C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert st == B.E_INVALID and "dP" in B.lib().blast_last_error().decode()
+        torch.cuda.synchronize()
     finally:
         plan.close()

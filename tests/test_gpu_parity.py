@@ -130,7 +130,8 @@ def test_batch_invariance_and_subsets(tiny):
         Pp = P if prec == "fp64" else P.float()
         Cb = plan.forward(Pp, K1, K2, cfg.n_g, cfg.n_s, precision=prec).cpu().numpy()
         for i in range(len(inps)):
-            Ci = plan.forward(Pp[i:i + 1].contiguous(), K1[i:i + 1].contiguous(), K2[i:i + 1].contiguous(),
+            # a copy: a view one cosmology into the batch need not be 16-byte aligned, as P must be
+            Ci = plan.forward(Pp[i:i + 1].clone(), K1[i:i + 1].contiguous(), K2[i:i + 1].contiguous(),
                               cfg.n_g, cfg.n_s, precision=prec).cpu().numpy()
             assert np.array_equal(Ci[0], Cb[i]), prec
     full = plan.forward(P, K1, K2, cfg.n_g, cfg.n_s).cpu().numpy()
@@ -270,7 +271,7 @@ def test_fused_batch_matches_single_calls_and_oracle(n_g, n_s, n_cheb, batch):
             Cb = plan.forward(P, K1, K2, n_g, n_s, precision=prec).cpu().numpy()
             worst = 0.0
             for i in list(range(0, batch, 7)) + [batch - 1]:
-                Ci = plan.forward(P[i:i + 1].contiguous(), K1[i:i + 1].contiguous(), K2[i:i + 1].contiguous(), n_g,
+                Ci = plan.forward(P[i:i + 1].clone(), K1[i:i + 1].contiguous(), K2[i:i + 1].contiguous(), n_g,
                                   n_s, precision=prec).cpu().numpy()[0]
                 worst = max(worst, g16_err(Cb[i], Ci, n_g, n_s).max())
             eo = g16_err(Cb[0], Cor, n_g, n_s).max()

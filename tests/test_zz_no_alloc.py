@@ -58,7 +58,7 @@ def test_noalloc_equals_forward_twice_second_smaller(precision, big):
         # second call: 2 cosmologies, clustering bins 0-1 and shear bin 0, multipoles 1, 2, 4, 6, 8
         bsel = [0, 1, 3]
         idx = np.array([1, 2, 4, 6, 8], dtype=np.int32)
-        P2 = P[3:5].contiguous()
+        P2 = P[3:5].clone()
         K1s, K2s = K1[3:5][:, bsel].contiguous(), K2[3:5][:, bsel].contiguous()
         st, got2, _ = _call_abi(plan, P2, K1s, K2s, 2, 1, precision, ell_idx=idx)
         assert st == B.OK, B.lib().blast_last_error()
