@@ -58,3 +58,42 @@ def test_benchmark_launch_matches_the_stored_oracle_values(full, prec, bar):
     d = max(g16_err(C[i], C[0], cfg.n_g, cfg.n_s).max() for i in SLOTS)
     print(prec, "batch 256 vs oracle", e, "copies", d, flush=True)
     assert e <= bar and d <= bar, (e, d)
+
+
+def test_gradient_at_the_benchmark_launch(full):
+    """The gradient step ``bench.py`` times (FP32: a forward keeping w and Y, then the adjoint to
+    dP, dK_chi and dK_chi2) at batch 256 on the full shapes, against the FP64 adjoint of the
+    stored cosmology alone, element by element with a floor of 1e-3 of the cosmology's largest
+    gradient (an entry is a sum of terms of both signs, and FP32 rounds the sum of their
+    magnitudes).  The adjoint to dP alone (a forward keeping nothing) gives the same dP bit for
+    bit."""
+    cfg, plan, inp, others, _ = full
+    nb = 256
+    P = torch.empty((nb, cfg.n_chi, cfg.n_R, cfg.n_cheb), dtype=torch.float32, device="cuda")
+    gold = torch.as_tensor(inp.P, dtype=torch.float32, device="cuda")
+    oth = [o.to(device="cuda", dtype=torch.float32) for o in others]
+    for i in range(nb):
+        P[i] = gold if i in SLOTS else oth[i % 3]
+    K1 = torch.as_tensor(inp.Kchi, device="cuda").unsqueeze(0).expand(nb, -1, -1).contiguous()
+    K2 = torch.as_tensor(inp.Kchi2, device="cuda").unsqueeze(0).expand(nb, -1, -1, -1).contiguous()
+    shape = (nb, B.n_pairs(cfg.n_g, cfg.n_s), plan.n_ell)
+    g1 = torch.randn(shape[1:], generator=torch.Generator(device="cpu").manual_seed(5), dtype=torch.float64)
+    G = g1.cuda().unsqueeze(0).expand(shape).contiguous()
+    w = torch.empty(nb * cfg.n_chi * cfg.n_R * plan.rows_pad, dtype=torch.float32, device="cuda")
+    y = torch.empty(plan.y_numel(nb, cfg.n_g + cfg.n_s), dtype=torch.float32, device="cuda")
+    print("full batch gradient", flush=True)
+    plan.forward(P, K1, K2, cfg.n_g, cfg.n_s, precision="fp32", w_save=w, y_save=y)
+    r32 = plan.backward(P, K1, K2, cfg.n_g, cfg.n_s, G, precision="fp32", w_save=w, y_save=y)
+    dp_only = plan.backward(P, K1, K2, cfg.n_g, cfg.n_s, G, precision="fp32", want=("P",))[0]
+    assert torch.equal(dp_only, r32[0])
+    P64 = torch.as_tensor(inp.P.astype(np.float32).astype(np.float64)[None], device="cuda")
+    r64 = plan.backward(P64, K1[:1].contiguous(), K2[:1].contiguous(), cfg.n_g, cfg.n_s, G[:1].contiguous(),
+                        precision="fp64")
+    for name, a, b in zip(("P", "K_chi", "K_chi2"), r64, r32):
+        assert torch.isfinite(b).all(), name
+        a = a[0].double().cpu().numpy()
+        floor = 1e-3 * np.abs(a).max()
+        for i in SLOTS:
+            e = float((np.abs(a - b[i].double().cpu().numpy()) / np.maximum(np.abs(a), floor)).max())
+            print("batch 256 FP32 adjoint vs FP64", name, "place", i, "max element-wise error %.2e" % e, flush=True)
+            assert e < 1e-3, (name, i, e)
