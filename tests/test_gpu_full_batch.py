@@ -4,7 +4,8 @@ cosmology tiles of 64, five row groups, every chi node).  The batch holds the st
 cosmology (Eq. final_cls evaluated by the FP64 oracle, ``tests/golden/c2_oracle.json``) at
 several places (the same kernel tables everywhere), the other places other seeded cosmologies;
 the stored copies are compared element by element at each path's bar (1e-3 for the mixed paths,
-1e-6 for FP64), and every output is checked finite."""
+1e-6 for FP64), and every output is checked finite.  The gradient step is checked at the same
+launch against the FP64 adjoint."""
 import json
 import os
 
