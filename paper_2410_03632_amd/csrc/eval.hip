@@ -1539,15 +1539,16 @@ __global__ __launch_bounds__(256 * kFusedTR) void contract_quad_kernel(
 //
 // Nodal variant (NOD): the basis operand is the nodal basis B = Ttilde D (the projection of
 // Eq. dft applied to the basis when the plan is made), contracted with the FP32 nodal values P
-// themselves, so no coefficients are made or stored per call.  Each wave moves 8 of the 64 P rows
+// themselves, so no coefficients are made or stored per call.  Each wave loads 8 of the 64 P rows
 // of a node (ncp floats each; past a row's n_cheb values, n_cheb % 4 == 0, its last 16-byte
-// granule again, where the basis columns are zero) into its own part of the node's c buffer, and
-// once they have landed splits them there in place: per row a power-of-two scale puts the largest
-// |P| in [2^14, 2^15), hi = fp16(v) and lo = fp16(v - hi), laid out as the coefficient rows (hi
-// then lo part of each row, granules permuted by row), the row's inverse scale beside the weights.
-// The split of node b + 1 runs after node b's MFMAs and R-sum, under the basis DMAs of node b + 1,
-// so one barrier per b still orders everything.  The inverse scale multiplies w with the basis row
-// scale (both powers of two).
+// granule again, where the basis columns are zero) into registers one node ahead and splits them
+// into the node's c buffer: per row a power-of-two scale puts the largest |P| in [2^14, 2^15),
+// hi = fp16(v) and lo = fp16(v - hi), laid out as the coefficient rows (hi then lo part of each
+// row, granules permuted by row), the row's inverse scale beside the weights.  After the barrier
+// of node b a wave issues the DMAs of node b + 1, splits its rows of node b + 1 (loaded during node
+// b - 1, so nothing waits), loads its rows of node b + 2 into the freed registers, then runs node
+// b's MFMAs and R-sum: the split runs under the DMAs and one barrier per b still orders
+// everything.  The inverse scale multiplies w with the basis row scale (both powers of two).
 constexpr int kWideTR = 4;
 
 template <int PREC, int NS, bool NOD = false>
@@ -1565,11 +1566,6 @@ struct WideShape {
     static constexpr size_t LDS = 2 * A_BUF + 2 * (C_BUF + X_BUF);
 };
 
-// one 16-byte LDS read at base + offset, waited for
-template <int O0>
-__device__ inline void lds_read1(uint32_t b0, U4 &r0) {
-    asm volatile("ds_read_b128 %0, %1 offset:%2\n\ts_waitcnt lgkmcnt(0)" : "=&v"(r0) : "v"(b0), "i"(O0) : "memory");
-}
 // two 4-byte LDS reads at base + offsets, waited for
 template <int O0, int O1>
 __device__ inline void lds_read_f2(uint32_t b0, float &r0, float &r1) {
@@ -1583,18 +1579,6 @@ __device__ inline void lds_write8(uint32_t a, uint64_t v) {
 }
 __device__ inline void lds_write4(uint32_t a, float v) {
     asm volatile("ds_write_b32 %0, %1" : : "v"(a), "v"(v) : "memory");
-}
-// vmcnt(n) for a wave-uniform n in [0, 6]
-__device__ inline void wait_vmcnt_n(int n) {
-    switch (n) {
-        case 0: wait_vmcnt<0>(); break;
-        case 1: wait_vmcnt<1>(); break;
-        case 2: wait_vmcnt<2>(); break;
-        case 3: wait_vmcnt<3>(); break;
-        case 4: wait_vmcnt<4>(); break;
-        case 5: wait_vmcnt<5>(); break;
-        default: wait_vmcnt<6>(); break;
-    }
 }
 // maximum over the 8 lanes of an aligned group (DPP: swap neighbours, swap pairs, mirror halves)
 __device__ inline float max8(float m) {
@@ -1618,7 +1602,7 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
     constexpr int SWZ = GPR % 16 == 0 ? 15 : (GPR % 8 == 0 ? 7 : (GPR % 4 == 0 ? 3 : (GPR % 2 == 0 ? 1 : 0)));
     constexpr bool KROT = NB == 16;
     static_assert(PREC == BLAST_FP16X3 && NB <= 16 && S::LDS <= 160 * 1024, "LDS of the wide fused kernel");
-    static_assert(!NOD || S::C_PW * 1024 == 8 * S::CROW, "nodal: a wave's P DMAs are its 8 rows");
+    static_assert(!NOD || S::C_PW * 1024 == 8 * S::CROW, "nodal: the 8 P rows of each wave fill the c buffer");
     __shared__ __align__(1024) unsigned char A0[S::A_BUF], A1[S::A_BUF];
     __shared__ __align__(1024) unsigned char C0[S::C_BUF + S::X_BUF], C1[S::C_BUF + S::X_BUF];
 
@@ -1694,24 +1678,10 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
         const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
         lds_dma16(srcX + ab * strideX, buf + S::C_BUF + (size_t)chX * 1024);
     };
-    // DMAs issued after a wave's c (or P) DMAs of one b: its weight or scale chunk and its basis
-    const int nXA = (w <= KCH ? 1 : 0) + nA;
-    const char *srcC[S::C_PW];
-    size_t cstride;
-    if constexpr (NOD) {
-        // wave w: chunks C_PW w .. C_PW w + C_PW - 1 = rows 8w .. 8w + 7 of P[beta][a, b][n]
-        const float *P = (const float *)cv;
-        const size_t NPN = (size_t)n_chi * n_R * n_cheb;
-        const int gmax = n_cheb / 4 - 1;
-#pragma unroll
-        for (int k = 0; k < S::C_PW; ++k) {
-            const int pos = (w * S::C_PW + k) * 1024 + lane * 16;
-            const int row = pos / S::CROW, gp = (pos % S::CROW) / 16;
-            const int bb = bt * 64 + (row < nb ? row : 0);
-            srcC[k] = (const char *)(P + (size_t)bb * NPN + 4 * min(gp, gmax));
-        }
-        cstride = (size_t)n_cheb * 4;
-    } else {
+    // coefficient path: the c rows of the tile by DMA (the nodal path loads P rows into registers)
+    const char *srcC[S::C_PW] = {};
+    size_t cstride = 0;
+    if constexpr (!NOD) {
         const uint16_t *c = (const uint16_t *)cv;
 #pragma unroll
         for (int k = 0; k < S::C_PW; ++k) {
@@ -1730,33 +1700,33 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
         const size_t ab = (size_t)a * n_R + (b < n_R ? b : n_R - 1);
 #pragma unroll
         for (int k = 0; k < S::C_PW; ++k)
-            lds_dma16(srcC[k] + ab * cstride,
-                      buf + (size_t)(NOD ? w * S::C_PW + k : min(w + k * S::NW, S::C_CH - 1)) * 1024);
+            lds_dma16(srcC[k] + ab * cstride, buf + (size_t)min(w + k * S::NW, S::C_CH - 1) * 1024);
     };
-    // nodal: split this wave's 8 P rows of a landed buffer in place (lane: row 8w + lane / 8,
-    // 16-byte granules lane % 8 + 8 (q ^ o) of it, o = r mod NS for NS = 2 and 4: the two rows of a
-    // 16-lane read phase read different 128-byte halves of the 64 banks, and the four rows of a
-    // 32-lane write phase write four different 64-byte quarters of a part)
-    auto split_rows = [&](unsigned char *__restrict__ buf) {
+    // nodal: lane (row r = 8w + lane / 8 of the tile, sub = lane % 8) holds the 16-byte granules
+    // sub + 8 (q ^ o) of its P row, o = r mod NS for NS = 2 and 4 (so that the four rows of a 32-lane
+    // write phase write four different 64-byte quarters of a part); granules past n_cheb / 4 repeat
+    // the last one
+    const float *prow = (const float *)cv;
+    int goff[NS];
+    if constexpr (NOD) {
+        const int r = 8 * w + (lane >> 3), sub = lane & 7;
+        const int o = NS == 4 ? (r & 3) : (NS == 2 ? (r & 1) : 0);
+        prow += (size_t)(bt * 64 + (r < nb ? r : 0)) * n_chi * n_R * n_cheb;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) goff[q] = 4 * min(sub + 8 * (q ^ o), n_cheb / 4 - 1);
+    }
+    auto load_P = [&](int b, U4 (&raw)[NS]) {
+        const float *pr = prow + ((size_t)a * n_R + (b < n_R ? b : n_R - 1)) * n_cheb;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) raw[q] = *(const U4 *)(pr + goff[q]);
+    };
+    // split a node's P rows held in registers into buf: the row max over the 8 lanes of a row, the
+    // power-of-two scale, FP16 hi and lo; then after() (which reloads raw), then the LDS writes
+    auto split_rows = [&](const U4 (&raw)[NS], unsigned char *__restrict__ buf, auto &&after) {
         if constexpr (NOD) {
             const int r = 8 * w + (lane >> 3), sub = lane & 7;
             const int o = NS == 4 ? (r & 3) : (NS == 2 ? (r & 1) : 0);
             const uint32_t rb = lds_addr(buf) + (uint32_t)(r * S::CROW);
-            int gq[NS];
-#pragma unroll
-            for (int q = 0; q < NS; ++q) gq[q] = sub + 8 * (q ^ o);
-            U4 raw[NS];
-            if constexpr (NS == 4) {
-                lds_read4<0, 0, 0, 0>(rb + 16 * gq[0], rb + 16 * gq[1], rb + 16 * gq[2], rb + 16 * gq[3], raw[0],
-                                      raw[1], raw[2], raw[3]);
-            } else if constexpr (NS == 2) {
-                lds_read2<0, 0>(rb + 16 * gq[0], rb + 16 * gq[1], raw[0], raw[1]);
-            } else if constexpr (NS == 3) {
-                lds_read2<0, 128>(rb + 16 * sub, rb + 16 * sub, raw[0], raw[1]);
-                lds_read1<256>(rb + 16 * sub, raw[2]);
-            } else {
-                lds_read1<0>(rb + 16 * sub, raw[0]);
-            }
             float m = 0.f;
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
@@ -1767,15 +1737,22 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
             m = max8(m);
             const int ex = __builtin_amdgcn_frexp_expf(m) - 1;  // floor(log2 m); -1 for m = 0
             const float sc = __builtin_amdgcn_ldexpf(1.f, 14 - ex);
+            h4v hh[NS], ll[NS];
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
                 const f4v x = __builtin_bit_cast(f4v, raw[q]) * sc;
-                const h4v h = __builtin_convertvector(x, h4v);
-                const h4v l = __builtin_convertvector(x - __builtin_convertvector(h, f4v), h4v);
-                const int gr = gq[q], G = gr >> 1;
-                const uint32_t o = rb + (uint32_t)(((G ^ (r & SWZ)) << 4) | ((gr & 1) << 3));
-                lds_write8(o, __builtin_bit_cast(uint64_t, h));
-                lds_write8(o + S::ROWB, __builtin_bit_cast(uint64_t, l));
+                hh[q] = __builtin_convertvector(x, h4v);
+                ll[q] = __builtin_convertvector(x - __builtin_convertvector(hh[q], f4v), h4v);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            after();  // raw is free from here on
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const int gr = sub + 8 * (q ^ o), G = gr >> 1;
+                const uint32_t oo = rb + (uint32_t)(((G ^ (r & SWZ)) << 4) | ((gr & 1) << 3));
+                lds_write8(oo, __builtin_bit_cast(uint64_t, hh[q]));
+                lds_write8(oo + S::ROWB, __builtin_bit_cast(uint64_t, ll[q]));
             }
             if (sub == 0) lds_write4(lds_addr(buf) + PSC + 4 * r, __builtin_amdgcn_ldexpf(1.f, ex - 14));
             asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -1791,16 +1768,21 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
             for (int q = 0; q < NB; ++q) y[j][r][q] = 0.f;
     const int arow = min(ti, TR - 1) * NS * 64 + lane;
 
+    U4 R[NS];
     auto step = [&](int b, const unsigned char *__restrict__ Ab, const unsigned char *__restrict__ Cb,
                     unsigned char *__restrict__ Cnext, unsigned char *__restrict__ Anext) {
-        // everything issued one b ago has landed (this wave's DMAs), then all waves' (barrier)
+        // everything issued one b ago has landed (this wave's DMAs and P loads), then all waves'
+        // (barrier)
         wait_vmcnt<0>();
         __builtin_amdgcn_s_barrier();
         __builtin_amdgcn_sched_barrier(0);
-        dma_C(b + 1, Cnext);
+        if constexpr (!NOD) dma_C(b + 1, Cnext);
         dma_X(b + 1, Cnext);
         dma_A(b + 1, Anext);
         __builtin_amdgcn_sched_barrier(0);
+        // nodal: the P rows of b + 1 (loaded during b - 1) split into their buffer under the DMAs
+        // just issued, and the rows of b + 2 loaded into the same registers once converted
+        if constexpr (NOD) split_rows(R, Cnext, [&] { load_P(b + 2, R); });
         if (busy) {
             constexpr int NQ = NB / 4;
             constexpr int ALO = TR * NS * 1024, CLO = NOD ? S::ROWB : (int)(S::C_BUF / NPART);
@@ -1879,20 +1861,19 @@ __global__ __launch_bounds__(512) void contract_quad_wide_kernel(
             };
             static_for<0, 2>(rsum);
         }
-        if constexpr (NOD) {
-            // this wave's P rows of b + 1 (issued first) have landed; its weight and basis DMAs may not
-            wait_vmcnt_n(nXA);
-            split_rows(Cnext);
-        }
     };
 
     // issue order: c(0) + weights(0), A(0); then per b, after its barrier: c(b+1) + weights(b+1), A(b+1)
-    dma_C(0, C0);
+    if constexpr (NOD) {
+        load_P(0, R);
+    } else {
+        dma_C(0, C0);
+    }
     dma_X(0, C0);
     dma_A(0, A0);
     if constexpr (NOD) {
-        wait_vmcnt_n(nXA);
-        split_rows(C0);
+        wait_vmcnt<0>();
+        split_rows(R, C0, [&] { load_P(1, R); });
     }
     for (int b = 0; b < n_R; b += 2) {
         step(b, A0, C0, C1, A1);
