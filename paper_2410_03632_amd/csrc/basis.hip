@@ -823,7 +823,7 @@ blast_status derive_precisions(blast_plan *p, hipStream_t s) {
         if (e != hipSuccess) return p->d_dct16 = nullptr, fail(e, "FP16 projection table");
         hipLaunchKernelGGL(to_dct16_kernel, dim3((unsigned)((nent + 255) / 256)), dim3(256), 0, s, p->d_dctn64,
                            p->n_cheb, NT, NK, dct16_exp(p->n_cheb), p->d_dct16);
-        if (p->n_cheb % 4 == 0) {  // P rows of whole 16-byte granules: the nodal path's DMA unit
+        if (p->n_cheb % 4 == 0) {  // P rows of whole 16-byte granules, loaded as such by the FP16X3 nodal kernel
             e = hipMalloc(&p->basis.n16, n * sizeof(uint16_t));
             if (e != hipSuccess) return p->basis.n16 = nullptr, fail(e, "FP16 nodal basis");
             e = hipMalloc(&p->basis.nl16, n * sizeof(uint16_t));
